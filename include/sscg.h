@@ -1,0 +1,227 @@
+/*
+ * sscg.h -- C ABI of the adaptive s-step conjugate gradient library
+ * (E. Carson, "The adaptive s-step conjugate gradient method", arXiv 1701.03989)
+ * for AMD Instinct MI355X (gfx950).  Implementation: libsscg.so, hand-written HIP.
+ *
+ * Problem (Section 1): solve A x = b for a sparse symmetric positive definite
+ * A given in CSR form.  sscg_solve runs Algorithm 4 (adaptive s-step CG), or
+ * Algorithm 2 (fixed s) or Algorithm 3 (given schedule of s values), and
+ * returns x, the s_k schedule and the residual history.  The per-stage calls
+ * run one step of an outer block (Algorithm 4) on caller-provided device
+ * buffers.
+ *
+ * Conventions for every call
+ *  - All matrix and vector pointers are DEVICE pointers (hipMalloc'd or torch
+ *    tensors' data_ptr()) unless a comment says "host".  The caller owns them;
+ *    the library never frees or reallocates caller memory.
+ *  - FP64 throughout.  Every row sum, inner product and row-wise linear
+ *    combination is rounded once from its exact value (the terms' products
+ *    enter exactly), so results do not depend on the order of the terms.
+ *  - Work is enqueued on the context's stream.  Per-stage calls return once
+ *    their kernels are enqueued; sscg_solve and sscg_spectral_bounds return
+ *    after the stream has finished the call's work.
+ *  - Return value: SSCG_OK (0), or a positive numerical outcome (x is valid,
+ *    the history is complete), or a negative error code, in which case no
+ *    caller buffer has been written and sscg_last_error() says why.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef SSCG_H
+#define SSCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+  SSCG_OK = 0,             /* true relative residual <= tol                   */
+  SSCG_NOT_CONVERGED = 1,  /* max_iters inner iterations done, tol not reached */
+  SSCG_BREAKDOWN = 2,      /* a block could not take one step (p'^T G B p' <= 0
+                              or non-finite), or the residual became non-finite */
+  SSCG_ERR_ARG = -1,       /* invalid argument (message in sscg_last_error)    */
+  SSCG_ERR_HIP = -2,       /* HIP runtime error                               */
+  SSCG_ERR_OOM = -3        /* device allocation failed                        */
+};
+
+enum { SSCG_MODE_ADAPTIVE = 0, SSCG_MODE_FIXED = 1, SSCG_MODE_SCHEDULE = 2 };
+enum { SSCG_BASIS_MONOMIAL = 0, SSCG_BASIS_CHEBYSHEV = 1 };
+
+/* Largest s the library accepts: the (2s+1)-dimensional coordinate problem
+ * of a block is solved by one wavefront. */
+#define SSCG_S_LIMIT 16
+
+/* ---------------------------------------------------------------- types */
+typedef struct sscg_ctx sscg_ctx;
+
+/* Sparse SPD matrix in CSR form (device arrays).  rowptr[0] = 0, rowptr
+ * non-decreasing, rowptr[n] = nnz; col entries in [0, n).  Only the values
+ * are read as given: symmetry and positive definiteness are the caller's
+ * promise (a violation shows up as SSCG_BREAKDOWN or SSCG_NOT_CONVERGED). */
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* rowptr; /* n+1 */
+  const int32_t* col;    /* nnz */
+  const double* val;     /* nnz */
+} sscg_csr;
+
+/* Inputs of Algorithm 4 (its Require line) plus the basis choice. */
+typedef struct {
+  int32_t mode;          /* SSCG_MODE_*                                          */
+  int32_t basis;         /* SSCG_BASIS_* (Sections 2 and 5 name both)            */
+  double tol;            /* target relative residual; eps* = tol*||b||_2          */
+  int32_t s_max;         /* 1..SSCG_S_LIMIT                                      */
+  int32_t s0_bar;        /* initial basis size (0: s_max, as in Section 5)        */
+  int32_t f;             /* basis growth limit (0: s_max, as in Section 5)        */
+  int32_t fixed_s;       /* MODE_FIXED: s of Algorithm 2                          */
+  const int32_t* schedule; /* host; MODE_SCHEDULE: s_0, s_1, ... (the last repeats) */
+  int32_t schedule_len;
+  double c;              /* constant c_{k,j} of eqs. condy/check (default 1)      */
+  double lambda_min;     /* Chebyshev interval; NaN: estimated by                 */
+  double lambda_max;     /*   sscg_spectral_bounds (Lanczos / Gershgorin)         */
+  int32_t lanczos_steps; /* steps of that estimate (default 30)                   */
+  uint64_t lanczos_seed; /* SplitMix64 seed of its start vector (default 0)       */
+  int32_t equilibrate;   /* 1: solve D^-1/2 A D^-1/2 (Section 5), D_i = max|a_ij| */
+  int32_t inner_check;   /* 1: in-loop break of eq. check (Alg. 4); 0: s_k = s~   */
+  int32_t max_iters;     /* cap on total inner iterations                         */
+} sscg_opts;
+
+/* Per-solve outputs.  The arrays are HOST memory owned by the caller, each
+ * with room for `cap` blocks (any may be NULL); entry k describes outer
+ * block k.  Blocks beyond `cap` are still run, only not recorded. */
+typedef struct {
+  int32_t cap;
+  int32_t blocks;        /* outer blocks run (= global synchronizations)          */
+  int32_t iters;         /* inner iterations run, m                               */
+  int32_t status;        /* same as the return value                              */
+  double relres0;        /* ||b - A x_1|| / ||b||                                 */
+  double relres;         /* ||b - A x|| / ||b|| of the returned x                  */
+  double lambda_min, lambda_max;   /* Chebyshev interval used                      */
+  int64_t basis_vectors;           /* matrix-vector products of all bases          */
+  int64_t wasted_vectors;          /* of those, products not needed by s_k steps   */
+  int32_t* s_bar;        /* s_bar_k of Alg. 4 (s of Alg. 2/3)                      */
+  int32_t* s_built;      /* basis steps built, after the rank guard                */
+  int32_t* s_tilde;      /* s~_k chosen by eq. condy                               */
+  int32_t* s_k;          /* inner iterations performed                            */
+  double* gamma;         /* estimate of kappa(Y_{k,s~}) (NaN unless adaptive)       */
+  double* thr;           /* right-hand side of eq. condy                           */
+  double* res_updated;   /* (r'^T G r')^(1/2) after the block                      */
+  double* relres_true;   /* ||b - A x|| / ||b|| after the block                    */
+  double* kappa;         /* cap*s_max: kappa(G_{k,i}), i = 1..s_max (NaN if not
+                            computed); row k at kappa + k*s_max                    */
+} sscg_result;
+
+/* Device-side record of one block's coordinate solve (sscg_small_solve). */
+typedef struct {
+  int32_t s_tilde;       /* s~ (eq. condy), or the given iteration count          */
+  int32_t s_k;           /* iterations performed                                  */
+  int32_t status;        /* SSCG_OK or SSCG_BREAKDOWN                             */
+  int32_t d;             /* dimension of the coefficient vectors (2s+1 or s+1)    */
+  double gamma;          /* sqrt(kappa(G_{s~})) (adaptive)                        */
+  double thr;            /* eps* / (c eps ||r_{m+1}||) (adaptive)                  */
+  double rnorm;          /* ||r_{m+1}|| = sqrt(G[R0,R0]) (block 0: G[P0,P0])       */
+  double rr;             /* r'^T G r' after the last iteration                    */
+  double kappa[SSCG_S_LIMIT];      /* kappa(G_i), i = 1..s (adaptive)              */
+  double alpha[SSCG_S_LIMIT];      /* alpha_{m+j}, j = 1..s_k                      */
+  double beta[SSCG_S_LIMIT];       /* beta_{m+j}                                   */
+} sscg_block_info;
+
+/* Parameters of one block's coordinate solve. */
+typedef struct {
+  int32_t s;             /* basis steps built (s_bar after the rank guard)        */
+  int32_t first;         /* 1 in block 0: basis is P_0..P_s only                   */
+  int32_t adaptive;      /* 1: choose s~ <= s by eq. condy; 0: s~ = iters          */
+  int32_t iters;         /* iterations when !adaptive (1 <= iters <= s)            */
+  int32_t inner_check;   /* adaptive: break by eq. check                          */
+  int32_t basis;         /* SSCG_BASIS_*                                          */
+  double lambda_min, lambda_max;   /* Chebyshev interval                           */
+  double eps_star;       /* tol * ||b||                                           */
+  double c;              /* c_{k,j}                                               */
+} sscg_block_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `stream` (a
+ * hipStream_t; NULL = the null stream).  The context owns its workspace. */
+int sscg_create(sscg_ctx** ctx, int device, void* stream);
+void sscg_destroy(sscg_ctx* ctx);
+/* Message of the last failing call on ctx ("" if none).  Valid until the
+ * next call on ctx.  sscg_last_error(NULL) reports sscg_create failures. */
+const char* sscg_last_error(const sscg_ctx* ctx);
+/* Fill *opts with the defaults of Section 5 (adaptive, monomial, tol 1e-10,
+ * s_max 8, s0_bar = f = s_max, c = 1, inner checks on, no equilibration). */
+void sscg_opts_default(sscg_opts* opts);
+
+/* ---------------------------------------------------------------- solver */
+
+/* Algorithm 4 (opts->mode = ADAPTIVE), 2 (FIXED) or 3 (SCHEDULE) on A x = b.
+ * b: device, n.  x: device, n; x_1 on entry, the solution on return.
+ * res: may be NULL.  Block 0 builds the P block only (p_1 = r_1); later
+ * blocks build min(s_bar_k, m) steps (m = iterations so far), since a larger
+ * basis of the same Krylov space is rank deficient.  The solve stops after the
+ * first block whose true relative residual is <= tol. */
+int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x,
+               const sscg_opts* opts, sscg_result* res);
+
+/* ---------------------------------------------------------------- stages */
+
+/* Setup (Algorithm 4, first line): r = b - A x, and on the device
+ * out2[0] = ||r||^2, out2[1] = ||b||^2 (device, 2 doubles).  r may be NULL. */
+int sscg_residual(sscg_ctx* ctx, const sscg_csr* A, const double* b, const double* x,
+                  double* r, double* out2);
+
+/* Chebyshev interval: *lambda_max = max_i sum_j |a_ij| (Gershgorin) and
+ * *lambda_min = smallest Ritz value of `steps` Lanczos steps started from the
+ * SplitMix64(seed) vector u_i = (z_i >> 11) 2^-52 - 1.  Host outputs. */
+int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t seed,
+                         double* lambda_min, double* lambda_max);
+
+/* Matrix powers (eqs. cg-krylovbasis, polybasiscg): Y is n x ncol, column-major
+ * with leading dimension ldy >= n.  On entry column 0 holds p (P_0) and, unless
+ * first, column rcol holds r (R_0).  On return columns 1..s hold
+ * P_j = rho_j(A) p and, unless first, columns rcol+1..rcol+s-1 hold
+ * R_j = rho_j(A) r, with rho_j from the three-term recurrence of `basis` on
+ * [lambda_min, lambda_max] (ignored for the monomial basis).  Needs
+ * 1 <= s <= SSCG_S_LIMIT and, unless first, rcol >= s+1. */
+int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis,
+             double lambda_min, double lambda_max, double* Y, int64_t ldy, int rcol);
+
+/* Gram matrix (Section 2, Algorithm 4): G = Y_s^T Y_s of the basis columns
+ * [P_0..P_s, R_0..R_{s-1}] (first: [P_0..P_s]) laid out as in sscg_mpk.
+ * G: device, d x d with d = 2s+1 (first: s+1), both triangles written. */
+int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
+              double* G);
+
+/* One block's coordinate solve (Algorithm 4 from "Determine s~" to the end
+ * of the inner loop): kappa(G_i) for i = 1..s (Jacobi eigenvalues, when
+ * adaptive), s~ by eq. condy, B (eq. AVVB), the inner recurrence with the
+ * break of eq. check.  G: device d x d from sscg_gram.  Outputs (device):
+ * coef[0:d] = x', coef[d:2d] = r', coef[2d:3d] = p' in the order of G's
+ * columns; *info. */
+int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* prm,
+                     double* coef, sscg_block_info* info);
+
+/* Recovery (eq. coords): x <- x + Y x', r <- Y r', p <- Y p' with Y and the
+ * coefficient layout of sscg_gram / sscg_small_solve.  r and p may alias
+ * columns of Y (each row is read before it is written). */
+int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
+                 const double* coef, double* x, double* r, double* p);
+
+/* ---------------------------------------------------------------- timing */
+
+/* Kernel timing with HIP events on the context's stream (off by default).
+ * While on, sscg_solve records an event pair around every launch of each
+ * kernel family; sscg_kernel_stats returns, for family id (0 = matrix powers
+ * pass, 1 = Gram, 2 = recovery, 3 = coordinate solve), the launches, their
+ * summed duration in ms and their summed algorithmic bytes.  Resets on
+ * enabling. */
+int sscg_set_timing(sscg_ctx* ctx, int on);
+int sscg_kernel_stats(const sscg_ctx* ctx, int family, int64_t* launches, double* ms,
+                      double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSCG_H */

@@ -1,0 +1,735 @@
+// C ABI of libsscg: context, workspace, the outer block loop of
+// Algorithms 2-4 and the per-stage entry points.  All arithmetic of the
+// method runs in the kernels of spmv.hip, dense.hip and small.hip; the host
+// only sizes launches and steers the loop (s_bar, stopping) from the few
+// scalars it reads back once per block.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int NFAM = 4;  // timing families: mpk, gram, recover, small
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+hipError_t ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return hipSuccess;
+  if (b.p) {
+    // queued kernels may still use the old buffer
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    (void)hipFree(b.p);
+  }
+  b.p = nullptr;
+  b.cap = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e == hipSuccess) b.cap = bytes;
+  return e;
+}
+
+template <class T>
+T* as(Buf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+struct EvRec {
+  hipEvent_t a, b;
+  int fam;
+  double bytes;
+};
+
+thread_local std::string g_create_err;
+
+}  // namespace
+
+struct sscg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // matrix copy
+  Buf width, off, scol, sval, scale;
+  // solver workspace
+  Buf Y, part, G, coef, info, scal, xw, bw, lz, lzab;
+  sscg_block_info* hinfo = nullptr;  // pinned
+  double* hscal = nullptr;            // pinned
+  // timing
+  bool timing = false;
+  int64_t launches[NFAM] = {0, 0, 0, 0};
+  double ms[NFAM] = {0, 0, 0, 0};
+  double bytes[NFAM] = {0, 0, 0, 0};
+  std::vector<EvRec> ev;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+int fail(sscg_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? SSCG_ERR_OOM : SSCG_ERR_HIP,          \
+                  "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+int set_device(sscg_ctx* ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  return SSCG_OK;
+}
+
+// ---- timing helpers
+hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, size_t* slot) {
+  if (!c->timing) return hipSuccess;
+  if (c->ev_used == c->ev.size()) {
+    EvRec r;
+    hipError_t e = hipEventCreate(&r.a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&r.b);
+    if (e != hipSuccess) return e;
+    c->ev.push_back(r);
+  }
+  *slot = c->ev_used++;
+  c->ev[*slot].fam = fam;
+  c->ev[*slot].bytes = bytes;
+  return hipEventRecord(c->ev[*slot].a, c->stream);
+}
+
+hipError_t ev_end(sscg_ctx* c, size_t slot) {
+  if (!c->timing) return hipSuccess;
+  return hipEventRecord(c->ev[slot].b, c->stream);
+}
+
+// Accumulate the recorded pairs (the stream must have passed them).
+hipError_t ev_collect(sscg_ctx* c) {
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float t = 0.f;
+    hipError_t e = hipEventElapsedTime(&t, c->ev[i].a, c->ev[i].b);
+    if (e != hipSuccess) return e;
+    c->launches[c->ev[i].fam] += 1;
+    c->ms[c->ev[i].fam] += t;
+    c->bytes[c->ev[i].fam] += c->ev[i].bytes;
+  }
+  c->ev_used = 0;
+  return hipSuccess;
+}
+
+// ---- CSR -> SELL-64 copy (optionally equilibrated)
+int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
+  const int n = A->n;
+  const int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
+  HIPCHK(ensure(ctx->width, sizeof(int32_t) * (nslices + 2)));
+  HIPCHK(ensure(ctx->off, sizeof(int64_t) * (nslices + 1)));
+  // structural check first: every later kernel gathers through col[]
+  int32_t* flag = as<int32_t>(ctx->width) + nslices;
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_check_csr(A->rowptr, A->col, n, A->nnz, flag, ctx->stream));
+  int32_t bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (bad)
+    return fail(ctx, SSCG_ERR_ARG,
+                "invalid CSR: rowptr not non-decreasing or a column index outside [0, n)");
+  HIPCHK(launch_sell_widths(A->rowptr, n, as<int32_t>(ctx->width), ctx->stream));
+  HIPCHK(launch_scan_offsets(as<int32_t>(ctx->width), nslices, as<int64_t>(ctx->off), ctx->stream));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, as<int64_t>(ctx->off) + nslices, sizeof total,
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(ensure(ctx->scol, sizeof(int32_t) * total));
+  HIPCHK(ensure(ctx->sval, sizeof(double) * total));
+  const double* scale = nullptr;
+  if (equilibrate) {
+    HIPCHK(ensure(ctx->scale, sizeof(double) * n));
+    HIPCHK(launch_row_scale(A->rowptr, A->val, n, as<double>(ctx->scale), ctx->stream));
+    scale = as<double>(ctx->scale);
+  }
+  HIPCHK(launch_sell_fill(A->rowptr, A->col, A->val, n, scale, as<int64_t>(ctx->off),
+                          as<int32_t>(ctx->scol), as<double>(ctx->sval), ctx->stream));
+  M->n = n;
+  M->nslices = nslices;
+  M->off = as<int64_t>(ctx->off);
+  M->col = as<int32_t>(ctx->scol);
+  M->val = as<double>(ctx->sval);
+  return SSCG_OK;
+}
+
+int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
+  if (!A) return fail(ctx, SSCG_ERR_ARG, "A is NULL");
+  if (A->n < 1) return fail(ctx, SSCG_ERR_ARG, "n = %d must be >= 1", A->n);
+  if (A->nnz < 0) return fail(ctx, SSCG_ERR_ARG, "nnz = %d must be >= 0", A->nnz);
+  if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val)))
+    return fail(ctx, SSCG_ERR_ARG, "CSR arrays must not be NULL");
+  int32_t ends[2] = {-1, -1};
+  HIPCHK(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(&ends[1], A->rowptr + A->n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ends[0] != 0 || ends[1] != A->nnz)
+    return fail(ctx, SSCG_ERR_ARG, "rowptr[0] = %d, rowptr[n] = %d (nnz = %d)", ends[0], ends[1],
+                A->nnz);
+  return SSCG_OK;
+}
+
+// Column of Y holding basis vector a of an s-step block (G's order
+// [P_0..P_s, R_0..R_{s-1}]), with R_0 at column rcol.
+void colmap_of(int s, int first, int rcol, int32_t* cm) {
+  int d = first ? s + 1 : 2 * s + 1;
+  for (int a = 0; a < d; ++a) cm[a] = a <= s ? a : rcol + (a - s - 1);
+}
+
+int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, double* Y,
+               int64_t ldy, int rcol, int64_t nnz) {
+  const int n = M.n;
+  auto col = [&](int c) { return Y + (int64_t)c * ldy; };
+  for (int j = 1; j <= s; ++j) {
+    MpkSeq sp{col(j - 1), j >= 2 ? col(j - 2) : nullptr, col(j)};
+    MpkSeq sr{nullptr, nullptr, nullptr};
+    int nrhs = 1;
+    if (!first && j <= s - 1) {
+      sr = MpkSeq{col(rcol + j - 1), j >= 2 ? col(rcol + j - 2) : nullptr, col(rcol + j)};
+      nrhs = 2;
+    }
+    double vec = 2.0 * nrhs + ((bp.cheb && j >= 2) ? nrhs : 0);
+    double bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n * vec;
+    size_t slot = 0;
+    HIPCHK(ev_begin(ctx, 0, bytes, &slot));
+    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, ctx->stream));
+    HIPCHK(ev_end(ctx, slot));
+  }
+  return SSCG_OK;
+}
+
+int gram_into(sscg_ctx* ctx, const double* Y, int64_t ldy, int n, int s, int first, int rcol,
+              double* G) {
+  int32_t cm[2 * SSCG_S_LIMIT + 1];
+  colmap_of(s, first, rcol, cm);
+  int d = first ? s + 1 : 2 * s + 1;
+  int np = gram_nparts(n);
+  HIPCHK(ensure(ctx->part, sizeof(double) * 2 * (size_t)np * (d * (d + 1) / 2)));
+  size_t slot = 0;
+  HIPCHK(ev_begin(ctx, 1, 8.0 * n * d, &slot));
+  HIPCHK(launch_gram(Y, ldy, n, d, cm, as<double>(ctx->part), np, ctx->stream));
+  HIPCHK(ev_end(ctx, slot));
+  HIPCHK(launch_gram_finalize(as<double>(ctx->part), np, d, G, ctx->stream));
+  return SSCG_OK;
+}
+
+int ensure_parts(sscg_ctx* ctx, int n, int count) {
+  int np = residual_nparts(n);
+  int np2 = (n + 255) / 256;
+  if (np2 > np) np = np2;
+  HIPCHK(ensure(ctx->part, sizeof(double) * 2 * (size_t)np * count));
+  return SSCG_OK;
+}
+
+int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, double* lmin,
+                        double* lmax) {
+  const int n = M.n;
+  if (steps < 1) steps = 1;
+  if (steps > 2 * SSCG_S_LIMIT + 1) steps = 2 * SSCG_S_LIMIT + 1;
+  int rc = ensure_parts(ctx, n, 1);
+  if (rc) return rc;
+  HIPCHK(ensure(ctx->lz, sizeof(double) * 3 * (size_t)n));
+  HIPCHK(ensure(ctx->lzab, sizeof(double) * (2 * 64 + 8)));
+  HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
+  double* v = as<double>(ctx->lz);
+  double* vp = v + n;
+  double* w = vp + n;
+  double* al = as<double>(ctx->lzab);
+  double* be = al + 64;
+  double* sc = be + 64;  // [0]: ||u||, [1]: gershgorin
+  double* part = as<double>(ctx->part);
+  int np = 0;
+  hipStream_t st = ctx->stream;
+  // Gershgorin
+  HIPCHK(launch_gershgorin(M, part, &np, st));
+  HIPCHK(launch_max_finalize(part, np, sc + 1, st));
+  // start vector
+  HIPCHK(launch_splitmix_vec(w, n, seed, st));
+  HIPCHK(launch_dot_parts(w, w, n, part, &np, st));
+  HIPCHK(launch_finalize(part, np, 1, sc, st));
+  HIPCHK(launch_sqrt_scalar(sc, st));
+  HIPCHK(launch_div_vec(w, sc, n, v, st));
+  bool have_prev = false;
+  for (int j = 0; j < steps; ++j) {
+    HIPCHK(launch_lanczos_step(M, v, have_prev ? vp : nullptr, have_prev ? be + j - 1 : nullptr, w,
+                               part, &np, st));
+    HIPCHK(launch_finalize(part, np, 1, al + j, st));
+    HIPCHK(launch_axpy_dot(w, v, al + j, part, &np, n, st));
+    HIPCHK(launch_finalize(part, np, 1, be + j, st));
+    HIPCHK(launch_sqrt_scalar(be + j, st));
+    if (j < steps - 1) {
+      HIPCHK(launch_div_vec(w, be + j, n, vp, st));  // vp <- w / beta (new v)
+      double* t = v;
+      v = vp;
+      vp = t;
+      have_prev = true;
+    }
+  }
+  double hb[64];
+  HIPCHK(hipMemcpyAsync(hb, be, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int k = steps;
+  for (int j = 0; j < steps - 1; ++j)
+    if (hb[j] == 0.0) {
+      k = j + 1;
+      break;
+    }
+  HIPCHK(launch_tridiag_eig(al, be, k, sc + 2, sc + 3, st));
+  double out[4];
+  HIPCHK(hipMemcpyAsync(out, sc, sizeof out, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *lmax = out[1];
+  *lmin = out[2];
+  return SSCG_OK;
+}
+
+int validate_opts(sscg_ctx* ctx, const sscg_opts* o) {
+  if (!o) return fail(ctx, SSCG_ERR_ARG, "opts is NULL");
+  if (o->mode < 0 || o->mode > 2) return fail(ctx, SSCG_ERR_ARG, "bad mode %d", o->mode);
+  if (o->basis < 0 || o->basis > 1) return fail(ctx, SSCG_ERR_ARG, "bad basis %d", o->basis);
+  if (!(o->tol > 0.0)) return fail(ctx, SSCG_ERR_ARG, "tol must be > 0");
+  if (o->s_max < 1 || o->s_max > SSCG_S_LIMIT)
+    return fail(ctx, SSCG_ERR_ARG, "s_max = %d outside [1, %d]", o->s_max, SSCG_S_LIMIT);
+  if (o->s0_bar < 0 || o->s0_bar > o->s_max) return fail(ctx, SSCG_ERR_ARG, "bad s0_bar");
+  if (o->f < 0) return fail(ctx, SSCG_ERR_ARG, "bad f");
+  if (o->mode == SSCG_MODE_FIXED && (o->fixed_s < 1 || o->fixed_s > o->s_max))
+    return fail(ctx, SSCG_ERR_ARG, "fixed_s = %d outside [1, s_max]", o->fixed_s);
+  if (o->mode == SSCG_MODE_SCHEDULE) {
+    if (!o->schedule || o->schedule_len < 1) return fail(ctx, SSCG_ERR_ARG, "empty schedule");
+    for (int i = 0; i < o->schedule_len; ++i)
+      if (o->schedule[i] < 1 || o->schedule[i] > o->s_max)
+        return fail(ctx, SSCG_ERR_ARG, "schedule[%d] = %d outside [1, s_max]", i, o->schedule[i]);
+  }
+  if (!(o->c > 0.0)) return fail(ctx, SSCG_ERR_ARG, "c must be > 0");
+  if (o->basis == SSCG_BASIS_CHEBYSHEV) {
+    bool nan_lo = isnan(o->lambda_min), nan_hi = isnan(o->lambda_max);
+    if (nan_lo != nan_hi) return fail(ctx, SSCG_ERR_ARG, "give both Chebyshev bounds or neither");
+    if (!nan_lo && !(o->lambda_max > o->lambda_min))
+      return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
+  }
+  if (o->max_iters < 1) return fail(ctx, SSCG_ERR_ARG, "max_iters must be >= 1");
+  return SSCG_OK;
+}
+
+__global__ void k_eps_star(const double* b2, double tol, double* out) {
+  if (threadIdx.x == 0) out[0] = tol * sqrt(b2[0]);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void sscg_opts_default(sscg_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->mode = SSCG_MODE_ADAPTIVE;
+  o->basis = SSCG_BASIS_MONOMIAL;
+  o->tol = 1e-10;
+  o->s_max = 8;
+  o->s0_bar = 0;
+  o->f = 0;
+  o->fixed_s = 4;
+  o->c = 1.0;
+  o->lambda_min = NAN;
+  o->lambda_max = NAN;
+  o->lanczos_steps = 30;
+  o->lanczos_seed = 0;
+  o->equilibrate = 0;
+  o->inner_check = 1;
+  o->max_iters = 100000;
+}
+
+int sscg_create(sscg_ctx** out, int device, void* stream) {
+  if (!out) {
+    g_create_err = "out is NULL";
+    return SSCG_ERR_ARG;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev) {
+    g_create_err = "no HIP device " + std::to_string(device);
+    return SSCG_ERR_ARG;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_err = hipGetErrorString(e);
+    return SSCG_ERR_HIP;
+  }
+  sscg_ctx* c = new sscg_ctx;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipHostMalloc((void**)&c->hinfo, sizeof(sscg_block_info)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hscal, sizeof(double) * 16) != hipSuccess) {
+    g_create_err = "pinned host allocation failed";
+    delete c;
+    return SSCG_ERR_OOM;
+  }
+  *out = c;
+  return SSCG_OK;
+}
+
+void sscg_destroy(sscg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y, &c->part, &c->G,
+                 &c->coef, &c->info, &c->scal, &c->xw, &c->bw, &c->lz, &c->lzab};
+  for (Buf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto& r : c->ev) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (c->hinfo) (void)hipHostFree(c->hinfo);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  delete c;
+}
+
+const char* sscg_last_error(const sscg_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+int sscg_set_timing(sscg_ctx* ctx, int on) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->timing = on != 0;
+  for (int f = 0; f < NFAM; ++f) {
+    ctx->launches[f] = 0;
+    ctx->ms[f] = 0;
+    ctx->bytes[f] = 0;
+  }
+  ctx->ev_used = 0;
+  return SSCG_OK;
+}
+
+int sscg_kernel_stats(const sscg_ctx* ctx, int family, int64_t* launches, double* ms,
+                      double* bytes) {
+  if (!ctx || family < 0 || family >= NFAM) return SSCG_ERR_ARG;
+  if (launches) *launches = ctx->launches[family];
+  if (ms) *ms = ctx->ms[family];
+  if (bytes) *bytes = ctx->bytes[family];
+  return SSCG_OK;
+}
+
+int sscg_residual(sscg_ctx* ctx, const sscg_csr* A, const double* b, const double* x, double* r,
+                  double* out2) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  if (!b || !x || !out2) return fail(ctx, SSCG_ERR_ARG, "b, x and out2 must not be NULL");
+  DevMat M;
+  if ((rc = build_mat(ctx, A, 0, &M))) return rc;
+  if ((rc = ensure_parts(ctx, A->n, 2))) return rc;
+  int np = residual_nparts(A->n);
+  double* part = as<double>(ctx->part);
+  HIPCHK(launch_residual(M, b, x, r, part, part + 2 * (size_t)np, &np, ctx->stream));
+  HIPCHK(launch_finalize(part, np, 2, out2, ctx->stream));
+  return SSCG_OK;
+}
+
+int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t seed,
+                         double* lambda_min, double* lambda_max) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  if (!lambda_min || !lambda_max) return fail(ctx, SSCG_ERR_ARG, "NULL output");
+  if (steps < 1 || steps > 2 * SSCG_S_LIMIT + 1)
+    return fail(ctx, SSCG_ERR_ARG, "steps = %d outside [1, %d]", steps, 2 * SSCG_S_LIMIT + 1);
+  DevMat M;
+  if ((rc = build_mat(ctx, A, 0, &M))) return rc;
+  return spectral_bounds_dev(ctx, M, steps, seed, lambda_min, lambda_max);
+}
+
+int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, double lambda_min,
+             double lambda_max, double* Y, int64_t ldy, int rcol) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  if (s < 1 || s > SSCG_S_LIMIT) return fail(ctx, SSCG_ERR_ARG, "s = %d outside [1, %d]", s,
+                                             SSCG_S_LIMIT);
+  if (!Y || ldy < A->n) return fail(ctx, SSCG_ERR_ARG, "Y NULL or ldy < n");
+  if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
+  if (basis == SSCG_BASIS_CHEBYSHEV && !(lambda_max > lambda_min))
+    return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
+  DevMat M;
+  if ((rc = build_mat(ctx, A, 0, &M))) return rc;
+  return mpk_passes(ctx, M, s, first ? 1 : 0, make_basis(basis, lambda_min, lambda_max), Y, ldy,
+                    rcol, A->nnz);
+}
+
+int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
+              double* G) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if (n < 1 || s < 1 || s > SSCG_S_LIMIT || !Y || !G || ldy < n)
+    return fail(ctx, SSCG_ERR_ARG, "bad Gram arguments");
+  if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
+  return gram_into(ctx, Y, ldy, n, s, first ? 1 : 0, rcol, G);
+}
+
+int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* prm, double* coef,
+                     sscg_block_info* info) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if (!G || !prm || !coef || !info) return fail(ctx, SSCG_ERR_ARG, "NULL argument");
+  if (prm->s < 1 || prm->s > SSCG_S_LIMIT) return fail(ctx, SSCG_ERR_ARG, "bad s");
+  if (!prm->adaptive && (prm->iters < 1 || prm->iters > prm->s))
+    return fail(ctx, SSCG_ERR_ARG, "iters must be in [1, s]");
+  if (prm->adaptive && !(prm->eps_star > 0.0 && prm->c > 0.0))
+    return fail(ctx, SSCG_ERR_ARG, "need eps_star > 0 and c > 0");
+  int d = prm->first ? prm->s + 1 : 2 * prm->s + 1;
+  if (prm->adaptive) HIPCHK(launch_kappa(G, d, prm->s, prm->first, info, ctx->stream));
+  HIPCHK(launch_inner(G, *prm, coef, info, ctx->stream));
+  return SSCG_OK;
+}
+
+int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
+                 const double* coef, double* x, double* r, double* p) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if (n < 1 || s < 1 || s > SSCG_S_LIMIT || !Y || !coef || !x || !r || !p || ldy < n)
+    return fail(ctx, SSCG_ERR_ARG, "bad recovery arguments");
+  if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
+  int32_t cm[2 * SSCG_S_LIMIT + 1];
+  colmap_of(s, first ? 1 : 0, rcol, cm);
+  int d = first ? s + 1 : 2 * s + 1;
+  HIPCHK(launch_recover(Y, ldy, n, d, cm, coef, x, r, p, ctx->stream));
+  return SSCG_OK;
+}
+
+int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x,
+               const sscg_opts* opts, sscg_result* res) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = validate_opts(ctx, opts))) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  if (!b || !x) return fail(ctx, SSCG_ERR_ARG, "b and x must not be NULL");
+  const sscg_opts& o = *opts;
+  const int n = A->n;
+  hipStream_t st = ctx->stream;
+  ctx->ev_used = 0;
+
+  DevMat M;
+  if ((rc = build_mat(ctx, A, o.equilibrate, &M))) return rc;
+
+  // working b and x (the scaled system when equilibrating)
+  const double* bw = b;
+  double* xw = x;
+  if (o.equilibrate) {
+    HIPCHK(ensure(ctx->bw, sizeof(double) * n));
+    HIPCHK(ensure(ctx->xw, sizeof(double) * n));
+    HIPCHK(launch_scale_vec(b, as<double>(ctx->scale), 1, n, as<double>(ctx->bw), st));
+    HIPCHK(launch_scale_vec(x, as<double>(ctx->scale), 0, n, as<double>(ctx->xw), st));
+    bw = as<double>(ctx->bw);
+    xw = as<double>(ctx->xw);
+  }
+  const int64_t ld = ((int64_t)n + 63) / 64 * 64;
+  const int rcol = o.s_max + 1;
+  HIPCHK(ensure(ctx->Y, sizeof(double) * ld * (2 * o.s_max + 1)));
+  HIPCHK(ensure(ctx->G, sizeof(double) * (2 * SSCG_S_LIMIT + 1) * (2 * SSCG_S_LIMIT + 1)));
+  HIPCHK(ensure(ctx->coef, sizeof(double) * 3 * (2 * SSCG_S_LIMIT + 1)));
+  HIPCHK(ensure(ctx->info, sizeof(sscg_block_info)));
+  HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
+  if ((rc = ensure_parts(ctx, n, 2))) return rc;
+  {
+    const int dmax = 2 * o.s_max + 1;
+    HIPCHK(ensure(ctx->part, std::max(ctx->part.cap, sizeof(double) * 2 * (size_t)gram_nparts(n) *
+                                                          (dmax * (dmax + 1) / 2))));
+  }
+  double* Y = as<double>(ctx->Y);
+  double* G = as<double>(ctx->G);
+  double* coef = as<double>(ctx->coef);
+  double* scal = as<double>(ctx->scal);  // [0] r2 [1] b2 [2] relres [3] eps*
+  sscg_block_info* dinfo = as<sscg_block_info>(ctx->info);
+  auto ycol = [&](int c) { return Y + (int64_t)c * ld; };
+
+  // r_1 = b - A x_1 into P_0; ||b||, eps*, relres_0
+  int np = residual_nparts(n);
+  double* part = as<double>(ctx->part);
+  HIPCHK(launch_residual(M, bw, xw, ycol(0), part, part + 2 * (size_t)np, &np, st));
+  HIPCHK(launch_finalize(part, np, 2, scal, st));
+  HIPCHK(launch_relres(scal, scal + 1, scal + 2, st));
+  hipLaunchKernelGGL(k_eps_star, dim3(1), dim3(64), 0, st, scal + 1, o.tol, scal + 3);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(ctx->hscal, scal, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double b2 = ctx->hscal[1];
+  const double eps_star = ctx->hscal[3];
+  double relres = ctx->hscal[2];
+
+  sscg_result dummy;
+  memset(&dummy, 0, sizeof dummy);
+  sscg_result& R = res ? *res : dummy;
+  R.blocks = 0;
+  R.iters = 0;
+  R.basis_vectors = 0;
+  R.wasted_vectors = 0;
+  R.lambda_min = o.lambda_min;
+  R.lambda_max = o.lambda_max;
+
+  auto finish = [&](int status) -> int {
+    if (o.equilibrate) {
+      hipError_t e = launch_scale_vec(xw, as<double>(ctx->scale), 1, n, x, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return fail(ctx, SSCG_ERR_HIP, "%s", hipGetErrorString(e));
+    }
+    R.status = status;
+    return status;
+  };
+
+  if (b2 == 0.0) {  // x = 0 solves A x = 0 exactly
+    HIPCHK(launch_fill(xw, n, 0.0, st));
+    HIPCHK(hipStreamSynchronize(st));
+    R.relres0 = 0.0;
+    R.relres = 0.0;
+    return finish(SSCG_OK);
+  }
+  R.relres0 = relres;
+  R.relres = relres;
+  if (relres <= o.tol) return finish(SSCG_OK);
+
+  BasisPrm bp = make_basis(o.basis, 0.0, 1.0);
+  double lmin = o.lambda_min, lmax = o.lambda_max;
+  if (o.basis == SSCG_BASIS_CHEBYSHEV) {
+    if (isnan(lmin)) {
+      if ((rc = spectral_bounds_dev(ctx, M, o.lanczos_steps, o.lanczos_seed, &lmin, &lmax)))
+        return rc;
+      if (!(lmax > lmin)) return fail(ctx, SSCG_ERR_HIP, "spectral estimate failed");
+    }
+    bp = make_basis(o.basis, lmin, lmax);
+    R.lambda_min = lmin;
+    R.lambda_max = lmax;
+  }
+
+  const int s0 = o.s0_bar > 0 ? o.s0_bar : o.s_max;
+  const int f = o.f > 0 ? o.f : o.s_max;
+  int m = 0, s_prev = 0, status = SSCG_NOT_CONVERGED;
+  for (int k = 0;; ++k) {
+    const int first = k == 0;
+    int s_bar, s;
+    if (o.mode == SSCG_MODE_FIXED) {
+      s_bar = s = o.fixed_s;
+    } else if (o.mode == SSCG_MODE_SCHEDULE) {
+      s_bar = s = o.schedule[k < o.schedule_len ? k : o.schedule_len - 1];
+    } else {
+      s_bar = first ? s0 : (s_prev + f < o.s_max ? s_prev + f : o.s_max);
+      s = first ? s_bar : (s_bar < (m > 1 ? m : 1) ? s_bar : (m > 1 ? m : 1));
+    }
+    // matrix powers, Gram, coordinate solve, recovery, true residual
+    if ((rc = mpk_passes(ctx, M, s, first, bp, Y, ld, rcol, A->nnz))) return rc;
+    if ((rc = gram_into(ctx, Y, ld, n, s, first, rcol, G))) return rc;
+    sscg_block_params prm;
+    prm.s = s;
+    prm.first = first;
+    prm.adaptive = o.mode == SSCG_MODE_ADAPTIVE;
+    prm.iters = s;
+    prm.inner_check = o.inner_check;
+    prm.basis = o.basis;
+    prm.lambda_min = lmin;
+    prm.lambda_max = lmax;
+    prm.eps_star = eps_star;
+    prm.c = o.c;
+    int d = first ? s + 1 : 2 * s + 1;
+    size_t slot = 0;
+    HIPCHK(ev_begin(ctx, 3, 0.0, &slot));
+    if (prm.adaptive) HIPCHK(launch_kappa(G, d, s, first, dinfo, st));
+    HIPCHK(launch_inner(G, prm, coef, dinfo, st));
+    HIPCHK(ev_end(ctx, slot));
+    int32_t cm[2 * SSCG_S_LIMIT + 1];
+    colmap_of(s, first, rcol, cm);
+    // bytes: columns the recovery reads are those of s_k steps, known only
+    // on the device; the estimate uses s (exact when s_k = s)
+    HIPCHK(ev_begin(ctx, 2, 8.0 * n * (d + 4), &slot));
+    HIPCHK(launch_recover(Y, ld, n, d, cm, coef, xw, ycol(rcol), ycol(0), st));
+    HIPCHK(ev_end(ctx, slot));
+    part = as<double>(ctx->part);
+    HIPCHK(launch_residual(M, bw, xw, nullptr, part, nullptr, &np, st));
+    HIPCHK(launch_finalize(part, np, 1, scal, st));
+    HIPCHK(launch_relres(scal, scal + 1, scal + 2, st));
+    HIPCHK(hipMemcpyAsync(ctx->hinfo, dinfo, sizeof(sscg_block_info), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hscal + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(ev_collect(ctx));
+    const sscg_block_info& I = *ctx->hinfo;
+    relres = ctx->hscal[2];
+    const int s_k = I.s_k;
+    R.basis_vectors += first ? s : 2 * s - 1;
+    if (s_k > 0) R.wasted_vectors += (int64_t)(s - s_k) * (first ? 1 : 2);
+    if (k < R.cap) {
+      if (R.s_bar) R.s_bar[k] = s_bar;
+      if (R.s_built) R.s_built[k] = s;
+      if (R.s_tilde) R.s_tilde[k] = I.s_tilde;
+      if (R.s_k) R.s_k[k] = s_k;
+      if (R.gamma) R.gamma[k] = I.gamma;
+      if (R.thr) R.thr[k] = I.thr;
+      if (R.res_updated) R.res_updated[k] = sqrt((0.0 > I.rr) ? 0.0 : I.rr);
+      if (R.relres_true) R.relres_true[k] = relres;
+      if (R.kappa)
+        for (int i = 0; i < o.s_max; ++i)
+          R.kappa[(int64_t)k * o.s_max + i] = (prm.adaptive && i < s) ? I.kappa[i] : NAN;
+    }
+    if (s_k == 0) {  // the block could not take a step
+      R.blocks = k;
+      status = SSCG_BREAKDOWN;
+      break;
+    }
+    R.blocks = k + 1;
+    m += s_k;
+    s_prev = s_k;
+    R.iters = m;
+    R.relres = relres;
+    if (relres <= o.tol) {
+      status = SSCG_OK;
+      break;
+    }
+    if (!isfinite(relres)) {
+      status = SSCG_BREAKDOWN;
+      break;
+    }
+    if (m >= o.max_iters) {
+      status = SSCG_NOT_CONVERGED;
+      break;
+    }
+  }
+  return finish(status);
+}
+
+}  // extern "C"

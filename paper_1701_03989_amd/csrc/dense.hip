@@ -1,0 +1,366 @@
+// Tall-skinny kernels: the Gram matrix G = Y^T Y, the recovery Y*coef, the
+// reductions that finish them, and small vector helpers.
+#include "common.h"
+
+namespace {
+
+constexpr int WG = 256;
+constexpr int GT = 32;            // rows of Y per LDS tile
+constexpr int MAXD = 2 * SSCG_S_LIMIT + 1;
+constexpr int MAXPAIRS = MAXD * (MAXD + 1) / 2;
+constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
+
+struct ColMap {
+  int32_t c[MAXD];
+};
+
+// ---------------------------------------------------------------- Gram
+//
+// Each workgroup owns a contiguous range of row tiles (XCD-aware) and keeps
+// one dd accumulator per upper-triangle entry (a <= b) it is assigned; tiles
+// of GT rows x d columns are staged in LDS (row-major, so the lanes of a wave
+// reading different columns of one row hit different banks).  Output: one dd
+// partial per (entry, workgroup), entry-major.
+__global__ __launch_bounds__(WG) void k_gram(const double* __restrict__ Y, int64_t ldy, int n,
+                                             int d, ColMap cm, double* __restrict__ part,
+                                             int nparts) {
+  __shared__ double tile[GT][MAXD + 1];
+  int lb = xcd_block(nparts);
+  if (lb >= nparts) return;
+  const int npairs = d * (d + 1) / 2;
+  int pa[PAIRS_PER_THREAD], pb[PAIRS_PER_THREAD];
+  dd acc[PAIRS_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+    int q = threadIdx.x + u * WG;
+    int a = 0, rem = q;
+    while (a < d && rem >= d - a) {
+      rem -= d - a;
+      ++a;
+    }
+    pa[u] = a < d ? a : 0;
+    pb[u] = a < d ? a + rem : 0;
+    acc[u] = dd_zero();
+  }
+  int ntiles = (n + GT - 1) / GT;
+  int per = (ntiles + nparts - 1) / nparts;
+  int t0 = lb * per, t1 = min(t0 + per, ntiles);
+  for (int t = t0; t < t1; ++t) {
+    int r0 = t * GT;
+    for (int e = threadIdx.x; e < GT * d; e += WG) {
+      int a = e / GT, r = e - a * GT;
+      int row = r0 + r;
+      tile[r][a] = row < n ? Y[(int64_t)cm.c[a] * ldy + row] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+      if (threadIdx.x + u * WG < npairs) {
+        int a = pa[u], b = pb[u];
+#pragma unroll 4
+        for (int r = 0; r < GT; ++r) dd_add_prod(acc[u], tile[r][a], tile[r][b]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+    int q = threadIdx.x + u * WG;
+    if (q < npairs) {
+      part[((int64_t)q * nparts + lb) * 2] = acc[u].s;
+      part[((int64_t)q * nparts + lb) * 2 + 1] = acc[u].e;
+    }
+  }
+}
+
+// Sum `nparts` dd partials of reduction blockIdx.x in a fixed order and
+// round once.  Gram variant writes both triangles of G.
+__device__ __forceinline__ dd reduce_parts(const double* __restrict__ p, int nparts) {
+  __shared__ double ls[WG / SSCG_WAVE], le[WG / SSCG_WAVE];
+  dd a = dd_zero();
+  for (int q = threadIdx.x; q < nparts; q += WG) dd_merge(a, dd{p[2 * q], p[2 * q + 1]});
+  a = dd_wave_reduce(a);
+  int wv = threadIdx.x / SSCG_WAVE;
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) {
+    ls[wv] = a.s;
+    le[wv] = a.e;
+  }
+  __syncthreads();
+  dd t{ls[0], le[0]};
+  for (int q = 1; q < WG / SSCG_WAVE; ++q) dd_merge(t, dd{ls[q], le[q]});
+  return t;
+}
+
+__global__ __launch_bounds__(WG) void k_gram_finalize(const double* __restrict__ part, int nparts,
+                                                      int d, double* __restrict__ G) {
+  int q = blockIdx.x;
+  dd t = reduce_parts(part + (int64_t)q * nparts * 2, nparts);
+  if (threadIdx.x == 0) {
+    int a = 0, rem = q;
+    while (rem >= d - a) {
+      rem -= d - a;
+      ++a;
+    }
+    int b = a + rem;
+    double g = dd_round(t);
+    G[a * d + b] = g;
+    G[b * d + a] = g;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int nparts,
+                                                 double* __restrict__ out) {
+  int k = blockIdx.x;
+  dd t = reduce_parts(part + (int64_t)k * nparts * 2, nparts);
+  if (threadIdx.x == 0) out[k] = dd_round(t);
+}
+
+__global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ part, int nparts,
+                                                     double* __restrict__ out) {
+  __shared__ double lm[WG / SSCG_WAVE];
+  double m = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += WG) m = fmax(m, part[q]);
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) m = fmax(m, __shfl_xor(m, k, SSCG_WAVE));
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) lm[threadIdx.x / SSCG_WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = lm[0];
+    for (int q = 1; q < WG / SSCG_WAVE; ++q) t = fmax(t, lm[q]);
+    out[0] = t;
+  }
+}
+
+// ---------------------------------------------------------------- recovery
+//
+// x_i <- RN(x_i + sum_a Y_ia x'_a), r_i <- RN(sum_a Y_ia r'_a),
+// p_i <- RN(sum_a Y_ia p'_a) (eq. coords).  Columns whose three coefficients
+// are all zero contribute nothing to the exact sums and are not read.
+__global__ __launch_bounds__(WG) void k_recover(const double* Y, int64_t ldy, int n, int d,
+                                                ColMap cm, const double* __restrict__ coef,
+                                                double* __restrict__ x, double* r, double* p) {
+  int nb = (n + WG - 1) / WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int i = lb * WG + threadIdx.x;
+  if (i >= n) return;
+  dd ax = dd_zero(), ar = dd_zero(), ap = dd_zero();
+  dd_add(ax, x[i]);
+  for (int a = 0; a < d; ++a) {
+    double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
+    if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
+    double y = Y[(int64_t)cm.c[a] * ldy + i];
+    dd_add_prod(ax, y, cx);
+    dd_add_prod(ar, y, cr);
+    dd_add_prod(ap, y, cp);
+  }
+  x[i] = dd_round(ax);
+  r[i] = dd_round(ar);
+  p[i] = dd_round(ap);
+}
+
+// ---------------------------------------------------------------- helpers
+
+__global__ __launch_bounds__(WG) void k_scale_vec(const double* __restrict__ in,
+                                                  const double* __restrict__ s, int mul, int n,
+                                                  double* __restrict__ out) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i < n) out[i] = mul ? in[i] * s[i] : in[i] / s[i];
+}
+
+__global__ __launch_bounds__(WG) void k_copy(const double* __restrict__ in, int n,
+                                             double* __restrict__ out) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+__global__ __launch_bounds__(WG) void k_fill(double* __restrict__ out, int n, double v) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+// out = sqrt(r2) / sqrt(b2): the true relative residual.
+__global__ void k_relres(const double* __restrict__ r2, const double* __restrict__ b2,
+                         double* __restrict__ out) {
+  if (threadIdx.x == 0) out[0] = sqrt(r2[0]) / sqrt(b2[0]);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): z_i from state seed + (i+1)*golden.
+__global__ __launch_bounds__(WG) void k_splitmix(double* __restrict__ out, int n, uint64_t seed) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  out[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
+}
+
+// w_i <- w_i - alpha v_i (two roundings); partials of w.w.
+__global__ __launch_bounds__(WG) void k_axpy_dot(double* __restrict__ w,
+                                                 const double* __restrict__ v,
+                                                 const double* __restrict__ alpha, int n,
+                                                 double* __restrict__ part) {
+  __shared__ double ls[WG / SSCG_WAVE], le[WG / SSCG_WAVE];
+  int nb = (n + WG - 1) / WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int i = lb * WG + threadIdx.x;
+  dd a = dd_zero();
+  if (i < n) {
+    double t = (*alpha) * v[i];
+    double wi = w[i] - t;
+    w[i] = wi;
+    dd_add_prod(a, wi, wi);
+  }
+  a = dd_wave_reduce(a);
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) {
+    ls[threadIdx.x / SSCG_WAVE] = a.s;
+    le[threadIdx.x / SSCG_WAVE] = a.e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd t{ls[0], le[0]};
+    for (int q = 1; q < WG / SSCG_WAVE; ++q) dd_merge(t, dd{ls[q], le[q]});
+    part[2 * lb] = t.s;
+    part[2 * lb + 1] = t.e;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_dot_parts(const double* __restrict__ x,
+                                                  const double* __restrict__ y, int n,
+                                                  double* __restrict__ part) {
+  __shared__ double ls[WG / SSCG_WAVE], le[WG / SSCG_WAVE];
+  int nb = (n + WG - 1) / WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int i = lb * WG + threadIdx.x;
+  dd a = dd_zero();
+  if (i < n) dd_add_prod(a, x[i], y[i]);
+  a = dd_wave_reduce(a);
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) {
+    ls[threadIdx.x / SSCG_WAVE] = a.s;
+    le[threadIdx.x / SSCG_WAVE] = a.e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd t{ls[0], le[0]};
+    for (int q = 1; q < WG / SSCG_WAVE; ++q) dd_merge(t, dd{ls[q], le[q]});
+    part[2 * lb] = t.s;
+    part[2 * lb + 1] = t.e;
+  }
+}
+
+__global__ void k_sqrt_scalar(double* x) {
+  if (threadIdx.x == 0) x[0] = sqrt(x[0]);
+}
+
+__global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
+                                                const double* __restrict__ beta, int n,
+                                                double* __restrict__ out) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i < n) out[i] = w[i] / (*beta);
+}
+
+ColMap make_colmap(const int32_t* c, int d) {
+  ColMap m;
+  for (int a = 0; a < MAXD; ++a) m.c[a] = a < d ? c[a] : 0;
+  return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launches
+
+int gram_nparts(int n) {
+  int ntiles = (n + GT - 1) / GT;
+  // about 8 tiles per workgroup, at most 2048 workgroups
+  int np = (ntiles + 7) / 8;
+  if (np > 2048) np = 2048;
+  return np < 1 ? 1 : np;
+}
+
+hipError_t launch_gram(const double* Y, int64_t ldy, int n, int d, const int32_t* colmap_host,
+                       double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram, dim3(xcd_grid(nparts)), dim3(WG), 0, st, Y, ldy, n, d,
+                     make_colmap(colmap_host, d), part, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_finalize(const double* part, int nparts, int d, double* G,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_finalize, dim3(d * (d + 1) / 2), dim3(WG), 0, st, part, nparts, d, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* part, int nparts, int count, double* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(count), dim3(WG), 0, st, part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_finalize(const double* part, int nparts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(WG), 0, st, part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_recover(const double* Y, int64_t ldy, int n, int d, const int32_t* colmap_host,
+                          const double* coef, double* x, double* r, double* p, hipStream_t st) {
+  int nb = (n + WG - 1) / WG;
+  hipLaunchKernelGGL(k_recover, dim3(xcd_grid(nb)), dim3(WG), 0, st, Y, ldy, n, d,
+                     make_colmap(colmap_host, d), coef, x, r, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_vec(const double* in, const double* s, int mul, int n, double* out,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_vec, dim3((n + WG - 1) / WG), dim3(WG), 0, st, in, s, mul, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* in, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3((n + WG - 1) / WG), dim3(WG), 0, st, in, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* out, int n, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3((n + WG - 1) / WG), dim3(WG), 0, st, out, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_relres(const double* r2, const double* b2, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_relres, dim3(1), dim3(SSCG_WAVE), 0, st, r2, b2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitmix_vec(double* out, int n, uint64_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_splitmix, dim3((n + WG - 1) / WG), dim3(WG), 0, st, out, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dot(double* w, const double* v, const double* alpha, double* part,
+                           int* nparts, int n, hipStream_t st) {
+  int nb = (n + WG - 1) / WG;
+  *nparts = nb;
+  hipLaunchKernelGGL(k_axpy_dot, dim3(xcd_grid(nb)), dim3(WG), 0, st, w, v, alpha, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_parts(const double* x, const double* y, int n, double* part, int* nparts,
+                            hipStream_t st) {
+  int nb = (n + WG - 1) / WG;
+  *nparts = nb;
+  hipLaunchKernelGGL(k_dot_parts, dim3(xcd_grid(nb)), dim3(WG), 0, st, x, y, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_scalar(double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_sqrt_scalar, dim3(1), dim3(SSCG_WAVE), 0, st, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_vec(const double* w, const double* beta, int n, double* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_div_vec, dim3((n + WG - 1) / WG), dim3(WG), 0, st, w, beta, n, out);
+  return hipGetLastError();
+}

@@ -1,0 +1,367 @@
+// Sparse kernels: SELL-64 conversion, the matrix-powers pass, the true
+// residual, the Gershgorin bound and the Lanczos step.
+//
+// Every row sum is accumulated exactly in double-double and rounded once, so
+// it equals (up to a vanishingly rare near-tie) the correctly rounded exact
+// row sum, independent of the order of the terms.
+#include "common.h"
+
+namespace {
+
+constexpr int WG = 256;              // 4 wavefronts
+constexpr int SLICES_PER_WG = WG / SSCG_WAVE;
+
+// ---------------------------------------------------------------- SELL-64
+
+__global__ __launch_bounds__(WG) void k_check_csr(const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col, int n, int nnz,
+                                                  int32_t* __restrict__ flag) {
+  int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+  int bad = 0;
+  if (t < n) bad |= rowptr[t + 1] < rowptr[t];
+  if (t < nnz) bad |= (col[t] < 0) | (col[t] >= n);
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(WG) void k_sell_widths(const int32_t* __restrict__ rowptr, int n,
+                                                    int nslices, int32_t* __restrict__ width) {
+  int slice = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= nslices) return;
+  int row = slice * SSCG_WAVE + (threadIdx.x & (SSCG_WAVE - 1));
+  int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) len = max(len, __shfl_xor(len, m, SSCG_WAVE));
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) width[slice] = len;
+}
+
+// Exclusive scan of 64*width into off[0..nslices]; one workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict__ width,
+                                                       int nslices, int64_t* __restrict__ off) {
+  __shared__ int64_t part[1024];
+  int t = threadIdx.x;
+  int per = (nslices + 1023) / 1024;
+  int lo = min(t * per, nslices), hi = min(lo + per, nslices);
+  int64_t s = 0;
+  for (int i = lo; i < hi; ++i) s += (int64_t)width[i] * SSCG_WAVE;
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    int64_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t base = part[t] - s;  // exclusive prefix of this thread's chunk
+  for (int i = lo; i < hi; ++i) {
+    off[i] = base;
+    base += (int64_t)width[i] * SSCG_WAVE;
+  }
+  if (t == 1023) off[nslices] = part[1023];
+}
+
+// s_i = 1 / sqrt(max_j |a_ij|) (equilibration, Section 5).
+__global__ __launch_bounds__(WG) void k_row_scale(const int32_t* __restrict__ rowptr,
+                                                  const double* __restrict__ val, int n,
+                                                  double* __restrict__ scale) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  double m = 0.0;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) m = fmax(m, fabs(val[k]));
+  scale[i] = 1.0 / sqrt(m);
+}
+
+// One thread per row (and per padding lane of the last slice).  Value
+// (a_ij s_i) s_j when a scale is given.
+__global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, int n,
+                                                  const double* __restrict__ scale,
+                                                  const int64_t* __restrict__ off, int nslices,
+                                                  int32_t* __restrict__ scol,
+                                                  double* __restrict__ sval) {
+  int row = blockIdx.x * WG + threadIdx.x;
+  int slice = row / SSCG_WAVE;
+  if (slice >= nslices) return;
+  int lane = row & (SSCG_WAVE - 1);
+  int64_t o = off[slice];
+  int w = (int)((off[slice + 1] - o) / SSCG_WAVE);
+  int k0 = 0, len = 0;
+  double si = 1.0;
+  if (row < n) {
+    k0 = rowptr[row];
+    len = rowptr[row + 1] - k0;
+    if (scale) si = scale[row];
+  }
+  for (int j = 0; j < w; ++j) {
+    int64_t dst = o + (int64_t)j * SSCG_WAVE + lane;
+    if (j < len) {
+      int c = col[k0 + j];
+      double v = val[k0 + j];
+      if (scale) v = (v * si) * scale[c];
+      scol[dst] = c;
+      sval[dst] = v;
+    } else {
+      scol[dst] = row < n ? row : 0;
+      sval[dst] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- MPK pass
+//
+// Pass j of the matrix-powers kernel for one or two sequences (P and R of
+// eq. cg-krylovbasis, advanced together so A is streamed once per pass):
+//   out_i = RN( sum_k a_ik u_k - theta u_i - sigma w_i ) / gamma.
+// One wavefront per 64-row slice, one lane per row.
+template <int NRHS, bool CHEB, bool HASW>
+__global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
+                                            MpkSeq s0, MpkSeq s1) {
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= A.nslices) return;
+  int lane = threadIdx.x & (SSCG_WAVE - 1);
+  int row = slice * SSCG_WAVE + lane;
+  int64_t o = A.off[slice] + lane;
+  int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+  const double* __restrict__ u0 = s0.u;
+  const double* __restrict__ u1 = s1.u;
+  dd a0 = dd_zero(), a1 = dd_zero();
+#pragma unroll 4
+  for (int j = 0; j < w; ++j) {
+    int64_t k = o + (int64_t)j * SSCG_WAVE;
+    double v = A.val[k];
+    int c = A.col[k];
+    dd_add_prod(a0, v, u0[c]);
+    if (NRHS == 2) dd_add_prod(a1, v, u1[c]);
+  }
+  if (row >= A.n) return;
+  if (CHEB) {
+    dd_add_prod(a0, -theta, u0[row]);
+    if (HASW) dd_add_prod(a0, -sigma, s0.w[row]);
+    s0.out[row] = dd_round(a0) / gamma;
+    if (NRHS == 2) {
+      dd_add_prod(a1, -theta, u1[row]);
+      if (HASW) dd_add_prod(a1, -sigma, s1.w[row]);
+      s1.out[row] = dd_round(a1) / gamma;
+    }
+  } else {
+    s0.out[row] = dd_round(a0);
+    if (NRHS == 2) s1.out[row] = dd_round(a1);
+  }
+}
+
+// Reduce a per-thread dd over the workgroup and store it as partial `slot`.
+__device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot) {
+  __shared__ double ls[SLICES_PER_WG], le[SLICES_PER_WG];
+  a = dd_wave_reduce(a);
+  int wv = threadIdx.x / SSCG_WAVE;
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) {
+    ls[wv] = a.s;
+    le[wv] = a.e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd t{ls[0], le[0]};
+    for (int q = 1; q < SLICES_PER_WG; ++q) dd_merge(t, dd{ls[q], le[q]});
+    part[2 * slot] = t.s;
+    part[2 * slot + 1] = t.e;
+  }
+}
+
+// res_i = RN(b_i - (A x)_i); partials of sum res_i^2 (and sum b_i^2).
+__global__ __launch_bounds__(WG) void k_residual(DevMat A, const double* __restrict__ b,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ r,
+                                                 double* __restrict__ rpart,
+                                                 double* __restrict__ bpart) {
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  int lane = threadIdx.x & (SSCG_WAVE - 1);
+  int row = slice * SSCG_WAVE + lane;
+  dd r2 = dd_zero(), b2 = dd_zero();
+  if (slice < A.nslices) {
+    int64_t o = A.off[slice] + lane;
+    int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    dd a = dd_zero();
+#pragma unroll 4
+    for (int j = 0; j < w; ++j) {
+      int64_t k = o + (int64_t)j * SSCG_WAVE;
+      dd_add_prod(a, A.val[k], x[A.col[k]]);
+    }
+    if (row < A.n) {
+      double bi = b[row];
+      dd_add(a, -bi);
+      double ri = -dd_round(a);
+      if (r) r[row] = ri;
+      dd_add_prod(r2, ri, ri);
+      dd_add_prod(b2, bi, bi);
+    }
+  }
+  wg_store_partial(r2, rpart, lb);
+  if (bpart) {
+    __syncthreads();
+    wg_store_partial(b2, bpart, lb);
+  }
+}
+
+// Gershgorin: partial maxima of RN(sum_j |a_ij|).
+__global__ __launch_bounds__(WG) void k_gershgorin(DevMat A, double* __restrict__ part) {
+  __shared__ double lm[SLICES_PER_WG];
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  int lane = threadIdx.x & (SSCG_WAVE - 1);
+  int row = slice * SSCG_WAVE + lane;
+  double m = 0.0;
+  if (slice < A.nslices && row < A.n) {
+    int64_t o = A.off[slice] + lane;
+    int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    dd a = dd_zero();
+    for (int j = 0; j < w; ++j) dd_add(a, fabs(A.val[o + (int64_t)j * SSCG_WAVE]));
+    m = dd_round(a);
+  }
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) m = fmax(m, __shfl_xor(m, k, SSCG_WAVE));
+  if (lane == 0) lm[threadIdx.x / SSCG_WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = lm[0];
+    for (int q = 1; q < SLICES_PER_WG; ++q) t = fmax(t, lm[q]);
+    part[lb] = t;
+  }
+}
+
+// Lanczos: w_i = RN((A v)_i - beta_prev vprev_i); partials of w.v.
+__global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __restrict__ v,
+                                                     const double* __restrict__ vprev,
+                                                     const double* __restrict__ beta_prev,
+                                                     double* __restrict__ w,
+                                                     double* __restrict__ part) {
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  int lane = threadIdx.x & (SSCG_WAVE - 1);
+  int row = slice * SSCG_WAVE + lane;
+  dd d = dd_zero();
+  if (slice < A.nslices) {
+    int64_t o = A.off[slice] + lane;
+    int wd = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    dd a = dd_zero();
+    for (int j = 0; j < wd; ++j) {
+      int64_t k = o + (int64_t)j * SSCG_WAVE;
+      dd_add_prod(a, A.val[k], v[A.col[k]]);
+    }
+    if (row < A.n) {
+      if (vprev) dd_add_prod(a, -(*beta_prev), vprev[row]);
+      double wi = dd_round(a);
+      w[row] = wi;
+      dd_add_prod(d, wi, v[row]);
+    }
+  }
+  wg_store_partial(d, part, lb);
+}
+
+inline int wg_count(int nslices) { return (nslices + SLICES_PER_WG - 1) / SLICES_PER_WG; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launches
+
+hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int nnz,
+                            int32_t* flag, hipStream_t st) {
+  int64_t m = n > nnz ? n : nnz;
+  hipLaunchKernelGGL(k_check_csr, dim3((unsigned)((m + WG - 1) / WG)), dim3(WG), 0, st, rowptr, col,
+                     n, nnz, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_widths(const int32_t* rowptr, int n, int32_t* width, hipStream_t st) {
+  int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
+  hipLaunchKernelGGL(k_sell_widths, dim3(wg_count(nslices)), dim3(WG), 0, st, rowptr, n, nslices,
+                     width);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_offsets(const int32_t* width, int nslices, int64_t* off, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, width, nslices, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_scale(const int32_t* rowptr, const double* val, int n, double* scale,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_row_scale, dim3((n + WG - 1) / WG), dim3(WG), 0, st, rowptr, val, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const double* val, int n,
+                            const double* scale, const int64_t* off, int32_t* scol, double* sval,
+                            hipStream_t st) {
+  int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
+  int threads = nslices * SSCG_WAVE;
+  hipLaunchKernelGGL(k_sell_fill, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr, col, val,
+                     n, scale, off, nslices, scol, sval);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
+                           hipStream_t st) {
+  dim3 grid(xcd_grid(wg_count(A.nslices))), blk(WG);
+  if (!bp.cheb) {
+    if (nrhs == 2)
+      hipLaunchKernelGGL((k_mpk<2, false, false>), grid, blk, 0, st, A, 0.0, 0.0, 1.0, s0, s1);
+    else
+      hipLaunchKernelGGL((k_mpk<1, false, false>), grid, blk, 0, st, A, 0.0, 0.0, 1.0, s0, s1);
+    return hipGetLastError();
+  }
+  double theta = bp.c0;
+  double gamma = j == 1 ? bp.h : bp.h2;
+  double sigma = bp.h2;
+  if (j == 1) {
+    if (nrhs == 2)
+      hipLaunchKernelGGL((k_mpk<2, true, false>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
+    else
+      hipLaunchKernelGGL((k_mpk<1, true, false>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
+  } else {
+    if (nrhs == 2)
+      hipLaunchKernelGGL((k_mpk<2, true, true>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
+    else
+      hipLaunchKernelGGL((k_mpk<1, true, true>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
+  }
+  return hipGetLastError();
+}
+
+int residual_nparts(int n) {
+  int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
+  return wg_count(nslices);
+}
+
+hipError_t launch_residual(const DevMat& A, const double* b, const double* x, double* r,
+                           double* rpart, double* bpart, int* nparts, hipStream_t st) {
+  int nb = wg_count(A.nslices);
+  *nparts = nb;
+  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, b, x, r, rpart, bpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_gershgorin(const DevMat& A, double* part, int* nparts, hipStream_t st) {
+  int nb = wg_count(A.nslices);
+  *nparts = nb;
+  hipLaunchKernelGGL(k_gershgorin, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* vprev,
+                               const double* beta_prev, double* w, double* part, int* nparts,
+                               hipStream_t st) {
+  int nb = wg_count(A.nslices);
+  *nparts = nb;
+  hipLaunchKernelGGL(k_lanczos_spmv, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v, vprev, beta_prev,
+                     w, part);
+  return hipGetLastError();
+}

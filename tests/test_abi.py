@@ -1,0 +1,78 @@
+"""The C ABI: the built library loads and exports every function that
+include/sscg.h declares, and the ctypes mirrors of its structs have the C
+layout (checked against gcc's own sizeof/offsetof).  No GPU needed."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sscg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sscg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1701_03989_amd import sscg
+
+    if not os.path.exists(sscg.LIB_PATH):
+        from paper_1701_03989_amd import build
+
+        build.build()
+    return sscg.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1701_03989_amd import sscg
+
+    assert sorted(sscg.EXPORTS) == names
+
+
+def test_struct_layouts_match_c(tmp_path):
+    from paper_1701_03989_amd import sscg
+
+    structs = {"sscg_csr": sscg.Csr, "sscg_opts": sscg.Opts, "sscg_result": sscg.Result,
+               "sscg_block_info": sscg.BlockInfo, "sscg_block_params": sscg.BlockParams}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", str(c), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    for ln in out:
+        if not ln:
+            continue
+        cname, field, val = ln.split()
+        py = structs[cname]
+        if field == "size":
+            assert ctypes.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, field).offset == int(val), (cname, field)
+
+
+def test_errors_without_a_device_or_context(lib):
+    # NULL context: argument error, no crash
+    assert lib.sscg_solve(None, None, None, None, None, None) == -1
+    assert lib.sscg_set_timing(None, 1) == -1
+    from paper_1701_03989_amd import sscg
+
+    o = sscg.Opts()
+    lib.sscg_opts_default(ctypes.byref(o))
+    assert o.s_max == 8 and o.tol == 1e-10 and o.c == 1.0 and o.inner_check == 1
+    assert o.mode == sscg.MODE_ADAPTIVE and o.basis == sscg.BASIS_MONOMIAL

@@ -1,0 +1,357 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, through the
+C ABI, on the same seeded inputs.
+
+Bar: the kernels round every row sum / inner product once from its exact
+value and the oracle does too, so stage outputs must agree to the last bit
+(the tests allow 1e-15 relative for the rare near-tie of the double-double
+accumulation and report exact-match fractions).  Whole solves: same s_k
+schedule and iterates within 1e-12 relative (the stated tolerance).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cg as ocg  # noqa: E402
+from oracle import kappa as okappa  # noqa: E402
+from oracle import spectral, sstep  # noqa: E402
+from oracle.arith import CR  # noqa: E402
+from paper_1701_03989_amd import problems, sscg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = sscg.sscg_create(0)
+    yield h
+    sscg.sscg_destroy(h)
+
+
+def dvec(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_bits(got, ref, what, rel=1e-15):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, what
+    same = got == ref
+    frac = same.mean() if same.size else 1.0
+    diff = np.abs(got - ref)
+    scale = np.maximum(np.abs(ref), 1e-300)
+    worst = float((diff / scale).max()) if diff.size else 0.0
+    say(f"{what}: exact {frac:.6f}, worst rel {worst:.2e}")
+    assert worst <= rel, f"{what}: worst relative difference {worst}"
+
+
+MATRICES = {
+    "poisson2d_32": lambda: problems.poisson2d(32),
+    "poisson2d_25x41": lambda: problems.poisson2d(25, 41),   # ragged: n = 1025
+    "poisson3d_11": lambda: problems.poisson3d(11),          # n = 1331
+    "laplacian_3001": lambda: problems.graph_laplacian(3001, 7),
+}
+
+
+def _Y_oracle(A, s, first, basis, lmin, lmax, p, r):
+    ar = CR()
+    prm = sstep.basis_params(basis, s, lmin, lmax, ar)
+    return sstep.krylov_basis(ar, A, p, r, s, first, prm)
+
+
+@pytest.mark.parametrize("name", list(MATRICES))
+@pytest.mark.parametrize("basis", ["monomial", "chebyshev"])
+@pytest.mark.parametrize("first", [True, False])
+def test_mpk_gram_recover_match_oracle(ctx, name, basis, first):
+    A = MATRICES[name]()
+    n = A.n
+    s = 5
+    say(f"mpk/gram/recover {name} n={n} basis={basis} first={first}")
+    lmin, lmax = (spectral.chebyshev_interval(A, 20, 1) if basis == "chebyshev" else (0.0, 1.0))
+    p = problems.uniform(n, 11)
+    r = problems.uniform(n, 12)
+    Yo = _Y_oracle(A, s, first, basis, lmin, lmax, p, r)
+    ld = (n + 63) // 64 * 64 + 64
+    rcol = s + 2  # a gap column, to check the column map
+    Y = torch.zeros((2 * s + 3) * ld, dtype=torch.float64, device=DEV)
+    Y[:n] = dvec(p)
+    if not first:
+        Y[rcol * ld: rcol * ld + n] = dvec(r)
+    Ad = sscg.DeviceCsr.from_host(A, DEV)
+    bcode = sscg.BASIS_CHEBYSHEV if basis == "chebyshev" else sscg.BASIS_MONOMIAL
+    sscg.sscg_mpk(ctx, Ad, s, first, bcode, lmin, lmax, Y, ld, rcol)
+    Yh = host(Y)
+    cols = list(range(s + 1)) + ([] if first else list(range(rcol, rcol + s)))
+    for a, c in enumerate(cols):
+        assert_bits(Yh[c * ld: c * ld + n], Yo[a], f"Y col {a}")
+    # Gram of the device basis vs the oracle's Gram of the same vectors
+    d = len(cols)
+    G = torch.zeros(d * d, dtype=torch.float64, device=DEV)
+    sscg.sscg_gram(ctx, n, s, first, Y, ld, rcol, G)
+    Gh = host(G).reshape(d, d)
+    Go = np.array(CR().gram([Yh[c * ld: c * ld + n] for c in cols]))
+    assert_bits(Gh, Go, "G")
+    # recovery with random coefficients
+    rng = np.random.default_rng(3)
+    coef = rng.standard_normal(3 * d)
+    coef[rng.random(3 * d) < 0.2] = 0.0
+    x0 = problems.uniform(n, 13)
+    xd = dvec(x0)
+    rd = torch.zeros(n, dtype=torch.float64, device=DEV)
+    pd = torch.zeros(n, dtype=torch.float64, device=DEV)
+    sscg.sscg_recover(ctx, n, s, first, Y, ld, rcol, dvec(coef), xd, rd, pd)
+    ys = [Yh[c * ld: c * ld + n] for c in cols]
+    xo, ro, po = sstep.recover(CR(), ys, coef[:d], coef[d:2 * d], coef[2 * d:], x0)
+    assert_bits(host(xd), xo, "x")
+    assert_bits(host(rd), ro, "r")
+    assert_bits(host(pd), po, "p")
+
+
+@pytest.mark.parametrize("first", [True, False])
+@pytest.mark.parametrize("basis", ["monomial", "chebyshev"])
+@pytest.mark.parametrize("adaptive", [True, False])
+def test_small_solve_matches_oracle(ctx, first, basis, adaptive):
+    """kappa list, s~, s_k, alpha/beta and coefficients from the same G."""
+    A = problems.poisson2d(32)
+    s = 8 if first else 5
+    lmin, lmax = (0.0181, 7.99) if basis == "chebyshev" else (0.0, 1.0)
+    Yo = _Y_oracle(A, s, first, basis, lmin, lmax, problems.uniform(A.n, 1),
+                   problems.uniform(A.n, 2))
+    ar = CR()
+    G = ar.gram(Yo)
+    d = len(G)
+    eps_star = 1e-10 * 30.0
+    say(f"small_solve first={first} basis={basis} adaptive={adaptive} d={d}")
+    prm = sscg.BlockParams(s=s, first=int(first), adaptive=int(adaptive), iters=s, inner_check=1,
+                           basis=sscg.BASIS_CHEBYSHEV if basis == "chebyshev" else 0,
+                           lambda_min=lmin, lambda_max=lmax, eps_star=eps_star, c=1.0)
+    coef = torch.zeros(3 * d, dtype=torch.float64, device=DEV)
+    info_t = torch.zeros(1024, dtype=torch.uint8, device=DEV)
+    sscg.sscg_small_solve(ctx, dvec(np.array(G).ravel()), prm, coef, info_t)
+    info = sscg.block_info_from(info_t)
+    # oracle
+    if adaptive:
+        rnorm = ar.sqrt(G[0][0] if first else G[s + 1][s + 1])
+        thr = ar.div(eps_star, (1.0 * sstep.EPS) * rnorm)
+        kap = [okappa.kappa_spd(sstep.principal(G, sstep.sub_indices(s, i, first)))
+               for i in range(1, s + 1)]
+        assert_bits(list(info.kappa)[:s], kap, "kappa")
+        st = 1
+        for i in range(1, s + 1):
+            if ar.sqrt(kap[i - 1]) <= thr:
+                st = i
+            else:
+                break
+        gam = ar.sqrt(kap[st - 1])
+        assert info.thr == thr and info.gamma == gam
+
+        def check(j, rr1):
+            return gam >= ar.div(eps_star, (1.0 * sstep.EPS) * ar.sqrt(max(rr1, 0.0)))
+    else:
+        st = s
+        check = None
+    assert info.s_tilde == st
+    idx = sstep.sub_indices(s, st, first)
+    Bs = sstep.assemble_B(ar, st, first, sstep.basis_params(basis, st, lmin, lmax, ar))
+    s_k, xc, rc, pc, al, be, rr, status = sstep.inner_loop(ar, sstep.principal(G, idx), Bs, st,
+                                                           first, check)
+    say(f"  s~={info.s_tilde} s_k={info.s_k} (oracle {s_k})")
+    assert info.s_k == s_k and info.status == status
+    assert_bits(list(info.alpha)[:s_k], al, "alpha")
+    assert_bits(list(info.beta)[:s_k], be, "beta")
+    full = np.zeros((3, d))
+    for a, fa in enumerate(idx):
+        full[0, fa], full[1, fa], full[2, fa] = xc[a], rc[a], pc[a]
+    assert_bits(host(coef), full.ravel(), "coef")
+
+
+@pytest.mark.parametrize("name", ["poisson2d_32", "poisson3d_11", "laplacian_3001"])
+def test_residual_and_spectral_bounds_match_oracle(ctx, name):
+    A = MATRICES[name]()
+    n = A.n
+    say(f"residual/spectral {name}")
+    b = problems.uniform(n, 4)
+    x = problems.uniform(n, 5)
+    Ad = sscg.DeviceCsr.from_host(A, DEV)
+    r = torch.zeros(n, dtype=torch.float64, device=DEV)
+    out2 = torch.zeros(2, dtype=torch.float64, device=DEV)
+    sscg.sscg_residual(ctx, Ad, dvec(b), dvec(x), r, out2)
+    ro = sstep.true_residual(CR(), A, b, x)
+    assert_bits(host(r), ro, "r = b - A x")
+    assert_bits(host(out2), [CR().dot(ro, ro), CR().dot(b, b)], "norms")
+    lo, hi = sscg.sscg_spectral_bounds(ctx, Ad, 30, 0)
+    olo, ohi = spectral.chebyshev_interval(A, 30, 0)
+    assert_bits([lo, hi], [olo, ohi], "Chebyshev interval")
+
+
+def _solve(ctx, A, b, x1, cap=4096, **kw):
+    Ad = sscg.DeviceCsr.from_host(A, DEV)
+    x = dvec(x1)
+    hist = sscg.History(cap, kw.get("s_max", 8))
+    rc = sscg.sscg_solve(ctx, Ad, dvec(b), x, sscg.make_opts(**kw), hist)
+    return rc, host(x), hist
+
+
+SOLVES = [
+    dict(mode="adaptive", s_max=8, tol=1e-10, equilibrate=True),
+    dict(mode="adaptive", s_max=8, tol=1e-14, equilibrate=True),
+    dict(mode="fixed", fixed_s=4, s_max=8, tol=1e-10, equilibrate=True),
+    dict(mode="fixed", fixed_s=1, s_max=8, tol=1e-10),
+    dict(mode="adaptive", s_max=10, tol=1e-12, basis="chebyshev", lmin=0.0181, lmax=8.0),
+    dict(mode="adaptive", s_max=16, tol=1e-10, basis="chebyshev", lmin=0.0181, lmax=8.0),
+    dict(mode="adaptive", s_max=8, tol=1e-10, inner_check=False),
+    dict(mode="adaptive", s_max=6, tol=1e-10, s0_bar=2, f=1, c=10.0),
+]
+
+
+@pytest.mark.parametrize("k", range(len(SOLVES)))
+def test_full_solve_matches_oracle_on_poisson_32(ctx, k):
+    """Same s_k schedule and the same iterates (1e-12 relative) as the oracle."""
+    kw = SOLVES[k]
+    A, b, x1, _ = problems.poisson2d_32_system(0)
+    say(f"solve {kw}")
+    ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
+    rc, x, hist = _solve(ctx, A, b, x1, **kw)
+    say(f"  gpu {hist.blocks} blocks {hist.schedule[:20]}  oracle {len(ref.blocks)} blocks")
+    assert rc == ref.status
+    assert hist.schedule == ref.schedule
+    for kb, blk in enumerate(ref.blocks):
+        assert hist.s_tilde[kb] == blk.s_tilde and hist.s_built[kb] == blk.s_built
+        if kw["mode"] == "adaptive":
+            # the device evaluates every candidate i; the oracle stops at the
+            # first one that fails eq. condy
+            gk = hist.kappas(kb)
+            assert len(gk) == blk.s_built and gk[: len(blk.kappas)] == blk.kappas, kb
+        assert hist.relres_true[kb] == pytest.approx(blk.relres_true, rel=1e-9)
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    say(f"  |x - x_oracle| / |x_oracle| = {err:.2e}")
+    assert err <= 1e-12
+    assert hist.res.relres <= kw["tol"] or rc != sscg.OK
+
+
+def test_schedule_replay_matches_oracle_iterates(ctx):
+    """Alg. 3 with the oracle's adaptive schedule: x after every block within
+    1e-12 (the GPU replays block by block through max_iters)."""
+    A, b, x1, _ = problems.poisson2d_32_system(0)
+    ref = sstep.solve(A, b, x1, sstep.Opts(mode="adaptive", s_max=8, tol=1e-10, equilibrate=True))
+    sched = ref.schedule
+    say(f"replay {sched}")
+    for nb in [1, 2, 3, len(sched) // 2, len(sched)]:
+        m = sum(sched[:nb])
+        o = sstep.solve(A, b, x1, sstep.Opts(mode="schedule", schedule=sched, s_max=8, tol=1e-30,
+                                             equilibrate=True, max_iters=m))
+        rc, x, hist = _solve(ctx, A, b, x1, mode="schedule", schedule=sched, s_max=8, tol=1e-30,
+                             equilibrate=True, max_iters=m)
+        assert hist.blocks == nb == len(o.blocks)
+        err = np.linalg.norm(x - o.x) / np.linalg.norm(o.x)
+        say(f"  after {nb} blocks: {err:.2e}")
+        assert err <= 1e-12
+        al_g = []  # alpha/beta are checked in test_small_solve_matches_oracle
+
+
+def test_classical_equivalence_on_gpu(ctx):
+    """Fixed s = 1 on the GPU against literal Algorithm 1 in the oracle."""
+    A, b, x1, _ = problems.poisson2d_32_system(0)
+    cl = ocg.cg(A, b, x1, tol=1e-10)
+    rc, x, hist = _solve(ctx, A, b, x1, mode="fixed", fixed_s=1, s_max=1, tol=1e-10)
+    say(f"classical {cl.iters} iterations, gpu s=1 {hist.blocks} blocks")
+    assert rc == sscg.OK and abs(hist.blocks - cl.iters) <= 1
+    assert np.linalg.norm(x - cl.x) / np.linalg.norm(cl.x) < 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1000])
+def test_tiny_and_ragged_sizes(ctx, n):
+    rng = np.random.default_rng(n)
+    M = np.diag(rng.uniform(1.0, 3.0, n))
+    for i in range(n - 1):
+        M[i, i + 1] = M[i + 1, i] = -0.4
+    A = problems.from_dense(M) if n <= 65 else problems.poisson2d(40, 25)
+    b = problems.uniform(A.n, 9)
+    x1 = np.zeros(A.n)
+    say(f"tiny/ragged n={A.n}")
+    for kw in [dict(mode="adaptive", s_max=8, tol=1e-12), dict(mode="fixed", fixed_s=3, tol=1e-12)]:
+        opts = sstep.Opts(**kw)
+        ref = sstep.solve(A, b, x1, opts)
+        rc, x, hist = _solve(ctx, A, b, x1, **kw)
+        assert rc == ref.status and hist.schedule == ref.schedule
+        assert np.linalg.norm(x - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+def test_degenerate_inputs(ctx):
+    A, b, x1, xt = problems.poisson2d_32_system(0)
+    say("zero rhs / exact start")
+    rc, x, hist = _solve(ctx, A, np.zeros(A.n), problems.uniform(A.n, 3))
+    assert rc == sscg.OK and hist.blocks == 0 and not x.any()
+    # start at the oracle's converged solution: no block needed
+    ref = sstep.solve(A, b, x1, sstep.Opts(tol=1e-10))
+    rc, x, hist = _solve(ctx, A, b, ref.x, tol=1e-8)
+    assert rc == sscg.OK and hist.blocks == 0 and np.array_equal(x, ref.x)
+    # tolerance below attainable accuracy: s_k = 1 blocks, then the cap
+    rc, x, hist = _solve(ctx, A, b, x1, tol=1e-19, max_iters=20)
+    assert rc == sscg.NOT_CONVERGED and hist.res.iters >= 20
+    assert all(s == 1 for s in hist.schedule[:3])
+
+
+def test_breakdown_and_argument_errors(ctx):
+    M = np.diag([1.0, -2.0, 3.0, 4.0])
+    M[0, 1] = M[1, 0] = 0.5
+    A = problems.from_dense(M)
+    say("breakdown / errors")
+    rc, x, hist = _solve(ctx, A, np.ones(4), np.zeros(4), mode="fixed", fixed_s=2, tol=1e-12,
+                         max_iters=50)
+    ref = sstep.solve(A, np.ones(4), np.zeros(4), sstep.Opts(mode="fixed", fixed_s=2, tol=1e-12,
+                                                              max_iters=50))
+    assert rc == ref.status
+    Ad = sscg.DeviceCsr.from_host(problems.poisson2d(8), DEV)
+    b = dvec(np.ones(64))
+    x = dvec(np.zeros(64))
+    for bad in [dict(s_max=0), dict(s_max=17), dict(tol=0.0), dict(mode="fixed", fixed_s=9),
+                dict(basis="chebyshev", lmin=2.0, lmax=1.0), dict(c=-1.0), dict(max_iters=0)]:
+        with pytest.raises(sscg.SscgError) as e:
+            sscg.sscg_solve(ctx, Ad, b, x, sscg.make_opts(**bad))
+        assert e.value.code == sscg.ERR_ARG
+    # malformed CSR: column out of range and a wrong nnz
+    broken = sscg.DeviceCsr(Ad.rowptr, Ad.col.clone(), Ad.val)
+    broken.col[5] = 64
+    with pytest.raises(sscg.SscgError) as e:
+        sscg.sscg_solve(ctx, broken, b, x, sscg.make_opts())
+    assert e.value.code == sscg.ERR_ARG and "column" in str(e.value)
+    short = sscg.DeviceCsr(Ad.rowptr, Ad.col[:-1], Ad.val[:-1])
+    with pytest.raises(sscg.SscgError):
+        sscg.sscg_solve(ctx, short, b, x, sscg.make_opts())
+    assert not host(x).any()
+
+
+def test_bitwise_deterministic(ctx):
+    A, b, x1, _ = problems.poisson2d_32_system(1)
+    say("determinism")
+    outs = [_solve(ctx, A, b, x1, mode="adaptive", s_max=8, tol=1e-12, basis="chebyshev",
+                   lmin=0.018, lmax=8.0)[1] for _ in range(3)]
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_timing_counters(ctx):
+    A, b, x1, _ = problems.poisson2d_32_system(0)
+    say("timing")
+    sscg.sscg_set_timing(ctx, True)
+    rc, x, hist = _solve(ctx, A, b, x1, mode="fixed", fixed_s=4, tol=1e-10)
+    n, ms, by = sscg.sscg_kernel_stats(ctx, "mpk")
+    sscg.sscg_set_timing(ctx, False)
+    assert n == sum(hist.s_built[: hist.blocks]) and ms > 0 and by > 0
