@@ -212,14 +212,13 @@ int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_
 /* ---------------------------------------------------------------- timing */
 
 /* Kernel timing with HIP events on the context's stream (off by default).
- * While on, sscg_solve records an event pair around every launch of each
- * kernel family; sscg_kernel_stats returns, for family id (0 = matrix powers
- * pass, 1 = Gram, 2 = recovery, 3 = coordinate solve), the launches, their
- * summed duration in ms and their summed algorithmic bytes.  Resets on
- * enabling. */
+ * While on, sscg_solve and the per-stage calls record an event pair around
+ * every launch of each kernel family; sscg_kernel_stats (which waits for the
+ * stream) returns, for family id (0 = matrix powers pass, 1 = Gram,
+ * 2 = recovery, 3 = coordinate solve), the launches, their summed duration
+ * in ms and their summed algorithmic bytes.  Resets on enabling. */
 int sscg_set_timing(sscg_ctx* ctx, int on);
-int sscg_kernel_stats(const sscg_ctx* ctx, int family, int64_t* launches, double* ms,
-                      double* bytes);
+int sscg_kernel_stats(sscg_ctx* ctx, int family, int64_t* launches, double* ms, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -426,9 +426,14 @@ int sscg_set_timing(sscg_ctx* ctx, int on) {
   return SSCG_OK;
 }
 
-int sscg_kernel_stats(const sscg_ctx* ctx, int family, int64_t* launches, double* ms,
-                      double* bytes) {
+int sscg_kernel_stats(sscg_ctx* ctx, int family, int64_t* launches, double* ms, double* bytes) {
   if (!ctx || family < 0 || family >= NFAM) return SSCG_ERR_ARG;
+  if (ctx->ev_used) {  // events of per-stage calls not yet collected
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(ev_collect(ctx));
+  }
   if (launches) *launches = ctx->launches[family];
   if (ms) *ms = ctx->ms[family];
   if (bytes) *bytes = ctx->bytes[family];

@@ -14,7 +14,7 @@
 namespace {
 
 constexpr int MAXK = 2 * SSCG_S_LIMIT + 1;  // largest sub-Gram dimension
-constexpr int LDK = MAXK + 1;
+constexpr int LDK = MAXK;                  // odd row stride: column walks hit distinct banks
 constexpr double EPS = 0x1p-53;            // unit round-off (Section 5)
 constexpr int MAX_SWEEPS = 40;
 
@@ -24,35 +24,40 @@ __device__ __forceinline__ int sub_index(int a, int i, int s, int first) {
   return s + 1 + (a - i - 1);
 }
 
-// Round-robin position of index `pos_i` at step t (m even).
+// Round-robin position of slot i at step t (m even).
 __device__ __forceinline__ int rr_pos(int i, int t, int m) {
   return i == 0 ? 0 : 1 + ((i - 1 + t) % (m - 1));
 }
 
-// Eigenvalues of the k x k symmetric matrix in A (LDS, leading dim LDK) by
-// cyclic Jacobi; on return the diagonal holds them.  Called by all 64 lanes.
-__device__ void jacobi(double (*A)[LDK], double (*B)[LDK], int k, double* wself, double* wother,
-                       int* partner, double* rt, double* rapp, double* raqq, double* rapq,
-                       int* rp, int* rq, int* nrot) {
-  const int lane = threadIdx.x;
+struct JacobiLds {
+  double A[MAXK * LDK];  // the matrix, row-major, both triangles kept equal
+  double B[MAXK * LDK];  // A J of the current step
+  double ws[MAXK], wo[MAXK];  // weights of index i: new_i = ws*old_i + wo*old_partner
+  double fd[MAXK];            // exact diagonal of a rotated index after the step
+  int pt[MAXK];               // partner of index i in this step, -1 if not rotated
+  int nrot[2];
+};
+
+// Eigenvalues of the k x k symmetric matrix in L.A (k <= MAXK) by cyclic
+// Jacobi, JT threads: thread t owns column t & 63 and rows (t >> 6) + 4j in
+// the application phases; threads t < m/2 form the rotations.
+constexpr int JT = 256;
+constexpr int RPT = (MAXK + 3) / 4;  // rows per thread in the application phases
+__device__ __forceinline__ void jacobi(JacobiLds& L, int k) {
+  const int t = threadIdx.x;
   const int m = (k & 1) ? k + 1 : k;
+  const int c = t & 63;
+  const int cc = c < k ? c : k - 1;  // clamped column: every load is in bounds
+  const int r0 = t >> 6;
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     int rotated = 0;
-    for (int t = 0; t < m - 1; ++t) {
-      // rotation parameters, one lane per pair
-      if (lane < MAXK) {
-        partner[lane] = -1;
-      }
-      __syncthreads();
-      if (lane == 0) *nrot = 0;
-      __syncthreads();
-      if (lane < m / 2) {
-        int a = rr_pos(lane, t, m), b = rr_pos(m - 1 - lane, t, m);
+    for (int st = 0; st < m - 1; ++st) {
+      bool rot = false;
+      if (t < m / 2) {
+        int a = rr_pos(t, st, m), b = rr_pos(m - 1 - t, st, m);
         int p = min(a, b), q = max(a, b);
-        int slot = lane;
-        rp[slot] = -1;
         if (q < k) {
-          double app = A[p][p], aqq = A[q][q], apq = A[p][q];
+          double app = L.A[p * LDK + p], aqq = L.A[q * LDK + q], apq = L.A[p * LDK + q];
           double thr = EPS * (sqrt(fabs(app)) * sqrt(fabs(aqq)));
           if (fabs(apq) > thr) {
             double tau = (aqq - app) / (2.0 * apq);
@@ -63,56 +68,74 @@ __device__ void jacobi(double (*A)[LDK], double (*B)[LDK], int k, double* wself,
               double sg = tau >= 0.0 ? 1.0 : -1.0;
               tt = sg / (fabs(tau) + sqrt(1.0 + tau * tau));
             }
-            double c = 1.0 / sqrt(1.0 + tt * tt);
-            double s = tt * c;
-            wself[p] = c;
-            wother[p] = -s;
-            partner[p] = q;
-            wself[q] = c;
-            wother[q] = s;
-            partner[q] = p;
-            rt[slot] = tt;
-            rapp[slot] = app;
-            raqq[slot] = aqq;
-            rapq[slot] = apq;
-            rp[slot] = p;
-            rq[slot] = q;
-            atomicAdd(nrot, 1);
+            double cs = 1.0 / sqrt(1.0 + tt * tt);
+            double s = tt * cs;
+            L.ws[p] = cs; L.wo[p] = -s; L.pt[p] = q;
+            L.ws[q] = cs; L.wo[q] = s; L.pt[q] = p;
+            L.fd[p] = app - tt * apq;
+            L.fd[q] = aqq + tt * apq;
+            rot = true;
+          } else {
+            L.pt[p] = -1; L.pt[q] = -1;
           }
+        } else if (p < k) {
+          L.pt[p] = -1;
+        }
+      }
+      if (t < 64) {
+        int nr = __popcll(__ballot(rot));
+        if (t == 0) L.nrot[st & 1] = nr;
+      }
+      __syncthreads();
+      const int nr = L.nrot[st & 1];
+      if (nr == 0) continue;
+      rotated += nr;
+      {  // B = A J, column cc, rows r0 + 4j
+        const int pc = L.pt[cc];
+        const int pcc = pc >= 0 ? pc : cc;
+        const double wsc = L.ws[cc], woc = L.wo[cc];
+        double av[RPT], aw[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int r = min(r0 + 4 * j, k - 1);
+          av[j] = L.A[r * LDK + cc];
+          aw[j] = L.A[r * LDK + pcc];
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int r = r0 + 4 * j;
+          const double v = pc >= 0 ? wsc * av[j] + woc * aw[j] : av[j];
+          if (c < k && r < k) L.B[r * LDK + c] = v;
         }
       }
       __syncthreads();
-      int nr = *nrot;
-      if (nr == 0) continue;
-      rotated += nr;
-      // B = A J (columns)
-      for (int e = lane; e < k * k; e += SSCG_WAVE) {
-        int r = e / k, c = e - r * k;
-        int pc = partner[c];
-        B[r][c] = pc >= 0 ? wself[c] * A[r][c] + wother[c] * A[r][pc] : A[r][c];
-      }
-      __syncthreads();
-      // A = J^T B (rows)
-      for (int e = lane; e < k * k; e += SSCG_WAVE) {
-        int r = e / k, c = e - r * k;
-        int pr = partner[r];
-        A[r][c] = pr >= 0 ? wself[r] * B[r][c] + wother[r] * B[pr][c] : B[r][c];
-      }
-      __syncthreads();
-      // mirror the upper triangle
-      for (int e = lane; e < k * k; e += SSCG_WAVE) {
-        int r = e / k, c = e - r * k;
-        if (r > c) A[r][c] = A[c][r];
-      }
-      __syncthreads();
-      // exact 2x2 updates of the rotated pairs (start-of-step values)
-      if (lane < m / 2 && rp[lane] >= 0) {
-        int p = rp[lane], q = rq[lane];
-        double tt = rt[lane];
-        A[p][p] = rapp[lane] - tt * rapq[lane];
-        A[q][q] = raqq[lane] + tt * rapq[lane];
-        A[p][q] = 0.0;
-        A[q][p] = 0.0;
+      {  // A = J^T B on and above the diagonal, mirrored; exact 2x2 blocks
+        const int pc = L.pt[cc];
+        double bv[RPT], bw[RPT], wr[RPT], wq[RPT];
+        int prr[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int r = min(r0 + 4 * j, k - 1);
+          const int pr = L.pt[r];
+          prr[j] = pr;
+          bv[j] = L.B[r * LDK + cc];
+          bw[j] = L.B[(pr >= 0 ? pr : r) * LDK + cc];
+          wr[j] = L.ws[r];
+          wq[j] = L.wo[r];
+        }
+        const double fdc = L.fd[cc];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int r = r0 + 4 * j;
+          double v;
+          if (r == c && pc >= 0) v = fdc;
+          else if (prr[j] == c) v = 0.0;
+          else v = prr[j] >= 0 ? wr[j] * bv[j] + wq[j] * bw[j] : bv[j];
+          if (c < k && r <= c) {
+            L.A[r * LDK + c] = v;
+            L.A[c * LDK + r] = v;
+          }
+        }
       }
       __syncthreads();
     }
@@ -120,21 +143,11 @@ __device__ void jacobi(double (*A)[LDK], double (*B)[LDK], int k, double* wself,
   }
 }
 
-struct JacobiLds {
-  double A[MAXK][LDK];
-  double B[MAXK][LDK];
-  double wself[MAXK + 1], wother[MAXK + 1];
-  int partner[MAXK + 1];
-  double rt[MAXK], rapp[MAXK], raqq[MAXK], rapq[MAXK];
-  int rp[MAXK], rq[MAXK];
-  int nrot;
-};
-
-__device__ double kappa_from_diag(double (*A)[LDK], int k) {
-  double lmin = A[0][0], lmax = A[0][0];
+__device__ double kappa_from_diag(const JacobiLds& L, int k) {
+  double lmin = L.A[0], lmax = L.A[0];
   bool nan = lmin != lmin;
   for (int a = 1; a < k; ++a) {
-    double v = A[a][a];
+    double v = L.A[a * LDK + a];
     if (v != v) nan = true;
     lmin = v < lmin ? v : lmin;
     lmax = v > lmax ? v : lmax;
@@ -144,43 +157,44 @@ __device__ double kappa_from_diag(double (*A)[LDK], int k) {
 }
 
 // grid = s workgroups of one wave; workgroup i-1 computes kappa(G_i).
-__global__ __launch_bounds__(SSCG_WAVE) void k_kappa(const double* __restrict__ G, int d, int s,
+__global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int d, int s,
                                                      int first, sscg_block_info* info) {
   __shared__ JacobiLds L;
   int i = blockIdx.x + 1;
   int k = first ? i + 1 : 2 * i + 1;
-  for (int e = threadIdx.x; e < k * k; e += SSCG_WAVE) {
-    int a = e / k, b = e - a * k;
-    L.A[a][b] = G[sub_index(a, i, s, first) * d + sub_index(b, i, s, first)];
+  if (threadIdx.x < k) {
+    int b = threadIdx.x;
+    int gb = sub_index(b, i, s, first);
+    for (int a = 0; a < k; ++a) L.A[a * LDK + b] = G[sub_index(a, i, s, first) * d + gb];
   }
   __syncthreads();
-  jacobi(L.A, L.B, k, L.wself, L.wother, L.partner, L.rt, L.rapp, L.raqq, L.rapq, L.rp, L.rq,
-         &L.nrot);
-  if (threadIdx.x == 0) info->kappa[i - 1] = kappa_from_diag(L.A, k);
+  jacobi(L, k);
+  if (threadIdx.x == 0) info->kappa[i - 1] = kappa_from_diag(L, k);
 }
 
 // Eigenvalue extremes of the Lanczos tridiagonal matrix (k <= MAXK).
-__global__ __launch_bounds__(SSCG_WAVE) void k_tridiag_eig(const double* __restrict__ alpha,
+__global__ __launch_bounds__(JT) void k_tridiag_eig(const double* __restrict__ alpha,
                                                            const double* __restrict__ beta, int k,
                                                            double* lmin, double* lmax) {
   __shared__ JacobiLds L;
-  for (int e = threadIdx.x; e < k * k; e += SSCG_WAVE) {
-    int a = e / k, b = e - a * k;
-    double v = 0.0;
-    if (a == b) v = alpha[a];
-    else if (b == a + 1) v = beta[a];
-    else if (a == b + 1) v = beta[b];
-    L.A[a][b] = v;
+  if (threadIdx.x < k) {
+    int b = threadIdx.x;
+    for (int a = 0; a < k; ++a) {
+      double v = 0.0;
+      if (a == b) v = alpha[a];
+      else if (b == a + 1) v = beta[a];
+      else if (a == b + 1) v = beta[b];
+      L.A[a * LDK + b] = v;
+    }
   }
   __syncthreads();
-  if (k > 1)
-    jacobi(L.A, L.B, k, L.wself, L.wother, L.partner, L.rt, L.rapp, L.raqq, L.rapq, L.rp, L.rq,
-           &L.nrot);
+  if (k > 1) jacobi(L, k);
   if (threadIdx.x == 0) {
-    double lo = L.A[0][0], hi = L.A[0][0];
+    double lo = L.A[0], hi = L.A[0];
     for (int a = 1; a < k; ++a) {
-      lo = L.A[a][a] < lo ? L.A[a][a] : lo;
-      hi = L.A[a][a] > hi ? L.A[a][a] : hi;
+      double v = L.A[a * LDK + a];
+      lo = v < lo ? v : lo;
+      hi = v > hi ? v : hi;
     }
     *lmin = lo;
     *lmax = hi;
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ 
 
 hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_info* info,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_kappa, dim3(s), dim3(SSCG_WAVE), 0, st, G, d, s, first, info);
+  hipLaunchKernelGGL(k_kappa, dim3(s), dim3(JT), 0, st, G, d, s, first, info);
   return hipGetLastError();
 }
 
@@ -364,6 +378,6 @@ hipError_t launch_inner(const double* G, const sscg_block_params& prm, double* c
 
 hipError_t launch_tridiag_eig(const double* alpha, const double* beta, int k, double* lmin,
                               double* lmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(SSCG_WAVE), 0, st, alpha, beta, k, lmin, lmax);
+  hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(JT), 0, st, alpha, beta, k, lmin, lmax);
   return hipGetLastError();
 }
