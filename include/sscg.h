@@ -111,6 +111,9 @@ typedef struct {
   double* relres_true;   /* ||b - A x|| / ||b|| after the block                    */
   double* kappa;         /* cap*s_max: kappa(G_{k,i}), i = 1..s_max (NaN if not
                             computed); row k at kappa + k*s_max                    */
+  int32_t spec_blocks;   /* blocks run ahead speculatively (s_k = s assumed while
+                            the exact s~/break decisions ran alongside)           */
+  int32_t spec_rejected; /* of those, blocks redone because the decisions differed */
 } sscg_result;
 
 /* Device-side record of one block's coordinate solve (sscg_small_solve). */
@@ -126,6 +129,11 @@ typedef struct {
   double kappa[SSCG_S_LIMIT];      /* kappa(G_i), i = 1..s (adaptive)              */
   double alpha[SSCG_S_LIMIT];      /* alpha_{m+j}, j = 1..s_k                      */
   double beta[SSCG_S_LIMIT];       /* beta_{m+j}                                   */
+  double rr_trace[SSCG_S_LIMIT];   /* r'^T G r' after iteration j = 1..s_k         */
+  double relres_in;      /* sscg_solve only: ||b - A x|| / ||b|| of the block's start */
+  int32_t spec;          /* sscg_solve only: 0 run directly, 1 speculative and
+                            confirmed, 2 speculative and rejected (block redone)  */
+  int32_t pad_;
 } sscg_block_info;
 
 /* Parameters of one block's coordinate solve. */

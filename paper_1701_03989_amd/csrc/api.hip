@@ -1,27 +1,21 @@
-// C ABI of libsscg: context, workspace, the outer block loop of
-// Algorithms 2-4 and the per-stage entry points.  All arithmetic of the
+// C ABI of libsscg: context, workspace, validation, the per-stage entry
+// points and the helpers the solver shares with them.  All arithmetic of the
 // method runs in the kernels of spmv.hip, dense.hip and small.hip; the host
-// only sizes launches and steers the loop (s_bar, stopping) from the few
-// scalars it reads back once per block.
+// only sizes launches and moves a few scalars.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
-#include <string>
-#include <vector>
 
-#include "common.h"
+#include "ctx.h"
 
 namespace {
+thread_local std::string g_create_err;
+}
 
-constexpr int NFAM = 4;  // timing families: mpk, gram, recover, small
-
-struct Buf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
+namespace sscg_host {
 
 hipError_t ensure(Buf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -39,42 +33,6 @@ hipError_t ensure(Buf& b, size_t bytes) {
   return e;
 }
 
-template <class T>
-T* as(Buf& b) {
-  return reinterpret_cast<T*>(b.p);
-}
-
-struct EvRec {
-  hipEvent_t a, b;
-  int fam;
-  double bytes;
-};
-
-thread_local std::string g_create_err;
-
-}  // namespace
-
-struct sscg_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  // matrix copy
-  Buf width, off, scol, sval, scale;
-  // solver workspace
-  Buf Y, part, G, coef, info, scal, xw, bw, lz, lzab;
-  sscg_block_info* hinfo = nullptr;  // pinned
-  double* hscal = nullptr;            // pinned
-  // timing
-  bool timing = false;
-  int64_t launches[NFAM] = {0, 0, 0, 0};
-  double ms[NFAM] = {0, 0, 0, 0};
-  double bytes[NFAM] = {0, 0, 0, 0};
-  std::vector<EvRec> ev;
-  size_t ev_used = 0;
-};
-
-namespace {
-
 int fail(sscg_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -85,21 +43,12 @@ int fail(sscg_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(ctx, e_ == hipErrorOutOfMemory ? SSCG_ERR_OOM : SSCG_ERR_HIP,          \
-                  "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
-  } while (0)
-
 int set_device(sscg_ctx* ctx) {
   HIPCHK(hipSetDevice(ctx->device));
   return SSCG_OK;
 }
 
-// ---- timing helpers
-hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, size_t* slot) {
+hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* slot) {
   if (!c->timing) return hipSuccess;
   if (c->ev_used == c->ev.size()) {
     EvRec r;
@@ -112,15 +61,15 @@ hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, size_t* slot) {
   *slot = c->ev_used++;
   c->ev[*slot].fam = fam;
   c->ev[*slot].bytes = bytes;
-  return hipEventRecord(c->ev[*slot].a, c->stream);
+  return hipEventRecord(c->ev[*slot].a, st);
 }
 
-hipError_t ev_end(sscg_ctx* c, size_t slot) {
+hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st) {
   if (!c->timing) return hipSuccess;
-  return hipEventRecord(c->ev[slot].b, c->stream);
+  return hipEventRecord(c->ev[slot].b, st);
 }
 
-// Accumulate the recorded pairs (the stream must have passed them).
+// Accumulate the recorded pairs (the streams must have passed them).
 hipError_t ev_collect(sscg_ctx* c) {
   for (size_t i = 0; i < c->ev_used; ++i) {
     float t = 0.f;
@@ -134,13 +83,30 @@ hipError_t ev_collect(sscg_ctx* c) {
   return hipSuccess;
 }
 
-// ---- CSR -> SELL-64 copy (optionally equilibrated)
+int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
+  if (!A) return fail(ctx, SSCG_ERR_ARG, "A is NULL");
+  if (A->n < 1) return fail(ctx, SSCG_ERR_ARG, "n = %d must be >= 1", A->n);
+  if (A->nnz < 0) return fail(ctx, SSCG_ERR_ARG, "nnz = %d must be >= 0", A->nnz);
+  if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val)))
+    return fail(ctx, SSCG_ERR_ARG, "CSR arrays must not be NULL");
+  int32_t ends[2] = {-1, -1};
+  HIPCHK(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(&ends[1], A->rowptr + A->n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ends[0] != 0 || ends[1] != A->nnz)
+    return fail(ctx, SSCG_ERR_ARG, "rowptr[0] = %d, rowptr[n] = %d (nnz = %d)", ends[0], ends[1],
+                A->nnz);
+  return SSCG_OK;
+}
+
+// CSR -> SELL-64 copy (optionally equilibrated), after a structural check.
 int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   const int n = A->n;
   const int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
   HIPCHK(ensure(ctx->width, sizeof(int32_t) * (nslices + 2)));
   HIPCHK(ensure(ctx->off, sizeof(int64_t) * (nslices + 1)));
-  // structural check first: every later kernel gathers through col[]
+  // every later kernel gathers through col[]
   int32_t* flag = as<int32_t>(ctx->width) + nslices;
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
   HIPCHK(launch_check_csr(A->rowptr, A->col, n, A->nnz, flag, ctx->stream));
@@ -174,64 +140,48 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   return SSCG_OK;
 }
 
-int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
-  if (!A) return fail(ctx, SSCG_ERR_ARG, "A is NULL");
-  if (A->n < 1) return fail(ctx, SSCG_ERR_ARG, "n = %d must be >= 1", A->n);
-  if (A->nnz < 0) return fail(ctx, SSCG_ERR_ARG, "nnz = %d must be >= 0", A->nnz);
-  if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val)))
-    return fail(ctx, SSCG_ERR_ARG, "CSR arrays must not be NULL");
-  int32_t ends[2] = {-1, -1};
-  HIPCHK(hipMemcpyAsync(&ends[0], A->rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(&ends[1], A->rowptr + A->n, sizeof(int32_t), hipMemcpyDeviceToHost,
-                        ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  if (ends[0] != 0 || ends[1] != A->nnz)
-    return fail(ctx, SSCG_ERR_ARG, "rowptr[0] = %d, rowptr[n] = %d (nnz = %d)", ends[0], ends[1],
-                A->nnz);
-  return SSCG_OK;
+ColPtr colptr_of(const BasisCols& bc, int s, int first) {
+  ColPtr c;
+  const int d = first ? s + 1 : 2 * s + 1;
+  for (int a = 0; a < 2 * SSCG_S_LIMIT + 1; ++a) {
+    if (a >= d) c.c[a] = bc.p0;
+    else if (a <= s) c.c[a] = bc.P(a);
+    else c.c[a] = bc.R(a - s - 1);
+  }
+  return c;
 }
 
-// Column of Y holding basis vector a of an s-step block (G's order
-// [P_0..P_s, R_0..R_{s-1}]), with R_0 at column rcol.
-void colmap_of(int s, int first, int rcol, int32_t* cm) {
-  int d = first ? s + 1 : 2 * s + 1;
-  for (int a = 0; a < d; ++a) cm[a] = a <= s ? a : rcol + (a - s - 1);
-}
-
-int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, double* Y,
-               int64_t ldy, int rcol, int64_t nnz) {
+int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
+               int64_t nnz, const int* stop, const MpkResidual& res) {
   const int n = M.n;
-  auto col = [&](int c) { return Y + (int64_t)c * ldy; };
   for (int j = 1; j <= s; ++j) {
-    MpkSeq sp{col(j - 1), j >= 2 ? col(j - 2) : nullptr, col(j)};
+    MpkSeq sp{bc.P(j - 1), j >= 2 ? bc.P(j - 2) : nullptr, bc.P(j)};
     MpkSeq sr{nullptr, nullptr, nullptr};
     int nrhs = 1;
     if (!first && j <= s - 1) {
-      sr = MpkSeq{col(rcol + j - 1), j >= 2 ? col(rcol + j - 2) : nullptr, col(rcol + j)};
+      sr = MpkSeq{bc.R(j - 1), j >= 2 ? bc.R(j - 2) : nullptr, bc.R(j)};
       nrhs = 2;
     }
-    double vec = 2.0 * nrhs + ((bp.cheb && j >= 2) ? nrhs : 0);
+    const bool withres = j == 1 && res.x;
+    double vec = 2.0 * nrhs + ((bp.cheb && j >= 2) ? nrhs : 0) + (withres ? 2 : 0);
     double bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n * vec;
     size_t slot = 0;
-    HIPCHK(ev_begin(ctx, 0, bytes, &slot));
-    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, ctx->stream));
-    HIPCHK(ev_end(ctx, slot));
+    HIPCHK(ev_begin(ctx, 0, bytes, ctx->stream, &slot));
+    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, stop, withres ? res : MpkResidual{},
+                           ctx->stream));
+    HIPCHK(ev_end(ctx, slot, ctx->stream));
   }
   return SSCG_OK;
 }
 
-int gram_into(sscg_ctx* ctx, const double* Y, int64_t ldy, int n, int s, int first, int rcol,
-              double* G) {
-  int32_t cm[2 * SSCG_S_LIMIT + 1];
-  colmap_of(s, first, rcol, cm);
-  int d = first ? s + 1 : 2 * s + 1;
+int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const int* stop) {
   int np = gram_nparts(n);
   HIPCHK(ensure(ctx->part, sizeof(double) * 2 * (size_t)np * (d * (d + 1) / 2)));
   size_t slot = 0;
-  HIPCHK(ev_begin(ctx, 1, 8.0 * n * d, &slot));
-  HIPCHK(launch_gram(Y, ldy, n, d, cm, as<double>(ctx->part), np, ctx->stream));
-  HIPCHK(ev_end(ctx, slot));
-  HIPCHK(launch_gram_finalize(as<double>(ctx->part), np, d, G, ctx->stream));
+  HIPCHK(ev_begin(ctx, 1, 8.0 * n * d, ctx->stream, &slot));
+  HIPCHK(launch_gram(cols, n, d, as<double>(ctx->part), np, stop, ctx->stream));
+  HIPCHK(ev_end(ctx, slot, ctx->stream));
+  HIPCHK(launch_gram_finalize(as<double>(ctx->part), np, d, G, stop, ctx->stream));
   return SSCG_OK;
 }
 
@@ -252,20 +202,17 @@ int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed
   if (rc) return rc;
   HIPCHK(ensure(ctx->lz, sizeof(double) * 3 * (size_t)n));
   HIPCHK(ensure(ctx->lzab, sizeof(double) * (2 * 64 + 8)));
-  HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
   double* v = as<double>(ctx->lz);
   double* vp = v + n;
   double* w = vp + n;
   double* al = as<double>(ctx->lzab);
   double* be = al + 64;
-  double* sc = be + 64;  // [0]: ||u||, [1]: gershgorin
+  double* sc = be + 64;  // [0]: ||u||, [1]: Gershgorin, [2], [3]: Ritz extremes
   double* part = as<double>(ctx->part);
   int np = 0;
   hipStream_t st = ctx->stream;
-  // Gershgorin
   HIPCHK(launch_gershgorin(M, part, &np, st));
   HIPCHK(launch_max_finalize(part, np, sc + 1, st));
-  // start vector
   HIPCHK(launch_splitmix_vec(w, n, seed, st));
   HIPCHK(launch_dot_parts(w, w, n, part, &np, st));
   HIPCHK(launch_finalize(part, np, 1, sc, st));
@@ -280,7 +227,7 @@ int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed
     HIPCHK(launch_finalize(part, np, 1, be + j, st));
     HIPCHK(launch_sqrt_scalar(be + j, st));
     if (j < steps - 1) {
-      HIPCHK(launch_div_vec(w, be + j, n, vp, st));  // vp <- w / beta (new v)
+      HIPCHK(launch_div_vec(w, be + j, n, vp, st));  // vp <- w / beta (the new v)
       double* t = v;
       v = vp;
       vp = t;
@@ -333,11 +280,9 @@ int validate_opts(sscg_ctx* ctx, const sscg_opts* o) {
   return SSCG_OK;
 }
 
-__global__ void k_eps_star(const double* b2, double tol, double* out) {
-  if (threadIdx.x == 0) out[0] = tol * sqrt(b2[0]);
-}
+}  // namespace sscg_host
 
-}  // namespace
+using namespace sscg_host;
 
 // ====================================================================== ABI
 
@@ -383,12 +328,19 @@ int sscg_create(sscg_ctx** out, int device, void* stream) {
   sscg_ctx* c = new sscg_ctx;
   c->device = device;
   c->stream = (hipStream_t)stream;
-  if (hipHostMalloc((void**)&c->hinfo, sizeof(sscg_block_info)) != hipSuccess ||
-      hipHostMalloc((void**)&c->hscal, sizeof(double) * 16) != hipSuccess) {
-    g_create_err = "pinned host allocation failed";
-    delete c;
+  bool ok = hipHostMalloc((void**)&c->hinfo, sizeof(sscg_block_info) * RING) == hipSuccess &&
+            hipHostMalloc((void**)&c->hscal, sizeof(double) * 16) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < RING; ++i)
+    ok = hipEventCreateWithFlags(&c->evG[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->evI[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->evV[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    g_create_err = "context allocation failed";
+    sscg_destroy(c);
     return SSCG_ERR_OOM;
   }
+  c->events_made = true;
   *out = c;
   return SSCG_OK;
 }
@@ -397,14 +349,23 @@ void sscg_destroy(sscg_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y, &c->part, &c->G,
-                 &c->coef, &c->info, &c->scal, &c->xw, &c->bw, &c->lz, &c->lzab};
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y,    &c->part,
+                 &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
+                 &c->x1,    &c->lz,  &c->lzab, &c->ctl};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
+  if (c->events_made)
+    for (int i = 0; i < RING; ++i) {
+      (void)hipEventDestroy(c->evG[i]);
+      (void)hipEventDestroy(c->evI[i]);
+      (void)hipEventDestroy(c->evV[i]);
+    }
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->hinfo) (void)hipHostFree(c->hinfo);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
@@ -432,6 +393,7 @@ int sscg_kernel_stats(sscg_ctx* ctx, int family, int64_t* launches, double* ms, 
     int rc = set_device(ctx);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->side));
     HIPCHK(ev_collect(ctx));
   }
   if (launches) *launches = ctx->launches[family];
@@ -480,16 +442,17 @@ int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, doub
   int rc = set_device(ctx);
   if (rc) return rc;
   if ((rc = check_csr(ctx, A))) return rc;
-  if (s < 1 || s > SSCG_S_LIMIT) return fail(ctx, SSCG_ERR_ARG, "s = %d outside [1, %d]", s,
-                                             SSCG_S_LIMIT);
+  if (s < 1 || s > SSCG_S_LIMIT)
+    return fail(ctx, SSCG_ERR_ARG, "s = %d outside [1, %d]", s, SSCG_S_LIMIT);
   if (!Y || ldy < A->n) return fail(ctx, SSCG_ERR_ARG, "Y NULL or ldy < n");
   if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
   if (basis == SSCG_BASIS_CHEBYSHEV && !(lambda_max > lambda_min))
     return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
   DevMat M;
   if ((rc = build_mat(ctx, A, 0, &M))) return rc;
-  return mpk_passes(ctx, M, s, first ? 1 : 0, make_basis(basis, lambda_min, lambda_max), Y, ldy,
-                    rcol, A->nnz);
+  BasisCols bc{Y, Y + (int64_t)rcol * ldy, Y, ldy, rcol};
+  return mpk_passes(ctx, M, s, first ? 1 : 0, make_basis(basis, lambda_min, lambda_max), bc,
+                    A->nnz, nullptr, MpkResidual{});
 }
 
 int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
@@ -501,7 +464,10 @@ int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t l
   if (n < 1 || s < 1 || s > SSCG_S_LIMIT || !Y || !G || ldy < n)
     return fail(ctx, SSCG_ERR_ARG, "bad Gram arguments");
   if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
-  return gram_into(ctx, Y, ldy, n, s, first ? 1 : 0, rcol, G);
+  double* Yw = const_cast<double*>(Y);
+  BasisCols bc{Y, Y + (int64_t)rcol * ldy, Yw, ldy, rcol};
+  const int f = first ? 1 : 0;
+  return gram_into(ctx, colptr_of(bc, s, f), n, f ? s + 1 : 2 * s + 1, G, nullptr);
 }
 
 int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* prm, double* coef,
@@ -517,8 +483,8 @@ int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* pr
   if (prm->adaptive && !(prm->eps_star > 0.0 && prm->c > 0.0))
     return fail(ctx, SSCG_ERR_ARG, "need eps_star > 0 and c > 0");
   int d = prm->first ? prm->s + 1 : 2 * prm->s + 1;
-  if (prm->adaptive) HIPCHK(launch_kappa(G, d, prm->s, prm->first, info, ctx->stream));
-  HIPCHK(launch_inner(G, *prm, coef, info, ctx->stream));
+  if (prm->adaptive) HIPCHK(launch_kappa(G, d, prm->s, prm->first, info, nullptr, ctx->stream));
+  HIPCHK(launch_inner(G, *prm, coef, info, nullptr, ctx->stream));
   return SSCG_OK;
 }
 
@@ -531,210 +497,12 @@ int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_
   if (n < 1 || s < 1 || s > SSCG_S_LIMIT || !Y || !coef || !x || !r || !p || ldy < n)
     return fail(ctx, SSCG_ERR_ARG, "bad recovery arguments");
   if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
-  int32_t cm[2 * SSCG_S_LIMIT + 1];
-  colmap_of(s, first ? 1 : 0, rcol, cm);
-  int d = first ? s + 1 : 2 * s + 1;
-  HIPCHK(launch_recover(Y, ldy, n, d, cm, coef, x, r, p, ctx->stream));
+  double* Yw = const_cast<double*>(Y);
+  BasisCols bc{Y, Y + (int64_t)rcol * ldy, Yw, ldy, rcol};
+  const int f = first ? 1 : 0;
+  HIPCHK(launch_recover(colptr_of(bc, s, f), n, f ? s + 1 : 2 * s + 1, coef, x, x, r, p, nullptr,
+                        ctx->stream));
   return SSCG_OK;
-}
-
-int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x,
-               const sscg_opts* opts, sscg_result* res) {
-  if (!ctx) return SSCG_ERR_ARG;
-  ctx->err.clear();
-  int rc = set_device(ctx);
-  if (rc) return rc;
-  if ((rc = validate_opts(ctx, opts))) return rc;
-  if ((rc = check_csr(ctx, A))) return rc;
-  if (!b || !x) return fail(ctx, SSCG_ERR_ARG, "b and x must not be NULL");
-  const sscg_opts& o = *opts;
-  const int n = A->n;
-  hipStream_t st = ctx->stream;
-  ctx->ev_used = 0;
-
-  DevMat M;
-  if ((rc = build_mat(ctx, A, o.equilibrate, &M))) return rc;
-
-  // working b and x (the scaled system when equilibrating)
-  const double* bw = b;
-  double* xw = x;
-  if (o.equilibrate) {
-    HIPCHK(ensure(ctx->bw, sizeof(double) * n));
-    HIPCHK(ensure(ctx->xw, sizeof(double) * n));
-    HIPCHK(launch_scale_vec(b, as<double>(ctx->scale), 1, n, as<double>(ctx->bw), st));
-    HIPCHK(launch_scale_vec(x, as<double>(ctx->scale), 0, n, as<double>(ctx->xw), st));
-    bw = as<double>(ctx->bw);
-    xw = as<double>(ctx->xw);
-  }
-  const int64_t ld = ((int64_t)n + 63) / 64 * 64;
-  const int rcol = o.s_max + 1;
-  HIPCHK(ensure(ctx->Y, sizeof(double) * ld * (2 * o.s_max + 1)));
-  HIPCHK(ensure(ctx->G, sizeof(double) * (2 * SSCG_S_LIMIT + 1) * (2 * SSCG_S_LIMIT + 1)));
-  HIPCHK(ensure(ctx->coef, sizeof(double) * 3 * (2 * SSCG_S_LIMIT + 1)));
-  HIPCHK(ensure(ctx->info, sizeof(sscg_block_info)));
-  HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
-  if ((rc = ensure_parts(ctx, n, 2))) return rc;
-  {
-    const int dmax = 2 * o.s_max + 1;
-    HIPCHK(ensure(ctx->part, std::max(ctx->part.cap, sizeof(double) * 2 * (size_t)gram_nparts(n) *
-                                                          (dmax * (dmax + 1) / 2))));
-  }
-  double* Y = as<double>(ctx->Y);
-  double* G = as<double>(ctx->G);
-  double* coef = as<double>(ctx->coef);
-  double* scal = as<double>(ctx->scal);  // [0] r2 [1] b2 [2] relres [3] eps*
-  sscg_block_info* dinfo = as<sscg_block_info>(ctx->info);
-  auto ycol = [&](int c) { return Y + (int64_t)c * ld; };
-
-  // r_1 = b - A x_1 into P_0; ||b||, eps*, relres_0
-  int np = residual_nparts(n);
-  double* part = as<double>(ctx->part);
-  HIPCHK(launch_residual(M, bw, xw, ycol(0), part, part + 2 * (size_t)np, &np, st));
-  HIPCHK(launch_finalize(part, np, 2, scal, st));
-  HIPCHK(launch_relres(scal, scal + 1, scal + 2, st));
-  hipLaunchKernelGGL(k_eps_star, dim3(1), dim3(64), 0, st, scal + 1, o.tol, scal + 3);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(ctx->hscal, scal, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const double b2 = ctx->hscal[1];
-  const double eps_star = ctx->hscal[3];
-  double relres = ctx->hscal[2];
-
-  sscg_result dummy;
-  memset(&dummy, 0, sizeof dummy);
-  sscg_result& R = res ? *res : dummy;
-  R.blocks = 0;
-  R.iters = 0;
-  R.basis_vectors = 0;
-  R.wasted_vectors = 0;
-  R.lambda_min = o.lambda_min;
-  R.lambda_max = o.lambda_max;
-
-  auto finish = [&](int status) -> int {
-    if (o.equilibrate) {
-      hipError_t e = launch_scale_vec(xw, as<double>(ctx->scale), 1, n, x, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return fail(ctx, SSCG_ERR_HIP, "%s", hipGetErrorString(e));
-    }
-    R.status = status;
-    return status;
-  };
-
-  if (b2 == 0.0) {  // x = 0 solves A x = 0 exactly
-    HIPCHK(launch_fill(xw, n, 0.0, st));
-    HIPCHK(hipStreamSynchronize(st));
-    R.relres0 = 0.0;
-    R.relres = 0.0;
-    return finish(SSCG_OK);
-  }
-  R.relres0 = relres;
-  R.relres = relres;
-  if (relres <= o.tol) return finish(SSCG_OK);
-
-  BasisPrm bp = make_basis(o.basis, 0.0, 1.0);
-  double lmin = o.lambda_min, lmax = o.lambda_max;
-  if (o.basis == SSCG_BASIS_CHEBYSHEV) {
-    if (isnan(lmin)) {
-      if ((rc = spectral_bounds_dev(ctx, M, o.lanczos_steps, o.lanczos_seed, &lmin, &lmax)))
-        return rc;
-      if (!(lmax > lmin)) return fail(ctx, SSCG_ERR_HIP, "spectral estimate failed");
-    }
-    bp = make_basis(o.basis, lmin, lmax);
-    R.lambda_min = lmin;
-    R.lambda_max = lmax;
-  }
-
-  const int s0 = o.s0_bar > 0 ? o.s0_bar : o.s_max;
-  const int f = o.f > 0 ? o.f : o.s_max;
-  int m = 0, s_prev = 0, status = SSCG_NOT_CONVERGED;
-  for (int k = 0;; ++k) {
-    const int first = k == 0;
-    int s_bar, s;
-    if (o.mode == SSCG_MODE_FIXED) {
-      s_bar = s = o.fixed_s;
-    } else if (o.mode == SSCG_MODE_SCHEDULE) {
-      s_bar = s = o.schedule[k < o.schedule_len ? k : o.schedule_len - 1];
-    } else {
-      s_bar = first ? s0 : (s_prev + f < o.s_max ? s_prev + f : o.s_max);
-      s = first ? s_bar : (s_bar < (m > 1 ? m : 1) ? s_bar : (m > 1 ? m : 1));
-    }
-    // matrix powers, Gram, coordinate solve, recovery, true residual
-    if ((rc = mpk_passes(ctx, M, s, first, bp, Y, ld, rcol, A->nnz))) return rc;
-    if ((rc = gram_into(ctx, Y, ld, n, s, first, rcol, G))) return rc;
-    sscg_block_params prm;
-    prm.s = s;
-    prm.first = first;
-    prm.adaptive = o.mode == SSCG_MODE_ADAPTIVE;
-    prm.iters = s;
-    prm.inner_check = o.inner_check;
-    prm.basis = o.basis;
-    prm.lambda_min = lmin;
-    prm.lambda_max = lmax;
-    prm.eps_star = eps_star;
-    prm.c = o.c;
-    int d = first ? s + 1 : 2 * s + 1;
-    size_t slot = 0;
-    HIPCHK(ev_begin(ctx, 3, 0.0, &slot));
-    if (prm.adaptive) HIPCHK(launch_kappa(G, d, s, first, dinfo, st));
-    HIPCHK(launch_inner(G, prm, coef, dinfo, st));
-    HIPCHK(ev_end(ctx, slot));
-    int32_t cm[2 * SSCG_S_LIMIT + 1];
-    colmap_of(s, first, rcol, cm);
-    // bytes: columns the recovery reads are those of s_k steps, known only
-    // on the device; the estimate uses s (exact when s_k = s)
-    HIPCHK(ev_begin(ctx, 2, 8.0 * n * (d + 4), &slot));
-    HIPCHK(launch_recover(Y, ld, n, d, cm, coef, xw, ycol(rcol), ycol(0), st));
-    HIPCHK(ev_end(ctx, slot));
-    part = as<double>(ctx->part);
-    HIPCHK(launch_residual(M, bw, xw, nullptr, part, nullptr, &np, st));
-    HIPCHK(launch_finalize(part, np, 1, scal, st));
-    HIPCHK(launch_relres(scal, scal + 1, scal + 2, st));
-    HIPCHK(hipMemcpyAsync(ctx->hinfo, dinfo, sizeof(sscg_block_info), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ctx->hscal + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(ev_collect(ctx));
-    const sscg_block_info& I = *ctx->hinfo;
-    relres = ctx->hscal[2];
-    const int s_k = I.s_k;
-    R.basis_vectors += first ? s : 2 * s - 1;
-    if (s_k > 0) R.wasted_vectors += (int64_t)(s - s_k) * (first ? 1 : 2);
-    if (k < R.cap) {
-      if (R.s_bar) R.s_bar[k] = s_bar;
-      if (R.s_built) R.s_built[k] = s;
-      if (R.s_tilde) R.s_tilde[k] = I.s_tilde;
-      if (R.s_k) R.s_k[k] = s_k;
-      if (R.gamma) R.gamma[k] = I.gamma;
-      if (R.thr) R.thr[k] = I.thr;
-      if (R.res_updated) R.res_updated[k] = sqrt((0.0 > I.rr) ? 0.0 : I.rr);
-      if (R.relres_true) R.relres_true[k] = relres;
-      if (R.kappa)
-        for (int i = 0; i < o.s_max; ++i)
-          R.kappa[(int64_t)k * o.s_max + i] = (prm.adaptive && i < s) ? I.kappa[i] : NAN;
-    }
-    if (s_k == 0) {  // the block could not take a step
-      R.blocks = k;
-      status = SSCG_BREAKDOWN;
-      break;
-    }
-    R.blocks = k + 1;
-    m += s_k;
-    s_prev = s_k;
-    R.iters = m;
-    R.relres = relres;
-    if (relres <= o.tol) {
-      status = SSCG_OK;
-      break;
-    }
-    if (!isfinite(relres)) {
-      status = SSCG_BREAKDOWN;
-      break;
-    }
-    if (m >= o.max_iters) {
-      status = SSCG_NOT_CONVERGED;
-      break;
-    }
-  }
-  return finish(status);
 }
 
 }  // extern "C"

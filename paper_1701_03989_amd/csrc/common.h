@@ -133,8 +133,15 @@ struct MpkSeq {
   const double* w;  // rho_{j-2}(A) v  (j >= 2, Chebyshev)
   double* out;      // rho_j(A) v
 };
+// Optional fused true residual of the block's starting iterate (x != NULL):
+// per-workgroup dd partials of sum (b - A x)_i^2 into part.
+struct MpkResidual {
+  const double* x;
+  const double* b;
+  double* part;
+};
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
-                           hipStream_t st);
+                           const int* stop, const MpkResidual& res, hipStream_t st);
 
 // res_i = RN(b_i - (A x)_i) (written if r != NULL); per-workgroup dd partials
 // of sum res_i^2 and (if bpart != NULL) sum b_i^2.
@@ -148,22 +155,40 @@ int residual_nparts(int n);
 hipError_t launch_finalize(const double* part, int nparts, int count, double* out,
                            hipStream_t st);
 
-// Gram of d columns given by a column map; partials then the finalize.
+// The d basis columns of a block in G's order [P_0..P_s, R_0..R_{s-1}].
+struct ColPtr {
+  const double* c[2 * SSCG_S_LIMIT + 1];
+};
+
+// Gram of the d columns; partials then the finalize.  stop may be NULL.
 int gram_nparts(int n);
-hipError_t launch_gram(const double* Y, int64_t ldy, int n, int d, const int32_t* colmap_host,
-                       double* part, int nparts, hipStream_t st);
+hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts,
+                       const int* stop, hipStream_t st);
 hipError_t launch_gram_finalize(const double* part, int nparts, int d, double* G,
-                                hipStream_t st);
+                                const int* stop, hipStream_t st);
 
-// Coordinate solve.
+// Coordinate solve.  stop may be NULL.
 hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_info* info,
-                        hipStream_t st);
+                        const int* stop, hipStream_t st);
+// The coordinate recurrence; with stop != NULL a block that cannot take a
+// single step (BREAKDOWN) sets *stop = 3.
 hipError_t launch_inner(const double* G, const sscg_block_params& prm, double* coef,
-                        sscg_block_info* info, hipStream_t st);
+                        sscg_block_info* info, int* stop, hipStream_t st);
+// Replays the decisions of eq. condy and eq. check from the kappa list and
+// the recorded r'^T G r' of a block run speculatively with s~ = s and no
+// break; if they would have chosen s_k != s, sets *stop = 2 (redo the block).
+hipError_t launch_validate(const double* G, const sscg_block_params& prm, sscg_block_info* info,
+                           int* stop, hipStream_t st);
+// Sum the fused residual partials: info->relres_in = sqrt(sum)/sqrt(*b2);
+// sets *stop = 1 if relres_in <= tol (or 3 if it is not finite).
+hipError_t launch_res_finalize(const double* part, int nparts, const double* b2, double tol,
+                               sscg_block_info* info, int* stop, hipStream_t st);
 
-// Recovery; colmap maps coefficient index a -> Y column.
-hipError_t launch_recover(const double* Y, int64_t ldy, int n, int d, const int32_t* colmap_host,
-                          const double* coef, double* x, double* r, double* p, hipStream_t st);
+// Recovery: x_out = RN(x_in + Y x'), r = RN(Y r'), p = RN(Y p').  x_out may
+// equal x_in; r and p may alias columns (each row is read before it is
+// written).  stop may be NULL.
+hipError_t launch_recover(const ColPtr& cols, int n, int d, const double* coef, const double* x_in,
+                          double* x_out, double* r, double* p, const int* stop, hipStream_t st);
 
 // Small helpers.
 hipError_t launch_scale_vec(const double* in, const double* s, int mul, int n, double* out,

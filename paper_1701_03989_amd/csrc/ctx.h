@@ -1,0 +1,105 @@
+// Host-side context of libsscg and the helpers shared by api.hip (context,
+// per-stage entry points) and solve.hip (the outer block loop).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace sscg_host {
+
+constexpr int NFAM = 4;  // timing families: mpk, gram, recover, small
+constexpr int RING = 8;  // per-block records in flight (device ring, pinned host copy)
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+// Grow b to at least `bytes` (waits for the device before freeing).
+hipError_t ensure(Buf& b, size_t bytes);
+
+template <class T>
+T* as(Buf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+struct EvRec {
+  hipEvent_t a, b;
+  int fam;
+  double bytes;
+};
+
+}  // namespace sscg_host
+
+struct sscg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;  // the caller's stream (main)
+  hipStream_t side = nullptr;    // second stream: speculative blocks' validation
+  std::string err;
+  // matrix copy
+  sscg_host::Buf width, off, scol, sval, scale;
+  // solver workspace
+  sscg_host::Buf Y, part, rpart, G, coef, info, scal, xw, bw, x1, lz, lzab, ctl;
+  sscg_block_info* hinfo = nullptr;  // pinned, RING entries
+  double* hscal = nullptr;            // pinned
+  hipEvent_t evG[sscg_host::RING], evI[sscg_host::RING], evV[sscg_host::RING];
+  bool events_made = false;
+  // timing
+  bool timing = false;
+  int64_t launches[sscg_host::NFAM] = {0, 0, 0, 0};
+  double ms[sscg_host::NFAM] = {0, 0, 0, 0};
+  double bytes[sscg_host::NFAM] = {0, 0, 0, 0};
+  std::vector<sscg_host::EvRec> ev;
+  size_t ev_used = 0;
+};
+
+namespace sscg_host {
+
+int fail(sscg_ctx* c, int code, const char* fmt, ...);
+
+#define HIPCHK(call)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return ::sscg_host::fail(ctx, e_ == hipErrorOutOfMemory ? SSCG_ERR_OOM : SSCG_ERR_HIP,   \
+                               "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                               __LINE__);                                                      \
+  } while (0)
+
+int set_device(sscg_ctx* ctx);
+hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* slot);
+hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st);
+hipError_t ev_collect(sscg_ctx* c);
+
+int check_csr(sscg_ctx* ctx, const sscg_csr* A);
+int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M);
+int ensure_parts(sscg_ctx* ctx, int n, int count);
+int validate_opts(sscg_ctx* ctx, const sscg_opts* o);
+int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, double* lmin,
+                        double* lmax);
+
+// Basis columns of an s-step block: P_0 and R_0 at p0 / r0, P_j (j >= 1) at
+// Y + j*ldy, R_j (j >= 1) at Y + (rcol + j)*ldy.
+struct BasisCols {
+  const double* p0;
+  const double* r0;
+  double* Y;
+  int64_t ldy;
+  int rcol;
+  double* P(int j) const { return j == 0 ? const_cast<double*>(p0) : Y + (int64_t)j * ldy; }
+  double* R(int j) const {
+    return j == 0 ? const_cast<double*>(r0) : Y + (int64_t)(rcol + j) * ldy;
+  }
+};
+ColPtr colptr_of(const BasisCols& bc, int s, int first);
+
+// The s passes of the matrix powers kernel of one block (res: fused residual
+// of the block's start, may be {NULL}); stop may be NULL.
+int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
+               int64_t nnz, const int* stop, const MpkResidual& res);
+// Gram of the block's basis into G (device, d x d).
+int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const int* stop);
+
+}  // namespace sscg_host

@@ -10,9 +10,6 @@ constexpr int MAXD = 2 * SSCG_S_LIMIT + 1;
 constexpr int MAXPAIRS = MAXD * (MAXD + 1) / 2;
 constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 
-struct ColMap {
-  int32_t c[MAXD];
-};
 
 // ---------------------------------------------------------------- Gram
 //
@@ -21,10 +18,10 @@ struct ColMap {
 // of GT rows x d columns are staged in LDS (row-major, so the lanes of a wave
 // reading different columns of one row hit different banks).  Output: one dd
 // partial per (entry, workgroup), entry-major.
-__global__ __launch_bounds__(WG) void k_gram(const double* __restrict__ Y, int64_t ldy, int n,
-                                             int d, ColMap cm, double* __restrict__ part,
-                                             int nparts) {
+__global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* __restrict__ part,
+                                             int nparts, const int* __restrict__ stop) {
   __shared__ double tile[GT][MAXD + 1];
+  if (stop && *stop) return;
   int lb = xcd_block(nparts);
   if (lb >= nparts) return;
   const int npairs = d * (d + 1) / 2;
@@ -50,7 +47,7 @@ __global__ __launch_bounds__(WG) void k_gram(const double* __restrict__ Y, int64
     for (int e = threadIdx.x; e < GT * d; e += WG) {
       int a = e / GT, r = e - a * GT;
       int row = r0 + r;
-      tile[r][a] = row < n ? Y[(int64_t)cm.c[a] * ldy + row] : 0.0;
+      tile[r][a] = row < n ? cols.c[a][row] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -92,7 +89,9 @@ __device__ __forceinline__ dd reduce_parts(const double* __restrict__ p, int npa
 }
 
 __global__ __launch_bounds__(WG) void k_gram_finalize(const double* __restrict__ part, int nparts,
-                                                      int d, double* __restrict__ G) {
+                                                      int d, double* __restrict__ G,
+                                                      const int* __restrict__ stop) {
+  if (stop && *stop) return;
   int q = blockIdx.x;
   dd t = reduce_parts(part + (int64_t)q * nparts * 2, nparts);
   if (threadIdx.x == 0) {
@@ -136,27 +135,43 @@ __global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ 
 // x_i <- RN(x_i + sum_a Y_ia x'_a), r_i <- RN(sum_a Y_ia r'_a),
 // p_i <- RN(sum_a Y_ia p'_a) (eq. coords).  Columns whose three coefficients
 // are all zero contribute nothing to the exact sums and are not read.
-__global__ __launch_bounds__(WG) void k_recover(const double* Y, int64_t ldy, int n, int d,
-                                                ColMap cm, const double* __restrict__ coef,
-                                                double* __restrict__ x, double* r, double* p) {
+__global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
+                                                const double* __restrict__ coef,
+                                                const double* x_in, double* x_out, double* r,
+                                                double* p, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   int nb = (n + WG - 1) / WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
   int i = lb * WG + threadIdx.x;
   if (i >= n) return;
   dd ax = dd_zero(), ar = dd_zero(), ap = dd_zero();
-  dd_add(ax, x[i]);
+  dd_add(ax, x_in[i]);
   for (int a = 0; a < d; ++a) {
     double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
     if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
-    double y = Y[(int64_t)cm.c[a] * ldy + i];
+    double y = cols.c[a][i];
     dd_add_prod(ax, y, cx);
     dd_add_prod(ar, y, cr);
     dd_add_prod(ap, y, cp);
   }
-  x[i] = dd_round(ax);
+  x_out[i] = dd_round(ax);
   r[i] = dd_round(ar);
   p[i] = dd_round(ap);
+}
+
+// Finish the residual fused into a block's first matrix-powers pass.
+__global__ __launch_bounds__(WG) void k_res_finalize(const double* __restrict__ part, int nparts,
+                                                     const double* __restrict__ b2, double tol,
+                                                     sscg_block_info* info, int* stop) {
+  if (*stop) return;
+  dd t = reduce_parts(part, nparts);
+  if (threadIdx.x == 0) {
+    double rel = sqrt(dd_round(t)) / sqrt(b2[0]);
+    info->relres_in = rel;
+    if (rel <= tol) *stop = 1;
+    else if (!isfinite(rel)) *stop = 3;
+  }
 }
 
 // ---------------------------------------------------------------- helpers
@@ -262,12 +277,6 @@ __global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
   if (i < n) out[i] = w[i] / (*beta);
 }
 
-ColMap make_colmap(const int32_t* c, int d) {
-  ColMap m;
-  for (int a = 0; a < MAXD; ++a) m.c[a] = a < d ? c[a] : 0;
-  return m;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- launches
@@ -280,16 +289,23 @@ int gram_nparts(int n) {
   return np < 1 ? 1 : np;
 }
 
-hipError_t launch_gram(const double* Y, int64_t ldy, int n, int d, const int32_t* colmap_host,
-                       double* part, int nparts, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram, dim3(xcd_grid(nparts)), dim3(WG), 0, st, Y, ldy, n, d,
-                     make_colmap(colmap_host, d), part, nparts);
+hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts,
+                       const int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part, nparts,
+                     stop);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_finalize(const double* part, int nparts, int d, double* G,
-                                hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_finalize, dim3(d * (d + 1) / 2), dim3(WG), 0, st, part, nparts, d, G);
+                                const int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_finalize, dim3(d * (d + 1) / 2), dim3(WG), 0, st, part, nparts, d, G,
+                     stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_res_finalize(const double* part, int nparts, const double* b2, double tol,
+                               sscg_block_info* info, int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_res_finalize, dim3(1), dim3(WG), 0, st, part, nparts, b2, tol, info, stop);
   return hipGetLastError();
 }
 
@@ -304,11 +320,11 @@ hipError_t launch_max_finalize(const double* part, int nparts, double* out, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_recover(const double* Y, int64_t ldy, int n, int d, const int32_t* colmap_host,
-                          const double* coef, double* x, double* r, double* p, hipStream_t st) {
+hipError_t launch_recover(const ColPtr& cols, int n, int d, const double* coef, const double* x_in,
+                          double* x_out, double* r, double* p, const int* stop, hipStream_t st) {
   int nb = (n + WG - 1) / WG;
-  hipLaunchKernelGGL(k_recover, dim3(xcd_grid(nb)), dim3(WG), 0, st, Y, ldy, n, d,
-                     make_colmap(colmap_host, d), coef, x, r, p);
+  hipLaunchKernelGGL(k_recover, dim3(xcd_grid(nb)), dim3(WG), 0, st, cols, n, d, coef, x_in, x_out,
+                     r, p, stop);
   return hipGetLastError();
 }
 

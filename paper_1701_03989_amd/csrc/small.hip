@@ -158,8 +158,10 @@ __device__ double kappa_from_diag(const JacobiLds& L, int k) {
 
 // grid = s workgroups of one wave; workgroup i-1 computes kappa(G_i).
 __global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int d, int s,
-                                                     int first, sscg_block_info* info) {
+                                              int first, sscg_block_info* info,
+                                              const int* __restrict__ stop) {
   __shared__ JacobiLds L;
+  if (stop && *stop) return;
   int i = blockIdx.x + 1;
   int k = first ? i + 1 : 2 * i + 1;
   if (threadIdx.x < k) {
@@ -258,8 +260,9 @@ __device__ __forceinline__ double quad(InnerLds& L, double va, int d) {
 __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ Gfull,
                                                      sscg_block_params prm,
                                                      double* __restrict__ coef,
-                                                     sscg_block_info* info) {
+                                                     sscg_block_info* info, int* stop) {
   __shared__ InnerLds L;
+  if (stop && *stop) return;
   const int a = threadIdx.x;
   const int s = prm.s, first = prm.first;
   const int dfull = first ? s + 1 : 2 * s + 1;
@@ -333,6 +336,7 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ 
     if (a == 0) {
       info->alpha[j - 1] = alpha;
       info->beta[j - 1] = beta;
+      info->rr_trace[j - 1] = rr1;
     }
     rr = rr1;
     if (prm.adaptive && prm.inner_check) {
@@ -359,20 +363,69 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ 
     info->thr = thr;
     info->rnorm = rnorm;
     info->rr = rr;
+    info->spec = 0;
+    if (stop && s_k == 0) *stop = 3;  // no step possible: later kernels stand down
   }
+}
+
+// Decisions of a block that ran speculatively (s~ = s, no break): eq. condy
+// from the kappa list (same prefix rule and operations as k_inner), then
+// eq. check at every iteration before the last from the recorded
+// r'^T G r'.  If either would have stopped short of s iterations, or the run
+// itself ended early, the speculation is rejected (*stop = 2).  It runs even
+// when the solve has already been stopped, so that a later block's result is
+// never accepted on top of an unchecked speculation.
+__global__ void k_validate(const double* __restrict__ Gfull, sscg_block_params prm,
+                           sscg_block_info* info, int* stop) {
+  if (threadIdx.x != 0) return;
+  const int s = prm.s, first = prm.first;
+  const int dfull = first ? s + 1 : 2 * s + 1;
+  const int r0 = first ? 0 : s + 1;
+  const double rnorm = sqrt(Gfull[r0 * dfull + r0]);
+  const double thr = prm.eps_star / ((prm.c * EPS) * rnorm);
+  int st = 1;
+  for (int i = 1; i <= s; ++i) {
+    if (sqrt(info->kappa[i - 1]) <= thr) st = i;
+    else break;
+  }
+  const double gam = sqrt(info->kappa[st - 1]);
+  bool ok = st == s && info->s_k == s;
+  if (ok && prm.inner_check) {
+    for (int j = 1; j < s; ++j) {
+      const double rr1 = info->rr_trace[j - 1];
+      const double m0 = (0.0 > rr1) ? 0.0 : rr1;
+      const double rhs = prm.eps_star / ((prm.c * EPS) * sqrt(m0));
+      if (gam >= rhs) {
+        ok = false;
+        break;
+      }
+    }
+  }
+  info->s_tilde = st;
+  info->gamma = gam;
+  info->thr = thr;
+  info->rnorm = rnorm;
+  info->spec = ok ? 1 : 2;
+  if (!ok) *stop = 2;
 }
 
 }  // namespace
 
 hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_info* info,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_kappa, dim3(s), dim3(JT), 0, st, G, d, s, first, info);
+                        const int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_kappa, dim3(s), dim3(JT), 0, st, G, d, s, first, info, stop);
   return hipGetLastError();
 }
 
 hipError_t launch_inner(const double* G, const sscg_block_params& prm, double* coef,
-                        sscg_block_info* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner, dim3(1), dim3(SSCG_WAVE), 0, st, G, prm, coef, info);
+                        sscg_block_info* info, int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_inner, dim3(1), dim3(SSCG_WAVE), 0, st, G, prm, coef, info, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const double* G, const sscg_block_params& prm, sscg_block_info* info,
+                           int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_validate, dim3(1), dim3(SSCG_WAVE), 0, st, G, prm, info, stop);
   return hipGetLastError();
 }
 

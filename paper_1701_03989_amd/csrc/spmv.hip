@@ -113,43 +113,64 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
 // eq. cg-krylovbasis, advanced together so A is streamed once per pass):
 //   out_i = RN( sum_k a_ik u_k - theta u_i - sigma w_i ) / gamma.
 // One wavefront per 64-row slice, one lane per row.
-template <int NRHS, bool CHEB, bool HASW>
+//
+// RES: the pass also forms the true residual of the block's starting iterate
+// x, res_i = RN(b_i - (A x)_i), from the same stream of A (x gathered as a
+// third sequence), and stores per-workgroup dd partials of sum res_i^2.
+// `stop` (may be NULL): the pass does nothing once the solve has stopped.
+__device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
+
+template <int NRHS, bool CHEB, bool HASW, bool RES>
 __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
-                                            MpkSeq s0, MpkSeq s1) {
+                                            MpkSeq s0, MpkSeq s1, const int* __restrict__ stop,
+                                            const double* __restrict__ xres,
+                                            const double* __restrict__ bres,
+                                            double* __restrict__ rpart) {
+  if (stop && *stop) return;
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  if (slice >= A.nslices) return;
   int lane = threadIdx.x & (SSCG_WAVE - 1);
   int row = slice * SSCG_WAVE + lane;
-  int64_t o = A.off[slice] + lane;
-  int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
-  const double* __restrict__ u0 = s0.u;
-  const double* __restrict__ u1 = s1.u;
-  dd a0 = dd_zero(), a1 = dd_zero();
+  dd r2 = dd_zero();
+  if (slice < A.nslices) {
+    int64_t o = A.off[slice] + lane;
+    int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    const double* __restrict__ u0 = s0.u;
+    const double* __restrict__ u1 = s1.u;
+    dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
 #pragma unroll 4
-  for (int j = 0; j < w; ++j) {
-    int64_t k = o + (int64_t)j * SSCG_WAVE;
-    double v = A.val[k];
-    int c = A.col[k];
-    dd_add_prod(a0, v, u0[c]);
-    if (NRHS == 2) dd_add_prod(a1, v, u1[c]);
-  }
-  if (row >= A.n) return;
-  if (CHEB) {
-    dd_add_prod(a0, -theta, u0[row]);
-    if (HASW) dd_add_prod(a0, -sigma, s0.w[row]);
-    s0.out[row] = dd_round(a0) / gamma;
-    if (NRHS == 2) {
-      dd_add_prod(a1, -theta, u1[row]);
-      if (HASW) dd_add_prod(a1, -sigma, s1.w[row]);
-      s1.out[row] = dd_round(a1) / gamma;
+    for (int j = 0; j < w; ++j) {
+      int64_t k = o + (int64_t)j * SSCG_WAVE;
+      double v = A.val[k];
+      int c = A.col[k];
+      dd_add_prod(a0, v, u0[c]);
+      if (NRHS == 2) dd_add_prod(a1, v, u1[c]);
+      if (RES) dd_add_prod(ax, v, xres[c]);
     }
-  } else {
-    s0.out[row] = dd_round(a0);
-    if (NRHS == 2) s1.out[row] = dd_round(a1);
+    if (row < A.n) {
+      if (CHEB) {
+        dd_add_prod(a0, -theta, u0[row]);
+        if (HASW) dd_add_prod(a0, -sigma, s0.w[row]);
+        s0.out[row] = dd_round(a0) / gamma;
+        if (NRHS == 2) {
+          dd_add_prod(a1, -theta, u1[row]);
+          if (HASW) dd_add_prod(a1, -sigma, s1.w[row]);
+          s1.out[row] = dd_round(a1) / gamma;
+        }
+      } else {
+        s0.out[row] = dd_round(a0);
+        if (NRHS == 2) s1.out[row] = dd_round(a1);
+      }
+      if (RES) {
+        dd_add(ax, -bres[row]);
+        double ri = -dd_round(ax);
+        dd_add_prod(r2, ri, ri);
+      }
+    }
   }
+  if (RES) wg_store_partial(r2, rpart, lb);
 }
 
 // Reduce a per-thread dd over the workgroup and store it as partial `slot`.
@@ -309,29 +330,34 @@ hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
   return hipGetLastError();
 }
 
+template <int NRHS, bool CHEB, bool HASW>
+void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
+                MpkSeq s1, const int* stop, const MpkResidual& res, hipStream_t st) {
+  if (res.x)
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true>), grid, dim3(WG), 0, st, A, theta, sigma,
+                       gamma, s0, s1, stop, res.x, res.b, res.part);
+  else
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false>), grid, dim3(WG), 0, st, A, theta, sigma,
+                       gamma, s0, s1, stop, nullptr, nullptr, nullptr);
+}
+
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
-                           hipStream_t st) {
-  dim3 grid(xcd_grid(wg_count(A.nslices))), blk(WG);
+                           const int* stop, const MpkResidual& res, hipStream_t st) {
+  dim3 grid(xcd_grid(wg_count(A.nslices)));
   if (!bp.cheb) {
-    if (nrhs == 2)
-      hipLaunchKernelGGL((k_mpk<2, false, false>), grid, blk, 0, st, A, 0.0, 0.0, 1.0, s0, s1);
-    else
-      hipLaunchKernelGGL((k_mpk<1, false, false>), grid, blk, 0, st, A, 0.0, 0.0, 1.0, s0, s1);
+    if (nrhs == 2) mpk_launch<2, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, stop, res, st);
+    else mpk_launch<1, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, stop, res, st);
     return hipGetLastError();
   }
   double theta = bp.c0;
   double gamma = j == 1 ? bp.h : bp.h2;
   double sigma = bp.h2;
   if (j == 1) {
-    if (nrhs == 2)
-      hipLaunchKernelGGL((k_mpk<2, true, false>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
-    else
-      hipLaunchKernelGGL((k_mpk<1, true, false>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
+    if (nrhs == 2) mpk_launch<2, true, false>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
+    else mpk_launch<1, true, false>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
   } else {
-    if (nrhs == 2)
-      hipLaunchKernelGGL((k_mpk<2, true, true>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
-    else
-      hipLaunchKernelGGL((k_mpk<1, true, true>), grid, blk, 0, st, A, theta, sigma, gamma, s0, s1);
+    if (nrhs == 2) mpk_launch<2, true, true>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
+    else mpk_launch<1, true, true>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
   }
   return hipGetLastError();
 }

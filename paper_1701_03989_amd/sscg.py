@@ -56,7 +56,8 @@ class Result(ctypes.Structure):
                 ("lambda_max", ctypes.c_double), ("basis_vectors", ctypes.c_int64),
                 ("wasted_vectors", ctypes.c_int64), ("s_bar", _ip), ("s_built", _ip),
                 ("s_tilde", _ip), ("s_k", _ip), ("gamma", _dp), ("thr", _dp),
-                ("res_updated", _dp), ("relres_true", _dp), ("kappa", _dp)]
+                ("res_updated", _dp), ("relres_true", _dp), ("kappa", _dp),
+                ("spec_blocks", ctypes.c_int32), ("spec_rejected", ctypes.c_int32)]
 
 
 class BlockInfo(ctypes.Structure):
@@ -64,7 +65,9 @@ class BlockInfo(ctypes.Structure):
                 ("d", ctypes.c_int32), ("gamma", ctypes.c_double), ("thr", ctypes.c_double),
                 ("rnorm", ctypes.c_double), ("rr", ctypes.c_double),
                 ("kappa", ctypes.c_double * S_LIMIT), ("alpha", ctypes.c_double * S_LIMIT),
-                ("beta", ctypes.c_double * S_LIMIT)]
+                ("beta", ctypes.c_double * S_LIMIT), ("rr_trace", ctypes.c_double * S_LIMIT),
+                ("relres_in", ctypes.c_double), ("spec", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class BlockParams(ctypes.Structure):
