@@ -28,8 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "solves/s + p99 latency at relres≤1e-10; basis+Gram HBM GB/s vs peak"
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "mpk_pass_poisson3d_128.pmc.json")
-MPK_SOURCE = os.path.join(ROOT, "paper_1701_03989_amd", "csrc", "spmv.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "mpk_pass_poisson3d_128.pmc.md")
+TRACE_SUMMARY = os.path.join(ROOT, "profiles", "solve_poisson3d_128.kernel_trace.md")
+# the matrix-powers kernel's source: its HBM counters are stale once these change
+MPK_SOURCES = [os.path.join(ROOT, "paper_1701_03989_amd", "csrc", f)
+               for f in ("spmv.hip", "common.h")]
+COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read and 1 GiB written per launch
 
 WORKLOADS = {
     "poisson3d_128": dict(N=128, s_max=10, tol=1e-12, basis="chebyshev"),
@@ -37,22 +41,135 @@ WORKLOADS = {
 }
 
 
-def source_hash(path: str) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile():
     """HBM bytes per matrix-powers launch from the committed rocprofv3 PMC
     summary, if it was taken on the current kernel source; else None."""
-    if not os.path.exists(PMC_SUMMARY):
-        return None
     try:
-        d = json.load(open(PMC_SUMMARY))
-    except (OSError, ValueError):
+        lines = open(PMC_SUMMARY).read().splitlines()
+        d = json.loads(next(l for l in lines if l.startswith('{"source_sha256_16"')))
+    except (OSError, ValueError, StopIteration):
         return None
-    if d.get("source_sha256_16") != source_hash(MPK_SOURCE):
+    if d.get("source_sha256_16") != source_hash(MPK_SOURCES):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+# ---------------------------------------------------------------- profile summaries
+def _short(name: str) -> str:
+    return name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+
+
+def _counter_rows(path):
+    import csv
+
+    out = {}
+    for r in csv.DictReader(open(path)):
+        out.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(d: str, cmd: str) -> None:
+    """profiles/<pmc summary> from four rocprofv3 --pmc runs under d:
+    pmc_FETCH_SIZE, pmc_WRITE_SIZE (bench.py, matrix-powers launches only) and
+    copy_FETCH_SIZE, copy_WRITE_SIZE (bench.py --copy-calibration).  Each
+    counter is scaled by COPY_BYTES / (what it reads for the plain copy)."""
+    f = {c: _counter_rows(os.path.join(d, f"pmc_{c}", "p_counter_collection.csv"))
+         for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    cp = {c: _counter_rows(os.path.join(d, f"copy_{c}", "p_counter_collection.csv"))
+          for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    scale = {}
+    for c, rows in cp.items():
+        v = [x for k, xs in rows.items() if "copyBuffer" in k for x in xs]
+        scale[c] = COPY_BYTES / (float(np.median(v)) * 1024.0)
+    lines = ["# HBM traffic of the matrix-powers pass (k_mpk), 3-D Poisson 128^3", "",
+             "Commands (repo root, MI355X; `cd /tmp && export TMPDIR=/tmp` first, R = repo root):", ""]
+    lines += ["    " + l for l in cmd.splitlines()]
+    lines += ["", "Counters are KiB per dispatch.  Calibration: a plain 1 GiB device copy "
+              "(torch copy_, bench.py --copy-calibration) reads "
+              f"{COPY_BYTES / 1024 / scale['FETCH_SIZE']:.0f} KiB of FETCH_SIZE and "
+              f"{COPY_BYTES / 1024 / scale['WRITE_SIZE']:.0f} KiB of WRITE_SIZE, so FETCH_SIZE "
+              f"is scaled by {scale['FETCH_SIZE']:.3f} and WRITE_SIZE by {scale['WRITE_SIZE']:.3f}.  "
+              "Launches that stood down after convergence (counters near 0) are left out.", "",
+              "| variant | launches | FETCH KiB | WRITE KiB | HBM MB (scaled) |", "|---|---|---|---|---|"]
+    tot_b, tot_n = 0.0, 0
+    for k in sorted(f["FETCH_SIZE"]):
+        if not k.startswith("k_mpk"):
+            continue
+        fe = np.array(f["FETCH_SIZE"][k])
+        wr = np.array(f["WRITE_SIZE"].get(k, []))
+        if len(wr) != len(fe):
+            continue
+        ran = fe > 0.01 * np.median(fe)
+        if not ran.any():
+            continue
+        b = fe[ran] * 1024 * scale["FETCH_SIZE"] + wr[ran] * 1024 * scale["WRITE_SIZE"]
+        tot_b += float(b.sum())
+        tot_n += int(ran.sum())
+        lines.append(f"| {k} | {int(ran.sum())} | {fe[ran].mean():.0f} | {wr[ran].mean():.0f} | "
+                     f"{b.mean() / 1e6:.1f} |")
+    per = tot_b / max(tot_n, 1)
+    lines += ["", f"Average over all {tot_n} launches: {per / 1e6:.1f} MB of HBM traffic per launch.",
+              "", "Machine-readable (bench.py reads this line; stale once the kernel source changes):",
+              "", json.dumps({"source_sha256_16": source_hash(MPK_SOURCES),
+                              "hbm_bytes_per_launch": per, "launches": tot_n,
+                              "fetch_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"]})]
+    open(PMC_SUMMARY, "w").write("\n".join(lines) + "\n")
+    print("wrote", PMC_SUMMARY)
+
+
+def summarize_trace(d: str, cmd: str) -> None:
+    """profiles/<trace summary> from a rocprofv3 --kernel-trace --stats run under d."""
+    import csv
+
+    stats = list(csv.DictReader(open(os.path.join(d, "kt_kernel_stats.csv"))))
+    trace = sorted(csv.DictReader(open(os.path.join(d, "kt_kernel_trace.csv"))),
+                   key=lambda r: int(r["Start_Timestamp"]))
+    lines = ["# Kernel trace: adaptive s-step CG solves, 3-D Poisson 128^3 (n = 2,097,152)", "",
+             "Command (repo root, MI355X; `cd /tmp && export TMPDIR=/tmp` first, R = repo root):", "",
+             "    " + cmd, "",
+             "Chebyshev basis, s_max = 10, tol 1e-12; every solve takes 62 blocks of s = 10.",
+             "rocprofv3 kernel statistics over the whole run (durations in microseconds):", "",
+             "| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.0f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    # one solve period of the uninstrumented timed region: from the second
+    # solve's k_eps_star (end of its set-up) to the third's (needs --warmup >= 1)
+    idx = [i for i, r in enumerate(trace) if "k_eps_star" in r["Kernel_Name"]]
+    if len(idx) >= 3:
+        seg = trace[idx[1]:idx[2]]
+        t0, t1 = int(seg[0]["Start_Timestamp"]), int(seg[-1]["End_Timestamp"])
+        q = {}
+        for r in seg:
+            q.setdefault(r["Queue_Id"], []).append(r)
+        main = max(q, key=lambda k: sum("k_mpk" in r["Kernel_Name"] for r in q[k]))
+        ms = q[main]
+        busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in ms)
+        gaps = {}
+        for a, b in zip(ms, ms[1:]):
+            key = (_short(a["Kernel_Name"]).split("<")[0], _short(b["Kernel_Name"]).split("<")[0])
+            gaps.setdefault(key, []).append(int(b["Start_Timestamp"]) - int(a["End_Timestamp"]))
+        lines += ["", f"One solve period without timing events (second timed solve, from the end of "
+                  f"its set-up to the end of the next one's): {(t1 - t0) / 1e3:.0f} us; the launch stream is busy {busy / 1e3:.0f} us "
+                  f"({100.0 * busy / (t1 - t0):.0f} %), the rest is idle time between its kernels:", "",
+                  "| after | before | count | mean gap us | total us |", "|---|---|---|---|---|"]
+        for (a, b), v in sorted(gaps.items(), key=lambda kv: -sum(kv[1]))[:10]:
+            lines.append(f"| {a} | {b} | {len(v)} | {np.mean(v) / 1e3:.1f} | {sum(v) / 1e3:.0f} |")
+        side = [r for k, rs in q.items() if k != main for r in rs]
+        if side:
+            sb = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in side)
+            names = sorted({_short(r["Kernel_Name"]) for r in side})
+            lines += ["", f"Second stream (validation of speculative blocks): {', '.join(names)}; "
+                      f"busy {sb / 1e3:.0f} us, overlapped with the launch stream."]
+    open(TRACE_SUMMARY, "w").write("\n".join(lines) + "\n")
+    print("wrote", TRACE_SUMMARY)
 
 
 def cpu_baseline(A, b, x1, wl, gpu_blocks, budget_s=20.0):
@@ -102,7 +219,18 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="write the PMC summary under profiles/ from rocprofv3 runs in DIR")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="write the kernel-trace summary under profiles/ from a rocprofv3 run in DIR")
+    ap.add_argument("--profile-cmd", default="", help="the command(s) to quote in a summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.profile_cmd)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.profile_cmd)
+        return
     if args.copy_calibration:
         import torch
 
@@ -142,7 +270,9 @@ def main():
     for _ in range(args.warmup):
         one_solve()
     torch.cuda.synchronize()
-    sscg.sscg_set_timing(ctx, True)
+    # timed region: K solves without instrumentation (an event record costs the
+    # stream a few microseconds, which would show up in solves/s)
+    sscg.sscg_set_timing(ctx, False)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -152,17 +282,26 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stats = {f: sscg.sscg_kernel_stats(ctx, f) for f in sscg.FAMILIES}
-    sscg.sscg_set_timing(ctx, False)
     # the returned x: true relative residual, recomputed independently in FP64
     x = xd.cpu().numpy()
+    # the roofline kernel: the same K solves again, HIP events around every
+    # matrix-powers launch on its own stream
+    sscg.sscg_set_timing(ctx, ["mpk"])
+    for _ in range(args.steps):
+        one_solve()
+    stats = {"mpk": sscg.sscg_kernel_stats(ctx, "mpk")}
+    # per-family breakdown from one more solve with every family timed
+    sscg.sscg_set_timing(ctx, True)
+    one_solve()
+    brk = {f: sscg.sscg_kernel_stats(ctx, f) for f in sscg.FAMILIES}
+    sscg.sscg_set_timing(ctx, False)
     relres = float(np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b))
     sscg.sscg_destroy(ctx)
 
     n_mpk, ms_mpk, by_mpk = stats["mpk"]
-    n_gram, ms_gram, by_gram = stats["gram"]
     mpk_gbs = by_mpk / (ms_mpk * 1e-3) / 1e9
-    bg_gbs = (by_mpk + by_gram) / ((ms_mpk + ms_gram) * 1e-3) / 1e9
+    bg_by = brk["mpk"][2] + brk["gram"][2]
+    bg_gbs = bg_by / ((brk["mpk"][1] + brk["gram"][1]) * 1e-3) / 1e9
     traffic = traffic_from_profile()
     sched = hist.schedule
     out = {
@@ -193,8 +332,8 @@ def main():
         "lambda": [hist.res.lambda_min, hist.res.lambda_max],
         "basis_gram_gbs": bg_gbs,
         "basis_gram_frac": bg_gbs / HBM_PEAK_GBS,
-        "kernel_ms": {f: stats[f][1] / max(stats[f][0], 1) for f in stats},
-        "kernel_launches": {f: stats[f][0] for f in stats},
+        "kernel_ms": {f: brk[f][1] / max(brk[f][0], 1) for f in brk},
+        "kernel_launches_per_solve": {f: brk[f][0] for f in brk},
         "roofline": {
             "kernel": "k_mpk (matrix-powers pass)",
             "bound": "hbm",
@@ -203,8 +342,10 @@ def main():
             "unit": "GB/s",
             "frac": mpk_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": by_mpk / max(n_mpk, 1),
             "avg_launch_ms": ms_mpk / max(n_mpk, 1),
+            "timed_launches": n_mpk,
         },
     }
     if not args.no_cpu_baseline:

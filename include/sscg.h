@@ -219,13 +219,17 @@ int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_
 
 /* ---------------------------------------------------------------- timing */
 
-/* Kernel timing with HIP events on the context's stream (off by default).
- * While on, sscg_solve and the per-stage calls record an event pair around
- * every launch of each kernel family; sscg_kernel_stats (which waits for the
- * stream) returns, for family id (0 = matrix powers pass, 1 = Gram,
- * 2 = recovery, 3 = coordinate solve), the launches, their summed duration
- * in ms and their summed algorithmic bytes.  Resets on enabling. */
-int sscg_set_timing(sscg_ctx* ctx, int on);
+/* Kernel timing with HIP events on the stream each kernel runs on (off by
+ * default).  families is a bit mask over the family ids (0 = matrix powers
+ * pass, 1 = Gram, 2 = recovery, 3 = condition estimate / coordinate solve;
+ * SSCG_TIME_ALL = all four, 0 = off).  While a family's bit is set,
+ * sscg_solve and the per-stage calls record an event pair around each of its
+ * launches (each pair costs a little time on the stream, so time only the
+ * families you need).  sscg_kernel_stats (which waits for the streams)
+ * returns, for one family id, the launches, their summed duration in ms and
+ * their summed algorithmic bytes.  Every call resets the counters. */
+#define SSCG_TIME_ALL 0xF
+int sscg_set_timing(sscg_ctx* ctx, int families);
 int sscg_kernel_stats(sscg_ctx* ctx, int family, int64_t* launches, double* ms, double* bytes);
 
 #ifdef __cplusplus

@@ -49,7 +49,8 @@ int set_device(sscg_ctx* ctx) {
 }
 
 hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* slot) {
-  if (!c->timing) return hipSuccess;
+  *slot = NO_EVENT;
+  if (!((c->timing >> fam) & 1u)) return hipSuccess;
   if (c->ev_used == c->ev.size()) {
     EvRec r;
     hipError_t e = hipEventCreate(&r.a);
@@ -61,17 +62,33 @@ hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* 
   *slot = c->ev_used++;
   c->ev[*slot].fam = fam;
   c->ev[*slot].bytes = bytes;
+  c->ev[*slot].gated = false;
   return hipEventRecord(c->ev[*slot].a, st);
 }
 
 hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st) {
-  if (!c->timing) return hipSuccess;
+  if (slot == NO_EVENT) return hipSuccess;
   return hipEventRecord(c->ev[slot].b, st);
 }
 
-// Accumulate the recorded pairs (the streams must have passed them).
+int* ev_ran(sscg_ctx* c, size_t slot) {
+  if (slot == NO_EVENT || slot >= RAN_CAP || !c->ran.p) return nullptr;
+  c->ev[slot].gated = true;
+  return as<int>(c->ran) + slot;
+}
+
+// Accumulate the recorded pairs (the streams must have passed them).  Gated
+// launches that stood down are left out: they moved none of their bytes.
 hipError_t ev_collect(sscg_ctx* c) {
+  const size_t nr = std::min(c->ev_used, RAN_CAP);
+  if (c->ran.p && nr) {
+    c->hran.assign(nr, 0);
+    hipError_t e = hipMemcpy(c->hran.data(), c->ran.p, sizeof(int) * nr, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(c->ran.p, 0, sizeof(int) * nr);
+    if (e != hipSuccess) return e;
+  }
   for (size_t i = 0; i < c->ev_used; ++i) {
+    if (c->ev[i].gated && !c->hran[i]) continue;
     float t = 0.f;
     hipError_t e = hipEventElapsedTime(&t, c->ev[i].a, c->ev[i].b);
     if (e != hipSuccess) return e;
@@ -167,8 +184,8 @@ int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, co
     double bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n * vec;
     size_t slot = 0;
     HIPCHK(ev_begin(ctx, 0, bytes, ctx->stream, &slot));
-    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, stop, withres ? res : MpkResidual{},
-                           ctx->stream));
+    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, Gate{stop, ev_ran(ctx, slot)},
+                           withres ? res : MpkResidual{}, ctx->stream));
     HIPCHK(ev_end(ctx, slot, ctx->stream));
   }
   return SSCG_OK;
@@ -179,7 +196,8 @@ int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const 
   HIPCHK(ensure(ctx->part, sizeof(double) * 2 * (size_t)np * (d * (d + 1) / 2)));
   size_t slot = 0;
   HIPCHK(ev_begin(ctx, 1, 8.0 * n * d, ctx->stream, &slot));
-  HIPCHK(launch_gram(cols, n, d, as<double>(ctx->part), np, stop, ctx->stream));
+  HIPCHK(launch_gram(cols, n, d, as<double>(ctx->part), np, Gate{stop, ev_ran(ctx, slot)},
+                     ctx->stream));
   HIPCHK(ev_end(ctx, slot, ctx->stream));
   HIPCHK(launch_gram_finalize(as<double>(ctx->part), np, d, G, stop, ctx->stream));
   return SSCG_OK;
@@ -332,8 +350,7 @@ int sscg_create(sscg_ctx** out, int device, void* stream) {
             hipHostMalloc((void**)&c->hscal, sizeof(double) * 16) == hipSuccess &&
             hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; ok && i < RING; ++i)
-    ok = hipEventCreateWithFlags(&c->evG[i], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&c->evI[i], hipEventDisableTiming) == hipSuccess &&
+    ok = hipEventCreateWithFlags(&c->evI[i], hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&c->evV[i], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     g_create_err = "context allocation failed";
@@ -352,7 +369,7 @@ void sscg_destroy(sscg_ctx* c) {
   if (c->side) (void)hipStreamSynchronize(c->side);
   Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y,    &c->part,
                  &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
-                 &c->x1,    &c->lz,  &c->lzab, &c->ctl};
+                 &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {
@@ -361,7 +378,6 @@ void sscg_destroy(sscg_ctx* c) {
   }
   if (c->events_made)
     for (int i = 0; i < RING; ++i) {
-      (void)hipEventDestroy(c->evG[i]);
       (void)hipEventDestroy(c->evI[i]);
       (void)hipEventDestroy(c->evV[i]);
     }
@@ -375,9 +391,15 @@ const char* sscg_last_error(const sscg_ctx* c) {
   return c ? c->err.c_str() : g_create_err.c_str();
 }
 
-int sscg_set_timing(sscg_ctx* ctx, int on) {
+int sscg_set_timing(sscg_ctx* ctx, int families) {
   if (!ctx) return SSCG_ERR_ARG;
-  ctx->timing = on != 0;
+  ctx->timing = (unsigned)families & ((1u << NFAM) - 1);
+  if (ctx->timing && !ctx->ran.p) {
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    HIPCHK(ensure(ctx->ran, sizeof(int) * RAN_CAP));
+    HIPCHK(hipMemset(ctx->ran.p, 0, sizeof(int) * RAN_CAP));
+  }
   for (int f = 0; f < NFAM; ++f) {
     ctx->launches[f] = 0;
     ctx->ms[f] = 0;
@@ -500,8 +522,8 @@ int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_
   double* Yw = const_cast<double*>(Y);
   BasisCols bc{Y, Y + (int64_t)rcol * ldy, Yw, ldy, rcol};
   const int f = first ? 1 : 0;
-  HIPCHK(launch_recover(colptr_of(bc, s, f), n, f ? s + 1 : 2 * s + 1, coef, x, x, r, p, nullptr,
-                        ctx->stream));
+  HIPCHK(launch_recover(colptr_of(bc, s, f), n, f ? s + 1 : 2 * s + 1, coef, x, x, r, p,
+                        Gate{nullptr, nullptr}, ctx->stream));
   return SSCG_OK;
 }
 

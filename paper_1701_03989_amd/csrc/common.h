@@ -115,6 +115,21 @@ __host__ __device__ inline BasisPrm make_basis(int basis, double lmin, double lm
 // ---------------------------------------------------------------- launches
 // (host wrappers; every one enqueues on `st` and returns the launch error)
 
+// Launch gate of the streaming kernels.  A launch stands down (every
+// workgroup returns at once) while *stop != 0; when `ran` is set, the first
+// workgroup of a launch that does run stores 1 there, so kernel timing can
+// tell launches that moved their bytes from launches that stood down.
+struct Gate {
+  const int* stop;
+  int* ran;
+};
+
+__device__ __forceinline__ bool gate_closed(const Gate& g) {
+  if (g.stop && *g.stop) return true;
+  if (g.ran && blockIdx.x == 0 && threadIdx.x == 0) *g.ran = 1;
+  return false;
+}
+
 // Sets *flag if rowptr decreases or a column index lies outside [0, n).
 hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int nnz,
                             int32_t* flag, hipStream_t st);
@@ -141,7 +156,7 @@ struct MpkResidual {
   double* part;
 };
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
-                           const int* stop, const MpkResidual& res, hipStream_t st);
+                           Gate g, const MpkResidual& res, hipStream_t st);
 
 // res_i = RN(b_i - (A x)_i) (written if r != NULL); per-workgroup dd partials
 // of sum res_i^2 and (if bpart != NULL) sum b_i^2.
@@ -162,8 +177,8 @@ struct ColPtr {
 
 // Gram of the d columns; partials then the finalize.  stop may be NULL.
 int gram_nparts(int n);
-hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts,
-                       const int* stop, hipStream_t st);
+hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts, Gate g,
+                       hipStream_t st);
 hipError_t launch_gram_finalize(const double* part, int nparts, int d, double* G,
                                 const int* stop, hipStream_t st);
 
@@ -186,9 +201,9 @@ hipError_t launch_res_finalize(const double* part, int nparts, const double* b2,
 
 // Recovery: x_out = RN(x_in + Y x'), r = RN(Y r'), p = RN(Y p').  x_out may
 // equal x_in; r and p may alias columns (each row is read before it is
-// written).  stop may be NULL.
+// written).
 hipError_t launch_recover(const ColPtr& cols, int n, int d, const double* coef, const double* x_in,
-                          double* x_out, double* r, double* p, const int* stop, hipStream_t st);
+                          double* x_out, double* r, double* p, Gate g, hipStream_t st);
 
 // Small helpers.
 hipError_t launch_scale_vec(const double* in, const double* s, int mul, int n, double* out,

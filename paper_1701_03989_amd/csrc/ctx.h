@@ -11,6 +11,7 @@ namespace sscg_host {
 
 constexpr int NFAM = 4;  // timing families: mpk, gram, recover, small
 constexpr int RING = 8;  // per-block records in flight (device ring, pinned host copy)
+constexpr size_t RAN_CAP = 16384;  // timed launches per collection that can carry a ran flag
 
 struct Buf {
   void* p = nullptr;
@@ -29,6 +30,7 @@ struct EvRec {
   hipEvent_t a, b;
   int fam;
   double bytes;
+  bool gated;  // the launch reports through ran[slot] whether it ran
 };
 
 }  // namespace sscg_host
@@ -44,15 +46,18 @@ struct sscg_ctx {
   sscg_host::Buf Y, part, rpart, G, coef, info, scal, xw, bw, x1, lz, lzab, ctl;
   sscg_block_info* hinfo = nullptr;  // pinned, RING entries
   double* hscal = nullptr;            // pinned
-  hipEvent_t evG[sscg_host::RING], evI[sscg_host::RING], evV[sscg_host::RING];
+  // per ring slot: inner loop done (S1), validation done (S2)
+  hipEvent_t evI[sscg_host::RING], evV[sscg_host::RING];
   bool events_made = false;
   // timing
-  bool timing = false;
+  unsigned timing = 0;  // bit f: time kernel family f
   int64_t launches[sscg_host::NFAM] = {0, 0, 0, 0};
   double ms[sscg_host::NFAM] = {0, 0, 0, 0};
   double bytes[sscg_host::NFAM] = {0, 0, 0, 0};
   std::vector<sscg_host::EvRec> ev;
   size_t ev_used = 0;
+  sscg_host::Buf ran;  // int[RAN_CAP] device flags of gated timed launches (zero between uses)
+  std::vector<int> hran;
 };
 
 namespace sscg_host {
@@ -69,8 +74,13 @@ int fail(sscg_ctx* c, int code, const char* fmt, ...);
   } while (0)
 
 int set_device(sscg_ctx* ctx);
+// event pair around one launch when its family is timed (slot NO_EVENT otherwise)
+constexpr size_t NO_EVENT = ~(size_t)0;
 hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* slot);
 hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st);
+// The ran flag of a timed launch (NULL if the slot is not timed): only launches
+// whose first workgroup ran are counted by the statistics.
+int* ev_ran(sscg_ctx* c, size_t slot);
 hipError_t ev_collect(sscg_ctx* c);
 
 int check_csr(sscg_ctx* ctx, const sscg_csr* A);

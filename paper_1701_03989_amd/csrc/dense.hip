@@ -19,9 +19,9 @@ constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 // reading different columns of one row hit different banks).  Output: one dd
 // partial per (entry, workgroup), entry-major.
 __global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* __restrict__ part,
-                                             int nparts, const int* __restrict__ stop) {
+                                             int nparts, Gate gate) {
   __shared__ double tile[GT][MAXD + 1];
-  if (stop && *stop) return;
+  if (gate_closed(gate)) return;
   int lb = xcd_block(nparts);
   if (lb >= nparts) return;
   const int npairs = d * (d + 1) / 2;
@@ -75,7 +75,17 @@ __global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* 
 __device__ __forceinline__ dd reduce_parts(const double* __restrict__ p, int nparts) {
   __shared__ double ls[WG / SSCG_WAVE], le[WG / SSCG_WAVE];
   dd a = dd_zero();
-  for (int q = threadIdx.x; q < nparts; q += WG) dd_merge(a, dd{p[2 * q], p[2 * q + 1]});
+  // batches of independent loads (all in flight at once), merged in index order
+  constexpr int U = 8;
+  int q = threadIdx.x;
+  for (; q + (U - 1) * WG < nparts; q += U * WG) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = reinterpret_cast<const double2*>(p)[q + u * WG];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dd_merge(a, dd{v[u].x, v[u].y});
+  }
+  for (; q < nparts; q += WG) dd_merge(a, dd{p[2 * q], p[2 * q + 1]});
   a = dd_wave_reduce(a);
   int wv = threadIdx.x / SSCG_WAVE;
   if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) {
@@ -138,8 +148,8 @@ __global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ 
 __global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
                                                 const double* __restrict__ coef,
                                                 const double* x_in, double* x_out, double* r,
-                                                double* p, const int* __restrict__ stop) {
-  if (stop && *stop) return;
+                                                double* p, Gate gate) {
+  if (gate_closed(gate)) return;
   int nb = (n + WG - 1) / WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
@@ -289,10 +299,9 @@ int gram_nparts(int n) {
   return np < 1 ? 1 : np;
 }
 
-hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts,
-                       const int* stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part, nparts,
-                     stop);
+hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts, Gate g,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_gram, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part, nparts, g);
   return hipGetLastError();
 }
 
@@ -321,10 +330,10 @@ hipError_t launch_max_finalize(const double* part, int nparts, double* out, hipS
 }
 
 hipError_t launch_recover(const ColPtr& cols, int n, int d, const double* coef, const double* x_in,
-                          double* x_out, double* r, double* p, const int* stop, hipStream_t st) {
+                          double* x_out, double* r, double* p, Gate g, hipStream_t st) {
   int nb = (n + WG - 1) / WG;
   hipLaunchKernelGGL(k_recover, dim3(xcd_grid(nb)), dim3(WG), 0, st, cols, n, d, coef, x_in, x_out,
-                     r, p, stop);
+                     r, p, g);
   return hipGetLastError();
 }
 

@@ -205,14 +205,6 @@ __global__ __launch_bounds__(JT) void k_tridiag_eig(const double* __restrict__ a
 
 // ---------------------------------------------------------------- inner loop
 
-// CR dot of lane-owned values over the wave (lanes >= d hold zeros).
-__device__ __forceinline__ double wave_dot(double x, double y) {
-  dd a = dd_zero();
-  dd_add_prod(a, x, y);
-  a = dd_wave_reduce(a);
-  return dd_round(a);
-}
-
 // (B v)_a for the s-step basis of s steps (first: P block only), R12 layout.
 __device__ __forceinline__ double bmul(const double* v, int a, int s, int first, BasisPrm bp) {
   // block offset, local index and block length
@@ -240,20 +232,49 @@ struct InnerLds {
   double G[MAXK][LDK];
   double v[MAXK + 1];
   double w[MAXK + 1];
+  double ps[SSCG_WAVE], pe[SSCG_WAVE];  // per-lane dd partials of the row sums
 };
 
-// (G v)_a then v . (G v), with v held one value per lane.
-__device__ __forceinline__ double quad(InnerLds& L, double va, int d) {
-  int a = threadIdx.x;
-  if (a < SSCG_WAVE) L.v[a < MAXK ? a : MAXK] = a < d ? va : 0.0;
+// CR dot of lane-owned values over the wave (lanes >= d hold zeros).
+__device__ __forceinline__ double wave_dot(double x, double y) {
+  dd a = dd_zero();
+  dd_add_prod(a, x, y);
+  a = dd_wave_reduce(a);
+  return dd_round(a);
+}
+
+// Lane a (< d) returns RN((G v)_a), v in L.v.  Each row sum is split over
+// P = 64 / d lanes (short dependent chains on a single wave), whose dd
+// partials are merged in lane order through LDS.
+__device__ __forceinline__ double gmul(InnerLds& L, int d) {
+  const int l = threadIdx.x;
+  const int P = SSCG_WAVE / d;
+  const int ch = (d + P - 1) / P;
+  const int row = l / P, part = l - row * P;
+  dd acc = dd_zero();
+  if (row < d) {
+    const int b0 = part * ch, b1 = min(b0 + ch, d);
+    for (int b = b0; b < b1; ++b) dd_add_prod(acc, L.G[row][b], L.v[b]);
+  }
+  L.ps[l] = acc.s;
+  L.pe[l] = acc.e;
   __syncthreads();
   double gv = 0.0;
-  if (a < d) {
-    dd acc = dd_zero();
-    for (int b = 0; b < d; ++b) dd_add_prod(acc, L.G[a][b], L.v[b]);
-    gv = dd_round(acc);
+  if (l < d) {
+    dd t{L.ps[l * P], L.pe[l * P]};
+    for (int q = 1; q < P; ++q) dd_merge(t, dd{L.ps[l * P + q], L.pe[l * P + q]});
+    gv = dd_round(t);
   }
   __syncthreads();
+  return gv;
+}
+
+// v^T G v, with v held one value per lane.
+__device__ __forceinline__ double quad(InnerLds& L, double va, int d) {
+  int a = threadIdx.x;
+  L.v[a < MAXK ? a : MAXK] = a < d ? va : 0.0;
+  __syncthreads();
+  double gv = gmul(L, d);
   return wave_dot(a < d ? va : 0.0, gv);
 }
 
@@ -305,13 +326,7 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ 
     // p . G (B p)
     L.v[a < MAXK ? a : MAXK] = a < d ? bpv : 0.0;
     __syncthreads();
-    double gbp = 0.0;
-    if (a < d) {
-      dd acc = dd_zero();
-      for (int b = 0; b < d; ++b) dd_add_prod(acc, L.G[a][b], L.v[b]);
-      gbp = dd_round(acc);
-    }
-    __syncthreads();
+    double gbp = gmul(L, d);
     double den = wave_dot(a < d ? p : 0.0, gbp);
     if (den == 0.0 || !(den > 0.0) || isinf(den)) {
       status = j == 1 ? SSCG_BREAKDOWN : SSCG_OK;

@@ -216,18 +216,19 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
                             hipMemcpyDeviceToHost, S1));
       HIPCHK(hipEventRecord(ctx->evV[slot], S1));
     } else {
-      HIPCHK(hipEventRecord(ctx->evG[slot], S1));
       HIPCHK(ev_begin(ctx, 3, 0.0, S1, &slot_t));
       HIPCHK(launch_inner(Gk, prm, coef, info, stop, S1));
       HIPCHK(ev_end(ctx, slot_t, S1));
+      // one event for both side-stream kernels: every event record or wait
+      // costs the launch stream a few microseconds, and kappa has a whole
+      // block's time to finish before the next recovery waits for it
       HIPCHK(hipEventRecord(ctx->evI[slot], S1));
       // exact decisions on the side stream (they run even after a stop so
       // that a rejected speculation is always reported)
-      HIPCHK(hipStreamWaitEvent(S2, ctx->evG[slot], 0));
+      HIPCHK(hipStreamWaitEvent(S2, ctx->evI[slot], 0));
       HIPCHK(ev_begin(ctx, 3, 0.0, S2, &slot_t));
       HIPCHK(launch_kappa(Gk, d, s, first, info, nullptr, S2));
       HIPCHK(ev_end(ctx, slot_t, S2));
-      HIPCHK(hipStreamWaitEvent(S2, ctx->evI[slot], 0));
       sscg_block_params pv = prm;
       pv.adaptive = 1;
       HIPCHK(launch_validate(Gk, pv, info, stop, S2));
@@ -239,8 +240,8 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
     // needed for a redo of that block
     if (prev_spec) HIPCHK(hipStreamWaitEvent(S1, ctx->evV[(k - 1) % RING], 0));
     HIPCHK(ev_begin(ctx, 2, 8.0 * n * (d + 4), S1, &slot_t));
-    HIPCHK(launch_recover(cols, n, d, coef, X[par], X[par ^ 1], R0[par ^ 1], P0[par ^ 1], stop,
-                          S1));
+    HIPCHK(launch_recover(cols, n, d, coef, X[par], X[par ^ 1], R0[par ^ 1], P0[par ^ 1],
+                          Gate{stop, ev_ran(ctx, slot_t)}, S1));
     HIPCHK(ev_end(ctx, slot_t, S1));
     return SSCG_OK;
   };

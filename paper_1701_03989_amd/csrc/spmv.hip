@@ -117,16 +117,16 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
 // RES: the pass also forms the true residual of the block's starting iterate
 // x, res_i = RN(b_i - (A x)_i), from the same stream of A (x gathered as a
 // third sequence), and stores per-workgroup dd partials of sum res_i^2.
-// `stop` (may be NULL): the pass does nothing once the solve has stopped.
+// The gate: the pass does nothing once the solve has stopped.
 __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 
 template <int NRHS, bool CHEB, bool HASW, bool RES>
 __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
-                                            MpkSeq s0, MpkSeq s1, const int* __restrict__ stop,
+                                            MpkSeq s0, MpkSeq s1, Gate gate,
                                             const double* __restrict__ xres,
                                             const double* __restrict__ bres,
                                             double* __restrict__ rpart) {
-  if (stop && *stop) return;
+  if (gate_closed(gate)) return;
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
@@ -140,14 +140,35 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
     const double* __restrict__ u0 = s0.u;
     const double* __restrict__ u1 = s1.u;
     dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
-#pragma unroll 4
-    for (int j = 0; j < w; ++j) {
-      int64_t k = o + (int64_t)j * SSCG_WAVE;
-      double v = A.val[k];
-      int c = A.col[k];
-      dd_add_prod(a0, v, u0[c]);
-      if (NRHS == 2) dd_add_prod(a1, v, u1[c]);
-      if (RES) dd_add_prod(ax, v, xres[c]);
+    // chunks of CH entries: every load of a chunk is issued before its first
+    // use (w is uniform over the wave, so the guards do not diverge)
+    constexpr int CH = 4;
+    for (int j0 = 0; j0 < w; j0 += CH) {
+      double v[CH], g0[CH], g1[CH], gx[CH];
+      int c[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
+        bool in = j0 + u < w;
+        v[u] = in ? A.val[k] : 0.0;
+        c[u] = in ? A.col[k] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (j0 + u < w) {
+          g0[u] = u0[c[u]];
+          if (NRHS == 2) g1[u] = u1[c[u]];
+          if (RES) gx[u] = xres[c[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (j0 + u < w) {
+          dd_add_prod(a0, v[u], g0[u]);
+          if (NRHS == 2) dd_add_prod(a1, v[u], g1[u]);
+          if (RES) dd_add_prod(ax, v[u], gx[u]);
+        }
+      }
     }
     if (row < A.n) {
       if (CHEB) {
@@ -332,32 +353,32 @@ hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
 
 template <int NRHS, bool CHEB, bool HASW>
 void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
-                MpkSeq s1, const int* stop, const MpkResidual& res, hipStream_t st) {
+                MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
   if (res.x)
     hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true>), grid, dim3(WG), 0, st, A, theta, sigma,
-                       gamma, s0, s1, stop, res.x, res.b, res.part);
+                       gamma, s0, s1, g, res.x, res.b, res.part);
   else
     hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false>), grid, dim3(WG), 0, st, A, theta, sigma,
-                       gamma, s0, s1, stop, nullptr, nullptr, nullptr);
+                       gamma, s0, s1, g, nullptr, nullptr, nullptr);
 }
 
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
-                           const int* stop, const MpkResidual& res, hipStream_t st) {
+                           Gate g, const MpkResidual& res, hipStream_t st) {
   dim3 grid(xcd_grid(wg_count(A.nslices)));
   if (!bp.cheb) {
-    if (nrhs == 2) mpk_launch<2, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, stop, res, st);
-    else mpk_launch<1, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, stop, res, st);
+    if (nrhs == 2) mpk_launch<2, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, g, res, st);
+    else mpk_launch<1, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, g, res, st);
     return hipGetLastError();
   }
   double theta = bp.c0;
   double gamma = j == 1 ? bp.h : bp.h2;
   double sigma = bp.h2;
   if (j == 1) {
-    if (nrhs == 2) mpk_launch<2, true, false>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
-    else mpk_launch<1, true, false>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
+    if (nrhs == 2) mpk_launch<2, true, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
+    else mpk_launch<1, true, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
   } else {
-    if (nrhs == 2) mpk_launch<2, true, true>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
-    else mpk_launch<1, true, true>(grid, A, theta, sigma, gamma, s0, s1, stop, res, st);
+    if (nrhs == 2) mpk_launch<2, true, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
+    else mpk_launch<1, true, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
   }
   return hipGetLastError();
 }

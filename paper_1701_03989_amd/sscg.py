@@ -297,8 +297,18 @@ def sscg_recover(ctx: int, n: int, s: int, first: bool, Y, ldy: int, rcol: int, 
                                           _f64(x), _ptr(r), _ptr(p)))
 
 
-def sscg_set_timing(ctx: int, on: bool) -> int:
-    return _check(ctx, lib().sscg_set_timing(ctx, int(on)))
+TIME_ALL = 0xF
+
+
+def sscg_set_timing(ctx: int, on) -> int:
+    """on: True (every family), False (off), or an iterable of family names."""
+    if isinstance(on, bool):
+        mask = TIME_ALL if on else 0
+    else:
+        mask = 0
+        for f in on:
+            mask |= 1 << (FAMILIES[f] if isinstance(f, str) else int(f))
+    return _check(ctx, lib().sscg_set_timing(ctx, mask))
 
 
 def sscg_kernel_stats(ctx: int, family) -> tuple[int, float, float]:
