@@ -217,6 +217,49 @@ int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* pr
 int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
                  const double* coef, double* x, double* r, double* p);
 
+/* ---------------------------------------------------------------- batches */
+
+/* Independent systems A_i x_i = b_i solved side by side, each by the same
+ * algorithm as sscg_solve (Algorithm 4, or 2 with opts->mode = FIXED) and to
+ * the same numbers: every stage of an outer block runs as one launch over all
+ * systems (a block-diagonal layout; each system's s_bar_k, s~_k, s_k, m and
+ * convergence are decided on the device), and the launches of one outer
+ * block are replayed as a HIP graph until every system has finished.
+ * Systems may differ in size, matrix and tolerance.  Not supported in a
+ * batch: MODE_SCHEDULE, equilibration, and the Chebyshev interval estimate
+ * (intervals are inputs).  All arrays of this struct are HOST arrays of
+ * length nsys; the pointers they hold are DEVICE pointers owned by the
+ * caller. */
+typedef struct {
+  int32_t nsys;
+  const sscg_csr* A;          /* system matrices                                      */
+  const double* const* b;     /* right-hand sides (n_i each)                          */
+  double* const* x;           /* x_1 on entry, the solution on return (n_i each)      */
+  const double* tol;          /* per-system target relative residual (NULL: opts->tol) */
+  const double* lambda_min;   /* Chebyshev intervals (required for BASIS_CHEBYSHEV)   */
+  const double* lambda_max;
+} sscg_batch;
+
+/* Per-system outputs: HOST arrays owned by the caller (any may be NULL);
+ * the per-block arrays hold `cap` rows per system, system i at i*cap. */
+typedef struct {
+  int32_t cap;
+  int32_t* status;        /* [nsys] SSCG_OK / NOT_CONVERGED / BREAKDOWN             */
+  int32_t* blocks;        /* [nsys] outer blocks of the system                      */
+  int32_t* iters;         /* [nsys] inner iterations m                             */
+  double* relres;         /* [nsys] ||b - A x|| / ||b|| of the returned x            */
+  int32_t* s_k;           /* [nsys*cap] schedule                                    */
+  int32_t* s_tilde;       /* [nsys*cap] s~_k of eq. condy                           */
+  double* relres_true;    /* [nsys*cap] true relative residual after each block     */
+  int32_t graph_launches; /* outer blocks replayed (all systems together)           */
+  int32_t rows;           /* rows of the batch layout (each system padded to 256)    */
+} sscg_batch_result;
+
+/* Returns SSCG_OK when every system converged, else the largest positive
+ * per-system status; negative codes as for sscg_solve (no x written). */
+int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* batch, const sscg_opts* opts,
+                     sscg_batch_result* res);
+
 /* ---------------------------------------------------------------- timing */
 
 /* Kernel timing with HIP events on the stream each kernel runs on (off by

@@ -348,6 +348,7 @@ int sscg_create(sscg_ctx** out, int device, void* stream) {
   c->stream = (hipStream_t)stream;
   bool ok = hipHostMalloc((void**)&c->hinfo, sizeof(sscg_block_info) * RING) == hipSuccess &&
             hipHostMalloc((void**)&c->hscal, sizeof(double) * 16) == hipSuccess &&
+            hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * 4) == hipSuccess &&
             hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; ok && i < RING; ++i)
     ok = hipEventCreateWithFlags(&c->evI[i], hipEventDisableTiming) == hipSuccess &&
@@ -372,6 +373,12 @@ void sscg_destroy(sscg_ctx* c) {
                  &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  BatchWs& w = c->batch;
+  Buf* bbufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag,    &w.Y,      &w.x,     &w.b,
+                  &w.sys,   &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,   &w.blk_sys,
+                  &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active};
+  for (Buf* b : bbufs)
+    if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -384,6 +391,7 @@ void sscg_destroy(sscg_ctx* c) {
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->hinfo) (void)hipHostFree(c->hinfo);
   if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->hactive) (void)hipHostFree(c->hactive);
   delete c;
 }
 

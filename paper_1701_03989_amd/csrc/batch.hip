@@ -1,0 +1,298 @@
+// sscg_batch_solve: independent systems advanced together, one outer block
+// (Algorithm 4, or 2) at a time for all of them.
+//
+// Layout: system q owns rows [row0_q, row0_q + npad_q) of one block-diagonal
+// SELL-64 matrix and of every batch vector, npad_q = n_q rounded up to a
+// multiple of 256, so that each 256-row block (one workgroup of the streaming
+// kernels), each Gram chunk and each slice belongs to one system.  Padding
+// rows are empty and their vector entries stay zero, so they add nothing to
+// any sum.  Every per-system decision (s_bar_k, the rank guard, s~_k, s_k,
+// convergence, the iteration cap) is taken on the device from the system
+// table, so one outer block is the same sequence of launches for every block:
+// it is captured once as a HIP graph and replayed until no system is left.
+// The per-system arithmetic is the single-system path's, kernel for kernel,
+// so a system's result does not depend on the rest of the batch.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace sscg_host;
+
+namespace {
+
+constexpr int CHUNK_ROWS = 1024;  // rows per Gram work item
+constexpr int GROUP = 4;          // blocks replayed between checks of the active count
+
+// One outer block for every unfinished system (enqueued on st; capturable).
+int enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st) {
+  HIPCHK(launch_batch_plan(c, st));
+  const int cheb = c.basis == SSCG_BASIS_CHEBYSHEV;
+  for (int j = 1; j <= c.S; ++j) {
+    MpkSeq sp{batch_col(c, j - 1), j >= 2 ? batch_col(c, j - 2) : nullptr, batch_col(c, j)};
+    const int rb = c.S + 1;  // R_j at column rb + j
+    MpkSeq sr{batch_col(c, rb + j - 1), j >= 2 ? batch_col(c, rb + j - 2) : nullptr,
+              batch_col(c, rb + j)};
+    const int nrhs = j <= c.S - 1 ? 2 : 1;
+    MpkResidual res{};
+    if (j == 1) res = MpkResidual{c.x, c.b, c.rpart};
+    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, res, st));
+    if (j == 1) HIPCHK(launch_batch_res_finalize(c, st));
+  }
+  HIPCHK(launch_gram_batch(c, st));
+  HIPCHK(launch_gram_finalize_batch(c, st));
+  if (c.mode == SSCG_MODE_ADAPTIVE) HIPCHK(launch_kappa_batch(c, st));
+  HIPCHK(launch_inner_batch(c, st));
+  HIPCHK(launch_recover_batch(c, st));
+  HIPCHK(launch_batch_count(c, st));
+  return SSCG_OK;
+}
+
+struct GraphGuard {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  ~GraphGuard() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
+}  // namespace
+
+extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_opts* opts,
+                                sscg_batch_result* res) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = validate_opts(ctx, opts))) return rc;
+  const sscg_opts& o = *opts;
+  if (!B || B->nsys < 1 || !B->A || !B->b || !B->x)
+    return fail(ctx, SSCG_ERR_ARG, "batch: nsys >= 1 and the A, b, x arrays are required");
+  if (o.mode == SSCG_MODE_SCHEDULE)
+    return fail(ctx, SSCG_ERR_ARG, "batch: MODE_SCHEDULE is not supported");
+  if (o.equilibrate) return fail(ctx, SSCG_ERR_ARG, "batch: equilibration is not supported");
+  const int nsys = B->nsys;
+  const bool cheb = o.basis == SSCG_BASIS_CHEBYSHEV;
+  if (cheb && (!B->lambda_min || !B->lambda_max))
+    return fail(ctx, SSCG_ERR_ARG, "batch: the Chebyshev basis needs per-system intervals");
+  for (int q = 0; q < nsys; ++q) {
+    if ((rc = check_csr(ctx, &B->A[q]))) return rc;
+    if (!B->b[q] || !B->x[q]) return fail(ctx, SSCG_ERR_ARG, "batch: b[%d] or x[%d] is NULL", q, q);
+    if (cheb && !(B->lambda_max[q] > B->lambda_min[q]))
+      return fail(ctx, SSCG_ERR_ARG, "batch: need lambda_max > lambda_min (system %d)", q);
+    if (B->tol && !(B->tol[q] > 0.0)) return fail(ctx, SSCG_ERR_ARG, "batch: tol[%d] <= 0", q);
+  }
+
+  // ---- layout
+  std::vector<BatchSys> hs(nsys);
+  std::vector<BatchChunk> hc;
+  int64_t rows = 0;
+  for (int q = 0; q < nsys; ++q) {
+    const int n = B->A[q].n;
+    const int64_t npad = std::max<int64_t>(BATCH_ROWS, ((int64_t)n + BATCH_ROWS - 1) / BATCH_ROWS *
+                                                           BATCH_ROWS);
+    BatchSys& s = hs[q];
+    memset(&s, 0, sizeof s);
+    s.row0 = (int32_t)rows;
+    s.n = n;
+    s.blk0 = (int32_t)(rows / BATCH_ROWS);
+    s.blk1 = (int32_t)((rows + npad) / BATCH_ROWS);
+    s.ch0 = (int32_t)hc.size();
+    for (int64_t r = rows; r < rows + npad; r += CHUNK_ROWS)
+      hc.push_back(BatchChunk{q, (int32_t)r, (int32_t)std::min(r + CHUNK_ROWS, rows + npad), 0});
+    s.ch1 = (int32_t)hc.size();
+    s.tol = B->tol ? B->tol[q] : o.tol;
+    s.lmin = cheb ? B->lambda_min[q] : 0.0;
+    s.lmax = cheb ? B->lambda_max[q] : 1.0;
+    rows += npad;
+  }
+  if (rows > INT32_MAX / 2) return fail(ctx, SSCG_ERR_ARG, "batch: %lld rows are too many",
+                                        (long long)rows);
+  const int N = (int)rows;
+  const int nblk = N / BATCH_ROWS, nslices = N / SSCG_WAVE, nchunks = (int)hc.size();
+  std::vector<int32_t> hblk(nblk);
+  for (int q = 0; q < nsys; ++q)
+    for (int k = hs[q].blk0; k < hs[q].blk1; ++k) hblk[k] = q;
+  const int S = o.mode == SSCG_MODE_FIXED ? o.fixed_s : o.s_max;
+  const int ncols = 2 * S + 1;  // P_0..P_S, R_0..R_{S-1}
+  const int cap = std::max(1, std::min(o.max_iters + 2, res && res->cap > 0 ? res->cap : 1));
+  const int dmax = 2 * S + 1, npairs = dmax * (dmax + 1) / 2;
+
+  // ---- workspace (nothing is reallocated once blocks run)
+  BatchWs& w = ctx->batch;
+  hipStream_t st = ctx->side;
+  HIPCHK(hipStreamSynchronize(ctx->stream));  // the caller's A, b, x are ready
+  HIPCHK(ensure(w.width, sizeof(int32_t) * (nslices + 1)));
+  HIPCHK(ensure(w.off, sizeof(int64_t) * (nslices + 1)));
+  HIPCHK(ensure(w.flag, sizeof(int32_t) * 4));
+  HIPCHK(ensure(w.Y, sizeof(double) * (size_t)N * ncols));
+  HIPCHK(ensure(w.x, sizeof(double) * (size_t)N));
+  HIPCHK(ensure(w.b, sizeof(double) * (size_t)N));
+  HIPCHK(ensure(w.sys, sizeof(BatchSys) * nsys));
+  HIPCHK(ensure(w.prm, sizeof(sscg_block_params) * nsys));
+  HIPCHK(ensure(w.info, sizeof(sscg_block_info) * nsys));
+  HIPCHK(ensure(w.G, sizeof(double) * (size_t)BATCH_GSZ * nsys));
+  HIPCHK(ensure(w.coef, sizeof(double) * (size_t)BATCH_CSZ * nsys));
+  HIPCHK(ensure(w.hist, sizeof(BatchHist) * (size_t)cap * nsys));
+  HIPCHK(ensure(w.blk_sys, sizeof(int32_t) * nblk));
+  HIPCHK(ensure(w.chunks, sizeof(BatchChunk) * nchunks));
+  HIPCHK(ensure(w.rpart, sizeof(double) * 2 * (size_t)nblk));
+  HIPCHK(ensure(w.bpart, sizeof(double) * 2 * (size_t)nblk));
+  HIPCHK(ensure(w.gpart, sizeof(double) * 2 * (size_t)npairs * nchunks));
+  HIPCHK(ensure(w.active, sizeof(int32_t) * 4));
+
+  // ---- block-diagonal SELL-64 copy (structure checked per system)
+  int32_t* width = as<int32_t>(w.width);
+  int64_t* off = as<int64_t>(w.off);
+  int32_t* flag = as<int32_t>(w.flag);
+  HIPCHK(hipMemsetAsync(width, 0, sizeof(int32_t) * (nslices + 1), st));
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  for (int q = 0; q < nsys; ++q) {
+    const sscg_csr& A = B->A[q];
+    const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
+    HIPCHK(launch_check_csr(A.rowptr, A.col, A.n, A.nnz, flag, st));
+    HIPCHK(launch_sell_widths_n(A.rowptr, A.n, npad / SSCG_WAVE, width + hs[q].row0 / SSCG_WAVE,
+                                st));
+  }
+  HIPCHK(launch_scan_offsets(width, nslices, off, st));
+  int64_t total = 0;
+  int32_t bad = 0;
+  HIPCHK(hipMemcpyAsync(&total, off + nslices, sizeof total, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad)
+    return fail(ctx, SSCG_ERR_ARG,
+                "batch: invalid CSR (rowptr not non-decreasing or a column index outside [0, n))");
+  HIPCHK(ensure(w.scol, sizeof(int32_t) * std::max<int64_t>(total, 1)));
+  HIPCHK(ensure(w.sval, sizeof(double) * std::max<int64_t>(total, 1)));
+  for (int q = 0; q < nsys; ++q) {
+    const sscg_csr& A = B->A[q];
+    const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
+    HIPCHK(launch_sell_fill_off(A.rowptr, A.col, A.val, A.n, npad / SSCG_WAVE,
+                                off + hs[q].row0 / SSCG_WAVE, hs[q].row0, as<int32_t>(w.scol),
+                                as<double>(w.sval), st));
+  }
+  DevMat M;
+  M.n = N;
+  M.nslices = nslices;
+  M.off = off;
+  M.col = as<int32_t>(w.scol);
+  M.val = as<double>(w.sval);
+
+  // ---- vectors, tables, set-up residual r_1 = b - A x_1 (into P_0)
+  BatchCfg c;
+  memset(&c, 0, sizeof c);
+  c.nsys = nsys;
+  c.S = S;
+  c.cap = cap;
+  c.nblk = nblk;
+  c.nchunks = nchunks;
+  c.mode = o.mode;
+  c.s_max = o.s_max;
+  c.s0 = o.s0_bar > 0 ? o.s0_bar : o.s_max;
+  c.f = o.f > 0 ? o.f : o.s_max;
+  c.fixed_s = o.fixed_s;
+  c.inner_check = o.inner_check;
+  c.basis = o.basis;
+  c.max_iters = o.max_iters;
+  c.ld = N;
+  c.c = o.c;
+  c.Y = as<double>(w.Y);
+  c.x = as<double>(w.x);
+  c.b = as<double>(w.b);
+  c.sys = as<BatchSys>(w.sys);
+  c.prm = as<sscg_block_params>(w.prm);
+  c.info = as<sscg_block_info>(w.info);
+  c.G = as<double>(w.G);
+  c.coef = as<double>(w.coef);
+  c.hist = as<BatchHist>(w.hist);
+  c.blk_sys = as<int32_t>(w.blk_sys);
+  c.chunks = as<BatchChunk>(w.chunks);
+  c.rpart = as<double>(w.rpart);
+  c.bpart = as<double>(w.bpart);
+  c.gpart = as<double>(w.gpart);
+  c.active = as<int32_t>(w.active);
+  HIPCHK(hipMemsetAsync(c.Y, 0, sizeof(double) * (size_t)N * ncols, st));
+  HIPCHK(hipMemsetAsync(c.x, 0, sizeof(double) * (size_t)N, st));
+  HIPCHK(hipMemsetAsync(as<double>(w.b), 0, sizeof(double) * (size_t)N, st));
+  for (int q = 0; q < nsys; ++q) {
+    const size_t nb = sizeof(double) * (size_t)hs[q].n;
+    HIPCHK(hipMemcpyAsync(c.x + hs[q].row0, B->x[q], nb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(as<double>(w.b) + hs[q].row0, B->b[q], nb, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(c.sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(as<int32_t>(w.blk_sys), hblk.data(), sizeof(int32_t) * nblk,
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(as<BatchChunk>(w.chunks), hc.data(), sizeof(BatchChunk) * nchunks,
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(c.hist, 0, sizeof(BatchHist) * (size_t)cap * nsys, st));
+  int np = 0;
+  HIPCHK(launch_residual(M, c.b, c.x, batch_col(c, 0), c.rpart, c.bpart, &np, st));
+  if (np != nblk) return fail(ctx, SSCG_ERR_HIP, "batch: residual partials %d != blocks %d", np, nblk);
+  HIPCHK(launch_batch_init(c, st));
+  HIPCHK(launch_batch_count(c, st));
+
+  // ---- one outer block as a graph, replayed
+  GraphGuard gg;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_block(ctx, M, c, st);
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(st, &graph);
+  gg.g = graph;
+  if (rc) return rc;
+  HIPCHK(ce);
+  HIPCHK(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+  // every replay adds >= 1 iteration to each unfinished system or finishes it
+  const int64_t limit = (int64_t)o.max_iters + 2;
+  int launches = 0;
+  HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  while (ctx->hactive[0] > 0 && launches < limit) {
+    const int g = (int)std::min<int64_t>(GROUP, limit - launches);
+    for (int i = 0; i < g; ++i) HIPCHK(hipGraphLaunch(gg.e, st));
+    launches += g;
+    HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+
+  // ---- results
+  std::vector<BatchHist> hh((size_t)cap * nsys);
+  HIPCHK(hipMemcpyAsync(hs.data(), c.sys, sizeof(BatchSys) * nsys, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hh.data(), c.hist, sizeof(BatchHist) * hh.size(), hipMemcpyDeviceToHost,
+                        st));
+  HIPCHK(hipStreamSynchronize(st));
+  int worst = SSCG_OK;
+  for (int q = 0; q < nsys; ++q) {
+    const BatchSys& s = hs[q];
+    const size_t nb = sizeof(double) * (size_t)s.n;
+    if (s.b2 == 0.0)
+      HIPCHK(launch_fill(B->x[q], s.n, 0.0, st));
+    else
+      HIPCHK(hipMemcpyAsync(B->x[q], c.x + s.row0, nb, hipMemcpyDeviceToDevice, st));
+    const int status = s.done ? s.status : SSCG_NOT_CONVERGED;
+    worst = std::max(worst, status);
+    if (!res) continue;
+    if (res->status) res->status[q] = status;
+    if (res->blocks) res->blocks[q] = s.blocks;
+    if (res->iters) res->iters[q] = s.m;
+    if (res->relres) res->relres[q] = s.relres;
+    if (res->cap > 0)
+      for (int k = 0; k < res->cap; ++k) {
+        const bool in = k < cap && k < s.blocks + (s.status == SSCG_BREAKDOWN ? 1 : 0);
+        const BatchHist* h = in ? &hh[(size_t)q * cap + k] : nullptr;
+        if (res->s_k) res->s_k[(size_t)q * res->cap + k] = h ? h->s_k : 0;
+        if (res->s_tilde) res->s_tilde[(size_t)q * res->cap + k] = h ? h->s_tilde : 0;
+        if (res->relres_true) res->relres_true[(size_t)q * res->cap + k] = h ? h->relres_true : NAN;
+      }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (res) {
+    res->graph_launches = launches;
+    res->rows = N;
+  }
+  return worst;
+}

@@ -228,3 +228,95 @@ hipError_t launch_dot_parts(const double* x, const double* y, int n, double* par
                             hipStream_t st);
 hipError_t launch_tridiag_eig(const double* alpha, const double* beta, int k, double* lmin,
                               double* lmax, hipStream_t st);
+
+// ---------------------------------------------------------------- batches
+//
+// A batch solves independent systems side by side.  System q owns rows
+// [row0, row0 + npad) of one block-diagonal SELL-64 matrix, npad = n rounded
+// up to a multiple of 256 (padding rows are empty and their vector entries
+// stay 0), so every 256-row block, Gram chunk and slice belongs to one
+// system.  All per-system decisions live in device tables, so the launches of
+// one outer block are the same for every block and can be replayed as a
+// graph.
+constexpr int BATCH_ROWS = 256;                                  // rows per block
+constexpr int BATCH_GSZ = (2 * SSCG_S_LIMIT + 1) * (2 * SSCG_S_LIMIT + 1);  // G per system
+constexpr int BATCH_CSZ = 3 * (2 * SSCG_S_LIMIT + 1);          // coefficients per system
+
+struct BatchSys {
+  int32_t done;        // 1: finished; every later kernel skips the system
+  int32_t status;      // SSCG_* once done
+  int32_t first;       // the next block is the system's block 0
+  int32_t m;           // inner iterations so far
+  int32_t s_prev;      // s_k of the previous block
+  int32_t blocks;      // blocks committed
+  int32_t s_bar;       // s_bar of the current block
+  int32_t row0, n;     // first row in the batch layout; rows
+  int32_t blk0, blk1;  // 256-row blocks [blk0, blk1)
+  int32_t ch0, ch1;    // Gram chunks [ch0, ch1)
+  int32_t pad_;
+  double tol;          // target relative residual
+  double eps_star;     // tol * ||b||
+  double b2;           // ||b||^2
+  double relres;       // latest true relative residual (relres0 before block 0)
+  double lmin, lmax;   // Chebyshev interval of the system
+  BasisPrm bp;         // basis parameters derived from it
+};
+
+struct BatchHist {  // one committed block of one system
+  int32_t s_bar, s_built, s_tilde, s_k;
+  double relres_true;  // true relative residual of the iterate after the block
+};
+
+struct BatchChunk {  // Gram work item: rows [r0, r1) of system sys
+  int32_t sys, r0, r1, pad_;
+};
+
+struct BatchCfg {
+  int32_t nsys, S, cap, nblk, nchunks;  // systems, passes per block, history rows, blocks, chunks
+  int32_t mode, s_max, s0, f, fixed_s, inner_check, basis, max_iters;
+  int64_t ld;                 // column stride of Y
+  double c;                   // c_{k,j}
+  double* Y;                  // columns P_0..P_S at 0..S, R_0..R_{S-1} at S+1..2S
+  double* x;                  // iterates, batch layout
+  const double* b;
+  BatchSys* sys;
+  sscg_block_params* prm;     // this block's parameters per system
+  sscg_block_info* info;
+  double* G;                  // BATCH_GSZ per system
+  double* coef;               // BATCH_CSZ per system
+  BatchHist* hist;            // nsys * cap
+  const int32_t* blk_sys;     // system of each 256-row block (-1: none)
+  const BatchChunk* chunks;   // Gram work items, grouped by system
+  double* rpart;              // dd partial per 256-row block (residual of x)
+  double* bpart;              // dd partial per 256-row block (||b||^2, set-up)
+  double* gpart;              // Gram partials: (pair * nchunks + chunk) * 2
+  int32_t* active;            // systems not done (after each block)
+};
+
+// P_j / R_j column of a batch (global row index applies on top).
+__host__ __device__ inline double* batch_col(const BatchCfg& c, int col) {
+  return c.Y + (int64_t)col * c.ld;
+}
+
+hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32_t* width,
+                                hipStream_t st);
+hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const double* val,
+                                int n, int nslices, const int64_t* off, int col_off, int32_t* scol,
+                                double* sval, hipStream_t st);
+hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
+                            const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
+                            hipStream_t st);
+// Set-up from the residual of x_1 (rpart) and ||b||^2 (bpart): relres0, eps*;
+// systems with b = 0 or relres0 <= tol are done before block 0.
+hipError_t launch_batch_init(const BatchCfg& c, hipStream_t st);
+// Sizes of this block per system (s_bar, rank guard) into prm.
+hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st);
+// Residual of each system's starting iterate; convergence / iteration cap.
+hipError_t launch_batch_res_finalize(const BatchCfg& c, hipStream_t st);
+hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st);
+hipError_t launch_gram_finalize_batch(const BatchCfg& c, hipStream_t st);
+hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st);
+// Coordinate solve and commit of the block (history, m, s_prev, breakdown).
+hipError_t launch_inner_batch(const BatchCfg& c, hipStream_t st);
+hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st);
+hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st);

@@ -26,6 +26,13 @@ T* as(Buf& b) {
   return reinterpret_cast<T*>(b.p);
 }
 
+// Workspace of sscg_batch_solve (kept between calls, grown on demand).
+struct BatchWs {
+  Buf width, off, scol, sval, flag;  // block-diagonal SELL-64 matrix
+  Buf Y, x, b;                       // basis columns, iterates, right-hand sides
+  Buf sys, prm, info, G, coef, hist, blk_sys, chunks, rpart, bpart, gpart, active;
+};
+
 struct EvRec {
   hipEvent_t a, b;
   int fam;
@@ -58,6 +65,8 @@ struct sscg_ctx {
   size_t ev_used = 0;
   sscg_host::Buf ran;  // int[RAN_CAP] device flags of gated timed launches (zero between uses)
   std::vector<int> hran;
+  sscg_host::BatchWs batch;
+  int32_t* hactive = nullptr;  // pinned
 };
 
 namespace sscg_host {

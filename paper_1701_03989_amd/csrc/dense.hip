@@ -18,12 +18,12 @@ constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 // of GT rows x d columns are staged in LDS (row-major, so the lanes of a wave
 // reading different columns of one row hit different banks).  Output: one dd
 // partial per (entry, workgroup), entry-major.
-__global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* __restrict__ part,
-                                             int nparts, Gate gate) {
+// Upper-triangle dd partials of the Gram matrix of columns cols[0..d) over
+// rows [rb, re): entry q (a <= b, row-major over the triangle) goes to
+// part[(q * nparts + slot) * 2].
+__device__ __forceinline__ void gram_rows(const ColPtr& cols, int d, int rb, int re,
+                                          double* __restrict__ part, int nparts, int slot) {
   __shared__ double tile[GT][MAXD + 1];
-  if (gate_closed(gate)) return;
-  int lb = xcd_block(nparts);
-  if (lb >= nparts) return;
   const int npairs = d * (d + 1) / 2;
   int pa[PAIRS_PER_THREAD], pb[PAIRS_PER_THREAD];
   dd acc[PAIRS_PER_THREAD];
@@ -39,15 +39,11 @@ __global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* 
     pb[u] = a < d ? a + rem : 0;
     acc[u] = dd_zero();
   }
-  int ntiles = (n + GT - 1) / GT;
-  int per = (ntiles + nparts - 1) / nparts;
-  int t0 = lb * per, t1 = min(t0 + per, ntiles);
-  for (int t = t0; t < t1; ++t) {
-    int r0 = t * GT;
+  for (int r0 = rb; r0 < re; r0 += GT) {
     for (int e = threadIdx.x; e < GT * d; e += WG) {
       int a = e / GT, r = e - a * GT;
       int row = r0 + r;
-      tile[r][a] = row < n ? cols.c[a][row] : 0.0;
+      tile[r][a] = row < re ? cols.c[a][row] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -64,10 +60,21 @@ __global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* 
   for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
     int q = threadIdx.x + u * WG;
     if (q < npairs) {
-      part[((int64_t)q * nparts + lb) * 2] = acc[u].s;
-      part[((int64_t)q * nparts + lb) * 2 + 1] = acc[u].e;
+      part[((int64_t)q * nparts + slot) * 2] = acc[u].s;
+      part[((int64_t)q * nparts + slot) * 2 + 1] = acc[u].e;
     }
   }
+}
+
+__global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* __restrict__ part,
+                                             int nparts, Gate gate) {
+  if (gate_closed(gate)) return;
+  int lb = xcd_block(nparts);
+  if (lb >= nparts) return;
+  int ntiles = (n + GT - 1) / GT;
+  int per = (ntiles + nparts - 1) / nparts;
+  int t0 = lb * per, t1 = min(t0 + per, ntiles);
+  gram_rows(cols, d, t0 * GT, min(t1 * GT, n), part, nparts, lb);
 }
 
 // Sum `nparts` dd partials of reduction blockIdx.x in a fixed order and
@@ -145,6 +152,11 @@ __global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ 
 // x_i <- RN(x_i + sum_a Y_ia x'_a), r_i <- RN(sum_a Y_ia r'_a),
 // p_i <- RN(sum_a Y_ia p'_a) (eq. coords).  Columns whose three coefficients
 // are all zero contribute nothing to the exact sums and are not read.
+__device__ __forceinline__ void recover_row(const ColPtr& cols, int d,
+                                            const double* __restrict__ coef, int i,
+                                            const double* x_in, double* x_out, double* r,
+                                            double* p);
+
 __global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
                                                 const double* __restrict__ coef,
                                                 const double* x_in, double* x_out, double* r,
@@ -155,6 +167,13 @@ __global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
   if (lb >= nb) return;
   int i = lb * WG + threadIdx.x;
   if (i >= n) return;
+  recover_row(cols, d, coef, i, x_in, x_out, r, p);
+}
+
+__device__ __forceinline__ void recover_row(const ColPtr& cols, int d,
+                                            const double* __restrict__ coef, int i,
+                                            const double* x_in, double* x_out, double* r,
+                                            double* p) {
   dd ax = dd_zero(), ar = dd_zero(), ap = dd_zero();
   dd_add(ax, x_in[i]);
   for (int a = 0; a < d; ++a) {
@@ -287,6 +306,135 @@ __global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
   if (i < n) out[i] = w[i] / (*beta);
 }
 
+
+// ---------------------------------------------------------------- batches
+
+// Gram columns of system q in this block: P_0..P_s, then R_0..R_{s-1}.
+__device__ __forceinline__ ColPtr batch_cols(const BatchCfg& c, int s, int first) {
+  ColPtr cols;
+  const int d = first ? s + 1 : 2 * s + 1;
+  for (int a = 0; a < MAXD; ++a) {
+    int col = 0;
+    if (a < d) col = a <= s ? a : c.S + 1 + (a - s - 1);
+    cols.c[a] = batch_col(c, col);
+  }
+  return cols;
+}
+
+__global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {
+  int lb = xcd_block(c.nchunks);
+  if (lb >= c.nchunks) return;
+  const BatchChunk ch = c.chunks[lb];
+  if (c.sys[ch.sys].done) return;
+  const sscg_block_params prm = c.prm[ch.sys];
+  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
+  gram_rows(batch_cols(c, prm.s, prm.first), d, ch.r0, ch.r1, c.gpart, c.nchunks, lb);
+}
+
+// grid (pairs, systems): entry blockIdx.x of system blockIdx.y.
+__global__ __launch_bounds__(WG) void k_gram_finalize_batch(BatchCfg c) {
+  const int q = blockIdx.y, e = blockIdx.x;
+  const BatchSys& sy = c.sys[q];
+  if (sy.done) return;
+  const sscg_block_params prm = c.prm[q];
+  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
+  if (e >= d * (d + 1) / 2) return;
+  dd t = reduce_parts(c.gpart + ((int64_t)e * c.nchunks + sy.ch0) * 2, sy.ch1 - sy.ch0);
+  if (threadIdx.x == 0) {
+    int a = 0, rem = e;
+    while (rem >= d - a) {
+      rem -= d - a;
+      ++a;
+    }
+    int b = a + rem;
+    double g = dd_round(t);
+    double* G = c.G + (int64_t)q * BATCH_GSZ;
+    G[a * d + b] = g;
+    G[b * d + a] = g;
+  }
+}
+
+// x <- x + Y x', r = Y r' (into R_0), p = Y p' (into P_0), per system.
+__global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
+  int lb = xcd_block(c.nblk);
+  if (lb >= c.nblk) return;
+  const int q = c.blk_sys[lb];
+  if (q < 0 || c.sys[q].done) return;
+  const sscg_block_params prm = c.prm[q];
+  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
+  const int i = lb * BATCH_ROWS + threadIdx.x;
+  recover_row(batch_cols(c, prm.s, prm.first), d, c.coef + (int64_t)q * BATCH_CSZ, i, c.x, c.x,
+              batch_col(c, c.S + 1), batch_col(c, 0));
+}
+
+// Set-up per system from the residual and ||b||^2 partials of its blocks.
+__global__ __launch_bounds__(WG) void k_batch_init(BatchCfg c) {
+  const int q = blockIdx.x;
+  BatchSys& sy = c.sys[q];
+  dd r = reduce_parts(c.rpart + (int64_t)sy.blk0 * 2, sy.blk1 - sy.blk0);
+  __syncthreads();
+  dd bb = reduce_parts(c.bpart + (int64_t)sy.blk0 * 2, sy.blk1 - sy.blk0);
+  if (threadIdx.x == 0) {
+    const double r2 = dd_round(r), b2 = dd_round(bb);
+    sy.b2 = b2;
+    sy.eps_star = sy.tol * sqrt(b2);
+    sy.first = 1;
+    sy.m = 0;
+    sy.s_prev = 0;
+    sy.blocks = 0;
+    sy.s_bar = 0;
+    sy.bp = make_basis(c.basis, sy.lmin, sy.lmax);
+    if (b2 == 0.0) {  // x = 0 solves A x = 0
+      sy.relres = 0.0;
+      sy.done = 1;
+      sy.status = SSCG_OK;
+    } else {
+      const double rel = sqrt(r2) / sqrt(b2);
+      sy.relres = rel;
+      sy.done = rel <= sy.tol ? 1 : 0;
+      sy.status = SSCG_OK;
+    }
+  }
+}
+
+// The true residual of each system's starting iterate (fused into the first
+// matrix-powers pass) decides convergence; after block 0 only.
+__global__ __launch_bounds__(WG) void k_batch_res_finalize(BatchCfg c) {
+  const int q = blockIdx.x;
+  BatchSys& sy = c.sys[q];
+  if (sy.done || sy.first) return;
+  dd t = reduce_parts(c.rpart + (int64_t)sy.blk0 * 2, sy.blk1 - sy.blk0);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(dd_round(t)) / sqrt(sy.b2);
+    sy.relres = rel;
+    if (sy.blocks >= 1 && sy.blocks - 1 < c.cap)
+      c.hist[(int64_t)q * c.cap + sy.blocks - 1].relres_true = rel;
+    if (rel <= sy.tol) {
+      sy.done = 1;
+      sy.status = SSCG_OK;
+    } else if (!isfinite(rel)) {
+      sy.done = 1;
+      sy.status = SSCG_BREAKDOWN;
+    } else if (sy.m >= c.max_iters) {
+      sy.done = 1;
+      sy.status = SSCG_NOT_CONVERGED;
+    }
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_batch_count(BatchCfg c) {
+  __shared__ int ls[WG];
+  int a = 0;
+  for (int q = threadIdx.x; q < c.nsys; q += WG) a += c.sys[q].done ? 0 : 1;
+  ls[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = WG / 2; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) ls[threadIdx.x] += ls[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *c.active = ls[0];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launches
@@ -387,5 +535,36 @@ hipError_t launch_sqrt_scalar(double* x, hipStream_t st) {
 hipError_t launch_div_vec(const double* w, const double* beta, int n, double* out,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_div_vec, dim3((n + WG - 1) / WG), dim3(WG), 0, st, w, beta, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_batch, dim3(xcd_grid(c.nchunks)), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_finalize_batch(const BatchCfg& c, hipStream_t st) {
+  const int dm = 2 * c.S + 1;
+  hipLaunchKernelGGL(k_gram_finalize_batch, dim3(dm * (dm + 1) / 2, c.nsys), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_recover_batch, dim3(xcd_grid(c.nblk)), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_init, dim3(c.nsys), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_res_finalize(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_res_finalize, dim3(c.nsys), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(WG), 0, st, c);
   return hipGetLastError();
 }

@@ -156,13 +156,9 @@ __device__ double kappa_from_diag(const JacobiLds& L, int k) {
   return lmax / lmin;
 }
 
-// grid = s workgroups of one wave; workgroup i-1 computes kappa(G_i).
-__global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int d, int s,
-                                              int first, sscg_block_info* info,
-                                              const int* __restrict__ stop) {
-  __shared__ JacobiLds L;
-  if (stop && *stop) return;
-  int i = blockIdx.x + 1;
+// kappa(G_i) of the s-step Gram matrix G (d x d) into info->kappa[i-1].
+__device__ void kappa_body(JacobiLds& L, const double* __restrict__ G, int d, int s, int first,
+                           int i, sscg_block_info* info) {
   int k = first ? i + 1 : 2 * i + 1;
   if (threadIdx.x < k) {
     int b = threadIdx.x;
@@ -172,6 +168,15 @@ __global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int 
   __syncthreads();
   jacobi(L, k);
   if (threadIdx.x == 0) info->kappa[i - 1] = kappa_from_diag(L, k);
+}
+
+// grid = s workgroups; workgroup i-1 computes kappa(G_i).
+__global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int d, int s,
+                                              int first, sscg_block_info* info,
+                                              const int* __restrict__ stop) {
+  __shared__ JacobiLds L;
+  if (stop && *stop) return;
+  kappa_body(L, G, d, s, first, blockIdx.x + 1, info);
 }
 
 // Eigenvalue extremes of the Lanczos tridiagonal matrix (k <= MAXK).
@@ -278,12 +283,11 @@ __device__ __forceinline__ double quad(InnerLds& L, double va, int d) {
   return wave_dot(a < d ? va : 0.0, gv);
 }
 
-__global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ Gfull,
-                                                     sscg_block_params prm,
-                                                     double* __restrict__ coef,
-                                                     sscg_block_info* info, int* stop) {
-  __shared__ InnerLds L;
-  if (stop && *stop) return;
+// The coordinate solve of one block (one wave).  With stop != NULL a block
+// that cannot take a single step sets *stop = 3.
+__device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
+                           const sscg_block_params& prm, double* __restrict__ coef,
+                           sscg_block_info* info, int* stop) {
   const int a = threadIdx.x;
   const int s = prm.s, first = prm.first;
   const int dfull = first ? s + 1 : 2 * s + 1;
@@ -383,6 +387,15 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ 
   }
 }
 
+__global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ Gfull,
+                                                     sscg_block_params prm,
+                                                     double* __restrict__ coef,
+                                                     sscg_block_info* info, int* stop) {
+  __shared__ InnerLds L;
+  if (stop && *stop) return;
+  inner_body(L, Gfull, prm, coef, info, stop);
+}
+
 // Decisions of a block that ran speculatively (s~ = s, no break): eq. condy
 // from the kappa list (same prefix rule and operations as k_inner), then
 // eq. check at every iteration before the last from the recorded
@@ -424,6 +437,85 @@ __global__ void k_validate(const double* __restrict__ Gfull, sscg_block_params p
   if (!ok) *stop = 2;
 }
 
+
+// ---------------------------------------------------------------- batches
+
+// Sizes of this block per system: s_bar_k (Alg. 4), the rank guard, and the
+// coordinate-solve parameters.
+__global__ void k_batch_plan(BatchCfg c) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= c.nsys) return;
+  BatchSys& sy = c.sys[q];
+  if (sy.done) return;
+  int s_bar, s;
+  if (c.mode == SSCG_MODE_FIXED) {
+    s_bar = s = c.fixed_s;
+  } else if (sy.first) {
+    s_bar = s = c.s0;
+  } else {
+    s_bar = min(sy.s_prev + c.f, c.s_max);
+    s = min(s_bar, max(sy.m, 1));
+  }
+  s = min(s, c.S);
+  sy.s_bar = s_bar;
+  sscg_block_params prm;
+  prm.s = s;
+  prm.first = sy.first;
+  prm.adaptive = c.mode == SSCG_MODE_ADAPTIVE ? 1 : 0;
+  prm.iters = s;
+  prm.inner_check = c.inner_check;
+  prm.basis = c.basis;
+  prm.lambda_min = sy.lmin;
+  prm.lambda_max = sy.lmax;
+  prm.eps_star = sy.eps_star;
+  prm.c = c.c;
+  c.prm[q] = prm;
+}
+
+// grid (s_max, systems): kappa(G_i) of system blockIdx.y, i = blockIdx.x + 1.
+__global__ __launch_bounds__(JT) void k_kappa_batch(BatchCfg c) {
+  __shared__ JacobiLds L;
+  const int q = blockIdx.y, i = blockIdx.x + 1;
+  if (c.sys[q].done) return;
+  const sscg_block_params prm = c.prm[q];
+  if (!prm.adaptive || i > prm.s) return;
+  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
+  kappa_body(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
+}
+
+// Coordinate solve of system blockIdx.x, then the block's commit.
+__global__ __launch_bounds__(SSCG_WAVE) void k_inner_batch(BatchCfg c) {
+  __shared__ InnerLds L;
+  const int q = blockIdx.x;
+  BatchSys& sy = c.sys[q];
+  if (sy.done) return;
+  const sscg_block_params prm = c.prm[q];
+  sscg_block_info* info = c.info + q;
+  inner_body(L, c.G + (int64_t)q * BATCH_GSZ, prm, c.coef + (int64_t)q * BATCH_CSZ, info,
+             nullptr);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int s_k = info->s_k;
+    if (sy.blocks < c.cap) {
+      BatchHist& h = c.hist[(int64_t)q * c.cap + sy.blocks];
+      h.s_bar = sy.s_bar;
+      h.s_built = prm.s;
+      h.s_tilde = info->s_tilde;
+      h.s_k = s_k;
+      h.relres_true = __builtin_nan("");
+    }
+    if (s_k == 0) {  // no step possible: x stays, the system stops
+      sy.done = 1;
+      sy.status = SSCG_BREAKDOWN;
+    } else {
+      sy.m += s_k;
+      sy.s_prev = s_k;
+      sy.blocks += 1;
+      sy.first = 0;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_info* info,
@@ -447,5 +539,20 @@ hipError_t launch_validate(const double* G, const sscg_block_params& prm, sscg_b
 hipError_t launch_tridiag_eig(const double* alpha, const double* beta, int k, double* lmin,
                               double* lmax, hipStream_t st) {
   hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(JT), 0, st, alpha, beta, k, lmin, lmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_plan, dim3((c.nsys + 63) / 64), dim3(64), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_kappa_batch, dim3(c.S, c.nsys), dim3(JT), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_batch(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_inner_batch, dim3(c.nsys), dim3(SSCG_WAVE), 0, st, c);
   return hipGetLastError();
 }

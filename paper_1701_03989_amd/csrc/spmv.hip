@@ -77,7 +77,7 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
                                                   const double* __restrict__ val, int n,
                                                   const double* __restrict__ scale,
                                                   const int64_t* __restrict__ off, int nslices,
-                                                  int32_t* __restrict__ scol,
+                                                  int col_off, int32_t* __restrict__ scol,
                                                   double* __restrict__ sval) {
   int row = blockIdx.x * WG + threadIdx.x;
   int slice = row / SSCG_WAVE;
@@ -98,10 +98,10 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
       int c = col[k0 + j];
       double v = val[k0 + j];
       if (scale) v = (v * si) * scale[c];
-      scol[dst] = c;
+      scol[dst] = c + col_off;
       sval[dst] = v;
     } else {
-      scol[dst] = row < n ? row : 0;
+      scol[dst] = (row < n ? row : 0) + col_off;
       sval[dst] = 0.0;
     }
   }
@@ -120,17 +120,13 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
 // The gate: the pass does nothing once the solve has stopped.
 __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 
+// The rows of one slice (lane = row within it); returns the lane's res_i^2
+// contribution when RES.
 template <int NRHS, bool CHEB, bool HASW, bool RES>
-__global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
-                                            MpkSeq s0, MpkSeq s1, Gate gate,
-                                            const double* __restrict__ xres,
-                                            const double* __restrict__ bres,
-                                            double* __restrict__ rpart) {
-  if (gate_closed(gate)) return;
-  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
-  int lb = xcd_block(nb);
-  if (lb >= nb) return;
-  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+__device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
+                                        double gamma, const MpkSeq& s0, const MpkSeq& s1,
+                                        const double* __restrict__ xres,
+                                        const double* __restrict__ bres) {
   int lane = threadIdx.x & (SSCG_WAVE - 1);
   int row = slice * SSCG_WAVE + lane;
   dd r2 = dd_zero();
@@ -191,6 +187,48 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
       }
     }
   }
+  return r2;
+}
+
+template <int NRHS, bool CHEB, bool HASW, bool RES>
+__global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
+                                            MpkSeq s0, MpkSeq s1, Gate gate,
+                                            const double* __restrict__ xres,
+                                            const double* __restrict__ bres,
+                                            double* __restrict__ rpart) {
+  if (gate_closed(gate)) return;
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+  if (RES) wg_store_partial(r2, rpart, lb);
+}
+
+// Batched pass j: every 256-row block belongs to one system (blk_sys), whose
+// basis parameters and state come from the system table; blocks of finished
+// systems (or of no system, -1) return at once.
+template <int NRHS, bool CHEB, bool RES>
+__global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, MpkSeq s1,
+                                                  const BatchSys* __restrict__ sys,
+                                                  const int32_t* __restrict__ blk_sys,
+                                                  const double* __restrict__ xres,
+                                                  const double* __restrict__ bres,
+                                                  double* __restrict__ rpart) {
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  const int q = blk_sys[lb];
+  if (q < 0 || sys[q].done) return;
+  const BasisPrm bp = sys[q].bp;
+  const double theta = CHEB ? bp.c0 : 0.0, sigma = CHEB ? bp.h2 : 0.0;
+  const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  dd r2;
+  if (j >= 2)
+    r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+  else
+    r2 = mpk_slice<NRHS, CHEB, false, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
 }
 
@@ -347,7 +385,42 @@ hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
   int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
   int threads = nslices * SSCG_WAVE;
   hipLaunchKernelGGL(k_sell_fill, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr, col, val,
-                     n, scale, off, nslices, scol, sval);
+                     n, scale, off, nslices, 0, scol, sval);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32_t* width,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_widths, dim3(wg_count(nslices)), dim3(WG), 0, st, rowptr, n, nslices,
+                     width);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const double* val,
+                                int n, int nslices, const int64_t* off, int col_off, int32_t* scol,
+                                double* sval, hipStream_t st) {
+  int threads = nslices * SSCG_WAVE;
+  hipLaunchKernelGGL(k_sell_fill, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr, col, val,
+                     n, (const double*)nullptr, off, nslices, col_off, scol, sval);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
+                            const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
+                            hipStream_t st) {
+  dim3 grid(xcd_grid(wg_count(A.nslices)));
+  const bool r = res.x != nullptr;
+#define SSCG_MPK_BATCH(N, C, R)                                                                 \
+  hipLaunchKernelGGL((k_mpk_batch<N, C, R>), grid, dim3(WG), 0, st, A, j, s0, s1, sys, blk_sys, \
+                     res.x, res.b, res.part)
+  if (nrhs == 2) {
+    if (cheb) { if (r) SSCG_MPK_BATCH(2, true, true); else SSCG_MPK_BATCH(2, true, false); }
+    else { if (r) SSCG_MPK_BATCH(2, false, true); else SSCG_MPK_BATCH(2, false, false); }
+  } else {
+    if (cheb) { if (r) SSCG_MPK_BATCH(1, true, true); else SSCG_MPK_BATCH(1, true, false); }
+    else { if (r) SSCG_MPK_BATCH(1, false, true); else SSCG_MPK_BATCH(1, false, false); }
+  }
+#undef SSCG_MPK_BATCH
   return hipGetLastError();
 }
 

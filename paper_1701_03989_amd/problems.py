@@ -151,7 +151,8 @@ def graph_laplacian(n: int, seed: int, avg_degree: int = 8, wlo: float = 0.1,
     i, j = i[keep], j[keep]
     lo = np.minimum(i, j)
     hi = np.maximum(i, j)
-    key = np.unique(lo.astype(np.int64) * n + hi)[:m]
+    key = np.unique(lo.astype(np.int64) * n + hi)
+    key = np.sort(rng.permutation(key)[:m])  # m distinct edges, uniformly among the drawn
     lo = key // n
     hi = key % n
     w = rng.uniform(wlo, whi, size=key.size)
@@ -187,3 +188,55 @@ def poisson3d_128_system(seed: int = 0, N: int = 128):
     A = poisson3d(N)
     b = uniform(A.n, seed)
     return A, b, np.zeros(A.n)
+
+
+@dataclass
+class BatchSystem:
+    """One system of a batch: A x = b from x_1 = 0, with a Chebyshev interval
+    [lmin, lmax] that contains the spectrum of A."""
+    A: CSR
+    b: np.ndarray
+    lmin: float
+    lmax: float
+    kind: str
+
+
+def poisson_interval(N: int, dim: int) -> tuple[float, float]:
+    """Extreme eigenvalues of the Dirichlet Poisson matrix on N^dim points (a
+    sum of dim copies of tridiag(-1, 2, -1), whose eigenvalues are
+    4 sin^2(k pi / (2(N+1)))): 4*dim*sin^2(pi / (2(N+1))) and
+    4*dim*cos^2(pi / (2(N+1)))."""
+    t = np.pi / (2 * (N + 1))
+    return 4 * dim * np.sin(t) ** 2, 4 * dim * np.cos(t) ** 2
+
+
+def batch_systems(count: int, seed: int = 0, nlo: float = 1e3, nhi: float = 2e5):
+    """A batch of uneven SPD systems: sizes n_i = round(exp(U[ln nlo, ln nhi]));
+    even i: Dirichlet Poisson, alternating 2-D (N = round(sqrt n_i)) and 3-D
+    (N = round(cbrt n_i)), interval in closed form; odd i: graph Laplacian of
+    n_i nodes with 4 n_i distinct edges (average degree 8), weights U[0.1, 1],
+    plus delta*I with delta = 1e-3 * (max weighted degree), interval
+    [delta, Gershgorin bound 2 * max degree + delta].  b ~ U[-1, 1] with seed
+    seed + 1000 + i; the graph of system i uses seed + i."""
+    rng = np.random.default_rng(seed)
+    sizes = np.round(np.exp(rng.uniform(np.log(nlo), np.log(nhi), size=count))).astype(np.int64)
+    out = []
+    for i, ni in enumerate(sizes):
+        if i % 2 == 0:
+            if (i // 2) % 2 == 0:
+                N = max(2, int(round(np.sqrt(ni))))
+                A, (lo, hi), kind = poisson2d(N), poisson_interval(N, 2), f"poisson2d_{N}"
+            else:
+                N = max(2, int(round(np.cbrt(ni))))
+                A, (lo, hi), kind = poisson3d(N), poisson_interval(N, 3), f"poisson3d_{N}"
+        else:
+            A = graph_laplacian(int(ni), seed + i)
+            rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+            on = rows == A.col
+            diag = np.zeros(A.n)
+            diag[rows[on]] = A.val[on]
+            deg = np.bincount(rows[~on], weights=np.abs(A.val[~on]), minlength=A.n)
+            # L + delta I: spectrum in [delta, max_i (2 deg_i + delta)] (Gershgorin)
+            lo, hi, kind = float(np.min(diag - deg)), float(np.max(diag + deg)), f"graph_{A.n}"
+        out.append(BatchSystem(A, uniform(A.n, seed + 1000 + i), float(lo), float(hi), kind))
+    return out

@@ -60,6 +60,18 @@ class Result(ctypes.Structure):
                 ("spec_blocks", ctypes.c_int32), ("spec_rejected", ctypes.c_int32)]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [("nsys", ctypes.c_int32), ("A", ctypes.POINTER(Csr)),
+                ("b", ctypes.POINTER(ctypes.c_void_p)), ("x", ctypes.POINTER(ctypes.c_void_p)),
+                ("tol", _dp), ("lambda_min", _dp), ("lambda_max", _dp)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int32), ("status", _ip), ("blocks", _ip), ("iters", _ip),
+                ("relres", _dp), ("s_k", _ip), ("s_tilde", _ip), ("relres_true", _dp),
+                ("graph_launches", ctypes.c_int32), ("rows", ctypes.c_int32)]
+
+
 class BlockInfo(ctypes.Structure):
     _fields_ = [("s_tilde", ctypes.c_int32), ("s_k", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("gamma", ctypes.c_double), ("thr", ctypes.c_double),
@@ -102,6 +114,8 @@ EXPORTS = {
     "sscg_recover": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sscg_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch),
+                                        ctypes.POINTER(Opts), ctypes.POINTER(BatchResult)]),
     "sscg_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sscg_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
@@ -257,6 +271,61 @@ def sscg_solve(ctx: int, A: DeviceCsr, b, x, opts: Opts, hist: History | None = 
     c = A.cstruct()
     rc = lib().sscg_solve(ctx, ctypes.byref(c), _f64(b), _f64(x), ctypes.byref(opts),
                           ctypes.byref(hist.res) if hist is not None else None)
+    return _check(ctx, rc)
+
+
+class BatchHistory:
+    """Host arrays receiving the per-system outputs of a batched solve."""
+
+    def __init__(self, nsys: int, cap: int):
+        self.nsys, self.cap = nsys, cap
+        self.status = np.zeros(nsys, np.int32)
+        self.blocks = np.zeros(nsys, np.int32)
+        self.iters = np.zeros(nsys, np.int32)
+        self.relres = np.full(nsys, np.nan)
+        self.s_k = np.zeros(nsys * cap, np.int32)
+        self.s_tilde = np.zeros(nsys * cap, np.int32)
+        self.relres_true = np.full(nsys * cap, np.nan)
+        r = self.res = BatchResult()
+        r.cap = cap
+        r.status = self.status.ctypes.data_as(_ip)
+        r.blocks = self.blocks.ctypes.data_as(_ip)
+        r.iters = self.iters.ctypes.data_as(_ip)
+        r.relres = self.relres.ctypes.data_as(_dp)
+        r.s_k = self.s_k.ctypes.data_as(_ip)
+        r.s_tilde = self.s_tilde.ctypes.data_as(_ip)
+        r.relres_true = self.relres_true.ctypes.data_as(_dp)
+
+    def schedule(self, i: int):
+        return self.s_k[i * self.cap:i * self.cap + min(int(self.blocks[i]), self.cap)].tolist()
+
+
+def sscg_batch_solve(ctx: int, systems, bs, xs, opts: Opts, tol=None, lambda_min=None,
+                     lambda_max=None, hist: BatchHistory | None = None) -> int:
+    """Solve the systems (DeviceCsr list) with right-hand sides bs and iterates
+    xs (CUDA float64 tensors; x_1 in, solution out) side by side.  tol and the
+    Chebyshev intervals are optional per-system sequences.  Waits for the
+    device; returns the worst per-system status."""
+    import torch
+
+    torch.cuda.current_stream().synchronize()
+    n = len(systems)
+    A = (Csr * n)(*[S.cstruct() for S in systems])
+    b = (ctypes.c_void_p * n)(*[_f64(t) for t in bs])
+    x = (ctypes.c_void_p * n)(*[_f64(t) for t in xs])
+    keep = []
+
+    def darr(v):
+        if v is None:
+            return None
+        a = np.ascontiguousarray(v, dtype=np.float64)
+        assert a.size == n
+        keep.append(a)
+        return a.ctypes.data_as(_dp)
+
+    B = Batch(n, A, b, x, darr(tol), darr(lambda_min), darr(lambda_max))
+    rc = lib().sscg_batch_solve(ctx, ctypes.byref(B), ctypes.byref(opts),
+                                ctypes.byref(hist.res) if hist is not None else None)
     return _check(ctx, rc)
 
 

@@ -1,0 +1,157 @@
+"""Batched solves (sscg_batch_solve) against the CPU oracle and against the
+single-system path, through the C ABI.
+
+Every system of a batch must give what the oracle gives for it alone (same
+s_k schedule, iterates within 1e-12 relative, same status), and the same bits
+as sscg_solve on that system alone and as a batch of one: a system's result
+does not depend on the rest of the batch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import sstep  # noqa: E402
+from paper_1701_03989_amd import problems, sscg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = sscg.sscg_create(0)
+    yield h
+    sscg.sscg_destroy(h)
+
+
+def dvec(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
+
+
+def run_batch(ctx, systems, x1s=None, tols=None, cap=512, **kw):
+    devA = [sscg.DeviceCsr.from_host(s.A, DEV) for s in systems]
+    bs = [dvec(s.b) for s in systems]
+    xs = [dvec(np.zeros(s.A.n) if x1s is None else x1s[i]) for i, s in enumerate(systems)]
+    hist = sscg.BatchHistory(len(systems), cap)
+    cheb = kw.get("basis") == "chebyshev"
+    rc = sscg.sscg_batch_solve(ctx, devA, bs, xs, sscg.make_opts(**kw), tol=tols,
+                               lambda_min=[s.lmin for s in systems] if cheb else None,
+                               lambda_max=[s.lmax for s in systems] if cheb else None, hist=hist)
+    torch.cuda.synchronize()
+    return rc, [x.cpu().numpy() for x in xs], hist
+
+
+def oracle_opts(kw, s, tol=None):
+    o = dict(kw)
+    if o.get("basis") == "chebyshev":
+        o["lmin"], o["lmax"] = s.lmin, s.lmax
+    if tol is not None:
+        o["tol"] = tol
+    return sstep.Opts(**o)
+
+
+CASES = [
+    dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10),
+    dict(mode="adaptive", s_max=6, tol=1e-10, s0_bar=2, f=1),
+    dict(mode="fixed", fixed_s=4, s_max=8, tol=1e-10),
+    dict(mode="adaptive", s_max=8, tol=1e-10, inner_check=False, c=10.0),
+]
+
+
+@pytest.mark.parametrize("k", range(len(CASES)))
+def test_batch_matches_oracle_and_single_path(ctx, k):
+    kw = CASES[k]
+    systems = problems.batch_systems(6, seed=1 + k, nlo=100, nhi=3000)
+    say(f"batch {kw}: {[s.kind for s in systems]}")
+    rc, xs, hist = run_batch(ctx, systems, **kw)
+    say(f"  status {hist.status.tolist()} blocks {hist.blocks.tolist()} "
+        f"replays {hist.res.graph_launches} rows {hist.res.rows}")
+    for i, s in enumerate(systems):
+        ref = sstep.solve(s.A, s.b, np.zeros(s.A.n), oracle_opts(kw, s))
+        sched = hist.schedule(i)
+        assert int(hist.status[i]) == ref.status, (i, hist.status[i], ref.status)
+        assert sched == ref.schedule, (i, sched[:12], ref.schedule[:12])
+        err = np.linalg.norm(xs[i] - ref.x) / np.linalg.norm(ref.x)
+        assert err <= 1e-12, (i, err)
+        # the single-system path: the same bits
+        single_kw = dict(kw)
+        if kw.get("basis") == "chebyshev":
+            single_kw.update(lmin=s.lmin, lmax=s.lmax)
+        x = dvec(np.zeros(s.A.n))
+        h1 = sscg.History(512, kw.get("s_max", 8))
+        rc1 = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b), x,
+                              sscg.make_opts(**single_kw), h1)
+        assert rc1 == int(hist.status[i]) and h1.schedule == sched
+        assert np.array_equal(x.cpu().numpy(), xs[i]), i
+    assert rc == max(int(v) for v in hist.status)
+
+
+def test_batch_result_independent_of_the_mix(ctx):
+    """Each system alone (a batch of one) and in the mix: identical bits."""
+    kw = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    systems = problems.batch_systems(5, seed=11, nlo=200, nhi=2000)
+    say("mix vs alone")
+    _, xs, hist = run_batch(ctx, systems, **kw)
+    for i, s in enumerate(systems):
+        _, x1, h1 = run_batch(ctx, [s], **kw)
+        assert h1.schedule(0) == hist.schedule(i)
+        assert np.array_equal(x1[0], xs[i]), i
+
+
+def test_batch_per_system_tolerances_and_degenerate_systems(ctx):
+    kw = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    systems = problems.batch_systems(4, seed=21, nlo=200, nhi=1500)
+    tols = [1e-6, 1e-8, 1e-10, 1e-12]
+    x1s = [np.zeros(s.A.n) for s in systems]
+    # system 1: zero right-hand side; system 2: x_1 already solves it exactly
+    systems[1].b = np.zeros(systems[1].A.n)
+    xt = problems.uniform(systems[2].A.n, 5)
+    x1s[2] = xt
+    systems[2].b = systems[2].A.matvec(xt)
+    say("tolerances / degenerate")
+    rc, xs, hist = run_batch(ctx, systems, x1s=x1s, tols=tols, **kw)
+    assert rc == sscg.OK and all(int(v) == sscg.OK for v in hist.status)
+    assert np.all(xs[1] == 0.0) and hist.blocks[1] == 0
+    for i in (0, 3):
+        s = systems[i]
+        ref = sstep.solve(s.A, s.b, np.zeros(s.A.n), oracle_opts(kw, s, tol=tols[i]))
+        assert hist.schedule(i) == ref.schedule
+        assert np.linalg.norm(xs[i] - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+        assert hist.relres[i] <= tols[i]
+    ref = sstep.solve(systems[2].A, systems[2].b, xt, oracle_opts(kw, systems[2], tol=tols[2]))
+    assert hist.blocks[2] == len(ref.blocks) and np.array_equal(xs[2], ref.x)
+
+
+def test_batch_iteration_cap(ctx):
+    kw = dict(mode="adaptive", basis="chebyshev", s_max=4, tol=1e-14, max_iters=9)
+    systems = problems.batch_systems(3, seed=31, nlo=500, nhi=2000)
+    rc, xs, hist = run_batch(ctx, systems, **kw)
+    for i, s in enumerate(systems):
+        ref = sstep.solve(s.A, s.b, np.zeros(s.A.n), oracle_opts(kw, s))
+        assert int(hist.status[i]) == ref.status == sscg.NOT_CONVERGED
+        assert hist.schedule(i) == ref.schedule and int(hist.iters[i]) == sum(ref.schedule)
+        assert np.linalg.norm(xs[i] - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+def test_batch_argument_errors(ctx):
+    systems = problems.batch_systems(2, seed=41, nlo=100, nhi=300)
+    with pytest.raises(sscg.SscgError):
+        run_batch(ctx, systems, mode="schedule", schedule=[2])
+    with pytest.raises(sscg.SscgError):
+        run_batch(ctx, systems, equilibrate=True)
+    devA = [sscg.DeviceCsr.from_host(s.A, DEV) for s in systems]
+    with pytest.raises(sscg.SscgError):  # Chebyshev without intervals
+        sscg.sscg_batch_solve(ctx, devA, [dvec(s.b) for s in systems],
+                              [dvec(np.zeros(s.A.n)) for s in systems],
+                              sscg.make_opts(basis="chebyshev"))
