@@ -209,12 +209,112 @@ def cpu_baseline(A, b, x1, wl, gpu_blocks, budget_s=20.0):
     }
 
 
+def bench_batch(args) -> None:
+    """The batch workload: uneven SPD systems (half Dirichlet Poisson 2-D/3-D,
+    half shifted random graph Laplacians, sizes log-uniform in [1e3, 2e5]),
+    adaptive s-step CG with the Chebyshev basis on each system's interval,
+    s_max = 8, relres <= 1e-10 each.  A step is one batched solve of all
+    systems (sscg_batch_solve); the same systems solved one at a time with
+    sscg_solve are timed beside it (same algorithm, same FP64 results)."""
+    import torch
+
+    from paper_1701_03989_amd import problems, sscg
+
+    t0 = time.perf_counter()
+    systems = problems.batch_systems(args.batch_count, seed=0)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    devA = [sscg.DeviceCsr.from_host(s.A, dev) for s in systems]
+    bs = [torch.as_tensor(s.b, device=dev) for s in systems]
+    xs = [torch.zeros(s.A.n, dtype=torch.float64, device=dev) for s in systems]
+    lmin = [s.lmin for s in systems]
+    lmax = [s.lmax for s in systems]
+    opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    ctx = sscg.sscg_create(0)
+    hist = sscg.BatchHistory(len(systems), 4096)
+
+    def batched():
+        for x in xs:
+            x.zero_()
+        rc = sscg.sscg_batch_solve(ctx, devA, bs, xs, opts, lambda_min=lmin, lambda_max=lmax,
+                                   hist=hist)
+        assert rc == sscg.OK, f"batch status {rc}"
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        batched()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # accuracy: true relative residuals recomputed in FP64 on the host
+    worst = 0.0
+    for s, x in zip(systems, xs):
+        xh = x.cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(s.b - s.A.matvec(xh)) / np.linalg.norm(s.b)))
+    blocks = hist.blocks.copy()
+    # one at a time (same systems, same options, same results)
+    h1 = sscg.History(4096, 8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for A_, b_, x_, s in zip(devA, bs, xs, systems):
+        x_.zero_()
+        o1 = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10,
+                            lmin=s.lmin, lmax=s.lmax)
+        rc = sscg.sscg_solve(ctx, A_, b_, x_, o1, h1)
+        assert rc == sscg.OK
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    sscg.sscg_destroy(ctx)
+    nsys = len(systems)
+    rows = sum(s.A.n for s in systems)
+    nnz = sum(s.A.nnz for s in systems)
+    out = {
+        "metric": "batched solves/s (systems per second) + p99 latency of a batch at relres<=1e-10",
+        "value": nsys * args.steps / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch256: {nsys} SPD systems, rows log-uniform [1e3, 2e5] (total {rows}, "
+                        f"nnz {nnz}), half Dirichlet Poisson 2-D/3-D, half graph Laplacians + "
+                        f"1e-3*maxdeg*I, b~U[-1,1], x1=0",
+            "method": "adaptive s-step CG (Alg. 4), batched launches, one block per graph replay",
+            "basis": "chebyshev", "s_max": 8, "tol": 1e-10,
+        },
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "worst_relres": worst,
+        "max_blocks": int(blocks.max()),
+        "graph_replays": int(hist.res.graph_launches),
+        "sequential_solves_per_s": nsys / t_seq,
+        "speedup_vs_sequential": (nsys * args.steps / wall) / (nsys / t_seq),
+        "generation_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="poisson3d_128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="poisson3d_128",
+                    choices=sorted(WORKLOADS) + ["batch256"])
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="batch256 workload: number of systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -240,6 +340,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": x.numel() * 8, "copies": 5}))
+        return
+    if args.workload == "batch256" and args.gpus == 1:
+        bench_batch(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
