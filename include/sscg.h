@@ -260,6 +260,45 @@ typedef struct {
 int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* batch, const sscg_opts* opts,
                      sscg_batch_result* res);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A solve server: continuous batching of independent systems on one GPU.
+ * Requests are queued by sscg_server_submit and admitted first come, first
+ * served, as soon as a slot and room in the pools are free (admission by
+ * device-memory footprint: the request's SELL-64 matrix in the nnz pool and
+ * its rows, padded to 1024, in the row pool, which holds the 2 s_max + 3
+ * vectors of every row).  Each sscg_server_step runs one outer block for all
+ * admitted systems (the same batched launches as sscg_batch_solve, replayed
+ * from one HIP graph over the whole pool), retires finished systems (x is
+ * copied back to the caller's buffer before the step returns) and admits
+ * waiting ones; their work overlaps on the device.  Each result is the one
+ * sscg_solve gives for that system alone.  Options as for batches
+ * (MODE_SCHEDULE and equilibration are not supported). */
+typedef struct sscg_server sscg_server;
+
+/* pool_rows: rows of all admitted systems together (each padded to 1024);
+ * pool_nnz: SELL-64 entries of all admitted matrices; slots: admitted
+ * systems at once.  The server owns its device memory and a stream of its
+ * own; ctx must outlive it. */
+int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t pool_rows, int64_t pool_nnz,
+                       int32_t slots, sscg_server** server);
+void sscg_server_destroy(sscg_server* server);
+/* Queue A x = b (device arrays; b and x must stay valid until the request is
+ * done; x holds x_1).  tol <= 0: opts->tol; lambda_min/max: the Chebyshev
+ * interval (ignored for the monomial basis).  A request that could never fit
+ * the pools is refused (SSCG_ERR_ARG). */
+int sscg_server_submit(sscg_server* server, const sscg_csr* A, const double* b, double* x,
+                       double tol, double lambda_min, double lambda_max, int64_t* id);
+/* One outer block for every admitted system, then retirement and admission.
+ * Outputs (may be NULL): systems running, requests waiting, requests retired
+ * by this call. */
+int sscg_server_step(sscg_server* server, int32_t* running, int32_t* queued, int32_t* retired);
+/* state: 0 queued, 1 running, 2 done (x written).  The other outputs are
+ * valid once done; status as for sscg_solve (SSCG_ERR_ARG if its matrix was
+ * found malformed at admission). */
+int sscg_server_poll(sscg_server* server, int64_t id, int32_t* state, int32_t* status,
+                     int32_t* blocks, int32_t* iters, double* relres);
+
 /* ---------------------------------------------------------------- timing */
 
 /* Kernel timing with HIP events on the stream each kernel runs on (off by

@@ -148,10 +148,12 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
     scale = as<double>(ctx->scale);
   }
   HIPCHK(launch_sell_fill(A->rowptr, A->col, A->val, n, scale, as<int64_t>(ctx->off),
+                          as<int32_t>(ctx->width),
                           as<int32_t>(ctx->scol), as<double>(ctx->sval), ctx->stream));
   M->n = n;
   M->nslices = nslices;
   M->off = as<int64_t>(ctx->off);
+  M->width = as<int32_t>(ctx->width);
   M->col = as<int32_t>(ctx->scol);
   M->val = as<double>(ctx->sval);
   return SSCG_OK;

@@ -27,8 +27,20 @@ namespace {
 constexpr int CHUNK_ROWS = 1024;  // rows per Gram work item
 constexpr int GROUP = 4;          // blocks replayed between checks of the active count
 
+struct GraphGuard {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  ~GraphGuard() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
+}  // namespace
+
 // One outer block for every unfinished system (enqueued on st; capturable).
-int enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st) {
+int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c,
+                                   hipStream_t st) {
   HIPCHK(launch_batch_plan(c, st));
   const int cheb = c.basis == SSCG_BASIS_CHEBYSHEV;
   for (int j = 1; j <= c.S; ++j) {
@@ -50,17 +62,6 @@ int enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t
   HIPCHK(launch_batch_count(c, st));
   return SSCG_OK;
 }
-
-struct GraphGuard {
-  hipGraph_t g = nullptr;
-  hipGraphExec_t e = nullptr;
-  ~GraphGuard() {
-    if (e) (void)hipGraphExecDestroy(e);
-    if (g) (void)hipGraphDestroy(g);
-  }
-};
-
-}  // namespace
 
 extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_opts* opts,
                                 sscg_batch_result* res) {
@@ -173,13 +174,15 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
     const sscg_csr& A = B->A[q];
     const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
     HIPCHK(launch_sell_fill_off(A.rowptr, A.col, A.val, A.n, npad / SSCG_WAVE,
-                                off + hs[q].row0 / SSCG_WAVE, hs[q].row0, as<int32_t>(w.scol),
+                                off + hs[q].row0 / SSCG_WAVE, width + hs[q].row0 / SSCG_WAVE,
+                                hs[q].row0, as<int32_t>(w.scol),
                                 as<double>(w.sval), st));
   }
   DevMat M;
   M.n = N;
   M.nslices = nslices;
   M.off = off;
+  M.width = width;
   M.col = as<int32_t>(w.scol);
   M.val = as<double>(w.sval);
 
@@ -239,7 +242,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   // ---- one outer block as a graph, replayed
   GraphGuard gg;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  rc = enqueue_block(ctx, M, c, st);
+  rc = batch_enqueue_block(ctx, M, c, st);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(st, &graph);
   gg.g = graph;

@@ -90,7 +90,8 @@ __device__ __forceinline__ int xcd_block(int nb) {
 struct DevMat {
   int32_t n;
   int32_t nslices;
-  const int64_t* off;   // nslices + 1
+  const int64_t* off;     // start of each slice's entries
+  const int32_t* width;   // entries per row of each slice
   const int32_t* col;
   const double* val;
 };
@@ -135,11 +136,15 @@ hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, in
                             int32_t* flag, hipStream_t st);
 hipError_t launch_sell_widths(const int32_t* rowptr, int n, int32_t* width, hipStream_t st);
 hipError_t launch_scan_offsets(const int32_t* width, int nslices, int64_t* off, hipStream_t st);
+// off[i] = base + 64 * (width[0] + ... + width[i-1]) for i < nslices, the
+// total (base included) to *end.
+hipError_t launch_scan_offsets_base(const int32_t* width, int nslices, int64_t base, int64_t* off,
+                                    int64_t* end, hipStream_t st);
 hipError_t launch_row_scale(const int32_t* rowptr, const double* val, int n, double* scale,
                             hipStream_t st);
 hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const double* val, int n,
-                            const double* scale, const int64_t* off, int32_t* scol, double* sval,
-                            hipStream_t st);
+                            const double* scale, const int64_t* off, const int32_t* width,
+                            int32_t* scol, double* sval, hipStream_t st);
 
 // One matrix-powers pass: for each of nrhs (1 or 2) sequences v,
 // out = RN(A u - theta u - sigma w) / gamma_{j-1}, j >= 1 (w unused for j = 1).
@@ -301,14 +306,16 @@ __host__ __device__ inline double* batch_col(const BatchCfg& c, int col) {
 hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32_t* width,
                                 hipStream_t st);
 hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const double* val,
-                                int n, int nslices, const int64_t* off, int col_off, int32_t* scol,
-                                double* sval, hipStream_t st);
+                                int n, int nslices, const int64_t* off, const int32_t* width,
+                                int col_off, int32_t* scol, double* sval, hipStream_t st);
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
                             const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
                             hipStream_t st);
 // Set-up from the residual of x_1 (rpart) and ||b||^2 (bpart): relres0, eps*;
 // systems with b = 0 or relres0 <= tol are done before block 0.
 hipError_t launch_batch_init(const BatchCfg& c, hipStream_t st);
+// The same for systems [q0, q0 + count) only.
+hipError_t launch_batch_init_range(const BatchCfg& c, int q0, int count, hipStream_t st);
 // Sizes of this block per system (s_bar, rank guard) into prm.
 hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st);
 // Residual of each system's starting iterate; convergence / iteration cap.

@@ -121,4 +121,7 @@ int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, co
 // Gram of the block's basis into G (device, d x d).
 int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const int* stop);
 
+// One outer block of a batch for every unfinished system (capturable).
+int batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st);
+
 }  // namespace sscg_host

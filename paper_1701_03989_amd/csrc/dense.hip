@@ -325,8 +325,9 @@ __global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {
   int lb = xcd_block(c.nchunks);
   if (lb >= c.nchunks) return;
   const BatchChunk ch = c.chunks[lb];
-  if (c.sys[ch.sys].done) return;
-  const sscg_block_params prm = c.prm[ch.sys];
+  const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
+  if (q < 0 || c.sys[q].done) return;
+  const sscg_block_params prm = c.prm[q];
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
   gram_rows(batch_cols(c, prm.s, prm.first), d, ch.r0, ch.r1, c.gpart, c.nchunks, lb);
 }
@@ -368,8 +369,8 @@ __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
 }
 
 // Set-up per system from the residual and ||b||^2 partials of its blocks.
-__global__ __launch_bounds__(WG) void k_batch_init(BatchCfg c) {
-  const int q = blockIdx.x;
+__global__ __launch_bounds__(WG) void k_batch_init(BatchCfg c, int q0) {
+  const int q = q0 + blockIdx.x;
   BatchSys& sy = c.sys[q];
   dd r = reduce_parts(c.rpart + (int64_t)sy.blk0 * 2, sy.blk1 - sy.blk0);
   __syncthreads();
@@ -555,7 +556,12 @@ hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st) {
 }
 
 hipError_t launch_batch_init(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_init, dim3(c.nsys), dim3(WG), 0, st, c);
+  hipLaunchKernelGGL(k_batch_init, dim3(c.nsys), dim3(WG), 0, st, c, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init_range(const BatchCfg& c, int q0, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_init, dim3(count), dim3(WG), 0, st, c, q0);
   return hipGetLastError();
 }
 

@@ -36,7 +36,9 @@ __global__ __launch_bounds__(WG) void k_sell_widths(const int32_t* __restrict__ 
 
 // Exclusive scan of 64*width into off[0..nslices]; one workgroup of 1024.
 __global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict__ width,
-                                                       int nslices, int64_t* __restrict__ off) {
+                                                       int nslices, int64_t base0,
+                                                       int64_t* __restrict__ off,
+                                                       int64_t* __restrict__ end) {
   __shared__ int64_t part[1024];
   int t = threadIdx.x;
   int per = (nslices + 1023) / 1024;
@@ -51,12 +53,12 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict
     part[t] += v;
     __syncthreads();
   }
-  int64_t base = part[t] - s;  // exclusive prefix of this thread's chunk
+  int64_t base = base0 + part[t] - s;  // exclusive prefix of this thread's chunk
   for (int i = lo; i < hi; ++i) {
     off[i] = base;
     base += (int64_t)width[i] * SSCG_WAVE;
   }
-  if (t == 1023) off[nslices] = part[1023];
+  if (t == 1023) *end = base0 + part[1023];
 }
 
 // s_i = 1 / sqrt(max_j |a_ij|) (equilibration, Section 5).
@@ -76,7 +78,8 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
                                                   const int32_t* __restrict__ col,
                                                   const double* __restrict__ val, int n,
                                                   const double* __restrict__ scale,
-                                                  const int64_t* __restrict__ off, int nslices,
+                                                  const int64_t* __restrict__ off,
+                                                  const int32_t* __restrict__ width, int nslices,
                                                   int col_off, int32_t* __restrict__ scol,
                                                   double* __restrict__ sval) {
   int row = blockIdx.x * WG + threadIdx.x;
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
   if (slice >= nslices) return;
   int lane = row & (SSCG_WAVE - 1);
   int64_t o = off[slice];
-  int w = (int)((off[slice + 1] - o) / SSCG_WAVE);
+  int w = width[slice];
   int k0 = 0, len = 0;
   double si = 1.0;
   if (row < n) {
@@ -132,7 +135,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   dd r2 = dd_zero();
   if (slice < A.nslices) {
     int64_t o = A.off[slice] + lane;
-    int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    int w = A.width[slice];
     const double* __restrict__ u0 = s0.u;
     const double* __restrict__ u1 = s1.u;
     dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(WG) void k_residual(DevMat A, const double* __restr
   dd r2 = dd_zero(), b2 = dd_zero();
   if (slice < A.nslices) {
     int64_t o = A.off[slice] + lane;
-    int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    int w = A.width[slice];
     dd a = dd_zero();
 #pragma unroll 4
     for (int j = 0; j < w; ++j) {
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(WG) void k_gershgorin(DevMat A, double* __restrict_
   double m = 0.0;
   if (slice < A.nslices && row < A.n) {
     int64_t o = A.off[slice] + lane;
-    int w = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    int w = A.width[slice];
     dd a = dd_zero();
     for (int j = 0; j < w; ++j) dd_add(a, fabs(A.val[o + (int64_t)j * SSCG_WAVE]));
     m = dd_round(a);
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
   dd d = dd_zero();
   if (slice < A.nslices) {
     int64_t o = A.off[slice] + lane;
-    int wd = (int)((A.off[slice + 1] - A.off[slice]) / SSCG_WAVE);
+    int wd = A.width[slice];
     dd a = dd_zero();
     for (int j = 0; j < wd; ++j) {
       int64_t k = o + (int64_t)j * SSCG_WAVE;
@@ -369,7 +372,14 @@ hipError_t launch_sell_widths(const int32_t* rowptr, int n, int32_t* width, hipS
 }
 
 hipError_t launch_scan_offsets(const int32_t* width, int nslices, int64_t* off, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, width, nslices, off);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, width, nslices, (int64_t)0, off,
+                     off + nslices);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_offsets_base(const int32_t* width, int nslices, int64_t base, int64_t* off,
+                                    int64_t* end, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, width, nslices, base, off, end);
   return hipGetLastError();
 }
 
@@ -380,12 +390,12 @@ hipError_t launch_row_scale(const int32_t* rowptr, const double* val, int n, dou
 }
 
 hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const double* val, int n,
-                            const double* scale, const int64_t* off, int32_t* scol, double* sval,
-                            hipStream_t st) {
+                            const double* scale, const int64_t* off, const int32_t* width,
+                            int32_t* scol, double* sval, hipStream_t st) {
   int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
   int threads = nslices * SSCG_WAVE;
   hipLaunchKernelGGL(k_sell_fill, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr, col, val,
-                     n, scale, off, nslices, 0, scol, sval);
+                     n, scale, off, width, nslices, 0, scol, sval);
   return hipGetLastError();
 }
 
@@ -397,11 +407,11 @@ hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32
 }
 
 hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const double* val,
-                                int n, int nslices, const int64_t* off, int col_off, int32_t* scol,
-                                double* sval, hipStream_t st) {
+                                int n, int nslices, const int64_t* off, const int32_t* width,
+                                int col_off, int32_t* scol, double* sval, hipStream_t st) {
   int threads = nslices * SSCG_WAVE;
   hipLaunchKernelGGL(k_sell_fill, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr, col, val,
-                     n, (const double*)nullptr, off, nslices, col_off, scol, sval);
+                     n, (const double*)nullptr, off, width, nslices, col_off, scol, sval);
   return hipGetLastError();
 }
 

@@ -116,6 +116,16 @@ EXPORTS = {
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sscg_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch),
                                         ctypes.POINTER(Opts), ctypes.POINTER(BatchResult)]),
+    "sscg_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Opts), ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "sscg_server_destroy": (None, [ctypes.c_void_p]),
+    "sscg_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]),
+    "sscg_server_step": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
+    "sscg_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _ip, _ip, _ip, _ip,
+                                        _dp]),
     "sscg_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sscg_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
@@ -327,6 +337,49 @@ def sscg_batch_solve(ctx: int, systems, bs, xs, opts: Opts, tol=None, lambda_min
     rc = lib().sscg_batch_solve(ctx, ctypes.byref(B), ctypes.byref(opts),
                                 ctypes.byref(hist.res) if hist is not None else None)
     return _check(ctx, rc)
+
+
+def sscg_server_create(ctx: int, opts: Opts, pool_rows: int, pool_nnz: int, slots: int) -> int:
+    h = ctypes.c_void_p()
+    _check(ctx, lib().sscg_server_create(ctx, ctypes.byref(opts), pool_rows, pool_nnz, slots,
+                                         ctypes.byref(h)))
+    return h.value
+
+
+def sscg_server_destroy(server: int) -> None:
+    lib().sscg_server_destroy(server)
+
+
+def sscg_server_submit(ctx: int, server: int, A: DeviceCsr, b, x, tol: float = 0.0,
+                       lambda_min: float = 0.0, lambda_max: float = 1.0) -> int:
+    """Queue a request (b, x: CUDA float64 tensors kept alive by the caller
+    until it is done); returns its id.  Errors are reported through ctx."""
+    import torch
+
+    torch.cuda.current_stream().synchronize()
+    c = A.cstruct()
+    rid = ctypes.c_int64()
+    _check(ctx, lib().sscg_server_submit(server, ctypes.byref(c), _f64(b), _f64(x), tol,
+                                         lambda_min, lambda_max, ctypes.byref(rid)))
+    return rid.value
+
+
+def sscg_server_step(ctx: int, server: int) -> tuple[int, int, int]:
+    """One outer block for all admitted systems; returns (running, queued, retired)."""
+    run, q, ret = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, lib().sscg_server_step(server, ctypes.byref(run), ctypes.byref(q),
+                                       ctypes.byref(ret)))
+    return run.value, q.value, ret.value
+
+
+def sscg_server_poll(ctx: int, server: int, rid: int) -> dict:
+    st, status, blocks, iters = (ctypes.c_int32() for _ in range(4))
+    rel = ctypes.c_double()
+    _check(ctx, lib().sscg_server_poll(server, rid, ctypes.byref(st), ctypes.byref(status),
+                                       ctypes.byref(blocks), ctypes.byref(iters),
+                                       ctypes.byref(rel)))
+    return dict(state=st.value, status=status.value, blocks=blocks.value, iters=iters.value,
+                relres=rel.value)
 
 
 def sscg_residual(ctx: int, A: DeviceCsr, b, x, r, out2) -> int:

@@ -1,0 +1,149 @@
+"""The solve server (continuous batching) through the C ABI: every request's
+result must be the one sscg_solve gives for that system alone (same bits,
+schedule length and status), whatever else shares the device with it, however
+requests arrive, and however tight the pools are."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1701_03989_amd import problems, sscg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+KW = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = sscg.sscg_create(0)
+    yield h
+    sscg.sscg_destroy(h)
+
+
+def dvec(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
+
+
+def alone(ctx, s, tol):
+    x = dvec(np.zeros(s.A.n))
+    h = sscg.History(1024, 8)
+    kw = dict(KW, tol=tol, lmin=s.lmin, lmax=s.lmax)
+    rc = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b), x,
+                         sscg.make_opts(**kw), h)
+    return rc, x.cpu().numpy(), h.blocks
+
+
+class Client:
+    """Keeps every request's device buffers alive until it is checked."""
+
+    def __init__(self, ctx, srv):
+        self.ctx, self.srv, self.live = ctx, srv, {}
+
+    def submit(self, s, tol):
+        A = sscg.DeviceCsr.from_host(s.A, DEV)
+        b, x = dvec(s.b), dvec(np.zeros(s.A.n))
+        rid = sscg.sscg_server_submit(self.ctx, self.srv, A, b, x, tol, s.lmin, s.lmax)
+        self.live[rid] = (s, tol, A, b, x)
+        return rid
+
+    def step(self):
+        return sscg.sscg_server_step(self.ctx, self.srv)
+
+    def drain(self, limit=5000):
+        for _ in range(limit):
+            run, q, _ = self.step()
+            if run == 0 and q == 0:
+                return
+        raise AssertionError("server did not drain")
+
+    def check_all(self):
+        for rid, (s, tol, _, _, x) in self.live.items():
+            p = sscg.sscg_server_poll(self.ctx, self.srv, rid)
+            assert p["state"] == 2, (rid, p)
+            rc, xa, blocks = alone(self.ctx, s, tol)
+            assert p["status"] == rc and p["blocks"] == blocks, (rid, p, rc, blocks)
+            assert np.array_equal(x.cpu().numpy(), xa), (rid, s.kind)
+
+
+def make_server(ctx, rows=1 << 16, nnz=1 << 20, slots=64):
+    return sscg.sscg_server_create(ctx, sscg.make_opts(**KW), rows, nnz, slots)
+
+
+def test_server_results_equal_alone(ctx):
+    systems = problems.batch_systems(6, seed=51, nlo=200, nhi=4000)
+    srv = make_server(ctx)
+    try:
+        cl = Client(ctx, srv)
+        for s in systems:
+            cl.submit(s, 1e-10)
+        say("server: all at once", [s.kind for s in systems])
+        cl.drain()
+        cl.check_all()
+    finally:
+        sscg.sscg_server_destroy(srv)
+
+
+def test_server_staggered_arrivals_and_tolerances(ctx):
+    systems = problems.batch_systems(7, seed=61, nlo=200, nhi=4000)
+    tols = [1e-6, 1e-8, 1e-10, 1e-12, 1e-8, 1e-10, 1e-6]
+    srv = make_server(ctx)
+    try:
+        cl = Client(ctx, srv)
+        say("server: staggered")
+        order = iter(range(len(systems)))
+        for burst, steps in ((2, 3), (2, 2), (3, 1)):
+            for _ in range(burst):
+                i = next(order)
+                cl.submit(systems[i], tols[i])
+            for _ in range(steps):
+                cl.step()
+        cl.drain()
+        cl.check_all()
+        for rid, (s, tol, *_r) in cl.live.items():
+            assert sscg.sscg_server_poll(ctx, srv, rid)["relres"] <= tol
+    finally:
+        sscg.sscg_server_destroy(srv)
+
+
+def test_server_admission_waits_for_room(ctx):
+    """Pools that hold about one request at a time and two slots: requests
+    wait for room, all finish, results unchanged."""
+    systems = problems.batch_systems(5, seed=71, nlo=1500, nhi=3000)
+    npad = max((s.A.n + 1023) // 1024 * 1024 for s in systems)
+    srv = make_server(ctx, rows=npad + 1024, nnz=64 * max(s.A.nnz for s in systems), slots=2)
+    try:
+        cl = Client(ctx, srv)
+        for s in systems:
+            cl.submit(s, 1e-10)
+        say("server: tight pools")
+        seen_queue = False
+        for _ in range(5000):
+            run, q, _ = cl.step()
+            seen_queue |= q > 0 and run > 0
+            if run == 0 and q == 0:
+                break
+        assert seen_queue
+        cl.check_all()
+    finally:
+        sscg.sscg_server_destroy(srv)
+
+
+def test_server_refuses_what_never_fits(ctx):
+    s = problems.batch_systems(1, seed=81, nlo=5000, nhi=6000)[0]
+    srv = make_server(ctx, rows=2048, nnz=1 << 16, slots=4)
+    try:
+        with pytest.raises(sscg.SscgError):
+            Client(ctx, srv).submit(s, 1e-10)
+    finally:
+        sscg.sscg_server_destroy(srv)
