@@ -306,15 +306,148 @@ def bench_batch(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args) -> None:
+    """The serving workload: requests arrive as a Poisson process (rate
+    --serve-rate per second, --serve-requests of them, seeded gaps); each asks
+    for one SPD system drawn from a set of --serve-operators operators (sizes
+    log-uniform in [1e4, 4e6], half Dirichlet Poisson, half shifted graph
+    Laplacians), with its own right-hand side b ~ U[-1, 1] (seeded, drawn on the
+    device) and a tolerance drawn from {1e-6, 1e-8, 1e-10, 1e-12}.  The server
+    (continuous batching, admission by device-memory footprint) is timed from
+    the first arrival; latency = completion - arrival.  The same requests served
+    one at a time in arrival order by sscg_solve (FIFO, the measured solve
+    times) give the baseline."""
+    import torch
+
+    from paper_1701_03989_amd import problems, sscg
+
+    rng = np.random.default_rng(7)
+    t0 = time.perf_counter()
+    ops = problems.batch_systems(args.serve_operators, seed=100, nlo=1e4, nhi=4e6)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    devA = [sscg.DeviceCsr.from_host(s.A, dev) for s in ops]
+    nreq = args.serve_requests
+    arrive = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=nreq))
+    arrive -= arrive[0]
+    which = rng.integers(0, len(ops), size=nreq)
+    tols = rng.choice([1e-6, 1e-8, 1e-10, 1e-12], size=nreq)
+    gen = torch.Generator(device=dev)
+    bs = []
+    for i in range(nreq):
+        gen.manual_seed(1000 + i)
+        n = ops[which[i]].A.n
+        bs.append(torch.rand(n, dtype=torch.float64, device=dev, generator=gen) * 2.0 - 1.0)
+    xs = [torch.zeros_like(b) for b in bs]
+    opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    ctx = sscg.sscg_create(0)
+    rows_needed = sum(((ops[w].A.n + 1023) // 1024) * 1024 for w in which)
+    pool_rows = int(min(rows_needed, args.serve_pool_rows))
+    pool_nnz = int(12 * pool_rows)
+    srv = sscg.sscg_server_create(ctx, opts, pool_rows, pool_nnz, args.serve_slots)
+    torch.cuda.synchronize()
+    done_at = np.full(nreq, np.nan)
+    rid = {}
+    pending = set()
+    i = 0
+    steps = 0
+    start = time.perf_counter()
+    while i < nreq or pending:
+        now = time.perf_counter() - start
+        while i < nreq and arrive[i] <= now:
+            s = ops[which[i]]
+            r = sscg.sscg_server_submit(ctx, srv, devA[which[i]], bs[i], xs[i], float(tols[i]),
+                                        s.lmin, s.lmax)
+            rid[r] = i
+            pending.add(r)
+            i += 1
+        if not pending:
+            time.sleep(max(0.0, arrive[i] - (time.perf_counter() - start)))
+            continue
+        run, q, ret = sscg.sscg_server_step(ctx, srv)
+        steps += 1
+        if ret or (run == 0 and q == 0):
+            t = time.perf_counter() - start
+            for r in list(pending):
+                p = sscg.sscg_server_poll(ctx, srv, r)
+                if p["state"] == 2:
+                    assert p["status"] == sscg.OK, p
+                    done_at[rid[r]] = t
+                    pending.discard(r)
+    makespan = float(np.nanmax(done_at))
+    lat = done_at - arrive
+    sscg.sscg_server_destroy(srv)
+    # accuracy of every served result, recomputed in FP64 on the host
+    worst = 0.0
+    for k in range(nreq):
+        s = ops[which[k]]
+        b = bs[k].cpu().numpy()
+        x = xs[k].cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(b - s.A.matvec(x)) / np.linalg.norm(b) / tols[k]))
+    # one at a time, first come first served, with the measured solve times
+    h1 = sscg.History(8192, 8)
+    clock, seq_lat = 0.0, []
+    for k in range(nreq):
+        s = ops[which[k]]
+        xs[k].zero_()
+        o1 = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=float(tols[k]),
+                            lmin=s.lmin, lmax=s.lmax)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rc = sscg.sscg_solve(ctx, devA[which[k]], bs[k], xs[k], o1, h1)
+        d = time.perf_counter() - ts
+        assert rc == sscg.OK
+        clock = max(clock, arrive[k]) + d
+        seq_lat.append(clock - arrive[k])
+    sscg.sscg_destroy(ctx)
+    out = {
+        "metric": "served solves/s + p50/p99 latency (arrival to result) at per-request relres",
+        "value": nreq / makespan,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": makespan / max(steps, 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serve: {nreq} requests, Poisson arrivals {args.serve_rate}/s, "
+                        f"{len(ops)} operators of {sum(s.A.n for s in ops)} rows in total "
+                        f"(sizes log-uniform [1e4, 4e6]), tol in {{1e-6,1e-8,1e-10,1e-12}}",
+            "method": "continuous batching of adaptive s-step CG (Alg. 4), one outer block per "
+                      "step for all admitted systems",
+            "basis": "chebyshev", "s_max": 8, "pool_rows": pool_rows, "slots": args.serve_slots,
+        },
+        "offered_rate": args.serve_rate,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "worst_relres_over_tol": worst,
+        "sequential_solves_per_s": nreq / max(clock, 1e-9),
+        "sequential_p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
+        "sequential_p99_ms": float(np.percentile(seq_lat, 99) * 1e3),
+        "generation_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="poisson3d_128",
-                    choices=sorted(WORKLOADS) + ["batch256"])
+                    choices=sorted(WORKLOADS) + ["batch256", "serve"])
     ap.add_argument("--batch-count", type=int, default=256,
                     help="batch256 workload: number of systems")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrivals per second")
+    ap.add_argument("--serve-operators", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-pool-rows", type=int, default=96 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -343,6 +476,9 @@ def main():
         return
     if args.workload == "batch256" and args.gpus == 1:
         bench_batch(args)
+        return
+    if args.workload == "serve" and args.gpus == 1:
+        bench_serve(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "

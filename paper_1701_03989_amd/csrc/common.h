@@ -178,6 +178,7 @@ hipError_t launch_finalize(const double* part, int nparts, int count, double* ou
 // The d basis columns of a block in G's order [P_0..P_s, R_0..R_{s-1}].
 struct ColPtr {
   const double* c[2 * SSCG_S_LIMIT + 1];
+  __device__ __forceinline__ const double* at(int a) const { return c[a]; }
 };
 
 // Gram of the d columns; partials then the finalize.  stop may be NULL.

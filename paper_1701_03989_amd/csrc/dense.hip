@@ -21,7 +21,8 @@ constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 // Upper-triangle dd partials of the Gram matrix of columns cols[0..d) over
 // rows [rb, re): entry q (a <= b, row-major over the triangle) goes to
 // part[(q * nparts + slot) * 2].
-__device__ __forceinline__ void gram_rows(const ColPtr& cols, int d, int rb, int re,
+template <class Cols>
+__device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int re,
                                           double* __restrict__ part, int nparts, int slot) {
   __shared__ double tile[GT][MAXD + 1];
   const int npairs = d * (d + 1) / 2;
@@ -43,7 +44,7 @@ __device__ __forceinline__ void gram_rows(const ColPtr& cols, int d, int rb, int
     for (int e = threadIdx.x; e < GT * d; e += WG) {
       int a = e / GT, r = e - a * GT;
       int row = r0 + r;
-      tile[r][a] = row < re ? cols.c[a][row] : 0.0;
+      tile[r][a] = row < re ? cols.at(a)[row] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -152,7 +153,8 @@ __global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ 
 // x_i <- RN(x_i + sum_a Y_ia x'_a), r_i <- RN(sum_a Y_ia r'_a),
 // p_i <- RN(sum_a Y_ia p'_a) (eq. coords).  Columns whose three coefficients
 // are all zero contribute nothing to the exact sums and are not read.
-__device__ __forceinline__ void recover_row(const ColPtr& cols, int d,
+template <class Cols>
+__device__ __forceinline__ void recover_row(const Cols& cols, int d,
                                             const double* __restrict__ coef, int i,
                                             const double* x_in, double* x_out, double* r,
                                             double* p);
@@ -170,7 +172,8 @@ __global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
   recover_row(cols, d, coef, i, x_in, x_out, r, p);
 }
 
-__device__ __forceinline__ void recover_row(const ColPtr& cols, int d,
+template <class Cols>
+__device__ __forceinline__ void recover_row(const Cols& cols, int d,
                                             const double* __restrict__ coef, int i,
                                             const double* x_in, double* x_out, double* r,
                                             double* p) {
@@ -179,7 +182,7 @@ __device__ __forceinline__ void recover_row(const ColPtr& cols, int d,
   for (int a = 0; a < d; ++a) {
     double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
     if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
-    double y = cols.c[a][i];
+    double y = cols.at(a)[i];
     dd_add_prod(ax, y, cx);
     dd_add_prod(ar, y, cr);
     dd_add_prod(ap, y, cp);
@@ -309,16 +312,20 @@ __global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
 
 // ---------------------------------------------------------------- batches
 
-// Gram columns of system q in this block: P_0..P_s, then R_0..R_{s-1}.
-__device__ __forceinline__ ColPtr batch_cols(const BatchCfg& c, int s, int first) {
-  ColPtr cols;
-  const int d = first ? s + 1 : 2 * s + 1;
-  for (int a = 0; a < MAXD; ++a) {
-    int col = 0;
-    if (a < d) col = a <= s ? a : c.S + 1 + (a - s - 1);
-    cols.c[a] = batch_col(c, col);
+// Gram columns of a system in this block: P_0..P_s, then R_0..R_{s-1}; the
+// address is computed (an array of pointers would live in scratch memory).
+struct BatchCols {
+  double* Y;
+  int64_t ld;
+  int s, S;
+  __device__ __forceinline__ const double* at(int a) const {
+    return Y + (int64_t)(a <= s ? a : S + 1 + (a - s - 1)) * ld;
   }
-  return cols;
+};
+
+__device__ __forceinline__ BatchCols batch_cols(const BatchCfg& c, int s, int first) {
+  (void)first;  // block 0 uses P_0..P_s only: d = s + 1 never reaches the R columns
+  return BatchCols{c.Y, c.ld, s, c.S};
 }
 
 __global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {

@@ -27,6 +27,7 @@ using namespace sscg_host;
 namespace {
 
 constexpr int64_t ROW_UNIT = 1024;  // row allocation unit: one Gram chunk
+constexpr int NG = 8;               // graphs over the first 1/8, 2/8, ... of the row pool
 
 // First-fit allocator of ranges in [0, size).
 struct RangeAlloc {
@@ -86,8 +87,9 @@ struct sscg_server {
   BatchWs w;
   BatchCfg c;
   DevMat M;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[NG] = {};
+  hipGraphExec_t exec[NG] = {};
+  int64_t extent[NG] = {};  // rows covered by graph g
   RangeAlloc ra, na;
   std::vector<int> free_slots;
   std::vector<int64_t> slot_req;
@@ -109,8 +111,10 @@ namespace {
 void server_free(sscg_server* s) {
   if (!s) return;
   if (s->st) (void)hipStreamSynchronize(s->st);
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+  for (int g = 0; g < NG; ++g) {
+    if (s->exec[g]) (void)hipGraphExecDestroy(s->exec[g]);
+    if (s->graph[g]) (void)hipGraphDestroy(s->graph[g]);
+  }
   BatchWs& w = s->w;
   Buf* bufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag, &w.Y,       &w.x,
                  &w.b,     &w.sys,  &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,
@@ -355,17 +359,30 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   s->M.width = as<int32_t>(w.width);
   s->M.col = as<int32_t>(w.scol);
   s->M.val = as<double>(w.sval);
-  // one outer block over the whole pool, captured once
-  e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return bad(e);
-  rc = batch_enqueue_block(ctx, s->M, c, s->st);
-  e = hipStreamEndCapture(s->st, &s->graph);
-  if (rc) {
-    server_free(s);
-    return rc;
+  // one outer block over the first g/NG of the pool, captured once per g: a
+  // step replays the smallest one that covers every admitted system (the
+  // allocator is first-fit, so admitted rows stay low), so an idle tail of
+  // the pool costs no empty workgroups
+  for (int g = 0; g < NG; ++g) {
+    const int64_t ext = std::min(rows, ((rows * (g + 1) / NG) + ROW_UNIT - 1) / ROW_UNIT * ROW_UNIT);
+    s->extent[g] = ext;
+    BatchCfg cg = c;
+    cg.nblk = (int)(ext / BATCH_ROWS);
+    cg.nchunks = (int)(ext / ROW_UNIT);
+    DevMat Mg = s->M;
+    Mg.n = (int32_t)ext;
+    Mg.nslices = (int32_t)(ext / SSCG_WAVE);
+    e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bad(e);
+    rc = batch_enqueue_block(ctx, Mg, cg, s->st);
+    e = hipStreamEndCapture(s->st, &s->graph[g]);
+    if (rc) {
+      server_free(s);
+      return rc;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&s->exec[g], s->graph[g], nullptr, nullptr, 0);
+    if (e != hipSuccess) return bad(e);
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) return bad(e);
   s->ra.init(rows / ROW_UNIT);
   s->na.init(pool_nnz);
   s->slot_req.assign(slots, 0);
@@ -444,7 +461,15 @@ extern "C" int sscg_server_step(sscg_server* s, int32_t* running, int32_t* queue
   }
   // systems finished at set-up (b = 0 or x_1 converged) are retired by the next step
   if (s->running > 0) {
-    HIPCHK(hipGraphLaunch(s->exec, s->st));
+    int64_t hi = 0;
+    for (int q = 0; q < s->slots; ++q)
+      if (s->slot_req[q]) {
+        const Req& r = s->reqs[s->slot_req[q]];
+        hi = std::max(hi, r.row0 + r.npad);
+      }
+    int g = 0;
+    while (g < NG - 1 && s->extent[g] < hi) ++g;
+    HIPCHK(hipGraphLaunch(s->exec[g], s->st));
     HIPCHK(hipMemcpyAsync(s->hsys, s->c.sys, sizeof(BatchSys) * s->slots, hipMemcpyDeviceToHost,
                           s->st));
     HIPCHK(hipEventRecord(s->ev, s->st));
