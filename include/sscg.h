@@ -86,7 +86,22 @@ typedef struct {
   int32_t equilibrate;   /* 1: solve D^-1/2 A D^-1/2 (Section 5), D_i = max|a_ij| */
   int32_t inner_check;   /* 1: in-loop break of eq. check (Alg. 4); 0: s_k = s~   */
   int32_t max_iters;     /* cap on total inner iterations                         */
+  int32_t precision;     /* SSCG_PREC_FP64, or SSCG_PREC_MIXED (sscg_solve only):
+                            FP64 iterative refinement around FP32-basis solves    */
+  int32_t max_outer;     /* MIXED: cap on refinement steps (default 30)          */
+  double inner_tol;      /* MIXED: each inner solve reduces its residual by this
+                            factor (default 1e-5)                                  */
 } sscg_opts;
+
+/* Precision of sscg_solve.  MIXED: x_{j+1} = x_j + d_j, r_j = b - A x_j in FP64,
+ * where d_j approximately solves A d = r_j by adaptive s-step CG with the
+ * matrix powers and the basis in FP32 (each row sum accumulated in FP64 from
+ * exact products and rounded once to FP32), the Gram matrix of the FP32 basis
+ * from exact products accumulated in FP64, and the coefficient recurrence,
+ * kappa estimates (unit round-off 2^-24 in eqs. condy and check) and d_j in
+ * FP64.  Stops when ||r_j|| / ||b|| <= tol.  The result field `iters` counts
+ * inner iterations of all refinement steps, `blocks` their outer blocks. */
+enum { SSCG_PREC_FP64 = 0, SSCG_PREC_MIXED = 1 };
 
 /* Per-solve outputs.  The arrays are HOST memory owned by the caller, each
  * with room for `cap` blocks (any may be NULL); entry k describes outer
@@ -147,6 +162,7 @@ typedef struct {
   double lambda_min, lambda_max;   /* Chebyshev interval                           */
   double eps_star;       /* tol * ||b||                                           */
   double c;              /* c_{k,j}                                               */
+  double unit_roundoff;  /* eps of eqs. condy and check (0: 2^-53)                */
 } sscg_block_params;
 
 /* ---------------------------------------------------------------- context */
@@ -216,6 +232,17 @@ int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* pr
  * columns of Y (each row is read before it is written). */
 int sscg_recover(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
                  const double* coef, double* x, double* r, double* p);
+
+/* The FP32 stages of SSCG_PREC_MIXED (same layouts as sscg_mpk and sscg_gram,
+ * float basis).  sscg_mpk32: the s passes on the FP32 copy of A's values,
+ * each row sum accumulated in FP64 from the exact products of FP32 values
+ * (in the row's CSR order), the three-term correction and the division by
+ * gamma in FP64, then rounded once to FP32.  sscg_gram32: G = Y^T Y of the
+ * FP32 columns (exact products, FP64 sums; d x d FP64, both triangles). */
+int sscg_mpk32(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, double lambda_min,
+               double lambda_max, float* Y, int64_t ldy, int rcol);
+int sscg_gram32(sscg_ctx* ctx, int n, int s, int first, const float* Y, int64_t ldy, int rcol,
+                double* G);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsscg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["spmv.hip", "dense.hip", "small.hip", "api.hip", "solve.hip", "batch.hip", "serve.hip"]
+SOURCES = ["spmv.hip", "dense.hip", "small.hip", "api.hip", "solve.hip", "batch.hip", "serve.hip",
+           "mixed.hip"]
 ARCH = os.environ.get("SSCG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -141,6 +141,7 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   HIPCHK(ensure(ctx->scol, sizeof(int32_t) * total));
   HIPCHK(ensure(ctx->sval, sizeof(double) * total));
+  ctx->sell_total = total;
   const double* scale = nullptr;
   if (equilibrate) {
     HIPCHK(ensure(ctx->scale, sizeof(double) * n));
@@ -297,6 +298,11 @@ int validate_opts(sscg_ctx* ctx, const sscg_opts* o) {
       return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
   }
   if (o->max_iters < 1) return fail(ctx, SSCG_ERR_ARG, "max_iters must be >= 1");
+  if (o->precision < 0 || o->precision > 1)
+    return fail(ctx, SSCG_ERR_ARG, "bad precision %d", o->precision);
+  if (o->precision == SSCG_PREC_MIXED && (o->max_outer < 1 || !(o->inner_tol > 0.0) ||
+                                           !(o->inner_tol < 1.0)))
+    return fail(ctx, SSCG_ERR_ARG, "mixed precision needs max_outer >= 1 and 0 < inner_tol < 1");
   return SSCG_OK;
 }
 
@@ -326,6 +332,9 @@ void sscg_opts_default(sscg_opts* o) {
   o->equilibrate = 0;
   o->inner_check = 1;
   o->max_iters = 100000;
+  o->precision = SSCG_PREC_FP64;
+  o->max_outer = 30;
+  o->inner_tol = 1e-5;
 }
 
 int sscg_create(sscg_ctx** out, int device, void* stream) {

@@ -328,3 +328,34 @@ hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st);
 hipError_t launch_inner_batch(const BatchCfg& c, hipStream_t st);
 hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st);
 hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st);
+
+// ---------------------------------------------------------------- mixed precision
+//
+// The FP32 basis of an inner solve: P_0..P_s at columns 0..s, R_0..R_{s-1} at
+// columns rcol..rcol+s-1 of a float buffer with column stride ld.
+struct MpkSeq32 {
+  const float* u;  // rho_{j-1}(A) v
+  const float* w;  // rho_{j-2}(A) v (j >= 2, Chebyshev)
+  float* out;      // rho_j(A) v
+};
+struct Cols32 {
+  const float* Y;
+  int64_t ld;
+  int s, rcol;
+  __host__ __device__ __forceinline__ const float* at(int a) const {
+    return Y + (int64_t)(a <= s ? a : rcol + (a - s - 1)) * ld;
+  }
+};
+// out = RN32((sum_k a32_ik u_k computed exactly term by term and summed in
+// FP64) - theta u_i - sigma w_i) / gamma), FP64 in between.
+hipError_t launch_mpk32_pass(const DevMat& A, const float* val32, int j, BasisPrm bp, int nrhs,
+                             MpkSeq32 s0, MpkSeq32 s1, hipStream_t st);
+// Gram of d FP32 columns: exact products, FP64 sums per workgroup (partials
+// in the layout of launch_gram, finished by launch_gram_finalize).
+hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, int nparts,
+                         hipStream_t st);
+// dx += Y x' (FP64), r = RN32(Y r'), p = RN32(Y p') (r, p may alias columns).
+hipError_t launch_recover32(const Cols32& cols, int n, int d, const double* coef, double* dx,
+                            float* r, float* p, hipStream_t st);
+hipError_t launch_cast_f32(const double* in, int64_t n, float* out, hipStream_t st);
+hipError_t launch_add(double* x, const double* d, int n, hipStream_t st);  // x += d

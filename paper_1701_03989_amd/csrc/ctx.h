@@ -67,6 +67,9 @@ struct sscg_ctx {
   std::vector<int> hran;
   sscg_host::BatchWs batch;
   int32_t* hactive = nullptr;  // pinned
+  int64_t sell_total = 0;      // SELL-64 entries of the last matrix copy
+  // mixed precision: FP32 values of the SELL copy, FP32 basis, FP64 correction and residual
+  sscg_host::Buf sval32, Y32, dx, r64;
 };
 
 namespace sscg_host {
@@ -123,5 +126,11 @@ int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const 
 
 // One outer block of a batch for every unfinished system (capturable).
 int batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st);
+
+// sscg_solve with opts->precision = SSCG_PREC_MIXED (arguments checked).
+int solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x, const sscg_opts& o,
+                sscg_result* res);
+// The FP32 copy of the values of the current SELL matrix (after build_mat).
+int build_val32(sscg_ctx* ctx, float** val32);
 
 }  // namespace sscg_host

@@ -443,6 +443,89 @@ __global__ __launch_bounds__(WG) void k_batch_count(BatchCfg c) {
   if (threadIdx.x == 0) *c.active = ls[0];
 }
 
+
+// ---------------------------------------------------------------- FP32 basis
+// Gram of FP32 columns: the products are exact in FP64 and summed in FP64 per
+// thread (tiles of GT rows in LDS as before); partials as dd pairs (lo = 0).
+__global__ __launch_bounds__(WG) void k_gram32(Cols32 cols, int n, int d,
+                                               double* __restrict__ part, int nparts) {
+  __shared__ double tile[GT][MAXD + 1];
+  int lb = xcd_block(nparts);
+  if (lb >= nparts) return;
+  const int npairs = d * (d + 1) / 2;
+  int pa[PAIRS_PER_THREAD], pb[PAIRS_PER_THREAD];
+  double acc[PAIRS_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+    int q = threadIdx.x + u * WG;
+    int a = 0, rem = q;
+    while (a < d && rem >= d - a) {
+      rem -= d - a;
+      ++a;
+    }
+    pa[u] = a < d ? a : 0;
+    pb[u] = a < d ? a + rem : 0;
+    acc[u] = 0.0;
+  }
+  int ntiles = (n + GT - 1) / GT;
+  int per = (ntiles + nparts - 1) / nparts;
+  int t0 = lb * per, t1 = min(t0 + per, ntiles);
+  for (int t = t0; t < t1; ++t) {
+    int r0 = t * GT;
+    for (int e = threadIdx.x; e < GT * d; e += WG) {
+      int a = e / GT, r = e - a * GT;
+      int row = r0 + r;
+      tile[r][a] = row < n ? (double)cols.at(a)[row] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+      if (threadIdx.x + u * WG < npairs) {
+        int a = pa[u], b = pb[u];
+#pragma unroll 8
+        for (int r = 0; r < GT; ++r) acc[u] = acc[u] + tile[r][a] * tile[r][b];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+    int q = threadIdx.x + u * WG;
+    if (q < npairs) {
+      part[((int64_t)q * nparts + lb) * 2] = acc[u];
+      part[((int64_t)q * nparts + lb) * 2 + 1] = 0.0;
+    }
+  }
+}
+
+// dx_i += sum_a Y_ia x'_a; r_i = RN32(sum_a Y_ia r'_a); p_i likewise (FP64 sums).
+__global__ __launch_bounds__(WG) void k_recover32(Cols32 cols, int n, int d,
+                                                  const double* __restrict__ coef, double* dx,
+                                                  float* r, float* p) {
+  int nb = (n + WG - 1) / WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int i = lb * WG + threadIdx.x;
+  if (i >= n) return;
+  double ax = 0.0, ar = 0.0, ap = 0.0;
+  for (int a = 0; a < d; ++a) {
+    double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
+    if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
+    double y = (double)cols.at(a)[i];
+    ax = ax + y * cx;
+    ar = ar + y * cr;
+    ap = ap + y * cp;
+  }
+  dx[i] = dx[i] + ax;
+  r[i] = (float)ar;
+  p[i] = (float)ap;
+}
+
+__global__ __launch_bounds__(WG) void k_add(double* __restrict__ x, const double* __restrict__ d,
+                                            int n) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i < n) x[i] = x[i] + d[i];
+}
 }  // namespace
 
 // ---------------------------------------------------------------- launches
@@ -579,5 +662,23 @@ hipError_t launch_batch_res_finalize(const BatchCfg& c, hipStream_t st) {
 
 hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, int nparts,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gram32, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_recover32(const Cols32& cols, int n, int d, const double* coef, double* dx,
+                            float* r, float* p, hipStream_t st) {
+  int nb = (n + WG - 1) / WG;
+  hipLaunchKernelGGL(k_recover32, dim3(xcd_grid(nb)), dim3(WG), 0, st, cols, n, d, coef, dx, r, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(double* x, const double* d, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add, dim3((n + WG - 1) / WG), dim3(WG), 0, st, x, d, n);
   return hipGetLastError();
 }

@@ -289,6 +289,7 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
                            const sscg_block_params& prm, double* __restrict__ coef,
                            sscg_block_info* info, int* stop) {
   const int a = threadIdx.x;
+  const double ueps = prm.unit_roundoff > 0.0 ? prm.unit_roundoff : EPS;  // of the basis
   const int s = prm.s, first = prm.first;
   const int dfull = first ? s + 1 : 2 * s + 1;
   BasisPrm bp = make_basis(prm.basis, prm.lambda_min, prm.lambda_max);
@@ -298,7 +299,7 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
   if (prm.adaptive) {
     int r0 = first ? 0 : s + 1;
     rnorm = sqrt(Gfull[r0 * dfull + r0]);
-    thr = prm.eps_star / ((prm.c * EPS) * rnorm);
+    thr = prm.eps_star / ((prm.c * ueps) * rnorm);
     st = 1;
     for (int i = 1; i <= s; ++i) {
       if (sqrt(info->kappa[i - 1]) <= thr) st = i;
@@ -360,7 +361,7 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
     rr = rr1;
     if (prm.adaptive && prm.inner_check) {
       double m0 = (0.0 > rr1) ? 0.0 : rr1;
-      double rhs = prm.eps_star / ((prm.c * EPS) * sqrt(m0));
+      double rhs = prm.eps_star / ((prm.c * ueps) * sqrt(m0));
       if (gam >= rhs) break;
     }
   }
@@ -469,6 +470,7 @@ __global__ void k_batch_plan(BatchCfg c) {
   prm.lambda_max = sy.lmax;
   prm.eps_star = sy.eps_star;
   prm.c = c.c;
+  prm.unit_roundoff = 0.0;
   c.prm[q] = prm;
 }
 

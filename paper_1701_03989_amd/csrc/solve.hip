@@ -52,6 +52,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   if ((rc = validate_opts(ctx, opts))) return rc;
   if ((rc = check_csr(ctx, A))) return rc;
   if (!b || !x) return fail(ctx, SSCG_ERR_ARG, "b and x must not be NULL");
+  if (opts->precision == SSCG_PREC_MIXED) return solve_mixed(ctx, A, b, x, *opts, res);
   const sscg_opts& o = *opts;
   const int n = A->n;
   hipStream_t S1 = ctx->stream, S2 = ctx->side;
@@ -206,6 +207,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
     prm.lambda_max = lmax;
     prm.eps_star = eps_star;
     prm.c = o.c;
+    prm.unit_roundoff = 0.0;
     size_t slot_t = 0;
     if (!P.spec) {
       HIPCHK(ev_begin(ctx, 3, 0.0, S1, &slot_t));

@@ -352,6 +352,69 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
 
 inline int wg_count(int nslices) { return (nslices + SLICES_PER_WG - 1) / SLICES_PER_WG; }
 
+
+// ---------------------------------------------------------------- FP32 pass
+template <int NRHS, bool CHEB, bool HASW>
+__global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict__ val32,
+                                              double theta, double sigma, double gamma,
+                                              MpkSeq32 s0, MpkSeq32 s1) {
+  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= A.nslices) return;
+  int lane = threadIdx.x & (SSCG_WAVE - 1);
+  int row = slice * SSCG_WAVE + lane;
+  int64_t o = A.off[slice] + lane;
+  int w = A.width[slice];
+  const float* __restrict__ u0 = s0.u;
+  const float* __restrict__ u1 = s1.u;
+  double a0 = 0.0, a1 = 0.0;
+  constexpr int CH = 4;
+  for (int j0 = 0; j0 < w; j0 += CH) {
+    float v[CH], g0[CH], g1[CH];
+    int c[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
+      bool in = j0 + u < w;
+      v[u] = in ? val32[k] : 0.0f;
+      c[u] = in ? A.col[k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (j0 + u < w) {
+        g0[u] = u0[c[u]];
+        if (NRHS == 2) g1[u] = u1[c[u]];
+      }
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (j0 + u < w) {  // products of FP32 values are exact in FP64
+        a0 = a0 + (double)v[u] * (double)g0[u];
+        if (NRHS == 2) a1 = a1 + (double)v[u] * (double)g1[u];
+      }
+  }
+  if (row >= A.n) return;
+  if (CHEB) {
+    double t0 = a0 - theta * (double)u0[row];
+    if (HASW) t0 = t0 - sigma * (double)s0.w[row];
+    s0.out[row] = (float)(t0 / gamma);
+    if (NRHS == 2) {
+      double t1 = a1 - theta * (double)u1[row];
+      if (HASW) t1 = t1 - sigma * (double)s1.w[row];
+      s1.out[row] = (float)(t1 / gamma);
+    }
+  } else {
+    s0.out[row] = (float)a0;
+    if (NRHS == 2) s1.out[row] = (float)a1;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_cast_f32(const double* __restrict__ in, int64_t n,
+                                                 float* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
 }  // namespace
 
 // ---------------------------------------------------------------- launches
@@ -493,5 +556,36 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
   *nparts = nb;
   hipLaunchKernelGGL(k_lanczos_spmv, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v, vprev, beta_prev,
                      w, part);
+  return hipGetLastError();
+}
+
+template <int NRHS, bool CHEB, bool HASW>
+static void mpk32_launch(const DevMat& A, const float* val32, double th, double sg, double gm,
+                         MpkSeq32 s0, MpkSeq32 s1, hipStream_t st) {
+  dim3 grid(xcd_grid(wg_count(A.nslices)));
+  hipLaunchKernelGGL((k_mpk32<NRHS, CHEB, HASW>), grid, dim3(WG), 0, st, A, val32, th, sg, gm, s0,
+                     s1);
+}
+
+hipError_t launch_mpk32_pass(const DevMat& A, const float* val32, int j, BasisPrm bp, int nrhs,
+                             MpkSeq32 s0, MpkSeq32 s1, hipStream_t st) {
+  if (!bp.cheb) {
+    if (nrhs == 2) mpk32_launch<2, false, false>(A, val32, 0.0, 0.0, 1.0, s0, s1, st);
+    else mpk32_launch<1, false, false>(A, val32, 0.0, 0.0, 1.0, s0, s1, st);
+    return hipGetLastError();
+  }
+  const double gamma = j == 1 ? bp.h : bp.h2;
+  if (j == 1) {
+    if (nrhs == 2) mpk32_launch<2, true, false>(A, val32, bp.c0, bp.h2, gamma, s0, s1, st);
+    else mpk32_launch<1, true, false>(A, val32, bp.c0, bp.h2, gamma, s0, s1, st);
+  } else {
+    if (nrhs == 2) mpk32_launch<2, true, true>(A, val32, bp.c0, bp.h2, gamma, s0, s1, st);
+    else mpk32_launch<1, true, true>(A, val32, bp.c0, bp.h2, gamma, s0, s1, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(const double* in, int64_t n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st, in, n, out);
   return hipGetLastError();
 }

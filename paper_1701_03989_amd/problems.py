@@ -240,3 +240,62 @@ def batch_systems(count: int, seed: int = 0, nlo: float = 1e3, nhi: float = 2e5)
             lo, hi, kind = float(np.min(diag - deg)), float(np.max(diag + deg)), f"graph_{A.n}"
         out.append(BatchSystem(A, uniform(A.n, seed + 1000 + i), float(lo), float(hi), kind))
     return out
+
+
+def lognormal_field(N: int, seed: int, sigma: float = 2.0, corr: float = 16.0) -> np.ndarray:
+    """k = exp(sigma * g) on N x N cells, g a unit-variance Gaussian random field
+    with covariance exp(-r^2 / (2 corr^2)) (r in cells), sampled by circulant
+    embedding: white noise filtered with the square root of the covariance's
+    spectrum on a periodic 2N x 2N grid, the N x N corner kept and scaled to
+    unit sample variance."""
+    M = 2 * N
+    rng = np.random.default_rng(seed)
+    d = np.minimum(np.arange(M), M - np.arange(M)).astype(np.float64)
+    cov = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2.0 * corr * corr))
+    spec = np.sqrt(np.maximum(np.fft.rfft2(cov).real, 0.0))
+    noise = rng.standard_normal((M, M))
+    g = np.fft.irfft2(np.fft.rfft2(noise) * spec, s=(M, M))[:N, :N]
+    g = (g - g.mean()) / g.std()
+    return np.exp(sigma * g)
+
+
+def diffusion2d(k: np.ndarray) -> CSR:
+    """Cell-centred finite volumes for -div(k grad u) on the unit-spaced N x N
+    grid (rows in lexicographic order, x fastest), Dirichlet boundary: face
+    transmissibility 2 k_i k_j / (k_i + k_j) between cells, 2 k_i on a
+    boundary face; A = sum of transmissibilities on the diagonal, minus each
+    on its neighbour's column.  Symmetric positive definite."""
+    N = k.shape[0]
+    kk = k.astype(np.float64)
+    tx = 2.0 * kk[:, :-1] * kk[:, 1:] / (kk[:, :-1] + kk[:, 1:])  # faces between (i, j), (i, j+1)
+    ty = 2.0 * kk[:-1, :] * kk[1:, :] / (kk[:-1, :] + kk[1:, :])  # faces between (i, j), (i+1, j)
+    diag = np.zeros((N, N))
+    diag[:, :-1] += tx
+    diag[:, 1:] += tx
+    diag[:-1, :] += ty
+    diag[1:, :] += ty
+    diag[:, 0] += 2.0 * kk[:, 0]
+    diag[:, -1] += 2.0 * kk[:, -1]
+    diag[0, :] += 2.0 * kk[0, :]
+    diag[-1, :] += 2.0 * kk[-1, :]
+    idx = np.arange(N * N).reshape(N, N)
+    rows = [idx.ravel(), idx[:, :-1].ravel(), idx[:, 1:].ravel(), idx[:-1, :].ravel(),
+            idx[1:, :].ravel()]
+    cols = [idx.ravel(), idx[:, 1:].ravel(), idx[:, :-1].ravel(), idx[1:, :].ravel(),
+            idx[:-1, :].ravel()]
+    vals = [diag.ravel(), -tx.ravel(), -tx.ravel(), -ty.ravel(), -ty.ravel()]
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rowptr = np.zeros(N * N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=N * N), out=rowptr[1:])
+    return CSR(rowptr.astype(np.int32), c.astype(np.int32), v)
+
+
+def diffusion2d_system(N: int = 2048, seed: int = 0, sigma: float = 2.0, corr: float = 16.0):
+    """Variable-coefficient diffusion on N x N (2048^2: n = 4,194,304) with a
+    log-normal coefficient field (seed), b ~ U[-1, 1] (seed + 1), x_1 = 0."""
+    A = diffusion2d(lognormal_field(N, seed, sigma, corr))
+    return A, uniform(A.n, seed + 1), np.zeros(A.n)

@@ -21,6 +21,7 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_OOM = -1, -2, -3
 MODE_ADAPTIVE, MODE_FIXED, MODE_SCHEDULE = 0, 1, 2
 BASIS_MONOMIAL, BASIS_CHEBYSHEV = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
 S_LIMIT = 16
 FAMILIES = {"mpk": 0, "gram": 1, "recover": 2, "small": 3}
 
@@ -46,7 +47,9 @@ class Opts(ctypes.Structure):
                 ("c", ctypes.c_double), ("lambda_min", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("lanczos_steps", ctypes.c_int32),
                 ("lanczos_seed", ctypes.c_uint64), ("equilibrate", ctypes.c_int32),
-                ("inner_check", ctypes.c_int32), ("max_iters", ctypes.c_int32)]
+                ("inner_check", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -87,7 +90,7 @@ class BlockParams(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("inner_check", ctypes.c_int32),
                 ("basis", ctypes.c_int32), ("lambda_min", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("eps_star", ctypes.c_double),
-                ("c", ctypes.c_double)]
+                ("c", ctypes.c_double), ("unit_roundoff", ctypes.c_double)]
 
 
 _lib = None
@@ -114,6 +117,12 @@ EXPORTS = {
     "sscg_recover": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sscg_mpk32": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
+    "sscg_gram32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                   ctypes.c_void_p]),
     "sscg_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch),
                                         ctypes.POINTER(Opts), ctypes.POINTER(BatchResult)]),
     "sscg_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Opts), ctypes.c_int64,
@@ -422,6 +431,23 @@ def sscg_recover(ctx: int, n: int, s: int, first: bool, Y, ldy: int, rcol: int, 
 TIME_ALL = 0xF
 
 
+def sscg_mpk32(ctx: int, A: DeviceCsr, s: int, first: bool, basis: int, lmin: float, lmax: float,
+               Y, ldy: int, rcol: int) -> int:
+    import torch
+
+    assert Y.dtype == torch.float32
+    c = A.cstruct()
+    return _check(ctx, lib().sscg_mpk32(ctx, ctypes.byref(c), s, int(first), basis, lmin, lmax,
+                                        _ptr(Y), ldy, rcol))
+
+
+def sscg_gram32(ctx: int, n: int, s: int, first: bool, Y, ldy: int, rcol: int, G) -> int:
+    import torch
+
+    assert Y.dtype == torch.float32
+    return _check(ctx, lib().sscg_gram32(ctx, n, s, int(first), _ptr(Y), ldy, rcol, _f64(G)))
+
+
 def sscg_set_timing(ctx: int, on) -> int:
     """on: True (every family), False (off), or an iterable of family names."""
     if isinstance(on, bool):
@@ -451,7 +477,8 @@ def block_info_from(t) -> BlockInfo:
 
 def make_opts(mode="adaptive", basis="monomial", tol=1e-10, s_max=8, s0_bar=0, f=0, fixed_s=4,
               schedule=None, c=1.0, lmin=math.nan, lmax=math.nan, lanczos_steps=30,
-              lanczos_seed=0, equilibrate=False, inner_check=True, max_iters=100000) -> Opts:
+              lanczos_seed=0, equilibrate=False, inner_check=True, max_iters=100000,
+              precision="fp64", max_outer=30, inner_tol=1e-5) -> Opts:
     o = sscg_opts_default()
     o.mode = {"adaptive": MODE_ADAPTIVE, "fixed": MODE_FIXED, "schedule": MODE_SCHEDULE}[mode]
     o.basis = {"monomial": BASIS_MONOMIAL, "chebyshev": BASIS_CHEBYSHEV}[basis]
@@ -473,4 +500,7 @@ def make_opts(mode="adaptive", basis="monomial", tol=1e-10, s_max=8, s0_bar=0, f
     o.equilibrate = int(equilibrate)
     o.inner_check = int(inner_check)
     o.max_iters = max_iters
+    o.precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
+    o.max_outer = max_outer
+    o.inner_tol = inner_tol
     return o
