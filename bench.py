@@ -306,6 +306,85 @@ def bench_batch(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def bench_precision(args) -> None:
+    """Mixed precision against plain FP64 on one workload: the FP64 solve and
+    the mixed solve (FP32 basis inside FP64 refinement) of the same system to
+    the same tolerance, each timed over --steps solves; the error of the mixed
+    solution against the FP64 one is reported with both true residuals."""
+    import torch
+
+    from paper_1701_03989_amd import problems, sscg
+
+    if args.workload == "diffusion2048":
+        A, b, x1 = problems.diffusion2d_system(2048, 0)
+        kw = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10, equilibrate=True)
+        desc = ("diffusion2048: variable-coefficient 2-D FV diffusion 2048^2, n=4194304, "
+                "log-normal k (sigma 2, correlation length 16 cells, seed 0), b~U[-1,1], x1=0, "
+                "equilibrated")
+    else:
+        wl = WORKLOADS[args.workload]
+        A, b, x1 = problems.poisson3d_128_system(0, N=wl["N"])
+        kw = dict(mode="adaptive", basis=wl["basis"], s_max=wl["s_max"], tol=wl["tol"])
+        desc = f"{args.workload}: 3-D 7-point Poisson {wl['N']}^3, n={A.n}, b~U[-1,1] seed 0, x1=0"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    Ad = sscg.DeviceCsr.from_host(A, dev)
+    bd = torch.as_tensor(b, device=dev)
+    x1d = torch.as_tensor(x1, device=dev)
+    ctx = sscg.sscg_create(0)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        opts = sscg.make_opts(precision=prec, **kw)
+        hist = sscg.History(1 << 16, kw["s_max"])
+        xd = torch.empty_like(x1d)
+
+        def one():
+            xd.copy_(x1d)
+            rc = sscg.sscg_solve(ctx, Ad, bd, xd, opts, hist)
+            assert rc == sscg.OK, f"{prec} status {rc}"
+
+        for _ in range(args.warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        x = xd.cpu().numpy()
+        res[prec] = dict(solves_per_s=args.steps / wall, ms=wall / args.steps * 1e3, x=x,
+                         relres=float(np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)),
+                         iters=int(hist.res.iters), blocks=int(hist.res.blocks),
+                         lam=[hist.res.lambda_min, hist.res.lambda_max])
+    sscg.sscg_destroy(ctx)
+    xm, x64 = res["mixed"]["x"], res["fp64"]["x"]
+    out = {
+        "metric": "solves/s at the target relres, mixed precision (FP32 basis, FP64 refinement) "
+                  "vs plain FP64",
+        "value": res["mixed"]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["mixed"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 basis / f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": desc, "method": "adaptive s-step CG (Alg. 4)", **kw},
+        "fp64_solves_per_s": res["fp64"]["solves_per_s"],
+        "speedup_vs_fp64": res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"],
+        "relres_mixed": res["mixed"]["relres"],
+        "relres_fp64": res["fp64"]["relres"],
+        "error_mixed_vs_fp64": float(np.linalg.norm(xm - x64) / np.linalg.norm(x64)),
+        "iters_mixed": res["mixed"]["iters"], "blocks_mixed": res["mixed"]["blocks"],
+        "iters_fp64": res["fp64"]["iters"], "blocks_fp64": res["fp64"]["blocks"],
+        "lambda": res["fp64"]["lam"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args) -> None:
     """The serving workload: requests arrive as a Poisson process (rate
     --serve-rate per second, --serve-requests of them, seeded gaps); each asks
@@ -440,7 +519,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="poisson3d_128",
-                    choices=sorted(WORKLOADS) + ["batch256", "serve"])
+                    choices=sorted(WORKLOADS) + ["batch256", "serve", "diffusion2048"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: time the mixed-precision solve against plain FP64")
     ap.add_argument("--batch-count", type=int, default=256,
                     help="batch256 workload: number of systems")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -479,6 +560,9 @@ def main():
         return
     if args.workload == "serve" and args.gpus == 1:
         bench_serve(args)
+        return
+    if (args.precision == "mixed" or args.workload == "diffusion2048") and args.gpus == 1:
+        bench_precision(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
