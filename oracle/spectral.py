@@ -95,3 +95,42 @@ def chebyshev_interval(A, m: int = 30, seed: int = 0) -> tuple[float, float]:
     a, b = lanczos_tridiag(A, m, seed)
     rv = ritz_values(a, b)
     return float(rv[0]), gershgorin_max(A)
+
+
+def leja_order(points) -> list:
+    """Leja ordering of real points: first the one of largest modulus, then
+    repeatedly the one maximising prod_i |z - z_i| over the points already
+    chosen (the product taken left to right in the order of choice, plain FP64);
+    ties go to the earliest point of the given order.  Used as the shifts of the
+    Newton basis, the ordering the Newton-basis references cited in Section 2 use
+    for stability."""
+    pts = [float(z) for z in points]
+    left = list(range(len(pts)))
+    order = []
+    best = max(left, key=lambda i: (abs(pts[i]), -i))
+    order.append(best)
+    left.remove(best)
+    while left:
+        def score(i):
+            prod = 1.0
+            for c in order:
+                prod = prod * abs(pts[i] - pts[c])
+            return prod
+        best = left[0]
+        bs = score(best)
+        for i in left[1:]:
+            sc = score(i)
+            if sc > bs:
+                best, bs = i, sc
+        order.append(best)
+        left.remove(best)
+    return [pts[i] for i in order]
+
+
+def newton_shifts(A, m: int, seed: int = 0) -> list:
+    """m shifts of the Newton basis: the Ritz values of an m-step Lanczos run
+    from start_vector(n, seed) (Jacobi eigenvalues of the tridiagonal matrix,
+    ascending), Leja ordered; repeated cyclically if the run stopped early."""
+    a, b = lanczos_tridiag(A, m, seed)
+    z = leja_order(ritz_values(a, b))
+    return [z[i % len(z)] for i in range(m)]

@@ -78,6 +78,11 @@ class Opts:
     equilibrate: bool = False
     max_iters: int = 100000
     inner_check: bool = True
+    shifts: Optional[list] = None  # Newton basis: shifts theta_0, theta_1, ... (R15)
+    c_mode: str = "const"  # 'const': c_{k,j} = c; 'theory': 6 N_k j kappa(A) (R16)
+    kappa_a: Optional[float] = None  # theory mode: kappa(A)
+    norm_a: Optional[float] = None  # theory mode: ||A||_2
+    n_a: Optional[int] = None  # theory mode: max nonzeros per row (None: from A)
 
 
 @dataclass
@@ -120,12 +125,17 @@ class Result:
 # polynomial basis (eqs. cg-krylovbasis, polybasiscg) and B (eq. AVVB)
 
 
-def basis_params(basis: str, s: int, lmin=None, lmax=None, ar=None):
+def basis_params(basis: str, s: int, lmin=None, lmax=None, ar=None, shifts=None):
     """(theta, gamma, sigma), lists of length s+1, of the three-term recurrence."""
     one = ar.scalar(1) if ar is not None else 1.0
     zero = one - one
     if basis == "monomial":
         return [zero] * (s + 1), [one] * (s + 1), [zero] * (s + 1)
+    if basis == "newton":  # rho_j(z) = (z - theta_{j-1}) rho_{j-1}(z): gamma = 1, sigma = 0
+        if shifts is None or len(shifts) < s:
+            raise ValueError("the Newton basis needs s shifts")
+        theta = [ar.scalar(t) if ar is not None else t for t in shifts[:s]] + [zero]
+        return theta, [one] * (s + 1), [zero] * (s + 1)
     if basis == "chebyshev":
         half = one / 2
         c0 = (lmax + lmin) * half
@@ -290,6 +300,39 @@ def equilibrate(A):
     return _Scaled(rowptr, col, vs), s
 
 
+def b_norm_bound(B) -> float:
+    """sqrt(||B||_1 ||B||_inf) >= ||B||_2 for the tridiagonal-block B of R12:
+    column sums |B[j-1][j]| + |B[j][j]| + |B[j+1][j]| and row sums
+    |B[i][i-1]| + |B[i][i]| + |B[i][i+1]|, each added in that order (R16)."""
+    d = len(B)
+    n1 = 0.0
+    ni = 0.0
+    for j in range(d):
+        c = 0.0
+        for i in (j - 1, j, j + 1):
+            if 0 <= i < d:
+                c = c + abs(float(B[i][j]))
+        n1 = max(n1, c)
+        r = 0.0
+        for i in (j - 1, j, j + 1):
+            if 0 <= i < d:
+                r = r + abs(float(B[j][i]))
+        ni = max(ni, r)
+    return math.sqrt(n1 * ni)
+
+
+def c_theory(j: int, n_a: int, bnorm: float, norm_a: float, kappa_a: float) -> float:
+    """c_{k,j} = 6 N_k j kappa(A), N_k = 7 + 2 N_A + 14 ||B_k|| / ||A|| (Section 4.1,
+    the bound behind eq. fb), evaluated in this order in FP64 (R16)."""
+    tau = bnorm / norm_a
+    nk = (7.0 + 2.0 * n_a) + 14.0 * tau
+    return ((6.0 * nk) * j) * kappa_a
+
+
+def max_row_nnz(A) -> int:
+    return int(np.max(np.diff(np.asarray(A.rowptr)))) if len(A.rowptr) > 1 else 0
+
+
 def next_s(opts: Opts, k: int, s_prev: int, m: int):
     """(s_bar_k, steps to build) for block k."""
     if opts.mode == "fixed":
@@ -331,6 +374,10 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
     if opts.basis == "chebyshev":
         if opts.lmin is None or opts.lmax is None:
             raise ValueError("the Chebyshev basis needs lmin and lmax")
+    if opts.c_mode == "theory":
+        if opts.kappa_a is None or opts.norm_a is None:
+            raise ValueError("the theoretical c_{k,j} needs kappa_a and norm_a")
+        n_a = opts.n_a if opts.n_a is not None else max_row_nnz(A)
     r = true_residual(ar, A, b, x)
     p = r
     res = Result(x=x, status=NOT_CONVERGED)
@@ -346,7 +393,7 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
     while True:
         first = k == 0
         s_bar, s_built = next_s(opts, k, s_prev, m)
-        prm = basis_params(opts.basis, s_built, opts.lmin, opts.lmax, ar)
+        prm = basis_params(opts.basis, s_built, opts.lmin, opts.lmax, ar, opts.shifts)
         cols = krylov_basis(ar, A, p, r, s_built, first, prm)
         G = ar.gram(cols)
         kappas = []
@@ -356,7 +403,15 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
         check = None
         if opts.mode == "adaptive":
             rnorm = ar.sqrt(G[0][0] if first else G[s_built + 1][s_built + 1])  # R8
-            c_smax = opts.c
+            if opts.c_mode == "theory":  # R16: B of the block's built basis
+                bnorm = b_norm_bound(assemble_B(ar, s_built, first, prm))
+
+                def cfun(j, _b=bnorm):
+                    return c_theory(j, n_a, _b, opts.norm_a, opts.kappa_a)
+            else:
+                def cfun(j):
+                    return opts.c
+            c_smax = cfun(opts.s_max)
             thr = ar.div(eps_star, (c_smax * EPS) * rnorm)  # eq. condy
             imax = s_built
             s_tilde = 1
@@ -369,14 +424,15 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
                     break
             gam = ar.sqrt(kappas[s_tilde - 1])
             if opts.inner_check:
-                def check(j, rr1, _gam=gam):
-                    rhs = ar.div(eps_star, (opts.c * EPS) * ar.sqrt(max(rr1, 0.0)))
+                def check(j, rr1, _gam=gam, _c=cfun):
+                    rhs = ar.div(eps_star, (_c(j) * EPS) * ar.sqrt(max(rr1, 0.0)))
                     return _gam >= rhs
         else:
             s_tilde = s_built
         idx = sub_indices(s_built, s_tilde, first)
         Gs = principal(G, idx)
-        Bs = assemble_B(ar, s_tilde, first, basis_params(opts.basis, s_tilde, opts.lmin, opts.lmax, ar))
+        Bs = assemble_B(ar, s_tilde, first,
+                        basis_params(opts.basis, s_tilde, opts.lmin, opts.lmax, ar, opts.shifts))
         ys = [cols[a] for a in idx]
         s_k, xc, rc, pc, alphas, betas, rr, st = inner_loop(ar, Gs, Bs, s_tilde, first, check)
         if diag is not None:
