@@ -46,7 +46,13 @@ enum {
 };
 
 enum { SSCG_MODE_ADAPTIVE = 0, SSCG_MODE_FIXED = 1, SSCG_MODE_SCHEDULE = 2 };
-enum { SSCG_BASIS_MONOMIAL = 0, SSCG_BASIS_CHEBYSHEV = 1 };
+enum { SSCG_BASIS_MONOMIAL = 0, SSCG_BASIS_CHEBYSHEV = 1, SSCG_BASIS_NEWTON = 2 };
+/* c_{k,j} of eqs. condy and check: the constant opts->c, or the value the
+ * bound of Section 4.1 gives, 6 N_k j kappa(A) with N_k = 7 + 2 N_A +
+ * 14 ||B_k|| / ||A|| (N_A: most nonzeros in a row of A; ||B_k|| bounded by
+ * sqrt(||B||_1 ||B||_inf) of the block's built basis; eq. condy takes
+ * j = s_max). */
+enum { SSCG_C_CONST = 0, SSCG_C_THEORY = 1 };
 
 /* Largest s the library accepts: the (2s+1)-dimensional coordinate problem
  * of a block is solved by one wavefront. */
@@ -86,7 +92,12 @@ typedef struct {
   int32_t equilibrate;   /* 1: solve D^-1/2 A D^-1/2 (Section 5), D_i = max|a_ij| */
   int32_t inner_check;   /* 1: in-loop break of eq. check (Alg. 4); 0: s_k = s~   */
   int32_t max_iters;     /* cap on total inner iterations                         */
-  int32_t precision;     /* SSCG_PREC_FP64, or SSCG_PREC_MIXED (sscg_solve only):
+  int32_t c_mode;        /* SSCG_C_CONST (default) or SSCG_C_THEORY               */
+  double kappa_a;        /* THEORY: kappa(A) and ||A||_2; NaN: lambda_max/lambda_min */
+  double norm_a;         /*   and lambda_max of the spectral estimate              */
+  const double* shifts;  /* host; BASIS_NEWTON: s_max shifts theta_0, theta_1, ...;
+                            NULL: sscg_newton_shifts(m = s_max, lanczos_seed)     */
+  int32_t precision;    /* SSCG_PREC_FP64, or SSCG_PREC_MIXED (sscg_solve only):
                             FP64 iterative refinement around FP32-basis solves    */
   int32_t max_outer;     /* MIXED: cap on refinement steps (default 30)          */
   double inner_tol;      /* MIXED: each inner solve reduces its residual by this
@@ -161,8 +172,14 @@ typedef struct {
   int32_t basis;         /* SSCG_BASIS_*                                          */
   double lambda_min, lambda_max;   /* Chebyshev interval                           */
   double eps_star;       /* tol * ||b||                                           */
-  double c;              /* c_{k,j}                                               */
+  double c;              /* c_{k,j} (c_mode CONST)                                */
   double unit_roundoff;  /* eps of eqs. condy and check (0: 2^-53)                */
+  int32_t c_mode;        /* SSCG_C_CONST or SSCG_C_THEORY                         */
+  int32_t n_a;           /* THEORY: most nonzeros in a row of A                   */
+  int32_t s_max;         /* THEORY: eq. condy uses c_{k,s_max}                    */
+  int32_t pad_;
+  double kappa_a, norm_a;          /* THEORY: kappa(A), ||A||_2                    */
+  double shifts[SSCG_S_LIMIT];     /* BASIS_NEWTON: theta_0, theta_1, ...          */
 } sscg_block_params;
 
 /* ---------------------------------------------------------------- context */
@@ -201,6 +218,13 @@ int sscg_residual(sscg_ctx* ctx, const sscg_csr* A, const double* b, const doubl
  * SplitMix64(seed) vector u_i = (z_i >> 11) 2^-52 - 1.  Host outputs. */
 int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t seed,
                          double* lambda_min, double* lambda_max);
+/* Shifts of the Newton basis: the Ritz values of an m-step Lanczos run
+ * (m <= SSCG_S_LIMIT, start vector as for sscg_spectral_bounds), eigenvalues of
+ * the tridiagonal matrix by the Jacobi method of the kappa estimates, sorted
+ * ascending and then Leja ordered (first the largest in modulus, then each
+ * maximising the product of distances to those already chosen, ties to the
+ * earlier); repeated cyclically if the run ended early.  shifts: host, m. */
+int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, double* shifts);
 
 /* Matrix powers (eqs. cg-krylovbasis, polybasiscg): Y is n x ncol, column-major
  * with leading dimension ldy >= n.  On entry column 0 holds p (P_0) and, unless
@@ -211,6 +235,12 @@ int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t s
  * 1 <= s <= SSCG_S_LIMIT and, unless first, rcol >= s+1. */
 int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis,
              double lambda_min, double lambda_max, double* Y, int64_t ldy, int rcol);
+
+/* sscg_mpk for the Newton basis (Section 2): P_j = (A - theta_{j-1} I) P_{j-1},
+ * likewise R_j, each row rounded once.  shifts: host, s values theta_0..
+ * theta_{s-1}. */
+int sscg_mpk_newton(sscg_ctx* ctx, const sscg_csr* A, int s, int first, const double* shifts,
+                    double* Y, int64_t ldy, int rcol);
 
 /* Gram matrix (Section 2, Algorithm 4): G = Y_s^T Y_s of the basis columns
  * [P_0..P_s, R_0..R_{s-1}] (first: [P_0..P_s]) laid out as in sscg_mpk.

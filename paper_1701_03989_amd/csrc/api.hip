@@ -214,26 +214,24 @@ int ensure_parts(sscg_ctx* ctx, int n, int count) {
   return SSCG_OK;
 }
 
-int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, double* lmin,
-                        double* lmax) {
+// `steps` Lanczos steps on M from the SplitMix64 start vector: alpha_j and
+// beta_j stay in ctx->lzab (al, be); *k = steps, or fewer if some beta_j = 0
+// (invariant subspace: the run ends there).
+int lanczos_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, int* k) {
   const int n = M.n;
-  if (steps < 1) steps = 1;
-  if (steps > 2 * SSCG_S_LIMIT + 1) steps = 2 * SSCG_S_LIMIT + 1;
   int rc = ensure_parts(ctx, n, 1);
   if (rc) return rc;
   HIPCHK(ensure(ctx->lz, sizeof(double) * 3 * (size_t)n));
-  HIPCHK(ensure(ctx->lzab, sizeof(double) * (2 * 64 + 8)));
+  HIPCHK(ensure(ctx->lzab, sizeof(double) * (2 * 64 + 8 + SSCG_S_LIMIT)));
   double* v = as<double>(ctx->lz);
   double* vp = v + n;
   double* w = vp + n;
   double* al = as<double>(ctx->lzab);
   double* be = al + 64;
-  double* sc = be + 64;  // [0]: ||u||, [1]: Gershgorin, [2], [3]: Ritz extremes
+  double* sc = be + 64;  // [0]: ||u||
   double* part = as<double>(ctx->part);
   int np = 0;
   hipStream_t st = ctx->stream;
-  HIPCHK(launch_gershgorin(M, part, &np, st));
-  HIPCHK(launch_max_finalize(part, np, sc + 1, st));
   HIPCHK(launch_splitmix_vec(w, n, seed, st));
   HIPCHK(launch_dot_parts(w, w, n, part, &np, st));
   HIPCHK(launch_finalize(part, np, 1, sc, st));
@@ -258,12 +256,30 @@ int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed
   double hb[64];
   HIPCHK(hipMemcpyAsync(hb, be, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  int k = steps;
+  *k = steps;
   for (int j = 0; j < steps - 1; ++j)
     if (hb[j] == 0.0) {
-      k = j + 1;
+      *k = j + 1;
       break;
     }
+  return SSCG_OK;
+}
+
+int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, double* lmin,
+                        double* lmax) {
+  if (steps < 1) steps = 1;
+  if (steps > 2 * SSCG_S_LIMIT + 1) steps = 2 * SSCG_S_LIMIT + 1;
+  int k = 0;
+  int rc = lanczos_dev(ctx, M, steps, seed, &k);
+  if (rc) return rc;
+  double* al = as<double>(ctx->lzab);
+  double* be = al + 64;
+  double* sc = be + 64;  // [1]: Gershgorin, [2], [3]: Ritz extremes
+  double* part = as<double>(ctx->part);
+  int np = 0;
+  hipStream_t st = ctx->stream;
+  HIPCHK(launch_gershgorin(M, part, &np, st));
+  HIPCHK(launch_max_finalize(part, np, sc + 1, st));
   HIPCHK(launch_tridiag_eig(al, be, k, sc + 2, sc + 3, st));
   double out[4];
   HIPCHK(hipMemcpyAsync(out, sc, sizeof out, hipMemcpyDeviceToHost, st));
@@ -273,10 +289,76 @@ int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed
   return SSCG_OK;
 }
 
+int newton_shifts_dev(sscg_ctx* ctx, const DevMat& M, int m, uint64_t seed, double* shifts) {
+  int k = 0;
+  int rc = lanczos_dev(ctx, M, m, seed, &k);
+  if (rc) return rc;
+  double* al = as<double>(ctx->lzab);
+  double* be = al + 64;
+  double* sc = be + 64 + 8;  // m shifts
+  HIPCHK(launch_newton_shifts(al, be, k, m, sc, ctx->stream));
+  HIPCHK(hipMemcpyAsync(shifts, sc, sizeof(double) * m, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < m; ++i)
+    if (!isfinite(shifts[i])) return fail(ctx, SSCG_ERR_HIP, "Newton shift estimate failed");
+  return SSCG_OK;
+}
+
+int max_row_nnz_dev(sscg_ctx* ctx, const DevMat& M, int* n_a) {
+  int32_t* out = as<int32_t>(ctx->width) + M.nslices + 1;
+  HIPCHK(launch_max_width(M.width, M.nslices, out, ctx->stream));
+  HIPCHK(hipMemcpyAsync(n_a, out, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return SSCG_OK;
+}
+
+int method_setup(sscg_ctx* ctx, const DevMat& M, const sscg_opts& o, MethodSetup* ms) {
+  int rc = 0;
+  ms->lmin = o.lambda_min;
+  ms->lmax = o.lambda_max;
+  ms->bp = make_basis(o.basis, 0.0, 1.0);
+  for (int i = 0; i < SSCG_S_LIMIT; ++i) ms->shifts[i] = 0.0;
+  if (o.basis == SSCG_BASIS_CHEBYSHEV) {
+    if (isnan(ms->lmin)) {
+      if ((rc = spectral_bounds_dev(ctx, M, o.lanczos_steps, o.lanczos_seed, &ms->lmin,
+                                    &ms->lmax)))
+        return rc;
+      if (!(ms->lmax > ms->lmin)) return fail(ctx, SSCG_ERR_HIP, "spectral estimate failed");
+    }
+    ms->bp = make_basis(o.basis, ms->lmin, ms->lmax);
+  }
+  if (o.basis == SSCG_BASIS_NEWTON) {
+    if (o.shifts) {
+      for (int i = 0; i < o.s_max; ++i) ms->shifts[i] = o.shifts[i];
+    } else if ((rc = newton_shifts_dev(ctx, M, o.s_max, o.lanczos_seed, ms->shifts))) {
+      return rc;
+    }
+    ms->bp = make_basis(o.basis, 0.0, 1.0, ms->shifts);
+  }
+  ms->c_mode = o.c_mode;
+  ms->n_a = 0;
+  ms->s_max = o.s_max;
+  ms->kappa_a = o.kappa_a;
+  ms->norm_a = o.norm_a;
+  if (o.c_mode == SSCG_C_THEORY) {
+    if ((rc = max_row_nnz_dev(ctx, M, &ms->n_a))) return rc;
+    if (isnan(ms->kappa_a) || isnan(ms->norm_a)) {
+      double lo = ms->lmin, hi = ms->lmax;
+      if (isnan(lo) &&
+          (rc = spectral_bounds_dev(ctx, M, o.lanczos_steps, o.lanczos_seed, &lo, &hi)))
+        return rc;
+      if (!(lo > 0.0 && hi >= lo)) return fail(ctx, SSCG_ERR_HIP, "spectral estimate failed");
+      if (isnan(ms->kappa_a)) ms->kappa_a = hi / lo;
+      if (isnan(ms->norm_a)) ms->norm_a = hi;
+    }
+  }
+  return SSCG_OK;
+}
+
 int validate_opts(sscg_ctx* ctx, const sscg_opts* o) {
   if (!o) return fail(ctx, SSCG_ERR_ARG, "opts is NULL");
   if (o->mode < 0 || o->mode > 2) return fail(ctx, SSCG_ERR_ARG, "bad mode %d", o->mode);
-  if (o->basis < 0 || o->basis > 1) return fail(ctx, SSCG_ERR_ARG, "bad basis %d", o->basis);
+  if (o->basis < 0 || o->basis > 2) return fail(ctx, SSCG_ERR_ARG, "bad basis %d", o->basis);
   if (!(o->tol > 0.0)) return fail(ctx, SSCG_ERR_ARG, "tol must be > 0");
   if (o->s_max < 1 || o->s_max > SSCG_S_LIMIT)
     return fail(ctx, SSCG_ERR_ARG, "s_max = %d outside [1, %d]", o->s_max, SSCG_S_LIMIT);
@@ -298,6 +380,14 @@ int validate_opts(sscg_ctx* ctx, const sscg_opts* o) {
       return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
   }
   if (o->max_iters < 1) return fail(ctx, SSCG_ERR_ARG, "max_iters must be >= 1");
+  if (o->basis == SSCG_BASIS_NEWTON && o->shifts)
+    for (int i = 0; i < o->s_max; ++i)
+      if (!isfinite(o->shifts[i])) return fail(ctx, SSCG_ERR_ARG, "shifts[%d] not finite", i);
+  if (o->c_mode < 0 || o->c_mode > 1) return fail(ctx, SSCG_ERR_ARG, "bad c_mode %d", o->c_mode);
+  if (o->c_mode == SSCG_C_THEORY &&
+      ((!isnan(o->kappa_a) && !(o->kappa_a >= 1.0 && isfinite(o->kappa_a))) ||
+       (!isnan(o->norm_a) && !(o->norm_a > 0.0 && isfinite(o->norm_a)))))
+    return fail(ctx, SSCG_ERR_ARG, "theoretical c needs kappa_a >= 1 and norm_a > 0 (or NaN)");
   if (o->precision < 0 || o->precision > 1)
     return fail(ctx, SSCG_ERR_ARG, "bad precision %d", o->precision);
   if (o->precision == SSCG_PREC_MIXED && (o->max_outer < 1 || !(o->inner_tol > 0.0) ||
@@ -332,6 +422,10 @@ void sscg_opts_default(sscg_opts* o) {
   o->equilibrate = 0;
   o->inner_check = 1;
   o->max_iters = 100000;
+  o->c_mode = SSCG_C_CONST;
+  o->kappa_a = NAN;
+  o->norm_a = NAN;
+  o->shifts = nullptr;
   o->precision = SSCG_PREC_FP64;
   o->max_outer = 30;
   o->inner_tol = 1e-5;
@@ -476,6 +570,44 @@ int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t s
   return spectral_bounds_dev(ctx, M, steps, seed, lambda_min, lambda_max);
 }
 
+int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, double* shifts) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  if (!shifts) return fail(ctx, SSCG_ERR_ARG, "NULL output");
+  if (m < 1 || m > SSCG_S_LIMIT)
+    return fail(ctx, SSCG_ERR_ARG, "m = %d outside [1, %d]", m, SSCG_S_LIMIT);
+  DevMat M;
+  if ((rc = build_mat(ctx, A, 0, &M))) return rc;
+  return newton_shifts_dev(ctx, M, m, seed, shifts);
+}
+
+int sscg_mpk_newton(sscg_ctx* ctx, const sscg_csr* A, int s, int first, const double* shifts,
+                    double* Y, int64_t ldy, int rcol) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  if (s < 1 || s > SSCG_S_LIMIT)
+    return fail(ctx, SSCG_ERR_ARG, "s = %d outside [1, %d]", s, SSCG_S_LIMIT);
+  if (!Y || ldy < A->n) return fail(ctx, SSCG_ERR_ARG, "Y NULL or ldy < n");
+  if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
+  if (!shifts) return fail(ctx, SSCG_ERR_ARG, "shifts is NULL");
+  double th[SSCG_S_LIMIT];
+  for (int i = 0; i < s; ++i) {
+    th[i] = shifts[i];
+    if (!isfinite(th[i])) return fail(ctx, SSCG_ERR_ARG, "shifts[%d] not finite", i);
+  }
+  DevMat M;
+  if ((rc = build_mat(ctx, A, 0, &M))) return rc;
+  BasisCols bc{Y, Y + (int64_t)rcol * ldy, Y, ldy, rcol};
+  return mpk_passes(ctx, M, s, first ? 1 : 0, make_basis(SSCG_BASIS_NEWTON, 0.0, 1.0, th), bc,
+                    A->nnz, nullptr, MpkResidual{});
+}
+
 int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, double lambda_min,
              double lambda_max, double* Y, int64_t ldy, int rcol) {
   if (!ctx) return SSCG_ERR_ARG;
@@ -487,6 +619,9 @@ int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, doub
     return fail(ctx, SSCG_ERR_ARG, "s = %d outside [1, %d]", s, SSCG_S_LIMIT);
   if (!Y || ldy < A->n) return fail(ctx, SSCG_ERR_ARG, "Y NULL or ldy < n");
   if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
+  if (basis != SSCG_BASIS_MONOMIAL && basis != SSCG_BASIS_CHEBYSHEV)
+    return fail(ctx, SSCG_ERR_ARG, "basis %d: monomial or Chebyshev (Newton: sscg_mpk_newton)",
+                basis);
   if (basis == SSCG_BASIS_CHEBYSHEV && !(lambda_max > lambda_min))
     return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
   DevMat M;
@@ -521,8 +656,15 @@ int sscg_small_solve(sscg_ctx* ctx, const double* G, const sscg_block_params* pr
   if (prm->s < 1 || prm->s > SSCG_S_LIMIT) return fail(ctx, SSCG_ERR_ARG, "bad s");
   if (!prm->adaptive && (prm->iters < 1 || prm->iters > prm->s))
     return fail(ctx, SSCG_ERR_ARG, "iters must be in [1, s]");
-  if (prm->adaptive && !(prm->eps_star > 0.0 && prm->c > 0.0))
-    return fail(ctx, SSCG_ERR_ARG, "need eps_star > 0 and c > 0");
+  if (prm->basis < 0 || prm->basis > 2) return fail(ctx, SSCG_ERR_ARG, "bad basis");
+  if (prm->adaptive && !(prm->eps_star > 0.0))
+    return fail(ctx, SSCG_ERR_ARG, "need eps_star > 0");
+  if (prm->adaptive && prm->c_mode == SSCG_C_CONST && !(prm->c > 0.0))
+    return fail(ctx, SSCG_ERR_ARG, "need c > 0");
+  if (prm->adaptive && prm->c_mode == SSCG_C_THEORY &&
+      !(prm->kappa_a >= 1.0 && prm->norm_a > 0.0 && prm->n_a >= 0 && prm->s_max >= 1))
+    return fail(ctx, SSCG_ERR_ARG, "theoretical c needs kappa_a >= 1, norm_a > 0, n_a, s_max");
+  if (prm->c_mode < 0 || prm->c_mode > 1) return fail(ctx, SSCG_ERR_ARG, "bad c_mode");
   int d = prm->first ? prm->s + 1 : 2 * prm->s + 1;
   if (prm->adaptive) HIPCHK(launch_kappa(G, d, prm->s, prm->first, info, nullptr, ctx->stream));
   HIPCHK(launch_inner(G, *prm, coef, info, nullptr, ctx->stream));

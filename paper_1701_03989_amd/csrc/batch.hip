@@ -76,6 +76,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   if (o.mode == SSCG_MODE_SCHEDULE)
     return fail(ctx, SSCG_ERR_ARG, "batch: MODE_SCHEDULE is not supported");
   if (o.equilibrate) return fail(ctx, SSCG_ERR_ARG, "batch: equilibration is not supported");
+  if (o.basis == SSCG_BASIS_NEWTON || o.c_mode != SSCG_C_CONST)
+    return fail(ctx, SSCG_ERR_ARG, "batch: the Newton basis and the theoretical c are not supported");
   const int nsys = B->nsys;
   const bool cheb = o.basis == SSCG_BASIS_CHEBYSHEV;
   if (cheb && (!B->lambda_min || !B->lambda_max))

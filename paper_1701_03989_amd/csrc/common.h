@@ -98,18 +98,26 @@ struct DevMat {
 
 // Basis parameters of the three-term recurrence (monomial: theta = 0,
 // gamma = sigma = 1 unused).  Chebyshev on [lmin, lmax]:
-// theta_j = c0, gamma_0 = h, gamma_j = h/2, sigma_j = h/2.
+// theta_j = c0, gamma_0 = h, gamma_j = h/2, sigma_j = h/2.  Newton:
+// theta_j = th[j] (the shifts), gamma_j = 1, sigma_j = 0; th is a host array
+// read by the host-side launchers only (device code takes the shifts from
+// the block parameters).
 struct BasisPrm {
   int cheb;
+  int newton;
   double c0, h, h2;
+  const double* th;
 };
 
-__host__ __device__ inline BasisPrm make_basis(int basis, double lmin, double lmax) {
+__host__ __device__ inline BasisPrm make_basis(int basis, double lmin, double lmax,
+                                               const double* th = nullptr) {
   BasisPrm b;
   b.cheb = basis == SSCG_BASIS_CHEBYSHEV;
+  b.newton = basis == SSCG_BASIS_NEWTON;
   b.c0 = (lmax + lmin) * 0.5;
   b.h = (lmax - lmin) * 0.5;
   b.h2 = b.h * 0.5;
+  b.th = th;
   return b;
 }
 
@@ -221,6 +229,8 @@ hipError_t launch_relres(const double* r2, const double* b2, double* out, hipStr
 // Spectral bounds.
 hipError_t launch_gershgorin(const DevMat& A, double* part, int* nparts, hipStream_t st);
 hipError_t launch_max_finalize(const double* part, int nparts, double* out, hipStream_t st);
+// *out = max of the n ints width[] (the most nonzeros in a row of a SELL matrix).
+hipError_t launch_max_width(const int32_t* width, int n, int32_t* out, hipStream_t st);
 hipError_t launch_splitmix_vec(double* out, int n, uint64_t seed, hipStream_t st);
 hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* vprev,
                                const double* beta_prev, double* w, double* part, int* nparts,
@@ -234,6 +244,8 @@ hipError_t launch_dot_parts(const double* x, const double* y, int n, double* par
                             hipStream_t st);
 hipError_t launch_tridiag_eig(const double* alpha, const double* beta, int k, double* lmin,
                               double* lmax, hipStream_t st);
+hipError_t launch_newton_shifts(const double* alpha, const double* beta, int k, int m, double* out,
+                                hipStream_t st);
 
 // ---------------------------------------------------------------- batches
 //

@@ -101,6 +101,30 @@ int ensure_parts(sscg_ctx* ctx, int n, int count);
 int validate_opts(sscg_ctx* ctx, const sscg_opts* o);
 int spectral_bounds_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, double* lmin,
                         double* lmax);
+// Basis and c_{k,j} parameters of a solve on M: the Chebyshev interval and
+// the Newton shifts (given or estimated), and for the c_{k,j} of Section 4.1
+// N_A, kappa(A) and ||A|| (given, else from the spectral estimate).
+struct MethodSetup {
+  BasisPrm bp;
+  double lmin, lmax;
+  double shifts[SSCG_S_LIMIT];
+  int c_mode, n_a, s_max;
+  double kappa_a, norm_a;
+  void fill(sscg_block_params& prm) const {
+    prm.c_mode = c_mode;
+    prm.n_a = n_a;
+    prm.s_max = s_max;
+    prm.pad_ = 0;
+    prm.kappa_a = kappa_a;
+    prm.norm_a = norm_a;
+    for (int i = 0; i < SSCG_S_LIMIT; ++i) prm.shifts[i] = shifts[i];
+  }
+};
+int method_setup(sscg_ctx* ctx, const DevMat& M, const sscg_opts& o, MethodSetup* ms);
+// m Newton shifts (host output) from an m-step Lanczos run on M.
+int newton_shifts_dev(sscg_ctx* ctx, const DevMat& M, int m, uint64_t seed, double* shifts);
+// Most nonzeros in a row of M (from the SELL widths).
+int max_row_nnz_dev(sscg_ctx* ctx, const DevMat& M, int* n_a);
 
 // Basis columns of an s-step block: P_0 and R_0 at p0 / r0, P_j (j >= 1) at
 // Y + j*ldy, R_j (j >= 1) at Y + (rcol + j)*ldy.

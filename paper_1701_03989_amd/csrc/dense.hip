@@ -148,6 +148,23 @@ __global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ 
   }
 }
 
+// max of width[0..n) into *out (one workgroup).
+__global__ __launch_bounds__(WG) void k_max_width(const int32_t* __restrict__ width, int n,
+                                                  int32_t* __restrict__ out) {
+  __shared__ int lm[WG / SSCG_WAVE];
+  int m = 0;
+  for (int q = threadIdx.x; q < n; q += WG) m = max(m, (int)width[q]);
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) m = max(m, __shfl_xor(m, k, SSCG_WAVE));
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) lm[threadIdx.x / SSCG_WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = lm[0];
+    for (int q = 1; q < WG / SSCG_WAVE; ++q) t = max(t, lm[q]);
+    out[0] = t;
+  }
+}
+
 // ---------------------------------------------------------------- recovery
 //
 // x_i <- RN(x_i + sum_a Y_ia x'_a), r_i <- RN(sum_a Y_ia r'_a),
@@ -565,6 +582,11 @@ hipError_t launch_finalize(const double* part, int nparts, int count, double* ou
 
 hipError_t launch_max_finalize(const double* part, int nparts, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(WG), 0, st, part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_width(const int32_t* width, int n, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_max_width, dim3(1), dim3(WG), 0, st, width, n, out);
   return hipGetLastError();
 }
 

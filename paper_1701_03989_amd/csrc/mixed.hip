@@ -92,17 +92,11 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
   R.spec_blocks = 0;
   R.spec_rejected = 0;
 
-  // Chebyshev interval of A (estimated in FP64 if not given)
-  BasisPrm bp = make_basis(o.basis, 0.0, 1.0);
-  double lmin = o.lambda_min, lmax = o.lambda_max;
-  if (o.basis == SSCG_BASIS_CHEBYSHEV) {
-    if (isnan(lmin)) {
-      if ((rc = spectral_bounds_dev(ctx, M, o.lanczos_steps, o.lanczos_seed, &lmin, &lmax)))
-        return rc;
-      if (!(lmax > lmin)) return fail(ctx, SSCG_ERR_HIP, "spectral estimate failed");
-    }
-    bp = make_basis(o.basis, lmin, lmax);
-  }
+  // basis and c_{k,j} parameters of A (estimated in FP64 where not given)
+  MethodSetup ms;
+  if ((rc = method_setup(ctx, M, o, &ms))) return rc;
+  const BasisPrm bp = ms.bp;
+  const double lmin = ms.lmin, lmax = ms.lmax;
   R.lambda_min = lmin;
   R.lambda_max = lmax;
   const bool adaptive = o.mode == SSCG_MODE_ADAPTIVE;
@@ -189,6 +183,7 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
       prm.eps_star = eps_in;
       prm.c = o.c;
       prm.unit_roundoff = EPS32;
+      ms.fill(prm);
       if (adaptive) HIPCHK(launch_kappa(G, d, s, first, info, nullptr, st));
       HIPCHK(launch_inner(G, prm, coef, info, nullptr, st));
       HIPCHK(launch_recover32(cols, n, d, coef, dx, R0, P0, st));
@@ -242,6 +237,8 @@ extern "C" int sscg_mpk32(sscg_ctx* ctx, const sscg_csr* A, int s, int first, in
     return fail(ctx, SSCG_ERR_ARG, "s = %d outside [1, %d]", s, SSCG_S_LIMIT);
   if (!Y || ldy < A->n) return fail(ctx, SSCG_ERR_ARG, "Y NULL or ldy < n");
   if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
+  if (basis != SSCG_BASIS_MONOMIAL && basis != SSCG_BASIS_CHEBYSHEV)
+    return fail(ctx, SSCG_ERR_ARG, "basis %d: monomial or Chebyshev", basis);
   if (basis == SSCG_BASIS_CHEBYSHEV && !(lambda_max > lambda_min))
     return fail(ctx, SSCG_ERR_ARG, "need lambda_max > lambda_min");
   DevMat M;

@@ -256,6 +256,8 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   if ((rc = validate_opts(ctx, opts))) return rc;
   if (opts->mode == SSCG_MODE_SCHEDULE || opts->equilibrate)
     return fail(ctx, SSCG_ERR_ARG, "server: MODE_SCHEDULE and equilibration are not supported");
+  if (opts->basis == SSCG_BASIS_NEWTON || opts->c_mode != SSCG_C_CONST)
+    return fail(ctx, SSCG_ERR_ARG, "server: the Newton basis and the theoretical c are not supported");
   if (slots < 1 || slots > 65536) return fail(ctx, SSCG_ERR_ARG, "server: bad slot count %d", slots);
   const int64_t rows = (std::max<int64_t>(pool_rows, 1) + ROW_UNIT - 1) / ROW_UNIT * ROW_UNIT;
   if (rows > INT32_MAX / 2) return fail(ctx, SSCG_ERR_ARG, "server: pool_rows too large");

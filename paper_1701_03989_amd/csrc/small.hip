@@ -208,10 +208,79 @@ __global__ __launch_bounds__(JT) void k_tridiag_eig(const double* __restrict__ a
   }
 }
 
+// Shifts of the Newton basis from the Lanczos tridiagonal matrix (k <= MAXK):
+// all its eigenvalues, ascending, then in Leja order (largest modulus first;
+// then the point maximising the product of distances to the points already
+// chosen, multiplied in the order of choice; ties to the earlier point);
+// out[i] = z[i mod k], i < m.
+__global__ __launch_bounds__(JT) void k_newton_shifts(const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta, int k,
+                                                      int m, double* __restrict__ out) {
+  __shared__ JacobiLds L;
+  if (threadIdx.x < k) {
+    int b = threadIdx.x;
+    for (int a = 0; a < k; ++a) {
+      double v = 0.0;
+      if (a == b) v = alpha[a];
+      else if (b == a + 1) v = beta[a];
+      else if (a == b + 1) v = beta[b];
+      L.A[a * LDK + b] = v;
+    }
+  }
+  __syncthreads();
+  if (k > 1) jacobi(L, k);
+  if (threadIdx.x != 0) return;
+  double* z = L.ws;  // k values, ascending
+  for (int a = 0; a < k; ++a) {
+    const double v = L.A[a * LDK + a];
+    int p = a;
+    while (p > 0 && z[p - 1] > v) {
+      z[p] = z[p - 1];
+      --p;
+    }
+    z[p] = v;
+  }
+  int* ord = L.pt;
+  double* used = L.fd;  // 1: already chosen
+  for (int a = 0; a < k; ++a) used[a] = 0.0;
+  int best = 0;
+  for (int a = 1; a < k; ++a)
+    if (fabs(z[a]) > fabs(z[best])) best = a;
+  ord[0] = best;
+  used[best] = 1.0;
+  for (int t = 1; t < k; ++t) {
+    best = -1;
+    double bs = 0.0;
+    for (int a = 0; a < k; ++a) {
+      if (used[a] != 0.0) continue;
+      double prod = 1.0;
+      for (int u = 0; u < t; ++u) prod = prod * fabs(z[a] - z[ord[u]]);
+      if (best < 0 || prod > bs) {
+        best = a;
+        bs = prod;
+      }
+    }
+    ord[t] = best;
+    used[best] = 1.0;
+  }
+  for (int i = 0; i < m; ++i) out[i] = z[ord[i % k]];
+}
+
 // ---------------------------------------------------------------- inner loop
 
+// Coefficients of the three-term recurrence (eq. polybasiscg); th: the
+// Newton shifts (read only for the Newton basis, i < s).
+__device__ __forceinline__ double rec_theta(const BasisPrm& bp, const double* th, int i) {
+  return bp.cheb ? bp.c0 : (bp.newton ? th[i] : 0.0);
+}
+__device__ __forceinline__ double rec_gamma(const BasisPrm& bp, int i) {
+  return bp.cheb ? (i == 0 ? bp.h : bp.h2) : 1.0;
+}
+__device__ __forceinline__ double rec_sigma(const BasisPrm& bp) { return bp.cheb ? bp.h2 : 0.0; }
+
 // (B v)_a for the s-step basis of s steps (first: P block only), R12 layout.
-__device__ __forceinline__ double bmul(const double* v, int a, int s, int first, BasisPrm bp) {
+__device__ __forceinline__ double bmul(const double* v, int a, int s, int first, BasisPrm bp,
+                                       const double* th) {
   // block offset, local index and block length
   int off = 0, len = s + 1;
   if (!first && a > s) {
@@ -219,18 +288,50 @@ __device__ __forceinline__ double bmul(const double* v, int a, int s, int first,
     len = s;
   }
   int j = a - off;
-  double th = bp.cheb ? bp.c0 : 0.0;
   dd acc = dd_zero();
   // B[a][a-1] = gamma_{j-1}: column j-1 is not the block's last
-  if (j >= 1) {
-    double g = bp.cheb ? (j - 1 == 0 ? bp.h : bp.h2) : 1.0;
-    dd_add_prod(acc, g, v[a - 1]);
-  }
+  if (j >= 1) dd_add_prod(acc, rec_gamma(bp, j - 1), v[a - 1]);
   // B[a][a] = theta_j if column j is not the last
-  if (j < len - 1) dd_add_prod(acc, th, v[a]);
+  if (j < len - 1) dd_add_prod(acc, rec_theta(bp, th, j), v[a]);
   // B[a][a+1] = sigma_j if column j+1 is not the last
-  if (j + 1 < len - 1) dd_add_prod(acc, bp.cheb ? bp.h2 : 0.0, v[a + 1]);
+  if (j + 1 < len - 1) dd_add_prod(acc, rec_sigma(bp), v[a + 1]);
   return dd_round(acc);
+}
+
+// sqrt(||B||_1 ||B||_inf) >= ||B||_2 for the B of s steps (eq. AVVB): the
+// largest column and row sums of |B|, each summed in index order.
+__device__ double b_norm_bound(int s, int first, const BasisPrm& bp, const double* th) {
+  double n1 = 0.0, ni = 0.0;
+  for (int blk = 0; blk < (first ? 1 : 2); ++blk) {
+    const int len = blk == 0 ? s + 1 : s;
+    for (int j = 0; j < len; ++j) {
+      double c = 0.0, r = 0.0;
+      if (j < len - 1) {  // column j: sigma_{j-1}, theta_j, gamma_j (the last column is zero)
+        if (j >= 1) c = c + fabs(rec_sigma(bp));
+        c = c + fabs(rec_theta(bp, th, j));
+        c = c + fabs(rec_gamma(bp, j));
+      }
+      if (j >= 1) r = r + fabs(rec_gamma(bp, j - 1));  // row j: gamma_{j-1}, theta_j, sigma_j
+      if (j < len - 1) r = r + fabs(rec_theta(bp, th, j));
+      if (j + 1 < len - 1) r = r + fabs(rec_sigma(bp));
+      n1 = c > n1 ? c : n1;
+      ni = r > ni ? r : ni;
+    }
+  }
+  return sqrt(n1 * ni);
+}
+
+// c_{k,j} of eqs. condy and check: the given constant, or the bound of
+// Section 4.1, 6 N_k j kappa(A) with N_k = 7 + 2 N_A + 14 ||B_k|| / ||A||,
+// evaluated in this order with every operation rounded on its own.
+__device__ __forceinline__ double c_kj(const sscg_block_params& prm, double bnorm, int j) {
+  if (prm.c_mode != SSCG_C_THEORY) return prm.c;
+  {
+#pragma clang fp contract(off)
+    const double tau = bnorm / prm.norm_a;
+    const double nk = (7.0 + 2.0 * (double)prm.n_a) + 14.0 * tau;
+    return ((6.0 * nk) * (double)j) * prm.kappa_a;
+  }
 }
 
 struct InnerLds {
@@ -238,6 +339,7 @@ struct InnerLds {
   double v[MAXK + 1];
   double w[MAXK + 1];
   double ps[SSCG_WAVE], pe[SSCG_WAVE];  // per-lane dd partials of the row sums
+  double th[SSCG_S_LIMIT];               // Newton shifts
 };
 
 // CR dot of lane-owned values over the wave (lanes >= d hold zeros).
@@ -293,13 +395,17 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
   const int s = prm.s, first = prm.first;
   const int dfull = first ? s + 1 : 2 * s + 1;
   BasisPrm bp = make_basis(prm.basis, prm.lambda_min, prm.lambda_max);
+  if (a < SSCG_S_LIMIT) L.th[a] = prm.shifts[a];
+  __syncthreads();
+  // ||B|| bound of the built basis (c_{k,j} of Section 4.1 only)
+  const double bnorm = prm.c_mode == SSCG_C_THEORY ? b_norm_bound(s, first, bp, L.th) : 0.0;
 
   double gam = __builtin_nan(""), thr = __builtin_nan(""), rnorm = __builtin_nan("");
   int st;
   if (prm.adaptive) {
     int r0 = first ? 0 : s + 1;
     rnorm = sqrt(Gfull[r0 * dfull + r0]);
-    thr = prm.eps_star / ((prm.c * ueps) * rnorm);
+    thr = prm.eps_star / ((c_kj(prm, bnorm, prm.s_max) * ueps) * rnorm);
     st = 1;
     for (int i = 1; i <= s; ++i) {
       if (sqrt(info->kappa[i - 1]) <= thr) st = i;
@@ -326,7 +432,7 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
     // B p
     L.w[a < MAXK ? a : MAXK] = a < d ? p : 0.0;
     __syncthreads();
-    double bpv = a < d ? bmul(L.w, a, st, first, bp) : 0.0;
+    double bpv = a < d ? bmul(L.w, a, st, first, bp, L.th) : 0.0;
     __syncthreads();
     // p . G (B p)
     L.v[a < MAXK ? a : MAXK] = a < d ? bpv : 0.0;
@@ -347,7 +453,7 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
     x = x + q;
     L.w[a < MAXK ? a : MAXK] = a < d ? q : 0.0;
     __syncthreads();
-    double bq = a < d ? bmul(L.w, a, st, first, bp) : 0.0;
+    double bq = a < d ? bmul(L.w, a, st, first, bp, L.th) : 0.0;
     __syncthreads();
     r = r - bq;
     double rr1 = quad(L, r, d);
@@ -361,7 +467,7 @@ __device__ void inner_body(InnerLds& L, const double* __restrict__ Gfull,
     rr = rr1;
     if (prm.adaptive && prm.inner_check) {
       double m0 = (0.0 > rr1) ? 0.0 : rr1;
-      double rhs = prm.eps_star / ((prm.c * ueps) * sqrt(m0));
+      double rhs = prm.eps_star / ((c_kj(prm, bnorm, j) * ueps) * sqrt(m0));
       if (gam >= rhs) break;
     }
   }
@@ -406,12 +512,18 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner(const double* __restrict__ 
 // never accepted on top of an unchecked speculation.
 __global__ void k_validate(const double* __restrict__ Gfull, sscg_block_params prm,
                            sscg_block_info* info, int* stop) {
+  __shared__ double th[SSCG_S_LIMIT];
+  if (threadIdx.x < SSCG_S_LIMIT) th[threadIdx.x] = prm.shifts[threadIdx.x];
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  const double ueps = prm.unit_roundoff > 0.0 ? prm.unit_roundoff : EPS;
   const int s = prm.s, first = prm.first;
+  const BasisPrm bp = make_basis(prm.basis, prm.lambda_min, prm.lambda_max);
+  const double bnorm = prm.c_mode == SSCG_C_THEORY ? b_norm_bound(s, first, bp, th) : 0.0;
   const int dfull = first ? s + 1 : 2 * s + 1;
   const int r0 = first ? 0 : s + 1;
   const double rnorm = sqrt(Gfull[r0 * dfull + r0]);
-  const double thr = prm.eps_star / ((prm.c * EPS) * rnorm);
+  const double thr = prm.eps_star / ((c_kj(prm, bnorm, prm.s_max) * ueps) * rnorm);
   int st = 1;
   for (int i = 1; i <= s; ++i) {
     if (sqrt(info->kappa[i - 1]) <= thr) st = i;
@@ -423,7 +535,7 @@ __global__ void k_validate(const double* __restrict__ Gfull, sscg_block_params p
     for (int j = 1; j < s; ++j) {
       const double rr1 = info->rr_trace[j - 1];
       const double m0 = (0.0 > rr1) ? 0.0 : rr1;
-      const double rhs = prm.eps_star / ((prm.c * EPS) * sqrt(m0));
+      const double rhs = prm.eps_star / ((c_kj(prm, bnorm, j) * ueps) * sqrt(m0));
       if (gam >= rhs) {
         ok = false;
         break;
@@ -459,7 +571,7 @@ __global__ void k_batch_plan(BatchCfg c) {
   }
   s = min(s, c.S);
   sy.s_bar = s_bar;
-  sscg_block_params prm;
+  sscg_block_params prm = {};
   prm.s = s;
   prm.first = sy.first;
   prm.adaptive = c.mode == SSCG_MODE_ADAPTIVE ? 1 : 0;
@@ -491,7 +603,7 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner_batch(BatchCfg c) {
   const int q = blockIdx.x;
   BatchSys& sy = c.sys[q];
   if (sy.done) return;
-  const sscg_block_params prm = c.prm[q];
+  const sscg_block_params& prm = c.prm[q];
   sscg_block_info* info = c.info + q;
   inner_body(L, c.G + (int64_t)q * BATCH_GSZ, prm, c.coef + (int64_t)q * BATCH_CSZ, info,
              nullptr);
@@ -541,6 +653,12 @@ hipError_t launch_validate(const double* G, const sscg_block_params& prm, sscg_b
 hipError_t launch_tridiag_eig(const double* alpha, const double* beta, int k, double* lmin,
                               double* lmax, hipStream_t st) {
   hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(JT), 0, st, alpha, beta, k, lmin, lmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_shifts(const double* alpha, const double* beta, int k, int m, double* out,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_newton_shifts, dim3(1), dim3(JT), 0, st, alpha, beta, k, m, out);
   return hipGetLastError();
 }
 

@@ -151,18 +151,12 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   }
   if (relres0 <= o.tol) return finish(SSCG_OK, 0);
 
-  BasisPrm bp = make_basis(o.basis, 0.0, 1.0);
-  double lmin = o.lambda_min, lmax = o.lambda_max;
-  if (o.basis == SSCG_BASIS_CHEBYSHEV) {
-    if (isnan(lmin)) {
-      if ((rc = spectral_bounds_dev(ctx, M, o.lanczos_steps, o.lanczos_seed, &lmin, &lmax)))
-        return rc;
-      if (!(lmax > lmin)) return fail(ctx, SSCG_ERR_HIP, "spectral estimate failed");
-    }
-    bp = make_basis(o.basis, lmin, lmax);
-    R.lambda_min = lmin;
-    R.lambda_max = lmax;
-  }
+  MethodSetup ms;
+  if ((rc = method_setup(ctx, M, o, &ms))) return rc;
+  const BasisPrm bp = ms.bp;
+  const double lmin = ms.lmin, lmax = ms.lmax;
+  R.lambda_min = lmin;
+  R.lambda_max = lmax;
   const bool adaptive = o.mode == SSCG_MODE_ADAPTIVE;
   const int s0 = o.s0_bar > 0 ? o.s0_bar : o.s_max;
   const int f = o.f > 0 ? o.f : o.s_max;
@@ -208,6 +202,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
     prm.eps_star = eps_star;
     prm.c = o.c;
     prm.unit_roundoff = 0.0;
+    ms.fill(prm);
     size_t slot_t = 0;
     if (!P.spec) {
       HIPCHK(ev_begin(ctx, 3, 0.0, S1, &slot_t));

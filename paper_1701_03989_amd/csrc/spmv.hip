@@ -511,6 +511,12 @@ void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double g
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
                            Gate g, const MpkResidual& res, hipStream_t st) {
   dim3 grid(xcd_grid(wg_count(A.nslices)));
+  if (bp.newton) {  // (A - theta_{j-1} I) u: the j = 1 form, gamma = 1
+    const double th = bp.th[j - 1];
+    if (nrhs == 2) mpk_launch<2, true, false>(grid, A, th, 0.0, 1.0, s0, s1, g, res, st);
+    else mpk_launch<1, true, false>(grid, A, th, 0.0, 1.0, s0, s1, g, res, st);
+    return hipGetLastError();
+  }
   if (!bp.cheb) {
     if (nrhs == 2) mpk_launch<2, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, g, res, st);
     else mpk_launch<1, false, false>(grid, A, 0.0, 0.0, 1.0, s0, s1, g, res, st);
@@ -569,6 +575,12 @@ static void mpk32_launch(const DevMat& A, const float* val32, double th, double 
 
 hipError_t launch_mpk32_pass(const DevMat& A, const float* val32, int j, BasisPrm bp, int nrhs,
                              MpkSeq32 s0, MpkSeq32 s1, hipStream_t st) {
+  if (bp.newton) {
+    const double th = bp.th[j - 1];
+    if (nrhs == 2) mpk32_launch<2, true, false>(A, val32, th, 0.0, 1.0, s0, s1, st);
+    else mpk32_launch<1, true, false>(A, val32, th, 0.0, 1.0, s0, s1, st);
+    return hipGetLastError();
+  }
   if (!bp.cheb) {
     if (nrhs == 2) mpk32_launch<2, false, false>(A, val32, 0.0, 0.0, 1.0, s0, s1, st);
     else mpk32_launch<1, false, false>(A, val32, 0.0, 0.0, 1.0, s0, s1, st);

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libsscg.so")
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_OOM = -1, -2, -3
 MODE_ADAPTIVE, MODE_FIXED, MODE_SCHEDULE = 0, 1, 2
-BASIS_MONOMIAL, BASIS_CHEBYSHEV = 0, 1
+BASIS_MONOMIAL, BASIS_CHEBYSHEV, BASIS_NEWTON = 0, 1, 2
+C_CONST, C_THEORY = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 S_LIMIT = 16
 FAMILIES = {"mpk": 0, "gram": 1, "recover": 2, "small": 3}
@@ -48,6 +49,8 @@ class Opts(ctypes.Structure):
                 ("lambda_max", ctypes.c_double), ("lanczos_steps", ctypes.c_int32),
                 ("lanczos_seed", ctypes.c_uint64), ("equilibrate", ctypes.c_int32),
                 ("inner_check", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("c_mode", ctypes.c_int32), ("kappa_a", ctypes.c_double),
+                ("norm_a", ctypes.c_double), ("shifts", _dp),
                 ("precision", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double)]
 
@@ -90,7 +93,10 @@ class BlockParams(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("inner_check", ctypes.c_int32),
                 ("basis", ctypes.c_int32), ("lambda_min", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("eps_star", ctypes.c_double),
-                ("c", ctypes.c_double), ("unit_roundoff", ctypes.c_double)]
+                ("c", ctypes.c_double), ("unit_roundoff", ctypes.c_double),
+                ("c_mode", ctypes.c_int32), ("n_a", ctypes.c_int32), ("s_max", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("kappa_a", ctypes.c_double),
+                ("norm_a", ctypes.c_double), ("shifts", ctypes.c_double * S_LIMIT)]
 
 
 _lib = None
@@ -106,6 +112,11 @@ EXPORTS = {
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sscg_spectral_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_int,
                                             ctypes.c_uint64, _dp, _dp]),
+    "sscg_newton_shifts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_int,
+                                          ctypes.c_uint64, _dp]),
+    "sscg_mpk_newton": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_int,
+                                       ctypes.c_int, _dp, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_int]),
     "sscg_mpk": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                 ctypes.c_int64, ctypes.c_int]),
@@ -413,6 +424,21 @@ def sscg_mpk(ctx: int, A: DeviceCsr, s: int, first: bool, basis: int, lmin: floa
                                       _f64(Y), ldy, rcol))
 
 
+def sscg_newton_shifts(ctx: int, A: DeviceCsr, m: int, seed: int = 0) -> list:
+    c = A.cstruct()
+    out = (ctypes.c_double * m)()
+    _check(ctx, lib().sscg_newton_shifts(ctx, ctypes.byref(c), m, seed, out))
+    return list(out)
+
+
+def sscg_mpk_newton(ctx: int, A: DeviceCsr, s: int, first: bool, shifts, Y, ldy: int,
+                    rcol: int) -> int:
+    c = A.cstruct()
+    th = (ctypes.c_double * s)(*[float(t) for t in shifts[:s]])
+    return _check(ctx, lib().sscg_mpk_newton(ctx, ctypes.byref(c), s, int(first), th, _f64(Y), ldy,
+                                             rcol))
+
+
 def sscg_gram(ctx: int, n: int, s: int, first: bool, Y, ldy: int, rcol: int, G) -> int:
     return _check(ctx, lib().sscg_gram(ctx, n, s, int(first), _f64(Y), ldy, rcol, _f64(G)))
 
@@ -478,10 +504,19 @@ def block_info_from(t) -> BlockInfo:
 def make_opts(mode="adaptive", basis="monomial", tol=1e-10, s_max=8, s0_bar=0, f=0, fixed_s=4,
               schedule=None, c=1.0, lmin=math.nan, lmax=math.nan, lanczos_steps=30,
               lanczos_seed=0, equilibrate=False, inner_check=True, max_iters=100000,
-              precision="fp64", max_outer=30, inner_tol=1e-5) -> Opts:
+              precision="fp64", max_outer=30, inner_tol=1e-5, c_mode="const",
+              kappa_a=math.nan, norm_a=math.nan, shifts=None) -> Opts:
     o = sscg_opts_default()
     o.mode = {"adaptive": MODE_ADAPTIVE, "fixed": MODE_FIXED, "schedule": MODE_SCHEDULE}[mode]
-    o.basis = {"monomial": BASIS_MONOMIAL, "chebyshev": BASIS_CHEBYSHEV}[basis]
+    o.basis = {"monomial": BASIS_MONOMIAL, "chebyshev": BASIS_CHEBYSHEV,
+               "newton": BASIS_NEWTON}[basis]
+    o.c_mode = {"const": C_CONST, "theory": C_THEORY}[c_mode]
+    o.kappa_a = kappa_a
+    o.norm_a = norm_a
+    if shifts is not None:
+        arr = np.ascontiguousarray(shifts, dtype=np.float64)
+        o._shifts_keep = arr  # keep alive with the struct
+        o.shifts = arr.ctypes.data_as(_dp)
     o.tol = tol
     o.s_max = s_max
     o.s0_bar = s0_bar
