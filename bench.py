@@ -38,6 +38,7 @@ COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read and 1 GiB written per l
 WORKLOADS = {
     "poisson3d_128": dict(N=128, s_max=10, tol=1e-12, basis="chebyshev"),
     "poisson3d_64": dict(N=64, s_max=10, tol=1e-12, basis="chebyshev"),
+    "poisson3d_96": dict(N=96, s_max=10, tol=1e-12, basis="chebyshev"),
 }
 
 
@@ -529,6 +530,10 @@ def main():
     ap.add_argument("--serve-operators", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-pool-rows", type=int, default=96 << 20)
+    ap.add_argument("--basis", choices=["chebyshev", "monomial", "newton"], default=None,
+                    help="basis of the single-solve workloads (default: the workload's)")
+    ap.add_argument("--c-mode", choices=["const", "theory"], default="const",
+                    help="c_{k,j}: the constant 1, or 6 N_k j kappa(A) of Section 4.1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -573,7 +578,10 @@ def main():
 
     from paper_1701_03989_amd import problems, sscg
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    variant = args.basis not in (None, wl["basis"]) or args.c_mode != "const"
+    if args.basis:
+        wl["basis"] = args.basis
     A, b, x1 = problems.poisson3d_128_system(0, N=wl["N"])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -581,7 +589,8 @@ def main():
     bd = torch.as_tensor(b, device=dev)
     x1d = torch.as_tensor(x1, device=dev)
     xd = torch.empty_like(x1d)
-    opts = sscg.make_opts(mode="adaptive", basis=wl["basis"], s_max=wl["s_max"], tol=wl["tol"])
+    opts = sscg.make_opts(mode="adaptive", basis=wl["basis"], s_max=wl["s_max"], tol=wl["tol"],
+                          c_mode=args.c_mode)
     ctx = sscg.sscg_create(0)
     hist = sscg.History(4096, wl["s_max"])
 
@@ -645,6 +654,7 @@ def main():
                         f"b~U[-1,1] seed 0, x1=0",
             "method": "adaptive s-step CG (Alg. 4)",
             "basis": wl["basis"], "s_max": wl["s_max"], "tol": wl["tol"],
+            "c": "6 N_k j kappa(A), kappa estimated" if args.c_mode == "theory" else 1.0,
         },
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -671,7 +681,7 @@ def main():
             "timed_launches": n_mpk,
         },
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not variant:
         out["cpu_baseline"] = cpu_baseline(A, b, x1, wl, hist.blocks, args.cpu_budget)
     print(json.dumps(out), flush=True)
 

@@ -161,14 +161,8 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
 }
 
 ColPtr colptr_of(const BasisCols& bc, int s, int first) {
-  ColPtr c;
-  const int d = first ? s + 1 : 2 * s + 1;
-  for (int a = 0; a < 2 * SSCG_S_LIMIT + 1; ++a) {
-    if (a >= d) c.c[a] = bc.p0;
-    else if (a <= s) c.c[a] = bc.P(a);
-    else c.c[a] = bc.R(a - s - 1);
-  }
-  return c;
+  (void)first;  // block 0 has d = s + 1 columns: the R columns are never addressed
+  return ColPtr{bc.p0, bc.r0, bc.Y, bc.ldy, bc.rcol, s};
 }
 
 int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,

@@ -183,10 +183,22 @@ int residual_nparts(int n);
 hipError_t launch_finalize(const double* part, int nparts, int count, double* out,
                            hipStream_t st);
 
-// The d basis columns of a block in G's order [P_0..P_s, R_0..R_{s-1}].
+// The d basis columns of a block in G's order [P_0..P_s, R_0..R_{s-1}]
+// (block 0: P only): P_0 at p0, R_0 at r0, P_j (j >= 1) at Y + j ld and R_j
+// at Y + (rcol + j) ld.  Addresses are computed from the index, so a kernel
+// never loads a column pointer from memory.
 struct ColPtr {
-  const double* c[2 * SSCG_S_LIMIT + 1];
-  __device__ __forceinline__ const double* at(int a) const { return c[a]; }
+  const double* p0;
+  const double* r0;
+  const double* Y;
+  int64_t ld;
+  int rcol, s;
+  __device__ __forceinline__ const double* at(int a) const {
+    if (a == 0) return p0;
+    if (a <= s) return Y + (int64_t)a * ld;
+    if (a == s + 1) return r0;
+    return Y + (int64_t)(rcol + a - s - 1) * ld;
+  }
 };
 
 // Gram of the d columns; partials then the finalize.  stop may be NULL.

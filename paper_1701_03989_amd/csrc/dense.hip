@@ -24,8 +24,11 @@ constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 template <class Cols>
 __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int re,
                                           double* __restrict__ part, int nparts, int slot) {
-  __shared__ double tile[GT][MAXD + 1];
+  // two LDS tiles: tile t+1 is loaded into registers while tile t is used
+  __shared__ double tile[2][GT][MAXD + 1];
+  constexpr int LPT = (GT * MAXD + WG - 1) / WG;  // tile elements per thread
   const int npairs = d * (d + 1) / 2;
+  const int nel = GT * d;
   int pa[PAIRS_PER_THREAD], pb[PAIRS_PER_THREAD];
   dd acc[PAIRS_PER_THREAD];
 #pragma unroll
@@ -40,22 +43,38 @@ __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int r
     pb[u] = a < d ? a + rem : 0;
     acc[u] = dd_zero();
   }
-  for (int r0 = rb; r0 < re; r0 += GT) {
-    for (int e = threadIdx.x; e < GT * d; e += WG) {
-      int a = e / GT, r = e - a * GT;
-      int row = r0 + r;
-      tile[r][a] = row < re ? cols.at(a)[row] : 0.0;
+  // element e of a tile: column e / GT, row e % GT (a wave reads whole column runs)
+  double nx[LPT];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int e = threadIdx.x + k * WG;
+      const int a = e / GT, row = r0 + (e - a * GT);
+      nx[k] = (e < nel && row < re) ? cols.at(a)[row] : 0.0;
     }
+  };
+  if (rb < re) fetch(rb);
+  int buf = 0;
+  for (int r0 = rb; r0 < re; r0 += GT) {
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int e = threadIdx.x + k * WG;
+      const int a = e / GT;
+      if (e < nel) tile[buf][e - a * GT][a] = nx[k];
+    }
+    // one barrier per tile: a thread writes tile[buf] again two tiles later,
+    // after every thread has passed the next barrier, i.e. finished this tile
     __syncthreads();
+    if (r0 + GT < re) fetch(r0 + GT);
 #pragma unroll
     for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
       if (threadIdx.x + u * WG < npairs) {
-        int a = pa[u], b = pb[u];
+        const int a = pa[u], b = pb[u];
 #pragma unroll 4
-        for (int r = 0; r < GT; ++r) dd_add_prod(acc[u], tile[r][a], tile[r][b]);
+        for (int r = 0; r < GT; ++r) dd_add_prod(acc[u], tile[buf][r][a], tile[buf][r][b]);
       }
     }
-    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
@@ -176,6 +195,13 @@ __device__ __forceinline__ void recover_row(const Cols& cols, int d,
                                             const double* x_in, double* x_out, double* r,
                                             double* p);
 
+// The 3d coefficients of a block into LDS (every thread of the workgroup
+// must call it): the per-column zero tests then cost no memory waits.
+__device__ __forceinline__ void stage_coef(const double* __restrict__ coef, int d, double* cf) {
+  for (int e = threadIdx.x; e < 3 * d; e += blockDim.x) cf[e] = coef[e];
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
                                                 const double* __restrict__ coef,
                                                 const double* x_in, double* x_out, double* r,
@@ -184,9 +210,11 @@ __global__ __launch_bounds__(WG) void k_recover(ColPtr cols, int n, int d,
   int nb = (n + WG - 1) / WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
+  __shared__ double cf[3 * MAXD];
+  stage_coef(coef, d, cf);
   int i = lb * WG + threadIdx.x;
   if (i >= n) return;
-  recover_row(cols, d, coef, i, x_in, x_out, r, p);
+  recover_row(cols, d, cf, i, x_in, x_out, r, p);
 }
 
 template <class Cols>
@@ -196,13 +224,31 @@ __device__ __forceinline__ void recover_row(const Cols& cols, int d,
                                             double* p) {
   dd ax = dd_zero(), ar = dd_zero(), ap = dd_zero();
   dd_add(ax, x_in[i]);
-  for (int a = 0; a < d; ++a) {
-    double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
-    if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
-    double y = cols.at(a)[i];
-    dd_add_prod(ax, y, cx);
-    dd_add_prod(ar, y, cr);
-    dd_add_prod(ap, y, cp);
+  // groups of RC columns: all loads of a group are in flight before the sums
+  constexpr int RC = 8;
+  for (int a0 = 0; a0 < d; a0 += RC) {
+    double y[RC];
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      // unconditional loads (a branch per load would serialise them): a
+      // column past d or with three zero coefficients reads column 0's row
+      // again instead (a cache hit, and its value is not used)
+      const int a = a0 + u;
+      const bool use =
+          a < d && (coef[a] != 0.0 || coef[d + a] != 0.0 || coef[2 * d + a] != 0.0);
+      y[u] = cols.at(use ? a : 0)[i];
+    }
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int a = a0 + u;
+      if (a < d) {
+        const double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
+        if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
+        dd_add_prod(ax, y[u], cx);
+        dd_add_prod(ar, y[u], cr);
+        dd_add_prod(ap, y[u], cp);
+      }
+    }
   }
   x_out[i] = dd_round(ax);
   r[i] = dd_round(ar);
@@ -388,8 +434,10 @@ __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
   const sscg_block_params prm = c.prm[q];
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
   const int i = lb * BATCH_ROWS + threadIdx.x;
-  recover_row(batch_cols(c, prm.s, prm.first), d, c.coef + (int64_t)q * BATCH_CSZ, i, c.x, c.x,
-              batch_col(c, c.S + 1), batch_col(c, 0));
+  __shared__ double cf[3 * MAXD];
+  stage_coef(c.coef + (int64_t)q * BATCH_CSZ, d, cf);
+  recover_row(batch_cols(c, prm.s, prm.first), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
+              batch_col(c, 0));
 }
 
 // Set-up per system from the residual and ||b||^2 partials of its blocks.
