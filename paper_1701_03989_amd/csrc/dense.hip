@@ -18,10 +18,11 @@ constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 // of GT rows x d columns are staged in LDS (row-major, so the lanes of a wave
 // reading different columns of one row hit different banks).  Output: one dd
 // partial per (entry, workgroup), entry-major.
+//
 // Upper-triangle dd partials of the Gram matrix of columns cols[0..d) over
 // rows [rb, re): entry q (a <= b, row-major over the triangle) goes to
 // part[(q * nparts + slot) * 2].
-template <class Cols>
+template <int PPT, class Cols>
 __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int re,
                                           double* __restrict__ part, int nparts, int slot) {
   // two LDS tiles: tile t+1 is loaded into registers while tile t is used
@@ -29,10 +30,10 @@ __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int r
   constexpr int LPT = (GT * MAXD + WG - 1) / WG;  // tile elements per thread
   const int npairs = d * (d + 1) / 2;
   const int nel = GT * d;
-  int pa[PAIRS_PER_THREAD], pb[PAIRS_PER_THREAD];
-  dd acc[PAIRS_PER_THREAD];
+  int pa[PPT], pb[PPT];
+  dd acc[PPT];
 #pragma unroll
-  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+  for (int u = 0; u < PPT; ++u) {
     int q = threadIdx.x + u * WG;
     int a = 0, rem = q;
     while (a < d && rem >= d - a) {
@@ -67,7 +68,7 @@ __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int r
     __syncthreads();
     if (r0 + GT < re) fetch(r0 + GT);
 #pragma unroll
-    for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+    for (int u = 0; u < PPT; ++u) {
       if (threadIdx.x + u * WG < npairs) {
         const int a = pa[u], b = pb[u];
 #pragma unroll 4
@@ -77,7 +78,7 @@ __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int r
     buf ^= 1;
   }
 #pragma unroll
-  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
+  for (int u = 0; u < PPT; ++u) {
     int q = threadIdx.x + u * WG;
     if (q < npairs) {
       part[((int64_t)q * nparts + slot) * 2] = acc[u].s;
@@ -86,6 +87,8 @@ __device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int r
   }
 }
 
+// PPT: upper-triangle entries per thread (1 covers d <= 22)
+template <int PPT>
 __global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* __restrict__ part,
                                              int nparts, Gate gate) {
   if (gate_closed(gate)) return;
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* 
   int ntiles = (n + GT - 1) / GT;
   int per = (ntiles + nparts - 1) / nparts;
   int t0 = lb * per, t1 = min(t0 + per, ntiles);
-  gram_rows(cols, d, t0 * GT, min(t1 * GT, n), part, nparts, lb);
+  gram_rows<PPT>(cols, d, t0 * GT, min(t1 * GT, n), part, nparts, lb);
 }
 
 // Sum `nparts` dd partials of reduction blockIdx.x in a fixed order and
@@ -391,6 +394,7 @@ __device__ __forceinline__ BatchCols batch_cols(const BatchCfg& c, int s, int fi
   return BatchCols{c.Y, c.ld, s, c.S};
 }
 
+template <int PPT>
 __global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {
   int lb = xcd_block(c.nchunks);
   if (lb >= c.nchunks) return;
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {
   if (q < 0 || c.sys[q].done) return;
   const sscg_block_params prm = c.prm[q];
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  gram_rows(batch_cols(c, prm.s, prm.first), d, ch.r0, ch.r1, c.gpart, c.nchunks, lb);
+  gram_rows<PPT>(batch_cols(c, prm.s, prm.first), d, ch.r0, ch.r1, c.gpart, c.nchunks, lb);
 }
 
 // grid (pairs, systems): entry blockIdx.x of system blockIdx.y.
@@ -605,7 +609,12 @@ int gram_nparts(int n) {
 
 hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts, Gate g,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_gram, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part, nparts, g);
+  if (d * (d + 1) / 2 <= WG)
+    hipLaunchKernelGGL(k_gram<1>, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part,
+                       nparts, g);
+  else
+    hipLaunchKernelGGL(k_gram<PAIRS_PER_THREAD>, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n,
+                       d, part, nparts, g);
   return hipGetLastError();
 }
 
@@ -700,7 +709,12 @@ hipError_t launch_div_vec(const double* w, const double* beta, int n, double* ou
 }
 
 hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_batch, dim3(xcd_grid(c.nchunks)), dim3(WG), 0, st, c);
+  const int dmax = 2 * c.S + 1;  // the largest basis of any system
+  if (dmax * (dmax + 1) / 2 <= WG)
+    hipLaunchKernelGGL(k_gram_batch<1>, dim3(xcd_grid(c.nchunks)), dim3(WG), 0, st, c);
+  else
+    hipLaunchKernelGGL(k_gram_batch<PAIRS_PER_THREAD>, dim3(xcd_grid(c.nchunks)), dim3(WG), 0, st,
+                       c);
   return hipGetLastError();
 }
 
