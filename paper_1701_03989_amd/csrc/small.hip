@@ -39,8 +39,13 @@ struct JacobiLds {
 };
 
 // Eigenvalues of the k x k symmetric matrix in L.A (k <= MAXK) by cyclic
-// Jacobi, JT threads: thread t owns column t & 63 and rows (t >> 6) + 4j in
-// the application phases; threads t < m/2 form the rotations.
+// Jacobi, two mappings of the same operations.  Every matrix entry of a
+// step is computed by the same formula whichever thread computes it, so both
+// give the same bits.
+//
+// jacobi (latency: one problem on four wavefronts, JT threads): thread t owns
+// column t & 63 and rows (t >> 6) + 4j in the application phases; threads
+// t < m/2 form the rotations.
 constexpr int JT = 256;
 constexpr int RPT = (MAXK + 3) / 4;  // rows per thread in the application phases
 __device__ __forceinline__ void jacobi(JacobiLds& L, int k) {
@@ -143,6 +148,82 @@ __device__ __forceinline__ void jacobi(JacobiLds& L, int k) {
   }
 }
 
+// jacobi_wave (throughput: one problem per wavefront, many problems at once):
+// lanes t < m/2 form the rotations of a step; in the application phases
+// lane t works on column t % k, rows t / k, t / k + P, ... (P = 64 / k).
+__device__ __forceinline__ void jacobi_wave(JacobiLds& L, int k) {
+  const int t = threadIdx.x;
+  const int m = (k & 1) ? k + 1 : k;
+  const int P = SSCG_WAVE / k;               // lanes per column (>= 1 for k <= 64)
+  const int c = t % k, r0 = t / k;           // column and first row of this lane
+  const bool act = r0 < P;                   // lanes past P * k idle
+  for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+    int rotated = 0;
+    for (int st = 0; st < m - 1; ++st) {
+      bool rot = false;
+      if (t < m / 2) {
+        int a = rr_pos(t, st, m), b = rr_pos(m - 1 - t, st, m);
+        int p = min(a, b), q = max(a, b);
+        if (q < k) {
+          double app = L.A[p * LDK + p], aqq = L.A[q * LDK + q], apq = L.A[p * LDK + q];
+          double thr = EPS * (sqrt(fabs(app)) * sqrt(fabs(aqq)));
+          if (fabs(apq) > thr) {
+            double tau = (aqq - app) / (2.0 * apq);
+            double tt;
+            if (fabs(tau) > 1e150) {
+              tt = 0.5 / tau;
+            } else {
+              double sg = tau >= 0.0 ? 1.0 : -1.0;
+              tt = sg / (fabs(tau) + sqrt(1.0 + tau * tau));
+            }
+            double cs = 1.0 / sqrt(1.0 + tt * tt);
+            double s = tt * cs;
+            L.ws[p] = cs; L.wo[p] = -s; L.pt[p] = q;
+            L.ws[q] = cs; L.wo[q] = s; L.pt[q] = p;
+            L.fd[p] = app - tt * apq;
+            L.fd[q] = aqq + tt * apq;
+            rot = true;
+          } else {
+            L.pt[p] = -1; L.pt[q] = -1;
+          }
+        } else if (p < k) {
+          L.pt[p] = -1;
+        }
+      }
+      const int nr = __popcll(__ballot(rot));
+      __syncthreads();
+      if (nr == 0) continue;
+      rotated += nr;
+      if (act) {  // B = A J, column c
+        const int pc = L.pt[c];
+        if (pc >= 0) {
+          const double wsc = L.ws[c], woc = L.wo[c];
+          for (int r = r0; r < k; r += P) L.B[r * LDK + c] = wsc * L.A[r * LDK + c] + woc * L.A[r * LDK + pc];
+        } else {
+          for (int r = r0; r < k; r += P) L.B[r * LDK + c] = L.A[r * LDK + c];
+        }
+      }
+      __syncthreads();
+      if (act) {  // A = J^T B on and above the diagonal, mirrored; exact 2x2 blocks
+        const int pc = L.pt[c];
+        const double fdc = L.fd[c];
+        for (int r = r0; r <= c; r += P) {
+          const int pr = L.pt[r];
+          double v;
+          if (r == c && pc >= 0) v = fdc;
+          else if (pr == c) v = 0.0;
+          else v = pr >= 0 ? L.ws[r] * L.B[r * LDK + c] + L.wo[r] * L.B[pr * LDK + c]
+                           : L.B[r * LDK + c];
+          L.A[r * LDK + c] = v;
+          L.A[c * LDK + r] = v;
+        }
+      }
+      __syncthreads();
+    }
+    if (rotated == 0) break;
+  }
+}
+
 __device__ double kappa_from_diag(const JacobiLds& L, int k) {
   double lmin = L.A[0], lmax = L.A[0];
   bool nan = lmin != lmin;
@@ -156,7 +237,9 @@ __device__ double kappa_from_diag(const JacobiLds& L, int k) {
   return lmax / lmin;
 }
 
-// kappa(G_i) of the s-step Gram matrix G (d x d) into info->kappa[i-1].
+// kappa(G_i) of the s-step Gram matrix G (d x d) into info->kappa[i-1]
+// (WAVE: by jacobi_wave in a 64-thread workgroup, else by jacobi).
+template <bool WAVE>
 __device__ void kappa_body(JacobiLds& L, const double* __restrict__ G, int d, int s, int first,
                            int i, sscg_block_info* info) {
   int k = first ? i + 1 : 2 * i + 1;
@@ -166,7 +249,8 @@ __device__ void kappa_body(JacobiLds& L, const double* __restrict__ G, int d, in
     for (int a = 0; a < k; ++a) L.A[a * LDK + b] = G[sub_index(a, i, s, first) * d + gb];
   }
   __syncthreads();
-  jacobi(L, k);
+  if (WAVE) jacobi_wave(L, k);
+  else jacobi(L, k);
   if (threadIdx.x == 0) info->kappa[i - 1] = kappa_from_diag(L, k);
 }
 
@@ -176,7 +260,7 @@ __global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int 
                                               const int* __restrict__ stop) {
   __shared__ JacobiLds L;
   if (stop && *stop) return;
-  kappa_body(L, G, d, s, first, blockIdx.x + 1, info);
+  kappa_body<false>(L, G, d, s, first, blockIdx.x + 1, info);
 }
 
 // Eigenvalue extremes of the Lanczos tridiagonal matrix (k <= MAXK).
@@ -586,15 +670,16 @@ __global__ void k_batch_plan(BatchCfg c) {
   c.prm[q] = prm;
 }
 
-// grid (s_max, systems): kappa(G_i) of system blockIdx.y, i = blockIdx.x + 1.
-__global__ __launch_bounds__(JT) void k_kappa_batch(BatchCfg c) {
+// grid (s_max, systems): kappa(G_i) of system blockIdx.y, i = blockIdx.x + 1, one
+// wavefront each (many small problems at once: throughput over latency).
+__global__ __launch_bounds__(SSCG_WAVE) void k_kappa_batch(BatchCfg c) {
   __shared__ JacobiLds L;
   const int q = blockIdx.y, i = blockIdx.x + 1;
   if (c.sys[q].done) return;
   const sscg_block_params prm = c.prm[q];
   if (!prm.adaptive || i > prm.s) return;
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  kappa_body(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
+  kappa_body<true>(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
 }
 
 // Coordinate solve of system blockIdx.x, then the block's commit.
@@ -668,7 +753,7 @@ hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st) {
 }
 
 hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_kappa_batch, dim3(c.S, c.nsys), dim3(JT), 0, st, c);
+  hipLaunchKernelGGL(k_kappa_batch, dim3(c.S, c.nsys), dim3(SSCG_WAVE), 0, st, c);
   return hipGetLastError();
 }
 
