@@ -60,10 +60,12 @@ hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* 
     c->ev.push_back(r);
   }
   *slot = c->ev_used++;
-  c->ev[*slot].fam = fam;
-  c->ev[*slot].bytes = bytes;
-  c->ev[*slot].gated = false;
-  return hipEventRecord(c->ev[*slot].a, st);
+  EvRec& r = c->ev[*slot];
+  r.fam = fam;
+  r.bytes = bytes;
+  r.nsub = 0;
+  r.ran0 = 0;
+  return hipEventRecord(r.a, st);
 }
 
 hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st) {
@@ -71,16 +73,41 @@ hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st) {
   return hipEventRecord(c->ev[slot].b, st);
 }
 
-int* ev_ran(sscg_ctx* c, size_t slot) {
-  if (slot == NO_EVENT || slot >= RAN_CAP || !c->ran.p) return nullptr;
-  c->ev[slot].gated = true;
-  return as<int>(c->ran) + slot;
+int* ev_sub(sscg_ctx* c, size_t slot, double bytes) {
+  if (slot == NO_EVENT || !c->ran.p) return nullptr;
+  EvRec& r = c->ev[slot];
+  // a group's flags are consecutive: taken when its first launch registers
+  if (r.nsub == 0) r.ran0 = c->ran_used;
+  if (r.nsub >= SSCG_S_LIMIT || r.ran0 + r.nsub >= RAN_CAP || r.ran0 + r.nsub != c->ran_used)
+    return nullptr;  // out of flags: the launch is timed without one
+  r.sbytes[r.nsub] = bytes;
+  r.nsub += 1;
+  return as<int>(c->ran) + c->ran_used++;
 }
 
-// Accumulate the recorded pairs (the streams must have passed them).  Gated
-// launches that stood down are left out: they moved none of their bytes.
+int* ev_ran(sscg_ctx* c, size_t slot) {
+  if (slot == NO_EVENT) return nullptr;
+  int* f = ev_sub(c, slot, c->ev[slot].bytes);
+  if (f) c->ev[slot].bytes = 0.0;  // now carried by the gated launch
+  return f;
+}
+
+// Forget recorded intervals without counting them; their ran flags are
+// cleared (on the stream, ahead of any later launch that may set them).
+hipError_t ev_drop(sscg_ctx* c) {
+  hipError_t e = hipSuccess;
+  const size_t nr = std::min(c->ran_used, RAN_CAP);
+  if (c->ran.p && nr) e = hipMemsetAsync(c->ran.p, 0, sizeof(int) * nr, c->stream);
+  c->ev_used = 0;
+  c->ran_used = 0;
+  return e;
+}
+
+// Accumulate the recorded intervals (the streams must have passed them).
+// Gated launches that stood down are left out: they moved none of their
+// bytes; an interval none of whose launches ran is left out entirely.
 hipError_t ev_collect(sscg_ctx* c) {
-  const size_t nr = std::min(c->ev_used, RAN_CAP);
+  const size_t nr = std::min(c->ran_used, RAN_CAP);
   if (c->ran.p && nr) {
     c->hran.assign(nr, 0);
     hipError_t e = hipMemcpy(c->hran.data(), c->ran.p, sizeof(int) * nr, hipMemcpyDeviceToHost);
@@ -88,15 +115,24 @@ hipError_t ev_collect(sscg_ctx* c) {
     if (e != hipSuccess) return e;
   }
   for (size_t i = 0; i < c->ev_used; ++i) {
-    if (c->ev[i].gated && !c->hran[i]) continue;
+    const EvRec& r = c->ev[i];
+    int launches = r.nsub == 0 ? 1 : 0;
+    double bytes = r.bytes;
+    for (int k = 0; k < r.nsub; ++k)
+      if (c->hran[r.ran0 + k]) {
+        launches += 1;
+        bytes += r.sbytes[k];
+      }
+    if (launches == 0) continue;
     float t = 0.f;
-    hipError_t e = hipEventElapsedTime(&t, c->ev[i].a, c->ev[i].b);
+    hipError_t e = hipEventElapsedTime(&t, r.a, r.b);
     if (e != hipSuccess) return e;
-    c->launches[c->ev[i].fam] += 1;
-    c->ms[c->ev[i].fam] += t;
-    c->bytes[c->ev[i].fam] += c->ev[i].bytes;
+    c->launches[r.fam] += launches;
+    c->ms[r.fam] += t;
+    c->bytes[r.fam] += bytes;
   }
   c->ev_used = 0;
+  c->ran_used = 0;
   return hipSuccess;
 }
 
@@ -168,6 +204,9 @@ ColPtr colptr_of(const BasisCols& bc, int s, int first) {
 int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
                int64_t nnz, const int* stop, const MpkResidual& res) {
   const int n = M.n;
+  // the s passes run back to back: one timed interval, a ran flag per pass
+  size_t slot = 0;
+  HIPCHK(ev_begin(ctx, 0, 0.0, ctx->stream, &slot));
   for (int j = 1; j <= s; ++j) {
     MpkSeq sp{bc.P(j - 1), j >= 2 ? bc.P(j - 2) : nullptr, bc.P(j)};
     MpkSeq sr{nullptr, nullptr, nullptr};
@@ -179,12 +218,10 @@ int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, co
     const bool withres = j == 1 && res.x;
     double vec = 2.0 * nrhs + ((bp.cheb && j >= 2) ? nrhs : 0) + (withres ? 2 : 0);
     double bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n * vec;
-    size_t slot = 0;
-    HIPCHK(ev_begin(ctx, 0, bytes, ctx->stream, &slot));
-    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, Gate{stop, ev_ran(ctx, slot)},
+    HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, Gate{stop, ev_sub(ctx, slot, bytes)},
                            withres ? res : MpkResidual{}, ctx->stream));
-    HIPCHK(ev_end(ctx, slot, ctx->stream));
   }
+  HIPCHK(ev_end(ctx, slot, ctx->stream));
   return SSCG_OK;
 }
 
@@ -512,7 +549,7 @@ int sscg_set_timing(sscg_ctx* ctx, int families) {
     ctx->ms[f] = 0;
     ctx->bytes[f] = 0;
   }
-  ctx->ev_used = 0;
+  HIPCHK(ev_drop(ctx));
   return SSCG_OK;
 }
 

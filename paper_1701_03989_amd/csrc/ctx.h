@@ -33,11 +33,16 @@ struct BatchWs {
   Buf sys, prm, info, G, coef, hist, blk_sys, chunks, rpart, bpart, gpart, active;
 };
 
+// One timed interval on a stream: a single launch, or a group of launches
+// enqueued back to back (the passes of one matrix-powers build), each with
+// its bytes and, when gated, a ran flag of its own (ran[ran0 + i]).
 struct EvRec {
   hipEvent_t a, b;
   int fam;
-  double bytes;
-  bool gated;  // the launch reports through ran[slot] whether it ran
+  double bytes;                  // ungated interval: its bytes, one launch
+  int nsub;                      // gated launches in the interval
+  size_t ran0;                   // first ran flag of the interval
+  double sbytes[SSCG_S_LIMIT];   // bytes of each gated launch
 };
 
 }  // namespace sscg_host
@@ -63,6 +68,7 @@ struct sscg_ctx {
   double bytes[sscg_host::NFAM] = {0, 0, 0, 0};
   std::vector<sscg_host::EvRec> ev;
   size_t ev_used = 0;
+  size_t ran_used = 0;  // ran flags handed out since the last collection
   sscg_host::Buf ran;  // int[RAN_CAP] device flags of gated timed launches (zero between uses)
   std::vector<int> hran;
   sscg_host::BatchWs batch;
@@ -91,9 +97,13 @@ constexpr size_t NO_EVENT = ~(size_t)0;
 hipError_t ev_begin(sscg_ctx* c, int fam, double bytes, hipStream_t st, size_t* slot);
 hipError_t ev_end(sscg_ctx* c, size_t slot, hipStream_t st);
 // The ran flag of a timed launch (NULL if the slot is not timed): only launches
-// whose first workgroup ran are counted by the statistics.
+// whose first workgroup ran are counted by the statistics.  ev_ran: the
+// slot's single launch (its bytes from ev_begin); ev_sub: one more launch of
+// a group timed as one interval (up to SSCG_S_LIMIT per slot).
 int* ev_ran(sscg_ctx* c, size_t slot);
+int* ev_sub(sscg_ctx* c, size_t slot, double bytes);
 hipError_t ev_collect(sscg_ctx* c);
+hipError_t ev_drop(sscg_ctx* c);
 
 int check_csr(sscg_ctx* ctx, const sscg_csr* A);
 int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M);

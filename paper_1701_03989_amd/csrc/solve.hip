@@ -56,7 +56,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   const sscg_opts& o = *opts;
   const int n = A->n;
   hipStream_t S1 = ctx->stream, S2 = ctx->side;
-  ctx->ev_used = 0;
+  HIPCHK(ev_drop(ctx));
 
   DevMat M;
   if ((rc = build_mat(ctx, A, o.equilibrate, &M))) return rc;
