@@ -535,6 +535,8 @@ def main():
     ap.add_argument("--c-mode", choices=["const", "theory"], default="const",
                     help="c_{k,j}: the constant 1, or 6 N_k j kappa(A) of Section 4.1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-classical", action="store_true",
+                    help="skip timing classical CG (s = 1) beside the s-step solve")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
@@ -628,6 +630,29 @@ def main():
     brk = {f: sscg.sscg_kernel_stats(ctx, f) for f in sscg.FAMILIES}
     sscg.sscg_set_timing(ctx, False)
     relres = float(np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b))
+    # classical CG on the same system and tolerance: s_k = 1 in every block
+    # (Section 4.2), through the same kernels; time to solution for context
+    classical = None
+    if not args.no_classical:
+        oc = sscg.make_opts(mode="fixed", fixed_s=1, s_max=wl["s_max"], tol=wl["tol"])
+        hc = sscg.History(1 << 14, wl["s_max"])
+        xd.copy_(x1d)
+        sscg.sscg_solve(ctx, Ad, bd, xd, oc, hc)  # warm-up
+        kc = max(1, min(args.steps, 5))
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for _ in range(kc):
+            xd.copy_(x1d)
+            rc = sscg.sscg_solve(ctx, Ad, bd, xd, oc, hc)
+            assert rc == sscg.OK, f"classical CG status {rc}"
+        torch.cuda.synchronize()
+        wc = time.perf_counter() - tc
+        xc = xd.cpu().numpy()
+        classical = {
+            "solves_per_s": kc / wc, "ms_per_solve": wc / kc * 1e3, "iters": int(hc.res.iters),
+            "relres": float(np.linalg.norm(b - A.matvec(xc)) / np.linalg.norm(b)),
+            "method": "Algorithm 2 with s = 1 (classical CG), same kernels and tolerance",
+        }
     sscg.sscg_destroy(ctx)
 
     n_mpk, ms_mpk, by_mpk = stats["mpk"]
@@ -662,6 +687,7 @@ def main():
         "blocks": hist.blocks,
         "iters": int(hist.res.iters),
         "schedule_head": sched[:12],
+        "classical_cg": classical,
         "lambda": [hist.res.lambda_min, hist.res.lambda_max],
         "basis_gram_gbs": bg_gbs,
         "basis_gram_frac": bg_gbs / HBM_PEAK_GBS,
