@@ -428,6 +428,7 @@ def bench_serve(args) -> None:
     srv = sscg.sscg_server_create(ctx, opts, pool_rows, pool_nnz, args.serve_slots)
     torch.cuda.synchronize()
     done_at = np.full(nreq, np.nan)
+    status = np.full(nreq, -99)
     rid = {}
     pending = set()
     i = 0
@@ -452,7 +453,9 @@ def bench_serve(args) -> None:
             for r in list(pending):
                 p = sscg.sscg_server_poll(ctx, srv, r)
                 if p["state"] == 2:
-                    assert p["status"] == sscg.OK, p
+                    # a tolerance below what the method attains ends in
+                    # BREAKDOWN or NOT_CONVERGED (Algorithm 4 has no restart)
+                    status[rid[r]] = p["status"]
                     done_at[rid[r]] = t
                     pending.discard(r)
     makespan = float(np.nanmax(done_at))
@@ -460,11 +463,18 @@ def bench_serve(args) -> None:
     sscg.sscg_server_destroy(srv)
     # accuracy of every served result, recomputed in FP64 on the host
     worst = 0.0
+    unmet = []
     for k in range(nreq):
         s = ops[which[k]]
         b = bs[k].cpu().numpy()
         x = xs[k].cpu().numpy()
-        worst = max(worst, float(np.linalg.norm(b - s.A.matvec(x)) / np.linalg.norm(b) / tols[k]))
+        rel = float(np.linalg.norm(b - s.A.matvec(x)) / np.linalg.norm(b))
+        if status[k] == sscg.OK:
+            worst = max(worst, rel / tols[k])
+        else:
+            unmet.append({"request": k, "n": s.A.n, "operator": s.kind, "tol": float(tols[k]),
+                          "status": int(status[k]), "relres": rel})
+    met = int(np.sum(status == sscg.OK))
     # one at a time, first come first served, with the measured solve times
     h1 = sscg.History(8192, 8)
     clock, seq_lat = 0.0, []
@@ -477,13 +487,13 @@ def bench_serve(args) -> None:
         ts = time.perf_counter()
         rc = sscg.sscg_solve(ctx, devA[which[k]], bs[k], xs[k], o1, h1)
         d = time.perf_counter() - ts
-        assert rc == sscg.OK
+        assert rc == status[k], (k, rc, status[k])  # the same bits as served
         clock = max(clock, arrive[k]) + d
         seq_lat.append(clock - arrive[k])
     sscg.sscg_destroy(ctx)
     out = {
         "metric": "served solves/s + p50/p99 latency (arrival to result) at per-request relres",
-        "value": nreq / makespan,
+        "value": met / makespan,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": steps,
@@ -506,7 +516,9 @@ def bench_serve(args) -> None:
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "worst_relres_over_tol": worst,
-        "sequential_solves_per_s": nreq / max(clock, 1e-9),
+        "requests_meeting_tol": met,
+        "requests_unmet": unmet,
+        "sequential_solves_per_s": met / max(clock, 1e-9),
         "sequential_p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
         "sequential_p99_ms": float(np.percentile(seq_lat, 99) * 1e3),
         "generation_s": t_gen,
@@ -659,7 +671,8 @@ def main():
     mpk_gbs = by_mpk / (ms_mpk * 1e-3) / 1e9
     bg_by = brk["mpk"][2] + brk["gram"][2]
     bg_gbs = bg_by / ((brk["mpk"][1] + brk["gram"][1]) * 1e-3) / 1e9
-    traffic = traffic_from_profile()
+    # the committed counters were taken on the default workload and options
+    traffic = traffic_from_profile() if not variant and args.workload == "poisson3d_128" else None
     sched = hist.schedule
     out = {
         "metric": METRIC,
