@@ -66,6 +66,14 @@ __device__ __forceinline__ dd dd_wave_reduce(dd a) {
   return a;
 }
 
+// Batched kernels keep the natural workgroup order instead: consecutive
+// 256-row blocks then run on all eight XCDs at once, so the whole device
+// sweeps one system at a time and that system's vectors stay in the shared
+// Infinity Cache while its (possibly random) gathers reuse them; with one
+// contiguous range per XCD, eight systems' streams would share the cache at
+// once.  Measured: 256-system batch 609 -> 675 systems/s, serving 5.2 -> 8.6
+// solves/s; the single solve of a stencil keeps the remap (1.4 % faster).
+//
 // Workgroup index remapped so that each XCD works on one contiguous range of
 // logical blocks (workgroups are dispatched to XCDs round-robin): neighbouring
 // rows then share an L2.  Launch exactly xcd_grid(nb) workgroups; a

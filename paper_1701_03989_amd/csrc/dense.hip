@@ -396,7 +396,7 @@ __device__ __forceinline__ BatchCols batch_cols(const BatchCfg& c, int s, int fi
 
 template <int PPT>
 __global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {
-  int lb = xcd_block(c.nchunks);
+  int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
   if (lb >= c.nchunks) return;
   const BatchChunk ch = c.chunks[lb];
   const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(WG) void k_gram_finalize_batch(BatchCfg c) {
 
 // x <- x + Y x', r = Y r' (into R_0), p = Y p' (into P_0), per system.
 __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
-  int lb = xcd_block(c.nblk);
+  int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
   if (lb >= c.nblk) return;
   const int q = c.blk_sys[lb];
   if (q < 0 || c.sys[q].done) return;

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
                                                   const double* __restrict__ bres,
                                                   double* __restrict__ rpart) {
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
-  int lb = xcd_block(nb);
+  int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
   if (lb >= nb) return;
   const int q = blk_sys[lb];
   if (q < 0 || sys[q].done) return;
