@@ -187,12 +187,22 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   HIPCHK(launch_sell_fill(A->rowptr, A->col, A->val, n, scale, as<int64_t>(ctx->off),
                           as<int32_t>(ctx->width),
                           as<int32_t>(ctx->scol), as<double>(ctx->sval), ctx->stream));
+  // 16-bit column offsets for the matrix-powers pass when every one fits
+  HIPCHK(ensure(ctx->scol16, sizeof(int16_t) * total));
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_sell_compact(as<int32_t>(ctx->scol), n, as<int64_t>(ctx->off),
+                             as<int32_t>(ctx->width), as<int16_t>(ctx->scol16), flag,
+                             ctx->stream));
+  int32_t wide = 1;
+  HIPCHK(hipMemcpyAsync(&wide, flag, sizeof wide, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   M->n = n;
   M->nslices = nslices;
   M->off = as<int64_t>(ctx->off);
   M->width = as<int32_t>(ctx->width);
   M->col = as<int32_t>(ctx->scol);
   M->val = as<double>(ctx->sval);
+  M->col16 = wide ? nullptr : as<int16_t>(ctx->scol16);
   return SSCG_OK;
 }
 
@@ -506,7 +516,8 @@ void sscg_destroy(sscg_ctx* c) {
   if (c->side) (void)hipStreamSynchronize(c->side);
   Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y,    &c->part,
                  &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
-                 &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran};
+                 &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran,   &c->scol16,
+                 &c->sval32, &c->Y32, &c->dx,  &c->r64};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   BatchWs& w = c->batch;

@@ -102,6 +102,11 @@ struct DevMat {
   const int32_t* width;   // entries per row of each slice
   const int32_t* col;
   const double* val;
+  // Optional copy of col as 16-bit offsets from the slice's first row
+  // (col = 64 t + col16 for an entry of slice t; padding rows past n hold 0),
+  // present when every offset fits: the matrix-powers pass then reads 10
+  // bytes per entry instead of 12.
+  const int16_t* col16 = nullptr;
 };
 
 // Basis parameters of the three-term recurrence (monomial: theta = 0,
@@ -161,6 +166,11 @@ hipError_t launch_row_scale(const int32_t* rowptr, const double* val, int n, dou
 hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const double* val, int n,
                             const double* scale, const int64_t* off, const int32_t* width,
                             int32_t* scol, double* sval, hipStream_t st);
+// col16[e] = scol[e] - 64 t for the entries of slice t (0 for rows >= n); sets
+// *flag if an offset falls outside the int16 range.
+hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
+                               const int32_t* width, int16_t* col16, int32_t* flag,
+                               hipStream_t st);
 
 // One matrix-powers pass: for each of nrhs (1 or 2) sequences v,
 // out = RN(A u - theta u - sigma w) / gamma_{j-1}, j >= 1 (w unused for j = 1).

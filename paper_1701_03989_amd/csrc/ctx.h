@@ -54,6 +54,7 @@ struct sscg_ctx {
   std::string err;
   // matrix copy
   sscg_host::Buf width, off, scol, sval, scale;
+  sscg_host::Buf scol16;  // 16-bit column offsets of the SELL copy (when they fit)
   // solver workspace
   sscg_host::Buf Y, part, rpart, G, coef, info, scal, xw, bw, x1, lz, lzab, ctl;
   sscg_block_info* hinfo = nullptr;  // pinned, RING entries

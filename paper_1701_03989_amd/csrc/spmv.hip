@@ -110,6 +110,32 @@ __global__ __launch_bounds__(WG) void k_sell_fill(const int32_t* __restrict__ ro
   }
 }
 
+// 16-bit column offsets from each slice's first row (one thread per row).
+__global__ __launch_bounds__(WG) void k_sell_compact(const int32_t* __restrict__ scol, int n,
+                                                     const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ width,
+                                                     int nslices, int16_t* __restrict__ col16,
+                                                     int32_t* __restrict__ flag) {
+  const int row = blockIdx.x * WG + threadIdx.x;
+  const int slice = row / SSCG_WAVE;
+  if (slice >= nslices) return;
+  const int lane = row & (SSCG_WAVE - 1);
+  const int64_t o = off[slice];
+  const int w = width[slice];
+  const int base = slice * SSCG_WAVE;
+  int bad = 0;
+  for (int j = 0; j < w; ++j) {
+    const int64_t e = o + (int64_t)j * SSCG_WAVE + lane;
+    int d = 0;
+    if (row < n) {
+      d = scol[e] - base;
+      bad |= d < -32768 || d > 32767;
+    }
+    col16[e] = (int16_t)d;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------- MPK pass
 //
 // Pass j of the matrix-powers kernel for one or two sequences (P and R of
@@ -125,7 +151,7 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 
 // The rows of one slice (lane = row within it); returns the lane's res_i^2
 // contribution when RES.
-template <int NRHS, bool CHEB, bool HASW, bool RES>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeq& s0, const MpkSeq& s1,
                                         const double* __restrict__ xres,
@@ -150,7 +176,8 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
         int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
         bool in = j0 + u < w;
         v[u] = in ? A.val[k] : 0.0;
-        c[u] = in ? A.col[k] : 0;
+        if (C16) c[u] = in ? slice * SSCG_WAVE + (int)A.col16[k] : 0;
+        else c[u] = in ? A.col[k] : 0;
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -193,7 +220,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   return r2;
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool RES>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16>
 __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
                                             MpkSeq s0, MpkSeq s1, Gate gate,
                                             const double* __restrict__ xres,
@@ -204,7 +231,8 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   int lb = xcd_block(nb);
   if (lb >= nb) return;
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16>(A, slice, theta, sigma, gamma, s0, s1, xres,
+                                                  bres);
   if (RES) wg_store_partial(r2, rpart, lb);
 }
 
@@ -462,6 +490,16 @@ hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
   return hipGetLastError();
 }
 
+hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
+                               const int32_t* width, int16_t* col16, int32_t* flag,
+                               hipStream_t st) {
+  int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
+  int threads = nslices * SSCG_WAVE;
+  hipLaunchKernelGGL(k_sell_compact, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, scol, n, off,
+                     width, nslices, col16, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32_t* width,
                                 hipStream_t st) {
   hipLaunchKernelGGL(k_sell_widths, dim3(wg_count(nslices)), dim3(WG), 0, st, rowptr, n, nslices,
@@ -497,15 +535,24 @@ hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s
   return hipGetLastError();
 }
 
+template <int NRHS, bool CHEB, bool HASW, bool C16>
+void mpk_launch_c(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
+                  MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
+  if (res.x)
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16>), grid, dim3(WG), 0, st, A, theta,
+                       sigma, gamma, s0, s1, g, res.x, res.b, res.part);
+  else
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16>), grid, dim3(WG), 0, st, A, theta,
+                       sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
+}
+
 template <int NRHS, bool CHEB, bool HASW>
 void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                 MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
-  if (res.x)
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true>), grid, dim3(WG), 0, st, A, theta, sigma,
-                       gamma, s0, s1, g, res.x, res.b, res.part);
+  if (A.col16)
+    mpk_launch_c<NRHS, CHEB, HASW, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
   else
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false>), grid, dim3(WG), 0, st, A, theta, sigma,
-                       gamma, s0, s1, g, nullptr, nullptr, nullptr);
+    mpk_launch_c<NRHS, CHEB, HASW, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
 }
 
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
