@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -199,6 +200,33 @@ def cpu_baseline(A, b, x1, wl, gpu_blocks, budget_s=20.0):
     blocks = len(res.blocks)
     per_block = t_blocks / max(blocks, 1)
     t_solve = t_int + per_block * gpu_blocks
+    # the first outer block again on one core (a child process with one
+    # OpenMP thread; the interval estimate scaled by the same ratio)
+    one = None
+    code = ("import sys, time; sys.path.insert(0, %r); import numpy as np; "
+            "from oracle import sstep; from paper_1701_03989_amd import problems; "
+            "A, b, x1 = problems.poisson3d_128_system(0, N=%d); "
+            "o = sstep.Opts(mode='adaptive', basis='chebyshev', s_max=%d, tol=%r, lmin=%r, "
+            "lmax=%r, max_iters=1); t = time.perf_counter(); sstep.solve(A, b, x1, o); "
+            "print(time.perf_counter() - t)") % (os.path.dirname(os.path.abspath(__file__)),
+                                                  wl["N"], wl["s_max"], wl["tol"], lmin, lmax)
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=300)
+        t1b = float(r.stdout.strip().splitlines()[-1])
+        ratio = t1b / max(t_first, 1e-9)
+        one = {"value": 1.0 / (t_int * ratio + t1b * gpu_blocks), "s_per_block": t1b,
+               "sample": f"first outer block on 1 core ({t1b:.2f} s vs {t_first:.2f} s on "
+                         f"{native.num_threads()}); interval estimate scaled by the same ratio"}
+    except (OSError, ValueError, IndexError, subprocess.SubprocessError):
+        one = None
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                     if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
         "value": 1.0 / t_solve,
         "unit": "solves/s",
@@ -207,6 +235,9 @@ def cpu_baseline(A, b, x1, wl, gpu_blocks, budget_s=20.0):
         "sample": (f"Chebyshev interval estimate ({t_int:.2f} s) + first {blocks} outer blocks "
                    f"({t_blocks:.2f} s, {per_block:.2f} s/block) of the same solve; solve time "
                    f"extrapolated to the GPU run's {gpu_blocks} blocks"),
+        "single_core": one,
+        "nproc": os.cpu_count(),
+        "cpu_model": model,
     }
 
 
@@ -357,8 +388,12 @@ def bench_precision(args) -> None:
                          relres=float(np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)),
                          iters=int(hist.res.iters), blocks=int(hist.res.blocks),
                          lam=[hist.res.lambda_min, hist.res.lambda_max])
+    # the spectral estimate (30 Lanczos steps, Gershgorin) of the raw matrix; the solve's own
+    # interval is that of the matrix it iterates on (equilibrated when equilibrating)
+    raw_lo, raw_hi = sscg.sscg_spectral_bounds(ctx, Ad, 30, 0)
     sscg.sscg_destroy(ctx)
     xm, x64 = res["mixed"]["x"], res["fp64"]["x"]
+    lam = res["fp64"]["lam"]
     out = {
         "metric": "solves/s at the target relres, mixed precision (FP32 basis, FP64 refinement) "
                   "vs plain FP64",
@@ -381,7 +416,11 @@ def bench_precision(args) -> None:
         "error_mixed_vs_fp64": float(np.linalg.norm(xm - x64) / np.linalg.norm(x64)),
         "iters_mixed": res["mixed"]["iters"], "blocks_mixed": res["mixed"]["blocks"],
         "iters_fp64": res["fp64"]["iters"], "blocks_fp64": res["fp64"]["blocks"],
-        "lambda": res["fp64"]["lam"],
+        "lambda": lam,
+        "kappa_estimate": {"raw": raw_hi / raw_lo,
+                           ("equilibrated" if kw.get("equilibrate") else "solved"): lam[1] / lam[0],
+                           "method": "Gershgorin lambda_max / smallest Ritz value of 30 "
+                                     "Lanczos steps"},
     }
     print(json.dumps(out), flush=True)
 
