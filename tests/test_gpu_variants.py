@@ -272,3 +272,56 @@ def test_unsupported_variant_combinations_are_rejected(ctx):
         sscg.sscg_solve(ctx, Ad, dvec(b), dvec(x1),
                         sscg.make_opts(basis="newton", s_max=4, shifts=[1.0, math.inf, 2.0, 3.0]))
     assert e.value.code == sscg.ERR_ARG
+
+
+def banded_far(n, D, seed):
+    """SPD: tridiagonal plus a coupling at distance D in every row that has one
+    (diagonally dominant), CSR with ascending columns."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    off1 = -rng.uniform(0.1, 0.5, n - 1)
+    offD = -rng.uniform(0.1, 0.5, n - D)
+    M = sp.diags([off1, off1, offD, offD], [1, -1, D, -D], shape=(n, n), format="lil")
+    M.setdiag(2.5)
+    M = M.tocsr()
+    M.sort_indices()
+    return problems.CSR(M.indptr.astype(np.int32), M.indices.astype(np.int32),
+                        M.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("D", [32700, 32768, 40000])
+def test_column_offset_formats(ctx, D):
+    """The matrix-powers pass reads 16-bit column offsets from the slice's first
+    row when every one fits (D = 32700: at most 32700 + 63), else the 32-bit
+    indices (D = 32768, 40000): same bits as the oracle either way."""
+    A = banded_far(D + 4000, D, 3)
+    n, s = A.n, 5
+    lo, hi = 0.5, 4.5  # Gershgorin interval of banded_far
+    p = problems.uniform(n, 31)
+    r = problems.uniform(n, 32)
+    ar = CR()
+    Yo = sstep.krylov_basis(ar, A, p, r, s, False, sstep.basis_params("chebyshev", s, lo, hi, ar))
+    ld = (n + 63) // 64 * 64
+    rcol = s + 1
+    Y = torch.zeros((2 * s + 1) * ld, dtype=torch.float64, device=DEV)
+    Y[:n] = dvec(p)
+    Y[rcol * ld: rcol * ld + n] = dvec(r)
+    say(f"column offsets: n={n}, coupling distance {D}")
+    sscg.sscg_mpk(ctx, sscg.DeviceCsr.from_host(A, DEV), s, False, sscg.BASIS_CHEBYSHEV, lo, hi, Y,
+                  ld, rcol)
+    Yh = host(Y)
+    cols = list(range(s + 1)) + list(range(rcol, rcol + s))
+    for a, c in enumerate(cols):
+        assert_bits(Yh[c * ld: c * ld + n], Yo[a], f"Y col {a}")
+    # and a whole solve through sscg_solve
+    b = problems.uniform(n, 33)
+    ref = sstep.solve(A, b, np.zeros(n), sstep.Opts(mode="adaptive", basis="chebyshev", lmin=lo,
+                                                     lmax=hi, s_max=6, tol=1e-12))
+    x = dvec(np.zeros(n))
+    h = sscg.History(512, 6)
+    rc = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(A, DEV), dvec(b), x,
+                         sscg.make_opts(mode="adaptive", basis="chebyshev", lmin=lo, lmax=hi,
+                                        s_max=6, tol=1e-12), h)
+    assert rc == ref.status and h.schedule == ref.schedule
+    assert np.linalg.norm(host(x) - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
