@@ -2,7 +2,7 @@
 // to the end of the inner loop), solved in LDS by single wavefronts.
 //
 // k_kappa: kappa(G_i) = lambda_max / lambda_min of every candidate sub-Gram
-//   G_i (Section 4.2), one workgroup (one wave) per i, by two-sided cyclic
+//   G_i (Section 4.2), one workgroup per i, by two-sided cyclic
 //   Jacobi with the parallel round-robin ordering (Golub & Van Loan, Sec.
 //   8.5).  The operation sequence is fixed (skip rule, rotation formulas,
 //   column-then-row application, mirroring of the upper triangle, exact
@@ -26,209 +26,180 @@ __device__ __forceinline__ int sub_index(int a, int i, int s, int first) {
 
 // Round-robin position of slot i at step t (m even).
 __device__ __forceinline__ int rr_pos(int i, int t, int m) {
-  return i == 0 ? 0 : 1 + ((i - 1 + t) % (m - 1));
+  const int x = i - 1 + t;  // below 2 (m - 1) for 0 < i < m and 0 <= t < m - 1
+  return i == 0 ? 0 : 1 + (x >= m - 1 ? x - (m - 1) : x);
 }
 
+#ifndef SSCG_JT
+#define SSCG_JT 192
+#endif
+constexpr int JT = SSCG_JT;  // threads of a single Jacobi problem (latency)
+
+// LDS of one Jacobi eigenvalue problem: the matrix before and after a step,
+// and the rotations of two steps (those of step g + 1 are formed while step g
+// is applied, so that a step costs one barrier).
 struct JacobiLds {
-  double A[MAXK * LDK];  // the matrix, row-major, both triangles kept equal
-  double B[MAXK * LDK];  // A J of the current step
-  double ws[MAXK], wo[MAXK];  // weights of index i: new_i = ws*old_i + wo*old_partner
-  double fd[MAXK];            // exact diagonal of a rotated index after the step
-  int pt[MAXK];               // partner of index i in this step, -1 if not rotated
-  int nrot[2];
+  double A[2][MAXK * LDK];          // the matrix, row-major, both triangles kept equal
+  double ws[2][MAXK], wo[2][MAXK];  // weights of index i: new_i = ws*old_i + wo*old_partner
+  double fd[2][MAXK];               // exact diagonal of a rotated index after the step
+  int pt[2][MAXK];                  // partner of index i in the step, -1 if not rotated
+  int nrot[2];                      // rotations in the step
 };
 
-// Eigenvalues of the k x k symmetric matrix in L.A (k <= MAXK) by cyclic
-// Jacobi, two mappings of the same operations.  Every matrix entry of a
-// step is computed by the same formula whichever thread computes it, so both
-// give the same bits.
-//
-// jacobi (latency: one problem on four wavefronts, JT threads): thread t owns
-// column t & 63 and rows (t >> 6) + 4j in the application phases; threads
-// t < m/2 form the rotations.
-constexpr int JT = 256;
-constexpr int RPT = (MAXK + 3) / 4;  // rows per thread in the application phases
-__device__ __forceinline__ void jacobi(JacobiLds& L, int k) {
+// Entry (r, c), r <= c, of the matrix after one step (rotation tables ws, wo,
+// fd, pt) from the matrix A before it: B = A J by columns, then the rows of
+// J^T B; a rotated pair keeps the closed form of its diagonal entries and a
+// zero off-diagonal entry.  Every thread that needs an entry computes it by
+// this one sequence of operations, so the result does not depend on which
+// thread (or how many threads) did the work.  The loads are issued in two
+// rounds (the tables and a_rc, then the partners' entries) and the cases are
+// selected at the end; table values of an index that is not rotated are
+// loaded but never used.
+__device__ __forceinline__ double step_entry(const double* A, const double* ws, const double* wo,
+                                             const double* fd, const int* pt, int r, int c) {
+  const int pc = pt[c], pr = pt[r];
+  const double wsc = ws[c], woc = wo[c], wsr = ws[r], wor = wo[r], fdc = fd[c];
+  const double arc = A[r * LDK + c];
+  const int pcc = pc >= 0 ? pc : c, prr = pr >= 0 ? pr : r;
+  double arp = A[r * LDK + pcc], apc = A[prr * LDK + c], app = A[prr * LDK + pcc];
+  // keep the second round of loads unconditional (not sunk into the cases,
+  // which would serialise them); the empty statement changes no value
+  asm volatile("" : "+v"(arp), "+v"(apc), "+v"(app));
+  const double br = pc >= 0 ? wsc * arc + woc * arp : arc;  // B = A J, row r
+  const double bp = pc >= 0 ? wsc * apc + woc * app : apc;  // B = A J, row pr
+  const double v = pr >= 0 ? wsr * br + wor * bp : br;
+  return (r == c && pc >= 0) ? fdc : (pr == c ? 0.0 : v);
+}
+
+// Diagonal entry (i, i) after one step: step_entry(.., i, i), which reduces
+// to the closed form of a rotated index and to a_ii otherwise.
+__device__ __forceinline__ double step_diag(const double* A, const double* fd, const int* pt,
+                                            int i) {
+  const int pi = pt[i];
+  const double f = fd[i], a = A[i * LDK + i];
+  return pi >= 0 ? f : a;
+}
+
+// Rotation of the pair (p, q) from a_pp, a_qq, a_pq at the start of the step
+// (the symmetric 2x2 Schur decomposition); false when the skip rule holds.
+// The rotation is formed alongside the skip test (unused when skipped).
+__device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq, double& cs,
+                                              double& sn, double& tt) {
+  const double thr = EPS * (sqrt(fabs(app)) * sqrt(fabs(aqq)));
+  const double tau = (aqq - app) / (2.0 * apq);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  tt = fabs(tau) > 1e150 ? 0.5 / tau : sg / (fabs(tau) + sqrt(1.0 + tau * tau));
+  cs = 1.0 / sqrt(1.0 + tt * tt);
+  sn = tt * cs;
+  return fabs(apq) > thr;
+}
+
+// Rotations of round-robin step nst (into table slot ^ 1, with their count)
+// from the matrix after the step of table slot applied to L.A[cur].  Lane rl
+// (rl >= 0: the last m/2 threads of the NT) forms pair rl.
+template <int NT>
+__device__ __forceinline__ void form_rotations(JacobiLds& L, int cur, int slot, int k, int m,
+                                               int nst, int rl) {
+  bool rot = false;
+  const int o = slot ^ 1;
+  if (rl >= 0) {
+    const int a = rr_pos(rl, nst, m), b = rr_pos(m - 1 - rl, nst, m);
+    const int p = min(a, b), q = max(a, b);
+    if (q < k) {
+      const double* A = L.A[cur];
+      const double app = step_diag(A, L.fd[slot], L.pt[slot], p);
+      const double aqq = step_diag(A, L.fd[slot], L.pt[slot], q);
+      const double apq = step_entry(A, L.ws[slot], L.wo[slot], L.fd[slot], L.pt[slot], p, q);
+      double cs, sn, tt;
+      if (pair_rotation(app, aqq, apq, cs, sn, tt)) {
+        L.ws[o][p] = cs; L.wo[o][p] = -sn; L.pt[o][p] = q;
+        L.ws[o][q] = cs; L.wo[o][q] = sn; L.pt[o][q] = p;
+        L.fd[o][p] = app - tt * apq;
+        L.fd[o][q] = aqq + tt * apq;
+        rot = true;
+      } else {
+        L.pt[o][p] = -1; L.pt[o][q] = -1;
+      }
+    } else if (p < k) {
+      L.pt[o][p] = -1;
+    }
+  }
+  if ((int)threadIdx.x >= NT - SSCG_WAVE) {  // the wavefront of the rotation lanes
+    const int n = __popcll(__ballot(rot));
+    if ((int)threadIdx.x == NT - 1) L.nrot[o] = n;
+  }
+}
+
+// Eigenvalues of the k x k symmetric matrix in L.A[0] (k <= MAXK) by cyclic
+// Jacobi on NT threads (a multiple of the wavefront); returns the copy of
+// L.A that holds the result.  The first NA threads (all NT for one
+// wavefront, else all but the last wavefront) apply the upper-triangle
+// entries t, t + NA, ... (row by row) of each step; the last m/2 threads form
+// the next step's rotations from the entries they need, so with more than
+// one wavefront the rotations and the application of a step overlap.
+template <int NT>
+__device__ int jacobi(JacobiLds& L, int k) {
+  constexpr int NA = NT == SSCG_WAVE ? NT : NT - SSCG_WAVE;
+  constexpr int EPT = (MAXK * (MAXK + 1) / 2 + NA - 1) / NA;
   const int t = threadIdx.x;
   const int m = (k & 1) ? k + 1 : k;
-  const int c = t & 63;
-  const int cc = c < k ? c : k - 1;  // clamped column: every load is in bounds
-  const int r0 = t >> 6;
+  const int ne = k * (k + 1) / 2;
+  const int rl = t - (NT - m / 2);
+  int er[EPT], ec[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    int e = t + NA * j, r = 0;
+    if (t < NA && e < ne) {
+      while (e >= k - r) {
+        e -= k - r;
+        ++r;
+      }
+      er[j] = r;
+      ec[j] = r + e;
+    } else {
+      er[j] = -1;
+      ec[j] = 0;
+    }
+  }
+  for (int i = t; i < MAXK; i += NT) L.pt[1][i] = -1;  // table 1: a step without rotations
+  if (t == 0) L.nrot[1] = 0;
+  __syncthreads();
+  form_rotations<NT>(L, 0, 1, k, m, 0, rl);
+  __syncthreads();
+  int cur = 0, slot = 0;
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     int rotated = 0;
     for (int st = 0; st < m - 1; ++st) {
-      bool rot = false;
-      if (t < m / 2) {
-        int a = rr_pos(t, st, m), b = rr_pos(m - 1 - t, st, m);
-        int p = min(a, b), q = max(a, b);
-        if (q < k) {
-          double app = L.A[p * LDK + p], aqq = L.A[q * LDK + q], apq = L.A[p * LDK + q];
-          double thr = EPS * (sqrt(fabs(app)) * sqrt(fabs(aqq)));
-          if (fabs(apq) > thr) {
-            double tau = (aqq - app) / (2.0 * apq);
-            double tt;
-            if (fabs(tau) > 1e150) {
-              tt = 0.5 / tau;
-            } else {
-              double sg = tau >= 0.0 ? 1.0 : -1.0;
-              tt = sg / (fabs(tau) + sqrt(1.0 + tau * tau));
-            }
-            double cs = 1.0 / sqrt(1.0 + tt * tt);
-            double s = tt * cs;
-            L.ws[p] = cs; L.wo[p] = -s; L.pt[p] = q;
-            L.ws[q] = cs; L.wo[q] = s; L.pt[q] = p;
-            L.fd[p] = app - tt * apq;
-            L.fd[q] = aqq + tt * apq;
-            rot = true;
-          } else {
-            L.pt[p] = -1; L.pt[q] = -1;
-          }
-        } else if (p < k) {
-          L.pt[p] = -1;
-        }
-      }
-      if (t < 64) {
-        int nr = __popcll(__ballot(rot));
-        if (t == 0) L.nrot[st & 1] = nr;
-      }
-      __syncthreads();
-      const int nr = L.nrot[st & 1];
-      if (nr == 0) continue;
+      const int nr = L.nrot[slot];
       rotated += nr;
-      {  // B = A J, column cc, rows r0 + 4j
-        const int pc = L.pt[cc];
-        const int pcc = pc >= 0 ? pc : cc;
-        const double wsc = L.ws[cc], woc = L.wo[cc];
-        double av[RPT], aw[RPT];
+      if (t < NA && nr) {
+        const double* A = L.A[cur];
+        double* An = L.A[cur ^ 1];
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = min(r0 + 4 * j, k - 1);
-          av[j] = L.A[r * LDK + cc];
-          aw[j] = L.A[r * LDK + pcc];
-        }
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = r0 + 4 * j;
-          const double v = pc >= 0 ? wsc * av[j] + woc * aw[j] : av[j];
-          if (c < k && r < k) L.B[r * LDK + c] = v;
-        }
-      }
-      __syncthreads();
-      {  // A = J^T B on and above the diagonal, mirrored; exact 2x2 blocks
-        const int pc = L.pt[cc];
-        double bv[RPT], bw[RPT], wr[RPT], wq[RPT];
-        int prr[RPT];
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = min(r0 + 4 * j, k - 1);
-          const int pr = L.pt[r];
-          prr[j] = pr;
-          bv[j] = L.B[r * LDK + cc];
-          bw[j] = L.B[(pr >= 0 ? pr : r) * LDK + cc];
-          wr[j] = L.ws[r];
-          wq[j] = L.wo[r];
-        }
-        const double fdc = L.fd[cc];
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = r0 + 4 * j;
-          double v;
-          if (r == c && pc >= 0) v = fdc;
-          else if (prr[j] == c) v = 0.0;
-          else v = prr[j] >= 0 ? wr[j] * bv[j] + wq[j] * bw[j] : bv[j];
-          if (c < k && r <= c) {
-            L.A[r * LDK + c] = v;
-            L.A[c * LDK + r] = v;
+        for (int j = 0; j < EPT; ++j) {
+          if (er[j] >= 0) {
+            const double v =
+                step_entry(A, L.ws[slot], L.wo[slot], L.fd[slot], L.pt[slot], er[j], ec[j]);
+            An[er[j] * LDK + ec[j]] = v;
+            An[ec[j] * LDK + er[j]] = v;
           }
         }
       }
+      form_rotations<NT>(L, cur, slot, k, m, st + 1 < m - 1 ? st + 1 : 0, rl);
+      if (nr) cur ^= 1;
+      slot ^= 1;
       __syncthreads();
     }
     if (rotated == 0) break;
   }
+  return cur;
 }
 
-// jacobi_wave (throughput: one problem per wavefront, many problems at once):
-// lanes t < m/2 form the rotations of a step; in the application phases
-// lane t works on column t % k, rows t / k, t / k + P, ... (P = 64 / k).
-__device__ __forceinline__ void jacobi_wave(JacobiLds& L, int k) {
-  const int t = threadIdx.x;
-  const int m = (k & 1) ? k + 1 : k;
-  const int P = SSCG_WAVE / k;               // lanes per column (>= 1 for k <= 64)
-  const int c = t % k, r0 = t / k;           // column and first row of this lane
-  const bool act = r0 < P;                   // lanes past P * k idle
-  for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-    int rotated = 0;
-    for (int st = 0; st < m - 1; ++st) {
-      bool rot = false;
-      if (t < m / 2) {
-        int a = rr_pos(t, st, m), b = rr_pos(m - 1 - t, st, m);
-        int p = min(a, b), q = max(a, b);
-        if (q < k) {
-          double app = L.A[p * LDK + p], aqq = L.A[q * LDK + q], apq = L.A[p * LDK + q];
-          double thr = EPS * (sqrt(fabs(app)) * sqrt(fabs(aqq)));
-          if (fabs(apq) > thr) {
-            double tau = (aqq - app) / (2.0 * apq);
-            double tt;
-            if (fabs(tau) > 1e150) {
-              tt = 0.5 / tau;
-            } else {
-              double sg = tau >= 0.0 ? 1.0 : -1.0;
-              tt = sg / (fabs(tau) + sqrt(1.0 + tau * tau));
-            }
-            double cs = 1.0 / sqrt(1.0 + tt * tt);
-            double s = tt * cs;
-            L.ws[p] = cs; L.wo[p] = -s; L.pt[p] = q;
-            L.ws[q] = cs; L.wo[q] = s; L.pt[q] = p;
-            L.fd[p] = app - tt * apq;
-            L.fd[q] = aqq + tt * apq;
-            rot = true;
-          } else {
-            L.pt[p] = -1; L.pt[q] = -1;
-          }
-        } else if (p < k) {
-          L.pt[p] = -1;
-        }
-      }
-      const int nr = __popcll(__ballot(rot));
-      __syncthreads();
-      if (nr == 0) continue;
-      rotated += nr;
-      if (act) {  // B = A J, column c
-        const int pc = L.pt[c];
-        if (pc >= 0) {
-          const double wsc = L.ws[c], woc = L.wo[c];
-          for (int r = r0; r < k; r += P) L.B[r * LDK + c] = wsc * L.A[r * LDK + c] + woc * L.A[r * LDK + pc];
-        } else {
-          for (int r = r0; r < k; r += P) L.B[r * LDK + c] = L.A[r * LDK + c];
-        }
-      }
-      __syncthreads();
-      if (act) {  // A = J^T B on and above the diagonal, mirrored; exact 2x2 blocks
-        const int pc = L.pt[c];
-        const double fdc = L.fd[c];
-        for (int r = r0; r <= c; r += P) {
-          const int pr = L.pt[r];
-          double v;
-          if (r == c && pc >= 0) v = fdc;
-          else if (pr == c) v = 0.0;
-          else v = pr >= 0 ? L.ws[r] * L.B[r * LDK + c] + L.wo[r] * L.B[pr * LDK + c]
-                           : L.B[r * LDK + c];
-          L.A[r * LDK + c] = v;
-          L.A[c * LDK + r] = v;
-        }
-      }
-      __syncthreads();
-    }
-    if (rotated == 0) break;
-  }
-}
-
-__device__ double kappa_from_diag(const JacobiLds& L, int k) {
-  double lmin = L.A[0], lmax = L.A[0];
+__device__ double kappa_from_diag(const double* A, int k) {
+  double lmin = A[0], lmax = A[0];
   bool nan = lmin != lmin;
   for (int a = 1; a < k; ++a) {
-    double v = L.A[a * LDK + a];
+    double v = A[a * LDK + a];
     if (v != v) nan = true;
     lmin = v < lmin ? v : lmin;
     lmax = v > lmax ? v : lmax;
@@ -238,20 +209,19 @@ __device__ double kappa_from_diag(const JacobiLds& L, int k) {
 }
 
 // kappa(G_i) of the s-step Gram matrix G (d x d) into info->kappa[i-1]
-// (WAVE: by jacobi_wave in a 64-thread workgroup, else by jacobi).
-template <bool WAVE>
+// by jacobi on the NT threads of the workgroup.
+template <int NT>
 __device__ void kappa_body(JacobiLds& L, const double* __restrict__ G, int d, int s, int first,
                            int i, sscg_block_info* info) {
   int k = first ? i + 1 : 2 * i + 1;
   if (threadIdx.x < k) {
     int b = threadIdx.x;
     int gb = sub_index(b, i, s, first);
-    for (int a = 0; a < k; ++a) L.A[a * LDK + b] = G[sub_index(a, i, s, first) * d + gb];
+    for (int a = 0; a < k; ++a) L.A[0][a * LDK + b] = G[sub_index(a, i, s, first) * d + gb];
   }
   __syncthreads();
-  if (WAVE) jacobi_wave(L, k);
-  else jacobi(L, k);
-  if (threadIdx.x == 0) info->kappa[i - 1] = kappa_from_diag(L, k);
+  const int cur = jacobi<NT>(L, k);
+  if (threadIdx.x == 0) info->kappa[i - 1] = kappa_from_diag(L.A[cur], k);
 }
 
 // grid = s workgroups; workgroup i-1 computes kappa(G_i).
@@ -260,7 +230,7 @@ __global__ __launch_bounds__(JT) void k_kappa(const double* __restrict__ G, int 
                                               const int* __restrict__ stop) {
   __shared__ JacobiLds L;
   if (stop && *stop) return;
-  kappa_body<false>(L, G, d, s, first, blockIdx.x + 1, info);
+  kappa_body<JT>(L, G, d, s, first, blockIdx.x + 1, info);
 }
 
 // Eigenvalue extremes of the Lanczos tridiagonal matrix (k <= MAXK).
@@ -275,15 +245,16 @@ __global__ __launch_bounds__(JT) void k_tridiag_eig(const double* __restrict__ a
       if (a == b) v = alpha[a];
       else if (b == a + 1) v = beta[a];
       else if (a == b + 1) v = beta[b];
-      L.A[a * LDK + b] = v;
+      L.A[0][a * LDK + b] = v;
     }
   }
   __syncthreads();
-  if (k > 1) jacobi(L, k);
+  const int cur = k > 1 ? jacobi<JT>(L, k) : 0;
   if (threadIdx.x == 0) {
-    double lo = L.A[0], hi = L.A[0];
+    const double* D = L.A[cur];
+    double lo = D[0], hi = D[0];
     for (int a = 1; a < k; ++a) {
-      double v = L.A[a * LDK + a];
+      double v = D[a * LDK + a];
       lo = v < lo ? v : lo;
       hi = v > hi ? v : hi;
     }
@@ -308,15 +279,15 @@ __global__ __launch_bounds__(JT) void k_newton_shifts(const double* __restrict__
       if (a == b) v = alpha[a];
       else if (b == a + 1) v = beta[a];
       else if (a == b + 1) v = beta[b];
-      L.A[a * LDK + b] = v;
+      L.A[0][a * LDK + b] = v;
     }
   }
   __syncthreads();
-  if (k > 1) jacobi(L, k);
+  const int cur = k > 1 ? jacobi<JT>(L, k) : 0;
   if (threadIdx.x != 0) return;
-  double* z = L.ws;  // k values, ascending
+  double* z = L.ws[0];  // k values, ascending
   for (int a = 0; a < k; ++a) {
-    const double v = L.A[a * LDK + a];
+    const double v = L.A[cur][a * LDK + a];
     int p = a;
     while (p > 0 && z[p - 1] > v) {
       z[p] = z[p - 1];
@@ -324,8 +295,8 @@ __global__ __launch_bounds__(JT) void k_newton_shifts(const double* __restrict__
     }
     z[p] = v;
   }
-  int* ord = L.pt;
-  double* used = L.fd;  // 1: already chosen
+  int* ord = L.pt[0];
+  double* used = L.fd[0];  // 1: already chosen
   for (int a = 0; a < k; ++a) used[a] = 0.0;
   int best = 0;
   for (int a = 1; a < k; ++a)
@@ -670,16 +641,20 @@ __global__ void k_batch_plan(BatchCfg c) {
   c.prm[q] = prm;
 }
 
-// grid (s_max, systems): kappa(G_i) of system blockIdx.y, i = blockIdx.x + 1, one
-// wavefront each (many small problems at once: throughput over latency).
-__global__ __launch_bounds__(SSCG_WAVE) void k_kappa_batch(BatchCfg c) {
+// grid (s_max, systems): kappa(G_i) of system blockIdx.y, i = blockIdx.x + 1, on
+// KBT threads each.
+#ifndef SSCG_KBT
+#define SSCG_KBT 128
+#endif
+constexpr int KBT = SSCG_KBT;
+__global__ __launch_bounds__(KBT) void k_kappa_batch(BatchCfg c) {
   __shared__ JacobiLds L;
   const int q = blockIdx.y, i = blockIdx.x + 1;
   if (c.sys[q].done) return;
   const sscg_block_params prm = c.prm[q];
   if (!prm.adaptive || i > prm.s) return;
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  kappa_body<true>(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
+  kappa_body<KBT>(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
 }
 
 // Coordinate solve of system blockIdx.x, then the block's commit.
@@ -753,7 +728,7 @@ hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st) {
 }
 
 hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_kappa_batch, dim3(c.S, c.nsys), dim3(SSCG_WAVE), 0, st, c);
+  hipLaunchKernelGGL(k_kappa_batch, dim3(c.S, c.nsys), dim3(KBT), 0, st, c);
   return hipGetLastError();
 }
 
