@@ -66,6 +66,7 @@ CASES = [
     dict(mode="adaptive", s_max=6, tol=1e-10, s0_bar=2, f=1),
     dict(mode="fixed", fixed_s=4, s_max=8, tol=1e-10),
     dict(mode="adaptive", s_max=8, tol=1e-10, inner_check=False, c=10.0),
+    dict(mode="adaptive", basis="chebyshev", s_max=16, tol=1e-10),  # 33 x 33 sub-Gram matrices
 ]
 
 
