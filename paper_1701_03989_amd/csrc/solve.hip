@@ -3,8 +3,12 @@
 // Every block k runs on the context's stream S1: the s matrix-powers passes
 // (the first one also forms the true residual of the block's starting
 // iterate x_k), the Gram matrix, the coordinate solve and the recovery
-// x_{k+1} = x_k + Y x', r = Y r', p = Y p' into the other half of ping-pong
-// buffers, so block k's inputs survive until block k is accepted.
+// x_{k+1} = x_k + Y x', r = Y r', p = Y p'.  The inputs x_k, p_k, r_k and the
+// Gram matrix of block k live in set k mod NSET of rotating buffers: block
+// k's recovery overwrites the set of block k - 3, whose validation the host
+// has always seen complete by then (at most LOOKAHEAD - 1 = 2 blocks are
+// pending when a block is enqueued), so block k's inputs survive until it
+// is accepted without any wait between the streams.
 //
 // The host enqueues blocks ahead without waiting, steered by a device flag
 // that stops every later kernel (converged, breakdown, or a rejected
@@ -28,6 +32,7 @@ using namespace sscg_host;
 namespace {
 
 constexpr int LOOKAHEAD = 3;  // blocks enqueued but not yet examined by the host
+constexpr int NSET = LOOKAHEAD + 1;  // rotating sets of block inputs (x, p, r, G)
 
 __global__ void k_eps_star(const double* b2, double tol, double* out) {
   if (threadIdx.x == 0) out[0] = tol * sqrt(b2[0]);
@@ -64,12 +69,12 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   // ---- workspace (sized once: nothing may be reallocated while blocks run)
   const int64_t ld = ((int64_t)n + 63) / 64 * 64;
   const int rcol = o.s_max + 1;
-  const int ncols = 2 * o.s_max + 3;  // P_1.., R_1.., and P_0/R_0 of both parities
+  const int ncols = 2 * o.s_max + 1 + 2 * (NSET - 1);  // P_0.., R_0.., P_0/R_0 of the other sets
   const int dmax = 2 * o.s_max + 1;
   const size_t gsz = (size_t)(2 * SSCG_S_LIMIT + 1) * (2 * SSCG_S_LIMIT + 1);
   HIPCHK(ensure(ctx->Y, sizeof(double) * ld * ncols));
-  HIPCHK(ensure(ctx->x1, sizeof(double) * n));
-  HIPCHK(ensure(ctx->G, sizeof(double) * 2 * gsz));
+  HIPCHK(ensure(ctx->x1, sizeof(double) * n * (NSET - 1)));
+  HIPCHK(ensure(ctx->G, sizeof(double) * NSET * gsz));
   HIPCHK(ensure(ctx->coef, sizeof(double) * 3 * (2 * SSCG_S_LIMIT + 1)));
   HIPCHK(ensure(ctx->info, sizeof(sscg_block_info) * RING));
   HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
@@ -80,7 +85,9 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   const int np_res = residual_nparts(n);
   HIPCHK(ensure(ctx->rpart, sizeof(double) * 2 * (size_t)np_res));
   const double* bw = b;
-  double* X[2] = {x, as<double>(ctx->x1)};
+  double* X[NSET];
+  X[0] = x;
+  for (int q = 1; q < NSET; ++q) X[q] = as<double>(ctx->x1) + (size_t)(q - 1) * n;
   if (o.equilibrate) {
     HIPCHK(ensure(ctx->bw, sizeof(double) * n));
     HIPCHK(ensure(ctx->xw, sizeof(double) * n));
@@ -91,8 +98,13 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   }
   double* Y = as<double>(ctx->Y);
   auto ycol = [&](int c) { return Y + (int64_t)c * ld; };
-  double* P0[2] = {ycol(0), ycol(2 * o.s_max + 1)};
-  double* R0[2] = {ycol(rcol), ycol(2 * o.s_max + 2)};
+  double *P0[NSET], *R0[NSET];
+  P0[0] = ycol(0);
+  R0[0] = ycol(rcol);
+  for (int q = 1; q < NSET; ++q) {
+    P0[q] = ycol(2 * o.s_max + 2 * q - 1);
+    R0[q] = ycol(2 * o.s_max + 2 * q);
+  }
   double* Gbuf = as<double>(ctx->G);
   double* coef = as<double>(ctx->coef);
   double* scal = as<double>(ctx->scal);  // [0] r2 [1] b2 [2] relres [3] eps*
@@ -129,12 +141,12 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   R.relres0 = relres0;
   R.relres = relres0;
 
-  // copy the answer (ping-pong half `par`) to the caller's x, undoing the scaling
+  // copy the answer (set `par`) to the caller's x, undoing the scaling
   auto finish = [&](int status, int par) -> int {
     hipError_t e = hipStreamSynchronize(S1);
     if (e == hipSuccess) e = hipStreamSynchronize(S2);
     if (e == hipSuccess && ctx->timing) e = ev_collect(ctx);
-    if (e == hipSuccess && par == 1) e = launch_copy(X[1], n, X[0], S1);
+    if (e == hipSuccess && par != 0) e = launch_copy(X[par], n, X[0], S1);
     if (e == hipSuccess && o.equilibrate)
       e = launch_scale_vec(X[0], as<double>(ctx->scale), 1, n, x, S1);
     if (e == hipSuccess) e = hipStreamSynchronize(S1);
@@ -176,8 +188,9 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
     }
   };
 
-  auto enqueue = [&](const Pending& P, bool prev_spec) -> int {
-    const int k = P.k, s = P.s, first = P.first, par = k & 1, slot = k % RING;
+  auto enqueue = [&](const Pending& P) -> int {
+    const int k = P.k, s = P.s, first = P.first, par = k % NSET, nxt = (k + 1) % NSET;
+    const int slot = k % RING;
     sscg_block_info* info = dinfo + slot;
     const int d = first ? s + 1 : 2 * s + 1;
     BasisCols bc{P0[par], R0[par], Y, ld, rcol};
@@ -233,11 +246,8 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
                             hipMemcpyDeviceToHost, S2));
       HIPCHK(hipEventRecord(ctx->evV[slot], S2));
     }
-    // the recovery overwrites the inputs of block k-1: they must no longer be
-    // needed for a redo of that block
-    if (prev_spec) HIPCHK(hipStreamWaitEvent(S1, ctx->evV[(k - 1) % RING], 0));
     HIPCHK(ev_begin(ctx, 2, 8.0 * n * (d + 4), S1, &slot_t));
-    HIPCHK(launch_recover(cols, n, d, coef, X[par], X[par ^ 1], R0[par ^ 1], P0[par ^ 1],
+    HIPCHK(launch_recover(cols, n, d, coef, X[par], X[nxt], R0[nxt], P0[nxt],
                           Gate{stop, ev_ran(ctx, slot_t)}, S1));
     HIPCHK(ev_end(ctx, slot_t, S1));
     return SSCG_OK;
@@ -250,7 +260,6 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   int m_pred = 0, s_prev_pred = 0;  // including pending blocks (assumed full)
   int k_next = 0;
   int no_spec_k = -1;              // a block redone after a rejected speculation
-  bool last_enq_spec = false;
   for (;;) {
     // enqueue while allowed
     while ((int)pend.size() < LOOKAHEAD && (pend.empty() || pend.back().ahead) &&
@@ -262,8 +271,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
       const bool prev_full = pend.empty() ? last_full : true;
       P.spec = adaptive && !P.first && prev_full && P.s == P.s_bar && k_next != no_spec_k;
       P.ahead = adaptive ? P.spec : 1;
-      if ((rc = enqueue(P, last_enq_spec))) return rc;
-      last_enq_spec = P.spec;
+      if ((rc = enqueue(P))) return rc;
       pend.push_back(P);
       m_pred += P.s;
       s_prev_pred = P.s;
@@ -279,8 +287,8 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
       const double rel = I.relres_in;
       if (P.k - 1 < R.cap && R.relres_true) R.relres_true[P.k - 1] = rel;
       R.relres = rel;
-      if (rel <= o.tol) return finish(SSCG_OK, P.k & 1);
-      if (!isfinite(rel)) return finish(SSCG_BREAKDOWN, P.k & 1);
+      if (rel <= o.tol) return finish(SSCG_OK, P.k % NSET);
+      if (!isfinite(rel)) return finish(SSCG_BREAKDOWN, P.k % NSET);
     }
     if (P.spec) ++R.spec_blocks;
     if (P.spec && I.spec == 2) {  // rejected: redo block k the ordinary way
@@ -294,7 +302,6 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
       m_pred = m;
       s_prev_pred = s_prev;
       no_spec_k = P.k;
-      last_enq_spec = false;  // block k-1 is accepted; nothing to wait for
       continue;
     }
     pend.pop_front();
@@ -312,7 +319,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
           R.kappa[(int64_t)P.k * o.s_max + i] = (adaptive && i < P.s) ? I.kappa[i] : NAN;
     }
     R.basis_vectors += P.first ? P.s : 2 * P.s - 1;
-    if (s_k == 0) return finish(SSCG_BREAKDOWN, P.k & 1);
+    if (s_k == 0) return finish(SSCG_BREAKDOWN, P.k % NSET);
     R.wasted_vectors += (int64_t)(P.s - s_k) * (P.first ? 1 : 2);
     m += s_k;
     s_prev = s_k;
@@ -324,7 +331,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
       // the true residual of x_{k+1} decides the status
       HIPCHK(hipStreamSynchronize(S1));
       HIPCHK(hipStreamSynchronize(S2));
-      const int par = (P.k + 1) & 1;
+      const int par = (P.k + 1) % NSET;
       int np2 = np_res;
       HIPCHK(launch_residual(M, bw, X[par], nullptr, part, nullptr, &np2, S1));
       HIPCHK(launch_finalize(part, np2, 1, scal, S1));
