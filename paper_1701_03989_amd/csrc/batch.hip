@@ -6,7 +6,9 @@
 // multiple of 256, so that each 256-row block (one workgroup of the streaming
 // kernels), each Gram chunk and each slice belongs to one system.  Padding
 // rows are empty and their vector entries stay zero, so they add nothing to
-// any sum.  Every per-system decision (s_bar_k, the rank guard, s~_k, s_k,
+// any sum.  Within a system the rows are in the order of launch_row_order
+// (sorted by length in windows where that shrinks the SELL padding); b and
+// x are permuted on the way in and out.  Every per-system decision (s_bar_k, the rank guard, s~_k, s_k,
 // convergence, the iteration cap) is taken on the device from the system
 // table, so one outer block is the same sequence of launches for every block:
 // it is captured once as a HIP graph and replayed until no system is left.
@@ -147,6 +149,10 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(ensure(w.bpart, sizeof(double) * 2 * (size_t)nblk));
   HIPCHK(ensure(w.gpart, sizeof(double) * 2 * (size_t)npairs * nchunks));
   HIPCHK(ensure(w.active, sizeof(int32_t) * 4));
+  HIPCHK(ensure(w.perm, sizeof(int32_t) * (size_t)N));
+  HIPCHK(ensure(w.inv, sizeof(int32_t) * (size_t)N));
+  int32_t* perm = as<int32_t>(w.perm);
+  int32_t* inv = as<int32_t>(w.inv);
 
   // ---- block-diagonal SELL-64 copy (structure checked per system)
   int32_t* width = as<int32_t>(w.width);
@@ -158,8 +164,9 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
     const sscg_csr& A = B->A[q];
     const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
     HIPCHK(launch_check_csr(A.rowptr, A.col, A.n, A.nnz, flag, st));
-    HIPCHK(launch_sell_widths_n(A.rowptr, A.n, npad / SSCG_WAVE, width + hs[q].row0 / SSCG_WAVE,
-                                st));
+    HIPCHK(launch_row_order(A.rowptr, A.n, npad, hs[q].row0, perm, inv, st));
+    HIPCHK(launch_sell_widths_perm(A.rowptr, perm + hs[q].row0, npad / SSCG_WAVE,
+                                   width + hs[q].row0 / SSCG_WAVE, st));
   }
   HIPCHK(launch_scan_offsets(width, nslices, off, st));
   int64_t total = 0;
@@ -175,10 +182,10 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   for (int q = 0; q < nsys; ++q) {
     const sscg_csr& A = B->A[q];
     const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
-    HIPCHK(launch_sell_fill_off(A.rowptr, A.col, A.val, A.n, npad / SSCG_WAVE,
-                                off + hs[q].row0 / SSCG_WAVE, width + hs[q].row0 / SSCG_WAVE,
-                                hs[q].row0, as<int32_t>(w.scol),
-                                as<double>(w.sval), st));
+    HIPCHK(launch_sell_fill_perm(A.rowptr, A.col, A.val, perm + hs[q].row0, inv,
+                                 npad / SSCG_WAVE, off + hs[q].row0 / SSCG_WAVE,
+                                 width + hs[q].row0 / SSCG_WAVE, hs[q].row0, as<int32_t>(w.scol),
+                                 as<double>(w.sval), st));
   }
   DevMat M;
   M.n = N;
@@ -224,10 +231,10 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(hipMemsetAsync(c.Y, 0, sizeof(double) * (size_t)N * ncols, st));
   HIPCHK(hipMemsetAsync(c.x, 0, sizeof(double) * (size_t)N, st));
   HIPCHK(hipMemsetAsync(as<double>(w.b), 0, sizeof(double) * (size_t)N, st));
-  for (int q = 0; q < nsys; ++q) {
-    const size_t nb = sizeof(double) * (size_t)hs[q].n;
-    HIPCHK(hipMemcpyAsync(c.x + hs[q].row0, B->x[q], nb, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(as<double>(w.b) + hs[q].row0, B->b[q], nb, hipMemcpyDeviceToDevice, st));
+  for (int q = 0; q < nsys; ++q) {  // into the systems' row order
+    const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
+    HIPCHK(launch_gather_perm(B->x[q], perm + hs[q].row0, npad, c.x + hs[q].row0, st));
+    HIPCHK(launch_gather_perm(B->b[q], perm + hs[q].row0, npad, as<double>(w.b) + hs[q].row0, st));
   }
   HIPCHK(hipMemcpyAsync(c.sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(as<int32_t>(w.blk_sys), hblk.data(), sizeof(int32_t) * nblk,
@@ -273,11 +280,11 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   int worst = SSCG_OK;
   for (int q = 0; q < nsys; ++q) {
     const BatchSys& s = hs[q];
-    const size_t nb = sizeof(double) * (size_t)s.n;
     if (s.b2 == 0.0)
       HIPCHK(launch_fill(B->x[q], s.n, 0.0, st));
     else
-      HIPCHK(hipMemcpyAsync(B->x[q], c.x + s.row0, nb, hipMemcpyDeviceToDevice, st));
+      HIPCHK(launch_scatter_perm(c.x + s.row0, perm + s.row0, (s.blk1 - s.blk0) * BATCH_ROWS,
+                                 B->x[q], st));
     const int status = s.done ? s.status : SSCG_NOT_CONVERGED;
     worst = std::max(worst, status);
     if (!res) continue;

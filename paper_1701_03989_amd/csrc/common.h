@@ -351,6 +351,24 @@ hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32
 hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const double* val,
                                 int n, int nslices, const int64_t* off, const int32_t* width,
                                 int col_off, int32_t* scol, double* sval, hipStream_t st);
+// Row order of a batched system (positions [0, npad) at row0 of the batch):
+// perm[row0 + p] = original row at position p (-1: padding), inv[row0 + r] =
+// row0 + position of row r; rows sorted by length within windows where that
+// shrinks the SELL-64 padding.
+hipError_t launch_row_order(const int32_t* rowptr, int n, int npad, int row0, int32_t* perm,
+                            int32_t* inv, hipStream_t st);
+// SELL-64 of a batched system in that order (perm: the system's positions).
+hipError_t launch_sell_widths_perm(const int32_t* rowptr, const int32_t* perm, int nslices,
+                                   int32_t* width, hipStream_t st);
+hipError_t launch_sell_fill_perm(const int32_t* rowptr, const int32_t* col, const double* val,
+                                 const int32_t* perm, const int32_t* inv, int nslices,
+                                 const int64_t* off, const int32_t* width, int row0,
+                                 int32_t* scol, double* sval, hipStream_t st);
+// dst[p] = src[perm[p]] (0 for padding) and dst[perm[p]] = src[p], p < npad.
+hipError_t launch_gather_perm(const double* src, const int32_t* perm, int npad, double* dst,
+                              hipStream_t st);
+hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad, double* dst,
+                               hipStream_t st);
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
                             const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
                             hipStream_t st);

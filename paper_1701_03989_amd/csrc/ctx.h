@@ -31,6 +31,7 @@ struct BatchWs {
   Buf width, off, scol, sval, flag;  // block-diagonal SELL-64 matrix
   Buf Y, x, b;                       // basis columns, iterates, right-hand sides
   Buf sys, prm, info, G, coef, hist, blk_sys, chunks, rpart, bpart, gpart, active;
+  Buf perm, inv;                     // row order of every system (position <-> row)
 };
 
 // One timed interval on a stream: a single launch, or a group of launches

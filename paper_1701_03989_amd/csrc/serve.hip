@@ -118,7 +118,8 @@ void server_free(sscg_server* s) {
   BatchWs& w = s->w;
   Buf* bufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag, &w.Y,       &w.x,
                  &w.b,     &w.sys,  &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,
-                 &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active};
+                 &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active,
+                 &w.perm,  &w.inv};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (s->hsys) (void)hipHostFree(s->hsys);
@@ -137,8 +138,8 @@ int retire(sscg_server* s, int slot) {
   if (y.b2 == 0.0)
     HIPCHK(launch_fill(r.x, r.A.n, 0.0, s->st));
   else
-    HIPCHK(hipMemcpyAsync(r.x, s->c.x + r.row0, sizeof(double) * r.A.n, hipMemcpyDeviceToDevice,
-                          s->st));
+    HIPCHK(launch_scatter_perm(s->c.x + r.row0, as<int32_t>(s->w.perm) + r.row0, (int)r.npad, r.x,
+                               s->st));
   // its pool blocks belong to no system any more
   HIPCHK(hipMemsetAsync(as<int32_t>(s->w.blk_sys) + r.row0 / BATCH_ROWS, 0xFF,
                         sizeof(int32_t) * (r.npad / BATCH_ROWS), s->st));
@@ -172,8 +173,11 @@ int admit(sscg_server* s, int64_t id) {
   int32_t* flag = as<int32_t>(s->w.flag);
   // structure check and SELL widths, then the request's SELL size
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), s->st));
+  int32_t* perm = as<int32_t>(s->w.perm);
+  int32_t* inv = as<int32_t>(s->w.inv);
   HIPCHK(launch_check_csr(r.A.rowptr, r.A.col, r.A.n, r.A.nnz, flag, s->st));
-  HIPCHK(launch_sell_widths_n(r.A.rowptr, r.A.n, ns, width, s->st));
+  HIPCHK(launch_row_order(r.A.rowptr, r.A.n, (int)r.npad, (int)row0, perm, inv, s->st));
+  HIPCHK(launch_sell_widths_perm(r.A.rowptr, perm + row0, ns, width, s->st));
   HIPCHK(launch_scan_offsets_base(width, ns, 0, off, as<int64_t>(s->w.flag) + 1, s->st));
   HIPCHK(hipMemcpyAsync(s->hscan, flag, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
@@ -198,17 +202,16 @@ int admit(sscg_server* s, int64_t id) {
   r.nzlen = total;
   // the request's SELL-64 rows at [nz0, nz0 + total) of the nnz pool
   HIPCHK(launch_scan_offsets_base(width, ns, nz0, off, as<int64_t>(s->w.flag) + 1, s->st));
-  HIPCHK(launch_sell_fill_off(r.A.rowptr, r.A.col, r.A.val, r.A.n, ns, off, width, (int)row0,
-                              as<int32_t>(s->w.scol), as<double>(s->w.sval), s->st));
+  HIPCHK(launch_sell_fill_perm(r.A.rowptr, r.A.col, r.A.val, perm + row0, inv, ns, off, width,
+                               (int)row0, as<int32_t>(s->w.scol), as<double>(s->w.sval), s->st));
   // iterate, right-hand side, basis columns of its rows
   const size_t vb = sizeof(double) * (size_t)r.npad;
   HIPCHK(hipMemsetAsync(c.x + row0, 0, vb, s->st));
   HIPCHK(hipMemsetAsync(as<double>(s->w.b) + row0, 0, vb, s->st));
   for (int col = 0; col < 2 * s->S + 1; ++col)
     HIPCHK(hipMemsetAsync(batch_col(c, col) + row0, 0, vb, s->st));
-  HIPCHK(hipMemcpyAsync(c.x + row0, r.x, sizeof(double) * r.A.n, hipMemcpyDeviceToDevice, s->st));
-  HIPCHK(hipMemcpyAsync(as<double>(s->w.b) + row0, r.b, sizeof(double) * r.A.n,
-                        hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(launch_gather_perm(r.x, perm + row0, (int)r.npad, c.x + row0, s->st));
+  HIPCHK(launch_gather_perm(r.b, perm + row0, (int)r.npad, as<double>(s->w.b) + row0, s->st));
   // system table entry and block ownership
   const int blk0 = (int)(row0 / BATCH_ROWS), nb = (int)(r.npad / BATCH_ROWS);
   BatchSys& y = s->hnew[slot];
@@ -297,7 +300,8 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
       {&w.blk_sys, sizeof(int32_t) * nblk},        {&w.chunks, sizeof(BatchChunk) * nchunks},
       {&w.rpart, sizeof(double) * 2 * (size_t)nblk}, {&w.bpart, sizeof(double) * 2 * (size_t)nblk},
       {&w.gpart, sizeof(double) * 2 * (size_t)npairs * nchunks},
-      {&w.active, sizeof(int32_t) * 4}};
+      {&w.active, sizeof(int32_t) * 4},
+      {&w.perm, sizeof(int32_t) * (size_t)N},      {&w.inv, sizeof(int32_t) * (size_t)N}};
   for (const auto& p : sizes)
     if (e == hipSuccess) e = ensure(*p.first, p.second);
   if (e != hipSuccess) return bad(e);

@@ -438,6 +438,142 @@ __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict_
   }
 }
 
+// ---------------------------------------------------------------- row order of batched systems
+//
+// SELL-64 pads every slice to its longest row; for rows of uneven length (a
+// random graph's degrees) that stores up to twice the nonzeros.  A batched
+// system's rows are therefore ordered within windows of ROW_WIN rows by
+// descending length (stable), when that shrinks the window's padded size
+// by at least 5 %; otherwise (stencils, whose rows are nearly equal and whose
+// natural order keeps the gathers coalesced) the window keeps its order.
+// perm[p] = original row at position p (-1: padding), inv[row] = position.
+// Every row keeps its entries and their order, and every sum over rows is
+// correctly rounded, so the order changes no result.
+constexpr int ROW_WIN = 1024;
+
+__device__ __forceinline__ int win_padded(const uint32_t* key) {
+  // sum of the 16 slice widths of a window from the length groups in the keys
+  __shared__ int wsum[ROW_WIN / SSCG_WAVE];
+  const int t = threadIdx.x;
+  if (t < ROW_WIN / SSCG_WAVE) {
+    int w = 0;
+    for (int i = 0; i < SSCG_WAVE; ++i) {
+      const uint32_t k = key[t * SSCG_WAVE + i];
+      const int g = (int)(k >> 10);
+      w = max(w, k == 0xFFFFFFFFu || g >= 255 ? 0 : 254 - g);
+    }
+    wsum[t] = w;
+  }
+  __syncthreads();
+  int s = 0;
+  for (int i = 0; i < ROW_WIN / SSCG_WAVE; ++i) s += wsum[i];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(ROW_WIN / 2) void k_row_order(const int32_t* __restrict__ rowptr,
+                                                           int n, int npad, int row0,
+                                                           int32_t* __restrict__ perm,
+                                                           int32_t* __restrict__ inv) {
+  __shared__ uint32_t key[ROW_WIN];
+  const int w0 = blockIdx.x * ROW_WIN;
+  const int t = threadIdx.x;
+  for (int i = t; i < ROW_WIN; i += ROW_WIN / 2) {
+    const int r = w0 + i;
+    uint32_t k = 0xFFFFFFFFu;  // past the system: last
+    if (r < npad) {
+      int g = 255;  // padding rows after the system's rows
+      if (r < n) g = 254 - min(max(rowptr[r + 1] - rowptr[r], 0), 254);
+      k = ((uint32_t)g << 10) | (uint32_t)i;
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  const int natural = win_padded(key);
+  // bitonic sort, ascending: longer rows first, ties in row order
+  for (int k = 2; k <= ROW_WIN; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int i = 2 * t - (t & (j - 1));
+      const int l = i + j;
+      const uint32_t a = key[i], b = key[l];
+      if ((a > b) == ((i & k) == 0)) {
+        key[i] = b;
+        key[l] = a;
+      }
+      __syncthreads();
+    }
+  }
+  const bool sorted = (int64_t)win_padded(key) * 20 < (int64_t)natural * 19;
+  for (int i = t; i < ROW_WIN && w0 + i < npad; i += ROW_WIN / 2) {
+    const int r = w0 + (sorted ? (int)(key[i] & 1023u) : i);
+    perm[row0 + w0 + i] = r < n ? r : -1;
+    if (r < n) inv[row0 + r] = row0 + w0 + i;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_sell_widths_perm(const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ perm,
+                                                         int nslices, int32_t* __restrict__ width) {
+  int slice = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= nslices) return;
+  const int row = perm[slice * SSCG_WAVE + (threadIdx.x & (SSCG_WAVE - 1))];
+  int len = row >= 0 ? rowptr[row + 1] - rowptr[row] : 0;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) len = max(len, __shfl_xor(len, m, SSCG_WAVE));
+  if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) width[slice] = len;
+}
+
+// One thread per position; columns become positions (inv, global rows).
+__global__ __launch_bounds__(WG) void k_sell_fill_perm(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ inv, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ width, int nslices, int row0, int32_t* __restrict__ scol,
+    double* __restrict__ sval) {
+  const int pos = blockIdx.x * WG + threadIdx.x;
+  const int slice = pos / SSCG_WAVE;
+  if (slice >= nslices) return;
+  const int lane = pos & (SSCG_WAVE - 1);
+  const int64_t o = off[slice];
+  const int w = width[slice];
+  const int row = perm[pos];
+  int k0 = 0, len = 0;
+  if (row >= 0) {
+    k0 = rowptr[row];
+    len = rowptr[row + 1] - k0;
+  }
+  for (int j = 0; j < w; ++j) {
+    const int64_t dst = o + (int64_t)j * SSCG_WAVE + lane;
+    if (j < len) {
+      scol[dst] = inv[row0 + col[k0 + j]];
+      sval[dst] = val[k0 + j];
+    } else {
+      scol[dst] = row0 + pos;
+      sval[dst] = 0.0;
+    }
+  }
+}
+
+// dst[p] = src[perm[p]] (0 for padding), p < npad.
+__global__ __launch_bounds__(WG) void k_gather_perm(const double* __restrict__ src,
+                                                    const int32_t* __restrict__ perm, int npad,
+                                                    double* __restrict__ dst) {
+  const int p = blockIdx.x * WG + threadIdx.x;
+  if (p >= npad) return;
+  const int r = perm[p];
+  dst[p] = r >= 0 ? src[r] : 0.0;
+}
+
+// dst[perm[p]] = src[p] for the system's rows.
+__global__ __launch_bounds__(WG) void k_scatter_perm(const double* __restrict__ src,
+                                                     const int32_t* __restrict__ perm, int npad,
+                                                     double* __restrict__ dst) {
+  const int p = blockIdx.x * WG + threadIdx.x;
+  if (p >= npad) return;
+  const int r = perm[p];
+  if (r >= 0) dst[r] = src[p];
+}
+
 __global__ __launch_bounds__(WG) void k_cast_f32(const double* __restrict__ in, int64_t n,
                                                  float* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -513,6 +649,44 @@ hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const
   int threads = nslices * SSCG_WAVE;
   hipLaunchKernelGGL(k_sell_fill, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr, col, val,
                      n, (const double*)nullptr, off, width, nslices, col_off, scol, sval);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_order(const int32_t* rowptr, int n, int npad, int row0, int32_t* perm,
+                            int32_t* inv, hipStream_t st) {
+  hipLaunchKernelGGL(k_row_order, dim3((npad + ROW_WIN - 1) / ROW_WIN), dim3(ROW_WIN / 2), 0, st,
+                     rowptr, n, npad, row0, perm, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_widths_perm(const int32_t* rowptr, const int32_t* perm, int nslices,
+                                   int32_t* width, hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_widths_perm, dim3(wg_count(nslices)), dim3(WG), 0, st, rowptr, perm,
+                     nslices, width);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_fill_perm(const int32_t* rowptr, const int32_t* col, const double* val,
+                                 const int32_t* perm, const int32_t* inv, int nslices,
+                                 const int64_t* off, const int32_t* width, int row0,
+                                 int32_t* scol, double* sval, hipStream_t st) {
+  const int threads = nslices * SSCG_WAVE;
+  hipLaunchKernelGGL(k_sell_fill_perm, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr,
+                     col, val, perm, inv, off, width, nslices, row0, scol, sval);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_perm(const double* src, const int32_t* perm, int npad, double* dst,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_perm, dim3((npad + WG - 1) / WG), dim3(WG), 0, st, src, perm, npad,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad, double* dst,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_perm, dim3((npad + WG - 1) / WG), dim3(WG), 0, st, src, perm, npad,
+                     dst);
   return hipGetLastError();
 }
 
