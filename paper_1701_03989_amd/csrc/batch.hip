@@ -53,7 +53,11 @@ int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCf
     const int nrhs = j <= c.S - 1 ? 2 : 1;
     MpkResidual res{};
     if (j == 1) res = MpkResidual{c.x, c.b, c.rpart};
-    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, res, st));
+    // two-sequence passes gather (P_{j-1}, R_{j-1}) pairs from T[(j-1) & 1] and
+    // leave theirs in T[j & 1] when the next pass gathers pairs too
+    double2* tw = j + 1 <= c.S - 1 ? c.T[j & 1] : nullptr;
+    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, res, c.T[(j - 1) & 1], tw,
+                            st));
     if (j == 1) HIPCHK(launch_batch_res_finalize(c, st));
   }
   HIPCHK(launch_gram_batch(c, st));
@@ -150,6 +154,9 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(ensure(w.gpart, sizeof(double) * 2 * (size_t)npairs * nchunks));
   HIPCHK(ensure(w.active, sizeof(int32_t) * 4));
   HIPCHK(ensure(w.perm, sizeof(int32_t) * (size_t)N));
+  HIPCHK(ensure(w.T, sizeof(double2) * 2 * (size_t)N));
+  HIPCHK(ensure(w.ilcnt, sizeof(unsigned long long) * 2 * nsys));
+  unsigned long long* ilcnt = as<unsigned long long>(w.ilcnt);
   HIPCHK(ensure(w.inv, sizeof(int32_t) * (size_t)N));
   int32_t* perm = as<int32_t>(w.perm);
   int32_t* inv = as<int32_t>(w.inv);
@@ -177,6 +184,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   if (bad)
     return fail(ctx, SSCG_ERR_ARG,
                 "batch: invalid CSR (rowptr not non-decreasing or a column index outside [0, n))");
+  HIPCHK(hipMemsetAsync(ilcnt, 0, sizeof(unsigned long long) * 2 * nsys, st));
   HIPCHK(ensure(w.scol, sizeof(int32_t) * std::max<int64_t>(total, 1)));
   HIPCHK(ensure(w.sval, sizeof(double) * std::max<int64_t>(total, 1)));
   for (int q = 0; q < nsys; ++q) {
@@ -185,7 +193,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
     HIPCHK(launch_sell_fill_perm(A.rowptr, A.col, A.val, perm + hs[q].row0, inv,
                                  npad / SSCG_WAVE, off + hs[q].row0 / SSCG_WAVE,
                                  width + hs[q].row0 / SSCG_WAVE, hs[q].row0, as<int32_t>(w.scol),
-                                 as<double>(w.sval), st));
+                                 as<double>(w.sval), ilcnt + 2 * q, st));
   }
   DevMat M;
   M.n = N;
@@ -228,6 +236,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   c.bpart = as<double>(w.bpart);
   c.gpart = as<double>(w.gpart);
   c.active = as<int32_t>(w.active);
+  c.T[0] = as<double2>(w.T);
+  c.T[1] = c.T[0] + N;
   HIPCHK(hipMemsetAsync(c.Y, 0, sizeof(double) * (size_t)N * ncols, st));
   HIPCHK(hipMemsetAsync(c.x, 0, sizeof(double) * (size_t)N, st));
   HIPCHK(hipMemsetAsync(as<double>(w.b), 0, sizeof(double) * (size_t)N, st));
@@ -237,6 +247,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
     HIPCHK(launch_gather_perm(B->b[q], perm + hs[q].row0, npad, as<double>(w.b) + hs[q].row0, st));
   }
   HIPCHK(hipMemcpyAsync(c.sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_set_il(c.sys, ilcnt, 0, nsys, st));
   HIPCHK(hipMemcpyAsync(as<int32_t>(w.blk_sys), hblk.data(), sizeof(int32_t) * nblk,
                         hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(as<BatchChunk>(w.chunks), hc.data(), sizeof(BatchChunk) * nchunks,
@@ -245,6 +256,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   int np = 0;
   HIPCHK(launch_residual(M, c.b, c.x, batch_col(c, 0), c.rpart, c.bpart, &np, st));
   if (np != nblk) return fail(ctx, SSCG_ERR_HIP, "batch: residual partials %d != blocks %d", np, nblk);
+  HIPCHK(launch_pair(batch_col(c, 0), batch_col(c, c.S + 1), N, c.T[0], st));
   HIPCHK(launch_batch_init(c, st));
   HIPCHK(launch_batch_count(c, st));
 

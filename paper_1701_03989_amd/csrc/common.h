@@ -301,7 +301,7 @@ struct BatchSys {
   int32_t row0, n;     // first row in the batch layout; rows
   int32_t blk0, blk1;  // 256-row blocks [blk0, blk1)
   int32_t ch0, ch1;    // Gram chunks [ch0, ch1)
-  int32_t pad_;
+  int32_t il;          // 1: two-sequence passes gather (P, R) pairs (scattered columns)
   double tol;          // target relative residual
   double eps_star;     // tol * ||b||
   double b2;           // ||b||^2
@@ -339,6 +339,7 @@ struct BatchCfg {
   double* bpart;              // dd partial per 256-row block (||b||^2, set-up)
   double* gpart;              // Gram partials: (pair * nchunks + chunk) * 2
   int32_t* active;            // systems not done (after each block)
+  double2* T[2];              // (P_j, R_j) pairs for the gathers of pass j + 1 (T[j & 1])
 };
 
 // P_j / R_j column of a batch (global row index applies on top).
@@ -360,18 +361,29 @@ hipError_t launch_row_order(const int32_t* rowptr, int n, int npad, int row0, in
 // SELL-64 of a batched system in that order (perm: the system's positions).
 hipError_t launch_sell_widths_perm(const int32_t* rowptr, const int32_t* perm, int nslices,
                                    int32_t* width, hipStream_t st);
+// cnt[0] += stored entries, cnt[1] += those whose column, across the 64 rows
+// of their slice, spans 256 or more positions (a scattered gather).
 hipError_t launch_sell_fill_perm(const int32_t* rowptr, const int32_t* col, const double* val,
                                  const int32_t* perm, const int32_t* inv, int nslices,
                                  const int64_t* off, const int32_t* width, int row0,
-                                 int32_t* scol, double* sval, hipStream_t st);
+                                 int32_t* scol, double* sval, unsigned long long* cnt,
+                                 hipStream_t st);
+// sys[q].il = 1 when more than a quarter of system q's entries are scattered
+// (cnt[2q], cnt[2q + 1] from launch_sell_fill_perm), q in [q0, q0 + count).
+hipError_t launch_set_il(BatchSys* sys, const unsigned long long* cnt, int q0, int count,
+                         hipStream_t st);
 // dst[p] = src[perm[p]] (0 for padding) and dst[perm[p]] = src[p], p < npad.
 hipError_t launch_gather_perm(const double* src, const int32_t* perm, int npad, double* dst,
                               hipStream_t st);
 hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad, double* dst,
                                hipStream_t st);
+// Batched pass j; with two sequences the gathers read the pairs tg and the
+// outputs' pairs go to tw (if not NULL).
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
                             const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
-                            hipStream_t st);
+                            const double2* tg, double2* tw, hipStream_t st);
+// t[i] = (a[i], b[i]), i < n.
+hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, hipStream_t st);
 // Set-up from the residual of x_1 (rpart) and ||b||^2 (bpart): relres0, eps*;
 // systems with b = 0 or relres0 <= tol are done before block 0.
 hipError_t launch_batch_init(const BatchCfg& c, hipStream_t st);

@@ -32,6 +32,8 @@ struct BatchWs {
   Buf Y, x, b;                       // basis columns, iterates, right-hand sides
   Buf sys, prm, info, G, coef, hist, blk_sys, chunks, rpart, bpart, gpart, active;
   Buf perm, inv;                     // row order of every system (position <-> row)
+  Buf T;                             // (P_j, R_j) pairs for the gathers (two N-row halves)
+  Buf ilcnt;                         // per system: stored and scattered SELL entries
 };
 
 // One timed interval on a stream: a single launch, or a group of launches

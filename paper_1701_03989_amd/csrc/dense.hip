@@ -442,6 +442,8 @@ __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
   stage_coef(c.coef + (int64_t)q * BATCH_CSZ, d, cf);
   recover_row(batch_cols(c, prm.s, prm.first), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
               batch_col(c, 0));
+  // the (p, r) pairs the next block's first pass gathers (each thread its own row)
+  if (c.sys[q].il) c.T[0][i] = make_double2(batch_col(c, 0)[i], batch_col(c, c.S + 1)[i]);
 }
 
 // Set-up per system from the residual and ||b||^2 partials of its blocks.

@@ -119,7 +119,7 @@ void server_free(sscg_server* s) {
   Buf* bufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag, &w.Y,       &w.x,
                  &w.b,     &w.sys,  &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,
                  &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active,
-                 &w.perm,  &w.inv};
+                 &w.perm,  &w.inv,  &w.T,    &w.ilcnt};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (s->hsys) (void)hipHostFree(s->hsys);
@@ -202,8 +202,11 @@ int admit(sscg_server* s, int64_t id) {
   r.nzlen = total;
   // the request's SELL-64 rows at [nz0, nz0 + total) of the nnz pool
   HIPCHK(launch_scan_offsets_base(width, ns, nz0, off, as<int64_t>(s->w.flag) + 1, s->st));
+  unsigned long long* ilcnt = as<unsigned long long>(s->w.ilcnt);
+  HIPCHK(hipMemsetAsync(ilcnt + 2 * slot, 0, sizeof(unsigned long long) * 2, s->st));
   HIPCHK(launch_sell_fill_perm(r.A.rowptr, r.A.col, r.A.val, perm + row0, inv, ns, off, width,
-                               (int)row0, as<int32_t>(s->w.scol), as<double>(s->w.sval), s->st));
+                               (int)row0, as<int32_t>(s->w.scol), as<double>(s->w.sval),
+                               ilcnt + 2 * slot, s->st));
   // iterate, right-hand side, basis columns of its rows
   const size_t vb = sizeof(double) * (size_t)r.npad;
   HIPCHK(hipMemsetAsync(c.x + row0, 0, vb, s->st));
@@ -226,6 +229,7 @@ int admit(sscg_server* s, int64_t id) {
   y.lmin = r.lmin;
   y.lmax = r.lmax;
   HIPCHK(hipMemcpyAsync(c.sys + slot, &y, sizeof y, hipMemcpyHostToDevice, s->st));
+  HIPCHK(launch_set_il(c.sys, ilcnt, slot, 1, s->st));
   s->hblk.assign(nb, slot);
   HIPCHK(hipMemcpyAsync(as<int32_t>(s->w.blk_sys) + blk0, s->hblk.data(), sizeof(int32_t) * nb,
                         hipMemcpyHostToDevice, s->st));
@@ -239,6 +243,8 @@ int admit(sscg_server* s, int64_t id) {
   int np = 0;
   HIPCHK(launch_residual(V, as<double>(s->w.b) + row0, c.x, batch_col(c, 0) + row0,
                          c.rpart + (size_t)2 * blk0, c.bpart + (size_t)2 * blk0, &np, s->st));
+  HIPCHK(launch_pair(batch_col(c, 0) + row0, batch_col(c, s->S + 1) + row0, r.npad,
+                     c.T[0] + row0, s->st));
   HIPCHK(launch_batch_init_range(c, slot, 1, s->st));
   // staging buffers must outlive the copies
   HIPCHK(hipStreamSynchronize(s->st));
@@ -301,7 +307,9 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
       {&w.rpart, sizeof(double) * 2 * (size_t)nblk}, {&w.bpart, sizeof(double) * 2 * (size_t)nblk},
       {&w.gpart, sizeof(double) * 2 * (size_t)npairs * nchunks},
       {&w.active, sizeof(int32_t) * 4},
-      {&w.perm, sizeof(int32_t) * (size_t)N},      {&w.inv, sizeof(int32_t) * (size_t)N}};
+      {&w.perm, sizeof(int32_t) * (size_t)N},      {&w.inv, sizeof(int32_t) * (size_t)N},
+      {&w.T, sizeof(double2) * 2 * (size_t)N},
+      {&w.ilcnt, sizeof(unsigned long long) * 2 * (size_t)slots}};
   for (const auto& p : sizes)
     if (e == hipSuccess) e = ensure(*p.first, p.second);
   if (e != hipSuccess) return bad(e);
@@ -359,6 +367,8 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   c.bpart = as<double>(w.bpart);
   c.gpart = as<double>(w.gpart);
   c.active = as<int32_t>(w.active);
+  c.T[0] = as<double2>(w.T);
+  c.T[1] = c.T[0] + N;
   s->M.n = N;
   s->M.nslices = nslices;
   s->M.off = as<int64_t>(w.off);

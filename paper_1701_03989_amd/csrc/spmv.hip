@@ -151,11 +151,16 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 
 // The rows of one slice (lane = row within it); returns the lane's res_i^2
 // contribution when RES.
-template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false>
+// IL (two sequences): the gathers of u read the pairs tg[c] = (s0.u[c],
+// s1.u[c]), one 16-byte load instead of two 8-byte ones on different cache
+// lines (random gathers), and tw, if given, receives the pairs of the outputs.
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeq& s0, const MpkSeq& s1,
                                         const double* __restrict__ xres,
-                                        const double* __restrict__ bres) {
+                                        const double* __restrict__ bres,
+                                        const double2* __restrict__ tg = nullptr,
+                                        double2* __restrict__ tw = nullptr) {
   int lane = threadIdx.x & (SSCG_WAVE - 1);
   int row = slice * SSCG_WAVE + lane;
   dd r2 = dd_zero();
@@ -182,8 +187,14 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         if (j0 + u < w) {
-          g0[u] = u0[c[u]];
-          if (NRHS == 2) g1[u] = u1[c[u]];
+          if (IL && NRHS == 2) {
+            const double2 t = tg[c[u]];
+            g0[u] = t.x;
+            g1[u] = t.y;
+          } else {
+            g0[u] = u0[c[u]];
+            if (NRHS == 2) g1[u] = u1[c[u]];
+          }
           if (RES) gx[u] = xres[c[u]];
         }
       }
@@ -197,19 +208,23 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
       }
     }
     if (row < A.n) {
+      double o0, o1 = 0.0;
       if (CHEB) {
         dd_add_prod(a0, -theta, u0[row]);
         if (HASW) dd_add_prod(a0, -sigma, s0.w[row]);
-        s0.out[row] = dd_round(a0) / gamma;
+        o0 = dd_round(a0) / gamma;
         if (NRHS == 2) {
           dd_add_prod(a1, -theta, u1[row]);
           if (HASW) dd_add_prod(a1, -sigma, s1.w[row]);
-          s1.out[row] = dd_round(a1) / gamma;
+          o1 = dd_round(a1) / gamma;
         }
       } else {
-        s0.out[row] = dd_round(a0);
-        if (NRHS == 2) s1.out[row] = dd_round(a1);
+        o0 = dd_round(a0);
+        if (NRHS == 2) o1 = dd_round(a1);
       }
+      s0.out[row] = o0;
+      if (NRHS == 2) s1.out[row] = o1;
+      if (IL && NRHS == 2 && tw) tw[row] = make_double2(o0, o1);
       if (RES) {
         dd_add(ax, -bres[row]);
         double ri = -dd_round(ax);
@@ -245,21 +260,33 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
                                                   const int32_t* __restrict__ blk_sys,
                                                   const double* __restrict__ xres,
                                                   const double* __restrict__ bres,
-                                                  double* __restrict__ rpart) {
+                                                  double* __restrict__ rpart,
+                                                  const double2* __restrict__ tg,
+                                                  double2* __restrict__ tw) {
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
   if (lb >= nb) return;
   const int q = blk_sys[lb];
   if (q < 0 || sys[q].done) return;
+  const bool il = NRHS == 2 && sys[q].il;
   const BasisPrm bp = sys[q].bp;
   const double theta = CHEB ? bp.c0 : 0.0, sigma = CHEB ? bp.h2 : 0.0;
   const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
   dd r2;
-  if (j >= 2)
-    r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
-  else
-    r2 = mpk_slice<NRHS, CHEB, false, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+  if (il) {
+    if (j >= 2)
+      r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
+                                                         xres, bres, tg, tw);
+    else
+      r2 = mpk_slice<NRHS, CHEB, false, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
+                                                          xres, bres, tg, tw);
+  } else {
+    if (j >= 2)
+      r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+    else
+      r2 = mpk_slice<NRHS, CHEB, false, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+  }
   if (RES) wg_store_partial(r2, rpart, lb);
 }
 
@@ -529,10 +556,10 @@ __global__ __launch_bounds__(WG) void k_sell_fill_perm(
     const double* __restrict__ val, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ inv, const int64_t* __restrict__ off,
     const int32_t* __restrict__ width, int nslices, int row0, int32_t* __restrict__ scol,
-    double* __restrict__ sval) {
+    double* __restrict__ sval, unsigned long long* __restrict__ cnt) {
   const int pos = blockIdx.x * WG + threadIdx.x;
   const int slice = pos / SSCG_WAVE;
-  if (slice >= nslices) return;
+  if (slice >= nslices) return;  // whole wavefronts (nslices * 64 threads)
   const int lane = pos & (SSCG_WAVE - 1);
   const int64_t o = off[slice];
   const int w = width[slice];
@@ -542,16 +569,38 @@ __global__ __launch_bounds__(WG) void k_sell_fill_perm(
     k0 = rowptr[row];
     len = rowptr[row + 1] - k0;
   }
+  int scattered = 0;
   for (int j = 0; j < w; ++j) {
     const int64_t dst = o + (int64_t)j * SSCG_WAVE + lane;
+    int c;
     if (j < len) {
-      scol[dst] = inv[row0 + col[k0 + j]];
+      c = inv[row0 + col[k0 + j]];
       sval[dst] = val[k0 + j];
     } else {
-      scol[dst] = row0 + pos;
+      c = row0 + pos;
       sval[dst] = 0.0;
     }
+    scol[dst] = c;
+    int lo = c, hi = c;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      lo = min(lo, __shfl_xor(lo, m, SSCG_WAVE));
+      hi = max(hi, __shfl_xor(hi, m, SSCG_WAVE));
+    }
+    scattered += hi - lo >= 256;
   }
+  if (lane == 0) {
+    atomicAdd(cnt, (unsigned long long)w * SSCG_WAVE);
+    atomicAdd(cnt + 1, (unsigned long long)scattered * SSCG_WAVE);
+  }
+}
+
+__global__ void k_set_il(BatchSys* __restrict__ sys, const unsigned long long* __restrict__ cnt,
+                         int q0, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int q = q0 + i;
+  sys[q].il = cnt[2 * q + 1] * 4 > cnt[2 * q] ? 1 : 0;
 }
 
 // dst[p] = src[perm[p]] (0 for padding), p < npad.
@@ -572,6 +621,14 @@ __global__ __launch_bounds__(WG) void k_scatter_perm(const double* __restrict__ 
   if (p >= npad) return;
   const int r = perm[p];
   if (r >= 0) dst[r] = src[p];
+}
+
+// t[i] = (a[i], b[i]), i < n.
+__global__ __launch_bounds__(WG) void k_pair(const double* __restrict__ a,
+                                             const double* __restrict__ b, int64_t n,
+                                             double2* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) t[i] = make_double2(a[i], b[i]);
 }
 
 __global__ __launch_bounds__(WG) void k_cast_f32(const double* __restrict__ in, int64_t n,
@@ -669,10 +726,17 @@ hipError_t launch_sell_widths_perm(const int32_t* rowptr, const int32_t* perm, i
 hipError_t launch_sell_fill_perm(const int32_t* rowptr, const int32_t* col, const double* val,
                                  const int32_t* perm, const int32_t* inv, int nslices,
                                  const int64_t* off, const int32_t* width, int row0,
-                                 int32_t* scol, double* sval, hipStream_t st) {
+                                 int32_t* scol, double* sval, unsigned long long* cnt,
+                                 hipStream_t st) {
   const int threads = nslices * SSCG_WAVE;
   hipLaunchKernelGGL(k_sell_fill_perm, dim3((threads + WG - 1) / WG), dim3(WG), 0, st, rowptr,
-                     col, val, perm, inv, off, width, nslices, row0, scol, sval);
+                     col, val, perm, inv, off, width, nslices, row0, scol, sval, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_il(BatchSys* sys, const unsigned long long* cnt, int q0, int count,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_set_il, dim3((count + 63) / 64), dim3(64), 0, st, sys, cnt, q0, count);
   return hipGetLastError();
 }
 
@@ -690,14 +754,19 @@ hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad,
   return hipGetLastError();
 }
 
+hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, hipStream_t st) {
+  hipLaunchKernelGGL(k_pair, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st, a, b, n, t);
+  return hipGetLastError();
+}
+
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
                             const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
-                            hipStream_t st) {
+                            const double2* tg, double2* tw, hipStream_t st) {
   dim3 grid(xcd_grid(wg_count(A.nslices)));
   const bool r = res.x != nullptr;
 #define SSCG_MPK_BATCH(N, C, R)                                                                 \
   hipLaunchKernelGGL((k_mpk_batch<N, C, R>), grid, dim3(WG), 0, st, A, j, s0, s1, sys, blk_sys, \
-                     res.x, res.b, res.part)
+                     res.x, res.b, res.part, tg, tw)
   if (nrhs == 2) {
     if (cheb) { if (r) SSCG_MPK_BATCH(2, true, true); else SSCG_MPK_BATCH(2, true, false); }
     else { if (r) SSCG_MPK_BATCH(2, false, true); else SSCG_MPK_BATCH(2, false, false); }
