@@ -424,6 +424,8 @@ hipError_t launch_mpk32_pass(const DevMat& A, const float* val32, int j, BasisPr
                              MpkSeq32 s0, MpkSeq32 s1, hipStream_t st);
 // Gram of d FP32 columns: exact products, FP64 sums per workgroup (partials
 // in the layout of launch_gram, finished by launch_gram_finalize).
+// Partials of launch_gram32 for n rows (<= gram_nparts(n)).
+int gram32_nparts(int n);
 hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, int nparts,
                          hipStream_t st);
 // dx += Y x' (FP64), r = RN32(Y r'), p = RN32(Y p') (r, p may alias columns).

@@ -570,6 +570,89 @@ __global__ __launch_bounds__(WG) void k_gram32(Cols32 cols, int n, int d,
 }
 
 // dx_i += sum_a Y_ia x'_a; r_i = RN32(sum_a Y_ia r'_a); p_i likewise (FP64 sums).
+// Gram of FP32 columns for d <= D, one row per lane: wavefront w of the W
+// accumulates the entries [w NP / W, (w + 1) NP / W) of the row-major upper
+// triangle over the workgroup's rows from registers (no LDS, no barrier).
+// Products are exact in FP64 and summed with fma per lane (the same roundings
+// as sum + product), the 64 lane sums added in a fixed tree; partials as dd
+// pairs (lo = 0).
+template <int D>
+constexpr int g32_waves() {
+  return D <= 11 ? 4 : 8;  // at most 29 entries (58 VGPRs of sums) per wavefront
+}
+
+template <int D, int w>
+__device__ __forceinline__ void gram32_lr_wave(const Cols32& cols, int d, int r0, int r1,
+                                               double* __restrict__ part, int nparts, int slot) {
+  constexpr int NP = D * (D + 1) / 2;
+  constexpr int W = g32_waves<D>();
+  constexpr int Q0 = w * NP / W, Q1 = (w + 1) * NP / W;
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  const float* cp[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) cp[a] = a < d ? cols.at(a) : cols.Y;
+  double acc[Q1 - Q0];
+#pragma unroll
+  for (int q = 0; q < Q1 - Q0; ++q) acc[q] = 0.0;
+  float nx[D];
+  auto fetch = [&](int r) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) nx[a] = (a < d && r < r1) ? cp[a][r] : 0.0f;
+  };
+  fetch(r0 + lane);
+  for (int base = r0; base < r1; base += SSCG_WAVE) {
+    double v[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = (double)nx[a];
+    if (base + SSCG_WAVE < r1) fetch(base + SSCG_WAVE + lane);
+    // (a, b) and the entry index q are constants after unrolling, so v stays in registers
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+      for (int b = a; b < D; ++b) {
+        const int q = a * D - a * (a - 1) / 2 + (b - a);
+        if (q >= Q0 && q < Q1) acc[q - Q0] = __builtin_fma(v[a], v[b], acc[q - Q0]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll
+    for (int b = a; b < D; ++b) {
+      const int q = a * D - a * (a - 1) / 2 + (b - a);
+      if (q < Q0 || q >= Q1) continue;
+      double t = acc[q - Q0];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) t = t + shfl_xor_d(t, m);
+      if (lane == 0 && b < d) {
+        const int qd = a * d - a * (a - 1) / 2 + (b - a);  // the entry's index for dimension d
+        part[((int64_t)qd * nparts + slot) * 2] = t;
+        part[((int64_t)qd * nparts + slot) * 2 + 1] = 0.0;
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(g32_waves<D>() * SSCG_WAVE) void k_gram32_lr(Cols32 cols, int n, int d,
+                                                                double* __restrict__ part,
+                                                                int nparts) {
+  const int lb = xcd_block(nparts);
+  if (lb >= nparts) return;
+  const int nb = (n + SSCG_WAVE - 1) / SSCG_WAVE, per = (nb + nparts - 1) / nparts;
+  const int r0 = min(lb * per, nb) * SSCG_WAVE, r1 = min((lb + 1) * per * SSCG_WAVE, n);
+  switch (threadIdx.x / SSCG_WAVE) {
+    case 0: gram32_lr_wave<D, 0>(cols, d, r0, r1, part, nparts, lb); break;
+    case 1: gram32_lr_wave<D, 1>(cols, d, r0, r1, part, nparts, lb); break;
+    case 2: gram32_lr_wave<D, 2>(cols, d, r0, r1, part, nparts, lb); break;
+    case 3: gram32_lr_wave<D, 3>(cols, d, r0, r1, part, nparts, lb); break;
+    case 4: if constexpr (g32_waves<D>() > 4) gram32_lr_wave<D, 4>(cols, d, r0, r1, part, nparts, lb); break;
+    case 5: if constexpr (g32_waves<D>() > 5) gram32_lr_wave<D, 5>(cols, d, r0, r1, part, nparts, lb); break;
+    case 6: if constexpr (g32_waves<D>() > 6) gram32_lr_wave<D, 6>(cols, d, r0, r1, part, nparts, lb); break;
+    default: if constexpr (g32_waves<D>() > 7) gram32_lr_wave<D, 7>(cols, d, r0, r1, part, nparts, lb); break;
+  }
+}
+
 __global__ __launch_bounds__(WG) void k_recover32(Cols32 cols, int n, int d,
                                                   const double* __restrict__ coef, double* dx,
                                                   float* r, float* p) {
@@ -751,9 +834,25 @@ hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
+int gram32_nparts(int n) {
+  // at least 32 row blocks of 64 per workgroup (the lane sums stay cheap), at most 512
+  int nb = (n + SSCG_WAVE - 1) / SSCG_WAVE;
+  int np = (nb + 31) / 32;
+  if (np > 512) np = 512;
+  return np < 1 ? 1 : np;
+}
+
 hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, int nparts,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_gram32, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part, nparts);
+  if (d <= 11)
+    hipLaunchKernelGGL(k_gram32_lr<11>, dim3(xcd_grid(nparts)), dim3(g32_waves<11>() * SSCG_WAVE),
+                       0, st, cols, n, d, part, nparts);
+  else if (d <= 21)
+    hipLaunchKernelGGL(k_gram32_lr<21>, dim3(xcd_grid(nparts)), dim3(g32_waves<21>() * SSCG_WAVE),
+                       0, st, cols, n, d, part, nparts);
+  else
+    hipLaunchKernelGGL(k_gram32, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part,
+                       nparts);
   return hipGetLastError();
 }
 
