@@ -659,16 +659,34 @@ __global__ __launch_bounds__(WG) void k_recover32(Cols32 cols, int n, int d,
   int nb = (n + WG - 1) / WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
+  __shared__ double cf[3 * MAXD];
+  stage_coef(coef, d, cf);
   int i = lb * WG + threadIdx.x;
   if (i >= n) return;
   double ax = 0.0, ar = 0.0, ap = 0.0;
-  for (int a = 0; a < d; ++a) {
-    double cx = coef[a], cr = coef[d + a], cp = coef[2 * d + a];
-    if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
-    double y = (double)cols.at(a)[i];
-    ax = ax + y * cx;
-    ar = ar + y * cr;
-    ap = ap + y * cp;
+  // groups of RC columns, every load of a group in flight before the sums (a
+  // column with three zero coefficients reads column 0 again, unused); the
+  // sums keep the column order
+  constexpr int RC = 8;
+  for (int a0 = 0; a0 < d; a0 += RC) {
+    float y[RC];
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int a = a0 + u;
+      const bool use = a < d && (cf[a] != 0.0 || cf[d + a] != 0.0 || cf[2 * d + a] != 0.0);
+      y[u] = cols.at(use ? a : 0)[i];
+    }
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int a = a0 + u;
+      if (a >= d) continue;
+      const double cx = cf[a], cr = cf[d + a], cp = cf[2 * d + a];
+      if (cx == 0.0 && cr == 0.0 && cp == 0.0) continue;
+      const double yy = (double)y[u];
+      ax = ax + yy * cx;
+      ar = ar + yy * cr;
+      ap = ap + yy * cp;
+    }
   }
   dx[i] = dx[i] + ax;
   r[i] = (float)ar;
