@@ -409,7 +409,7 @@ inline int wg_count(int nslices) { return (nslices + SLICES_PER_WG - 1) / SLICES
 
 
 // ---------------------------------------------------------------- FP32 pass
-template <int NRHS, bool CHEB, bool HASW>
+template <int NRHS, bool CHEB, bool HASW, bool C16>
 __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict__ val32,
                                               double theta, double sigma, double gamma,
                                               MpkSeq32 s0, MpkSeq32 s1) {
@@ -434,7 +434,8 @@ __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict_
       int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
       bool in = j0 + u < w;
       v[u] = in ? val32[k] : 0.0f;
-      c[u] = in ? A.col[k] : 0;
+      if (C16) c[u] = in ? slice * SSCG_WAVE + (int)A.col16[k] : 0;
+      else c[u] = in ? A.col[k] : 0;
     }
 #pragma unroll
     for (int u = 0; u < CH; ++u)
@@ -855,12 +856,18 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
   return hipGetLastError();
 }
 
+// 16-bit column offsets (6 bytes per stored entry with the FP32 value) when
+// the matrix copy has them.
 template <int NRHS, bool CHEB, bool HASW>
 static void mpk32_launch(const DevMat& A, const float* val32, double th, double sg, double gm,
                          MpkSeq32 s0, MpkSeq32 s1, hipStream_t st) {
   dim3 grid(xcd_grid(wg_count(A.nslices)));
-  hipLaunchKernelGGL((k_mpk32<NRHS, CHEB, HASW>), grid, dim3(WG), 0, st, A, val32, th, sg, gm, s0,
-                     s1);
+  if (A.col16)
+    hipLaunchKernelGGL((k_mpk32<NRHS, CHEB, HASW, true>), grid, dim3(WG), 0, st, A, val32, th, sg,
+                       gm, s0, s1);
+  else
+    hipLaunchKernelGGL((k_mpk32<NRHS, CHEB, HASW, false>), grid, dim3(WG), 0, st, A, val32, th,
+                       sg, gm, s0, s1);
 }
 
 hipError_t launch_mpk32_pass(const DevMat& A, const float* val32, int j, BasisPrm bp, int nrhs,
