@@ -156,3 +156,51 @@ def test_batch_argument_errors(ctx):
         sscg.sscg_batch_solve(ctx, devA, [dvec(s.b) for s in systems],
                               [dvec(np.zeros(s.A.n)) for s in systems],
                               sscg.make_opts(basis="chebyshev"))
+
+
+def _arrow_system(n, seed):
+    """SPD arrow matrix: diagonal 4 + U[0,1], first row and column U[-1,1]/sqrt(n),
+    so that one row holds n entries and every other row two (rows of very uneven
+    length: the batch sorts them within windows)."""
+    rng = np.random.default_rng(seed)
+    d = 4.0 + rng.uniform(0.0, 1.0, n)
+    w = rng.uniform(-1.0, 1.0, n - 1) / np.sqrt(n)
+    rows, cols, vals = [0], [0], [d[0]]
+    rows += [0] * (n - 1)
+    cols += list(range(1, n))
+    vals += list(w)
+    for i in range(1, n):
+        rows += [i, i]
+        cols += [0, i]
+        vals += [w[i - 1], d[i]]
+    rows, cols, vals = np.array(rows), np.array(cols), np.array(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    A = problems.CSR(np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals)
+    dense = A.to_scipy().toarray()
+    ev = np.linalg.eigvalsh(dense)
+    b = rng.uniform(-1.0, 1.0, n)
+    return problems.BatchSystem(A, b, 0.9 * ev[0], 1.1 * ev[-1], f"arrow_{n}")
+
+
+def test_batch_uneven_rows_match_single_path_and_oracle(ctx):
+    """Row order and paired gathers: a batch mixing an arrow matrix (one row of
+    n entries), a graph Laplacian (scattered columns, uneven degrees) and a
+    stencil gives each system the bits sscg_solve gives it in natural order."""
+    kw = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    systems = [_arrow_system(1500, 3)] + problems.batch_systems(4, seed=11, nlo=500, nhi=4000)
+    say(f"batch {[s.kind for s in systems]}")
+    rc, xs, hist = run_batch(ctx, systems, **kw)
+    for i, s in enumerate(systems):
+        x = dvec(np.zeros(s.A.n))
+        h1 = sscg.History(512, 8)
+        rc1 = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b), x,
+                              sscg.make_opts(lmin=s.lmin, lmax=s.lmax, **kw), h1)
+        say(f"  {s.kind}: status {int(hist.status[i])}/{rc1}, blocks {int(hist.blocks[i])}/{h1.blocks}")
+        assert rc1 == int(hist.status[i]) and h1.schedule == hist.schedule(i)
+        assert np.array_equal(x.cpu().numpy(), xs[i]), s.kind
+        ref = sstep.solve(s.A, s.b, np.zeros(s.A.n), oracle_opts(kw, s))
+        err = np.linalg.norm(xs[i] - ref.x) / np.linalg.norm(ref.x)
+        assert hist.schedule(i) == ref.schedule and err <= 1e-12, (s.kind, err)
