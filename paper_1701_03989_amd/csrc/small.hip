@@ -1,5 +1,5 @@
 // The coordinate problem of one outer block (Algorithm 4 from "Determine s~"
-// to the end of the inner loop), solved in LDS by single wavefronts.
+// to the end of the inner loop), solved in LDS by single workgroups.
 //
 // k_kappa: kappa(G_i) = lambda_max / lambda_min of every candidate sub-Gram
 //   G_i (Section 4.2), one workgroup per i, by two-sided cyclic
