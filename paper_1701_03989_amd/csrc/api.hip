@@ -275,8 +275,7 @@ int lanczos_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, int* k
   hipStream_t st = ctx->stream;
   HIPCHK(launch_splitmix_vec(w, n, seed, st));
   HIPCHK(launch_dot_parts(w, w, n, part, &np, st));
-  HIPCHK(launch_finalize(part, np, 1, sc, st));
-  HIPCHK(launch_sqrt_scalar(sc, st));
+  HIPCHK(launch_finalize_sqrt(part, np, sc, st));
   HIPCHK(launch_div_vec(w, sc, n, v, st));
   bool have_prev = false;
   for (int j = 0; j < steps; ++j) {
@@ -284,8 +283,7 @@ int lanczos_dev(sscg_ctx* ctx, const DevMat& M, int steps, uint64_t seed, int* k
                                part, &np, st));
     HIPCHK(launch_finalize(part, np, 1, al + j, st));
     HIPCHK(launch_axpy_dot(w, v, al + j, part, &np, n, st));
-    HIPCHK(launch_finalize(part, np, 1, be + j, st));
-    HIPCHK(launch_sqrt_scalar(be + j, st));
+    HIPCHK(launch_finalize_sqrt(part, np, be + j, st));
     if (j < steps - 1) {
       HIPCHK(launch_div_vec(w, be + j, n, vp, st));  // vp <- w / beta (the new v)
       double* t = v;

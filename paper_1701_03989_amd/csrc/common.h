@@ -198,6 +198,8 @@ int residual_nparts(int n);
 // Sum dd partials (pairs) of `count` independent reductions, each with
 // nparts parts stored at part[(k * nparts + q) * 2]; out[k] = RN(sum).
 // If sqrt_div_by != NULL: out[k] = sqrt(sum) / *sqrt_div_by... see kernels.
+// out[0] = sqrt(RN(sum of the dd partials)).
+hipError_t launch_finalize_sqrt(const double* part, int nparts, double* out, hipStream_t st);
 hipError_t launch_finalize(const double* part, int nparts, int count, double* out,
                            hipStream_t st);
 
@@ -267,7 +269,6 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
                                hipStream_t st);
 hipError_t launch_axpy_dot(double* w, const double* v, const double* alpha, double* part,
                            int* nparts, int n, hipStream_t st);
-hipError_t launch_sqrt_scalar(double* x, hipStream_t st);
 hipError_t launch_div_vec(const double* w, const double* beta, int n, double* out,
                           hipStream_t st);
 hipError_t launch_dot_parts(const double* x, const double* y, int n, double* part, int* nparts,

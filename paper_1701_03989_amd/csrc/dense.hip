@@ -154,6 +154,13 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part
   if (threadIdx.x == 0) out[k] = dd_round(t);
 }
 
+// out[0] = sqrt(RN(sum)): the finalize and the square root of a norm.
+__global__ __launch_bounds__(WG) void k_finalize_sqrt(const double* __restrict__ part, int nparts,
+                                                      double* __restrict__ out) {
+  dd t = reduce_parts(part, nparts);
+  if (threadIdx.x == 0) out[0] = sqrt(dd_round(t));
+}
+
 __global__ __launch_bounds__(WG) void k_max_finalize(const double* __restrict__ part, int nparts,
                                                      double* __restrict__ out) {
   __shared__ double lm[WG / SSCG_WAVE];
@@ -362,10 +369,6 @@ __global__ __launch_bounds__(WG) void k_dot_parts(const double* __restrict__ x,
     part[2 * lb] = t.s;
     part[2 * lb + 1] = t.e;
   }
-}
-
-__global__ void k_sqrt_scalar(double* x) {
-  if (threadIdx.x == 0) x[0] = sqrt(x[0]);
 }
 
 __global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
@@ -734,6 +737,11 @@ hipError_t launch_res_finalize(const double* part, int nparts, const double* b2,
   return hipGetLastError();
 }
 
+hipError_t launch_finalize_sqrt(const double* part, int nparts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_sqrt, dim3(1), dim3(WG), 0, st, part, nparts, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double* part, int nparts, int count, double* out,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(count), dim3(WG), 0, st, part, nparts, out);
@@ -797,11 +805,6 @@ hipError_t launch_dot_parts(const double* x, const double* y, int n, double* par
   int nb = (n + WG - 1) / WG;
   *nparts = nb;
   hipLaunchKernelGGL(k_dot_parts, dim3(xcd_grid(nb)), dim3(WG), 0, st, x, y, n, part);
-  return hipGetLastError();
-}
-
-hipError_t launch_sqrt_scalar(double* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_sqrt_scalar, dim3(1), dim3(SSCG_WAVE), 0, st, x);
   return hipGetLastError();
 }
 

@@ -375,6 +375,7 @@ __global__ __launch_bounds__(WG) void k_gershgorin(DevMat A, double* __restrict_
 }
 
 // Lanczos: w_i = RN((A v)_i - beta_prev vprev_i); partials of w.v.
+template <bool C16>
 __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __restrict__ v,
                                                      const double* __restrict__ vprev,
                                                      const double* __restrict__ beta_prev,
@@ -391,9 +392,26 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
     int64_t o = A.off[slice] + lane;
     int wd = A.width[slice];
     dd a = dd_zero();
-    for (int j = 0; j < wd; ++j) {
-      int64_t k = o + (int64_t)j * SSCG_WAVE;
-      dd_add_prod(a, A.val[k], v[A.col[k]]);
+    // chunks of CH entries, every load of a chunk issued before its first use
+    // (the terms are added in entry order, as one at a time)
+    constexpr int CH = 4;
+    for (int j0 = 0; j0 < wd; j0 += CH) {
+      double av[CH], g[CH];
+      int c[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
+        const bool in = j0 + u < wd;
+        av[u] = in ? A.val[k] : 0.0;
+        if (C16) c[u] = in ? slice * SSCG_WAVE + (int)A.col16[k] : 0;
+        else c[u] = in ? A.col[k] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (j0 + u < wd) g[u] = v[c[u]];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (j0 + u < wd) dd_add_prod(a, av[u], g[u]);
     }
     if (row < A.n) {
       if (vprev) dd_add_prod(a, -(*beta_prev), vprev[row]);
@@ -851,8 +869,12 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
                                hipStream_t st) {
   int nb = wg_count(A.nslices);
   *nparts = nb;
-  hipLaunchKernelGGL(k_lanczos_spmv, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v, vprev, beta_prev,
-                     w, part);
+  if (A.col16)
+    hipLaunchKernelGGL(k_lanczos_spmv<true>, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v, vprev,
+                       beta_prev, w, part);
+  else
+    hipLaunchKernelGGL(k_lanczos_spmv<false>, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v, vprev,
+                       beta_prev, w, part);
   return hipGetLastError();
 }
 
