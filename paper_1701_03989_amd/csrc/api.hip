@@ -193,9 +193,17 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   HIPCHK(launch_sell_compact(as<int32_t>(ctx->scol), n, as<int64_t>(ctx->off),
                              as<int32_t>(ctx->width), as<int16_t>(ctx->scol16), flag,
                              ctx->stream));
-  int32_t wide = 1;
-  HIPCHK(hipMemcpyAsync(&wide, flag, sizeof wide, hipMemcpyDeviceToHost, ctx->stream));
+  // value indices when every slice holds few distinct values (stencils)
+  HIPCHK(ensure(ctx->svidx, std::max<int64_t>(total, 1)));
+  HIPCHK(ensure(ctx->svtab, sizeof(double) * VTAB * std::max(nslices, 1)));
+  HIPCHK(hipMemsetAsync(flag + 1, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_sell_vidx(as<double>(ctx->sval), as<int64_t>(ctx->off), as<int32_t>(ctx->width),
+                          nslices, as<double>(ctx->svtab), as<uint8_t>(ctx->svidx), flag + 1,
+                          ctx->stream));
+  int32_t fl[2] = {1, 1};
+  HIPCHK(hipMemcpyAsync(fl, flag, sizeof fl, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  const int32_t wide = fl[0], many = fl[1];
   M->n = n;
   M->nslices = nslices;
   M->off = as<int64_t>(ctx->off);
@@ -203,6 +211,8 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   M->col = as<int32_t>(ctx->scol);
   M->val = as<double>(ctx->sval);
   M->col16 = wide ? nullptr : as<int16_t>(ctx->scol16);
+  M->vidx = many ? nullptr : as<uint8_t>(ctx->svidx);
+  M->vtab = many ? nullptr : as<double>(ctx->svtab);
   return SSCG_OK;
 }
 
@@ -514,7 +524,7 @@ void sscg_destroy(sscg_ctx* c) {
   if (c->side) (void)hipStreamSynchronize(c->side);
   Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y,    &c->part,
                  &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
-                 &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran,   &c->scol16,
+                 &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran,   &c->scol16, &c->svidx, &c->svtab,
                  &c->sval32, &c->Y32, &c->dx,  &c->r64};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);

@@ -107,7 +107,14 @@ struct DevMat {
   // present when every offset fits: the matrix-powers pass then reads 10
   // bytes per entry instead of 12.
   const int16_t* col16 = nullptr;
+  // Optional value indices, present when no slice holds more than VTAB
+  // distinct stored values (bitwise, padding zeros included): entry k of slice
+  // t has the value vtab[VTAB t + vidx[k]], the same bits as val[k].  With
+  // col16 the matrix-powers pass then reads 3 bytes per entry.
+  const uint8_t* vidx = nullptr;
+  const double* vtab = nullptr;
 };
+constexpr int VTAB = 4;  // values in the table of a slice
 
 // Basis parameters of the three-term recurrence (monomial: theta = 0,
 // gamma = sigma = 1 unused).  Chebyshev on [lmin, lmax]:
@@ -168,6 +175,12 @@ hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
                             int32_t* scol, double* sval, hipStream_t st);
 // col16[e] = scol[e] - 64 t for the entries of slice t (0 for rows >= n); sets
 // *flag if an offset falls outside the int16 range.
+// Value tables and indices of the SELL copy (vtab: VTAB per slice); *flag = 1
+// if some slice holds more than VTAB distinct values (the indices are then
+// not usable).
+hipError_t launch_sell_vidx(const double* val, const int64_t* off, const int32_t* width,
+                            int nslices, double* vtab, uint8_t* vidx, int32_t* flag,
+                            hipStream_t st);
 hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
                                const int32_t* width, int16_t* col16, int32_t* flag,
                                hipStream_t st);

@@ -58,6 +58,7 @@ struct sscg_ctx {
   // matrix copy
   sscg_host::Buf width, off, scol, sval, scale;
   sscg_host::Buf scol16;  // 16-bit column offsets of the SELL copy (when they fit)
+  sscg_host::Buf svidx, svtab;  // value indices and per-slice value tables (when few values)
   // solver workspace
   sscg_host::Buf Y, part, rpart, G, coef, info, scal, xw, bw, x1, lz, lzab, ctl;
   sscg_block_info* hinfo = nullptr;  // pinned, RING entries

@@ -136,6 +136,48 @@ __global__ __launch_bounds__(WG) void k_sell_compact(const int32_t* __restrict__
   if (bad) atomicOr(flag, 1);
 }
 
+// Value table of each slice (one wavefront per slice): the distinct stored
+// values in order of first appearance (entry j, then lane), compared bit for
+// bit, and each entry's index into it.  More than VTAB values set *flag.
+__global__ __launch_bounds__(WG) void k_sell_vidx(const double* __restrict__ val,
+                                                  const int64_t* __restrict__ off,
+                                                  const int32_t* __restrict__ width, int nslices,
+                                                  double* __restrict__ vtab,
+                                                  uint8_t* __restrict__ vidx,
+                                                  int32_t* __restrict__ flag) {
+  const int slice = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= nslices) return;  // whole wavefronts
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  const int64_t o = off[slice] + lane;
+  const int w = width[slice];
+  long long tb = 0;  // lane l < m holds table entry l (as bits)
+  int m = 0;
+  bool over = false;
+  for (int j = 0; j < w; ++j) {
+    const int64_t k = o + (int64_t)j * SSCG_WAVE;
+    const long long bits = __double_as_longlong(val[k]);
+    int idx = -1;
+    for (int i = 0; i < m; ++i)
+      if (__shfl(tb, i, SSCG_WAVE) == bits && idx < 0) idx = i;
+    for (;;) {  // append the lanes' new values, lowest lane first
+      const unsigned long long need = __ballot(idx < 0);
+      if (need == 0) break;
+      if (m == VTAB) {
+        over = true;
+        if (idx < 0) idx = 0;
+        break;
+      }
+      const long long nb = __shfl(bits, __ffsll((long long)need) - 1, SSCG_WAVE);
+      if (lane == m) tb = nb;
+      if (idx < 0 && bits == nb) idx = m;
+      ++m;
+    }
+    vidx[k] = (uint8_t)idx;
+  }
+  if (lane < VTAB) vtab[(int64_t)slice * VTAB + lane] = __longlong_as_double(lane < m ? tb : 0);
+  if (over && lane == 0) *flag = 1;
+}
+
 // ---------------------------------------------------------------- MPK pass
 //
 // Pass j of the matrix-powers kernel for one or two sequences (P and R of
@@ -154,7 +196,8 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 // IL (two sequences): the gathers of u read the pairs tg[c] = (s0.u[c],
 // s1.u[c]), one 16-byte load instead of two 8-byte ones on different cache
 // lines (random gathers), and tw, if given, receives the pairs of the outputs.
-template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false,
+          bool VI = false>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeq& s0, const MpkSeq& s1,
                                         const double* __restrict__ xres,
@@ -169,6 +212,13 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
     int w = A.width[slice];
     const double* __restrict__ u0 = s0.u;
     const double* __restrict__ u1 = s1.u;
+    // VI: the slice's value table (wave-uniform) in scalar registers
+    double tv[VTAB];
+    if (VI) {
+      const int us = __builtin_amdgcn_readfirstlane(slice);
+#pragma unroll
+      for (int i = 0; i < VTAB; ++i) tv[i] = A.vtab[(int64_t)us * VTAB + i];
+    }
     dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
     // chunks of CH entries: every load of a chunk is issued before its first
     // use (w is uniform over the wave, so the guards do not diverge)
@@ -180,7 +230,14 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
       for (int u = 0; u < CH; ++u) {
         int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
         bool in = j0 + u < w;
-        v[u] = in ? A.val[k] : 0.0;
+        if (VI) {
+          const int ix = in ? (int)A.vidx[k] : 0;
+          double t = tv[VTAB - 1];
+#pragma unroll
+          for (int i = VTAB - 2; i >= 0; --i) t = ix == i ? tv[i] : t;
+          v[u] = in ? t : 0.0;
+        }
+        else v[u] = in ? A.val[k] : 0.0;
         if (C16) c[u] = in ? slice * SSCG_WAVE + (int)A.col16[k] : 0;
         else c[u] = in ? A.col[k] : 0;
       }
@@ -235,7 +292,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   return r2;
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16, bool VI>
 __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
                                             MpkSeq s0, MpkSeq s1, Gate gate,
                                             const double* __restrict__ xres,
@@ -246,8 +303,8 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   int lb = xcd_block(nb);
   if (lb >= nb) return;
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16>(A, slice, theta, sigma, gamma, s0, s1, xres,
-                                                  bres);
+  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI>(A, slice, theta, sigma, gamma, s0, s1,
+                                                            xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
 }
 
@@ -702,6 +759,14 @@ hipError_t launch_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
   return hipGetLastError();
 }
 
+hipError_t launch_sell_vidx(const double* val, const int64_t* off, const int32_t* width,
+                            int nslices, double* vtab, uint8_t* vidx, int32_t* flag,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_vidx, dim3(wg_count(nslices)), dim3(WG), 0, st, val, off, width,
+                     nslices, vtab, vidx, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
                                const int32_t* width, int16_t* col16, int32_t* flag,
                                hipStream_t st) {
@@ -797,24 +862,28 @@ hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s
   return hipGetLastError();
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool C16>
+template <int NRHS, bool CHEB, bool HASW, bool C16, bool VI>
 void mpk_launch_c(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                   MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
   if (res.x)
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16>), grid, dim3(WG), 0, st, A, theta,
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16, VI>), grid, dim3(WG), 0, st, A, theta,
                        sigma, gamma, s0, s1, g, res.x, res.b, res.part);
   else
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16>), grid, dim3(WG), 0, st, A, theta,
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16, VI>), grid, dim3(WG), 0, st, A, theta,
                        sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
 }
 
+// The compact forms the copy has: 16-bit column offsets, and value indices
+// with them.
 template <int NRHS, bool CHEB, bool HASW>
 void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                 MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
-  if (A.col16)
-    mpk_launch_c<NRHS, CHEB, HASW, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
+  if (A.col16 && A.vidx)
+    mpk_launch_c<NRHS, CHEB, HASW, true, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
+  else if (A.col16)
+    mpk_launch_c<NRHS, CHEB, HASW, true, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
   else
-    mpk_launch_c<NRHS, CHEB, HASW, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
+    mpk_launch_c<NRHS, CHEB, HASW, false, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
 }
 
 hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq s0, MpkSeq s1,
