@@ -226,6 +226,21 @@ int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t s
  * earlier); repeated cyclically if the run ended early.  shifts: host, m. */
 int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, double* shifts);
 
+/* The device form of A that the stages build and read (not an operation of the
+ * method: for callers that budget memory or bandwidth, or check which form a
+ * matrix gets).  A is stored as SELL-64: slices of 64 consecutive rows, each
+ * padded with zeros to its longest row; *stored gets the padded entry count.
+ * *format gets SSCG_FMT_COL16 when every column index lies within 32767 of its
+ * slice's first row: the matrix-powers pass then reads 16-bit offsets instead
+ * of 32-bit indices.  It also gets SSCG_FMT_VTAB when, in addition, no slice
+ * holds more than four distinct values, padding zeros included and compared
+ * bit for bit: the pass then reads a one-byte index per entry into a per-slice
+ * table of those values (the same bits, so no result changes).  Host outputs;
+ * either may be NULL. */
+#define SSCG_FMT_COL16 1
+#define SSCG_FMT_VTAB 2
+int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* stored);
+
 /* Matrix powers (eqs. cg-krylovbasis, polybasiscg): Y is n x ncol, column-major
  * with leading dimension ldy >= n.  On entry column 0 holds p (P_0) and, unless
  * first, column rcol holds r (R_0).  On return columns 1..s hold

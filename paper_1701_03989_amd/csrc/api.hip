@@ -620,6 +620,21 @@ int sscg_spectral_bounds(sscg_ctx* ctx, const sscg_csr* A, int steps, uint64_t s
   return spectral_bounds_dev(ctx, M, steps, seed, lambda_min, lambda_max);
 }
 
+int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* stored) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if ((rc = check_csr(ctx, A))) return rc;
+  DevMat M;
+  if ((rc = build_mat(ctx, A, 0, &M))) return rc;
+  // the forms the matrix-powers pass dispatches on: tables only with 16-bit offsets
+  const int f = (M.col16 ? SSCG_FMT_COL16 : 0) | (M.col16 && M.vidx ? SSCG_FMT_VTAB : 0);
+  if (format) *format = f;
+  if (stored) *stored = ctx->sell_total;
+  return SSCG_OK;
+}
+
 int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, double* shifts) {
   if (!ctx) return SSCG_ERR_ARG;
   ctx->err.clear();

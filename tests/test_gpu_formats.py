@@ -1,0 +1,219 @@
+"""GPU parity of the device forms of the matrix.
+
+The matrix-powers pass reads A in one of three forms: per-slice value tables
+with one-byte indices and 16-bit column offsets (no 64-row slice holds more
+than four distinct values), 16-bit offsets with the stored values, or 32-bit
+indices with the stored values.  Each form must give the oracle's row sums
+(eq. cg-krylovbasis, every row rounded once), and since a table entry carries
+the stored value's bits, the three forms must agree with each other to the last
+bit on the same rows.  Block-diagonal matrices put the same block into each
+form: a second block with five values in a slice, or with a column 33000 rows
+away from its slice, switches the whole matrix to the wider form while the rows
+of the first block keep their entries and their order.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import sstep  # noqa: E402
+from oracle.arith import CR  # noqa: E402
+from paper_1701_03989_amd import problems, sscg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+FULL = sscg.FMT_COL16 | sscg.FMT_VTAB
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = sscg.sscg_create(0)
+    yield h
+    sscg.sscg_destroy(h)
+
+
+def dvec(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def csr_of(n, rows, cols, vals):
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    order = np.lexsort((cols, rows))
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return problems.CSR(rowptr.astype(np.int32), cols[order].astype(np.int32),
+                        np.asarray(vals, dtype=np.float64)[order])
+
+
+def slice_valued(n, seed, lens, band, nvals):
+    """Row i: lens[i] distinct columns within `band` of i (cyclic), each value
+    drawn from the nvals values of row i's 64-row slice."""
+    rng = np.random.default_rng(seed)
+    tab = rng.standard_normal(((n + 63) // 64, nvals))
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        k = int(lens[i])
+        off = rng.choice(2 * band + 1, size=k, replace=False) - band
+        rows.append(np.full(k, i))
+        cols.append((i + off) % n)
+        vals.append(tab[i // 64, rng.integers(0, nvals, size=k)])
+    return csr_of(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def ring(n, seed, sigma=0.05):
+    """Weighted ring Laplacian + sigma I, edge (i, i+1 mod n) weighted by
+    c[i // 64]: every row has three entries and every slice four values."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.5, 2.0, size=(n + 63) // 64)
+    i = np.arange(n)
+    wr = c[i // 64]
+    wl = c[((i - 1) % n) // 64]
+    rows = np.concatenate([i, i, i])
+    cols = np.concatenate([i, (i + 1) % n, (i - 1) % n])
+    vals = np.concatenate([wl + wr + sigma, -wr, -wl])
+    return csr_of(n, rows, cols, vals), sigma, 4.0 * c.max() + sigma
+
+
+def block_diag(A, B):
+    n = A.n + B.n
+    ra = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    rb = np.repeat(np.arange(B.n), np.diff(B.rowptr)) + A.n
+    return csr_of(n, np.concatenate([ra, rb]),
+                  np.concatenate([A.col, B.col.astype(np.int64) + A.n]),
+                  np.concatenate([A.val, B.val]))
+
+
+def far_ring(n=33000):
+    """Cyclic tridiagonal block: row 0 holds column n - 1, beyond 16 bits."""
+    A, _, _ = ring(n, 5)
+    return A
+
+
+def mpk(ctx, A, s, p, r, lmin, lmax):
+    n = A.n
+    ld = (n + 63) // 64 * 64
+    rcol = s + 1
+    Y = torch.zeros((2 * s + 1) * ld, dtype=torch.float64, device=DEV)
+    Y[:n] = dvec(p)
+    Y[rcol * ld: rcol * ld + n] = dvec(r)
+    sscg.sscg_mpk(ctx, sscg.DeviceCsr.from_host(A, DEV), s, False, sscg.BASIS_CHEBYSHEV, lmin, lmax,
+                  Y, ld, rcol)
+    Yh = host(Y)
+    return [Yh[c * ld: c * ld + n] for c in range(2 * s + 1)]
+
+
+def oracle_basis(A, s, p, r, lmin, lmax):
+    ar = CR()
+    prm = sstep.basis_params("chebyshev", s, lmin, lmax, ar)
+    return sstep.krylov_basis(ar, A, p, r, s, False, prm)
+
+
+def check_against_oracle(got, A, s, p, r, lmin, lmax, what):
+    ref = oracle_basis(A, s, p, r, lmin, lmax)
+    worst, exact = 0.0, 0
+    for g, o in zip(got, ref):
+        worst = max(worst, float((np.abs(g - o) / np.maximum(np.abs(o), 1e-300)).max()))
+        exact += int(np.array_equal(g, o))
+    say(f"{what}: {exact}/{len(ref)} columns bit-identical, worst rel {worst:.2e}")
+    assert worst <= 1e-15, what
+
+
+S, LMIN, LMAX = 5, 0.5, 4.0
+
+
+def vecs(n, seed):
+    return problems.uniform(n, seed), problems.uniform(n, seed + 1)
+
+
+def test_forms_chosen_as_documented(ctx):
+    n = 64 * 8
+    cases = [
+        ("4 values per slice, no padding", slice_valued(n, 1, np.full(n, 6), 40, 4), FULL),
+        ("3 values + padding, ragged n",
+         slice_valued(64 * 7 + 17, 2, np.random.default_rng(2).integers(2, 8, 64 * 7 + 17), 40, 3),
+         FULL),
+        ("5 values in a slice", slice_valued(n, 3, np.full(n, 6), 40, 5), sscg.FMT_COL16),
+        ("column 32999 rows away", far_ring(), 0),
+        ("ring, per-slice weights", ring(64 * 8, 4)[0], FULL),
+        ("3-D Poisson", problems.poisson3d(12), FULL),
+        ("graph Laplacian", problems.graph_laplacian(3001, 7), sscg.FMT_COL16),
+    ]
+    for what, A, want in cases:
+        f, stored = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
+        lens = np.diff(A.rowptr)
+        nsl = (A.n + 63) // 64
+        pad = np.zeros(nsl * 64, dtype=np.int64)
+        pad[:A.n] = lens
+        want_stored = int(pad.reshape(nsl, 64).max(axis=1).sum()) * 64
+        say(f"{what}: n={A.n} format {f} stored {stored}")
+        assert f == want, what
+        assert stored == want_stored, what
+
+
+def test_table_form_matches_oracle_and_wider_forms_bitwise(ctx):
+    A = slice_valued(64 * 48, 11, np.full(64 * 48, 6), 60, 4)
+    B = slice_valued(64 * 4, 12, np.full(64 * 4, 6), 20, 5)
+    D1 = block_diag(A, B)
+    D2 = block_diag(A, far_ring())
+    fmts = [sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(M, DEV))[0] for M in (A, D1, D2)]
+    assert fmts == [FULL, sscg.FMT_COL16, 0]
+    p, r = vecs(A.n, 21)
+    ya = mpk(ctx, A, S, p, r, LMIN, LMAX)
+    check_against_oracle(ya, A, S, p, r, LMIN, LMAX, "value tables")
+    for D, what in [(D1, "16-bit offsets, stored values"), (D2, "32-bit indices")]:
+        pe, re_ = vecs(D.n, 31)
+        pe[:A.n], re_[:A.n] = p, r
+        yd = mpk(ctx, D, S, pe, re_, LMIN, LMAX)
+        for c in range(2 * S + 1):
+            assert np.array_equal(yd[c][:A.n], ya[c]), (what, c)
+        say(f"{what}: first {A.n} rows bit-identical to the table form")
+        check_against_oracle(yd, D, S, pe, re_, LMIN, LMAX, what)
+
+
+def test_ragged_table_form_with_padding_matches_oracle(ctx):
+    n = 64 * 37 + 29
+    A = slice_valued(n, 41, np.random.default_rng(41).integers(1, 10, n), 80, 3)
+    assert sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))[0] == FULL
+    p, r = vecs(n, 43)
+    check_against_oracle(mpk(ctx, A, S, p, r, LMIN, LMAX), A, S, p, r, LMIN, LMAX,
+                         "ragged value tables")
+
+
+@pytest.mark.parametrize("basis", ["monomial", "chebyshev"])
+def test_solve_on_per_slice_coefficients_matches_oracle(ctx, basis):
+    """Whole adaptive solve (Algorithm 4) on a matrix read through value tables
+    whose values differ from slice to slice: same s_k schedule, iterates
+    within 1e-12."""
+    A, lmin, lmax = ring(64 * 40, 51)
+    assert sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))[0] == FULL
+    b = problems.uniform(A.n, 52)
+    x1 = np.zeros(A.n)
+    kw = dict(mode="adaptive", s_max=8, tol=1e-11, basis=basis)
+    if basis == "chebyshev":
+        kw.update(lmin=lmin, lmax=lmax)
+    ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
+    x = dvec(x1)
+    hist = sscg.History(4096, kw["s_max"])
+    rc = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(A, DEV), dvec(b), x, sscg.make_opts(**kw),
+                         hist)
+    xh = host(x)
+    say(f"ring {basis}: gpu {hist.blocks} blocks {hist.schedule[:12]}, oracle {len(ref.blocks)}")
+    assert rc == ref.status == sscg.OK
+    assert hist.schedule == ref.schedule
+    assert np.linalg.norm(xh - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
