@@ -531,7 +531,8 @@ void sscg_destroy(sscg_ctx* c) {
   BatchWs& w = c->batch;
   Buf* bbufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag,    &w.Y,      &w.x,     &w.b,
                   &w.sys,   &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,   &w.blk_sys,
-                  &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active, &w.perm, &w.inv, &w.T, &w.ilcnt};
+                  &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active, &w.perm, &w.inv, &w.T, &w.ilcnt,
+                  &w.scol16, &w.svidx, &w.svtab, &w.vtcnt};
   for (Buf* b : bbufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {

@@ -252,6 +252,20 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
                         hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(as<BatchChunk>(w.chunks), hc.data(), sizeof(BatchChunk) * nchunks,
                         hipMemcpyHostToDevice, st));
+  // 16-bit offsets and value tables, read by the systems all of whose slices fit them
+  HIPCHK(ensure(w.scol16, sizeof(int16_t) * std::max<int64_t>(total, 1)));
+  HIPCHK(ensure(w.svidx, std::max<int64_t>(total, 1)));
+  HIPCHK(ensure(w.svtab, sizeof(double) * VTAB * (size_t)nslices));
+  HIPCHK(ensure(w.vtcnt, sizeof(int32_t) * nsys));
+  int32_t* vtcnt = as<int32_t>(w.vtcnt);
+  HIPCHK(hipMemsetAsync(vtcnt, 0, sizeof(int32_t) * nsys, st));
+  HIPCHK(launch_sell_forms_batch(M.col, M.val, off, width, 0, nslices, c.blk_sys,
+                                 as<int16_t>(w.scol16), as<double>(w.svtab),
+                                 as<uint8_t>(w.svidx), vtcnt, st));
+  HIPCHK(launch_set_vt(c.sys, vtcnt, 0, nsys, st));
+  M.col16 = as<int16_t>(w.scol16);
+  M.vidx = as<uint8_t>(w.svidx);
+  M.vtab = as<double>(w.svtab);
   HIPCHK(hipMemsetAsync(c.hist, 0, sizeof(BatchHist) * (size_t)cap * nsys, st));
   int np = 0;
   HIPCHK(launch_residual(M, c.b, c.x, batch_col(c, 0), c.rpart, c.bpart, &np, st));

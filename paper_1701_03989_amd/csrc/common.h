@@ -316,6 +316,7 @@ struct BatchSys {
   int32_t blk0, blk1;  // 256-row blocks [blk0, blk1)
   int32_t ch0, ch1;    // Gram chunks [ch0, ch1)
   int32_t il;          // 1: two-sequence passes gather (P, R) pairs (scattered columns)
+  int32_t vt;          // 1: passes read value tables and 16-bit offsets (all slices fit)
   double tol;          // target relative residual
   double eps_star;     // tol * ||b||
   double b2;           // ||b||^2
@@ -386,6 +387,15 @@ hipError_t launch_sell_fill_perm(const int32_t* rowptr, const int32_t* col, cons
 // (cnt[2q], cnt[2q + 1] from launch_sell_fill_perm), q in [q0, q0 + count).
 hipError_t launch_set_il(BatchSys* sys, const unsigned long long* cnt, int q0, int count,
                          hipStream_t st);
+// 16-bit column offsets and value tables of the batched matrix's slices
+// [sl0, sl0 + count) (blk_sys must be set for them); cnt[q] gains one for
+// each slice of system q that fits neither.  Then sys[q].vt = (cnt[q] == 0)
+// for q in [q0, q0 + count).
+hipError_t launch_sell_forms_batch(const int32_t* scol, const double* val, const int64_t* off,
+                                   const int32_t* width, int sl0, int count,
+                                   const int32_t* blk_sys, int16_t* col16, double* vtab,
+                                   uint8_t* vidx, int32_t* cnt, hipStream_t st);
+hipError_t launch_set_vt(BatchSys* sys, const int32_t* cnt, int q0, int count, hipStream_t st);
 // dst[p] = src[perm[p]] (0 for padding) and dst[perm[p]] = src[p], p < npad.
 hipError_t launch_gather_perm(const double* src, const int32_t* perm, int npad, double* dst,
                               hipStream_t st);

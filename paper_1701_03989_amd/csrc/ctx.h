@@ -34,6 +34,7 @@ struct BatchWs {
   Buf perm, inv;                     // row order of every system (position <-> row)
   Buf T;                             // (P_j, R_j) pairs for the gathers (two N-row halves)
   Buf ilcnt;                         // per system: stored and scattered SELL entries
+  Buf scol16, svidx, svtab, vtcnt;   // compact forms; per system: slices that miss them
 };
 
 // One timed interval on a stream: a single launch, or a group of launches

@@ -119,7 +119,8 @@ void server_free(sscg_server* s) {
   Buf* bufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag, &w.Y,       &w.x,
                  &w.b,     &w.sys,  &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,
                  &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active,
-                 &w.perm,  &w.inv,  &w.T,    &w.ilcnt};
+                 &w.perm,  &w.inv,  &w.T,    &w.ilcnt, &w.scol16, &w.svidx, &w.svtab,
+                 &w.vtcnt};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (s->hsys) (void)hipHostFree(s->hsys);
@@ -233,6 +234,14 @@ int admit(sscg_server* s, int64_t id) {
   s->hblk.assign(nb, slot);
   HIPCHK(hipMemcpyAsync(as<int32_t>(s->w.blk_sys) + blk0, s->hblk.data(), sizeof(int32_t) * nb,
                         hipMemcpyHostToDevice, s->st));
+  // 16-bit offsets and value tables of its slices, read if all of them fit
+  int32_t* vtcnt = as<int32_t>(s->w.vtcnt);
+  HIPCHK(hipMemsetAsync(vtcnt + slot, 0, sizeof(int32_t), s->st));
+  HIPCHK(launch_sell_forms_batch(as<int32_t>(s->w.scol), as<double>(s->w.sval),
+                                 as<int64_t>(s->w.off), as<int32_t>(s->w.width), (int)slice0, ns,
+                                 as<int32_t>(s->w.blk_sys), as<int16_t>(s->w.scol16),
+                                 as<double>(s->w.svtab), as<uint8_t>(s->w.svidx), vtcnt, s->st));
+  HIPCHK(launch_set_vt(c.sys, vtcnt, slot, 1, s->st));
   HIPCHK(hipMemsetAsync(c.hist + (size_t)slot * s->cap, 0, sizeof(BatchHist) * s->cap, s->st));
   // r_1 = b - A x_1 into P_0 over the request's slices, then its set-up
   DevMat V = s->M;
@@ -309,7 +318,10 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
       {&w.active, sizeof(int32_t) * 4},
       {&w.perm, sizeof(int32_t) * (size_t)N},      {&w.inv, sizeof(int32_t) * (size_t)N},
       {&w.T, sizeof(double2) * 2 * (size_t)N},
-      {&w.ilcnt, sizeof(unsigned long long) * 2 * (size_t)slots}};
+      {&w.ilcnt, sizeof(unsigned long long) * 2 * (size_t)slots},
+      {&w.scol16, sizeof(int16_t) * pool_nnz},     {&w.svidx, sizeof(uint8_t) * pool_nnz},
+      {&w.svtab, sizeof(double) * VTAB * (size_t)nslices},
+      {&w.vtcnt, sizeof(int32_t) * (size_t)slots}};
   for (const auto& p : sizes)
     if (e == hipSuccess) e = ensure(*p.first, p.second);
   if (e != hipSuccess) return bad(e);
@@ -375,6 +387,9 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   s->M.width = as<int32_t>(w.width);
   s->M.col = as<int32_t>(w.scol);
   s->M.val = as<double>(w.sval);
+  s->M.col16 = as<int16_t>(w.scol16);
+  s->M.vidx = as<uint8_t>(w.svidx);
+  s->M.vtab = as<double>(w.svtab);
   // one outer block over the first g/NG of the pool, captured once per g: a
   // step replays the smallest one that covers every admitted system (the
   // allocator is first-fit, so admitted rows stay low), so an idle tail of

@@ -136,9 +136,34 @@ __global__ __launch_bounds__(WG) void k_sell_compact(const int32_t* __restrict__
   if (bad) atomicOr(flag, 1);
 }
 
-// Value table of each slice (one wavefront per slice): the distinct stored
-// values in order of first appearance (entry j, then lane), compared bit for
-// bit, and each entry's index into it.  More than VTAB values set *flag.
+// One entry per lane of a slice's value table build (called by the whole
+// wavefront): the distinct stored values in order of first appearance (entry
+// j, then lane), compared bit for bit.  Lane l < m holds table entry l in tb.
+// Returns this lane's index; once a value finds no room, over is set (the
+// same on every lane) and the index is meaningless.
+__device__ __forceinline__ int vtab_index(double v, int lane, long long& tb, int& m, bool& over) {
+  const long long bits = __double_as_longlong(v);
+  int idx = -1;
+  for (int i = 0; i < m; ++i)
+    if (__shfl(tb, i, SSCG_WAVE) == bits && idx < 0) idx = i;
+  for (;;) {  // append the lanes' new values, lowest lane first
+    const unsigned long long need = __ballot(idx < 0);
+    if (need == 0) break;
+    if (m == VTAB) {
+      over = true;
+      if (idx < 0) idx = 0;
+      break;
+    }
+    const long long nb = __shfl(bits, __ffsll((long long)need) - 1, SSCG_WAVE);
+    if (lane == m) tb = nb;
+    if (idx < 0 && bits == nb) idx = m;
+    ++m;
+  }
+  return idx;
+}
+
+// Value table of each slice (one wavefront per slice) and each entry's index
+// into it.  More than VTAB values set *flag.
 __global__ __launch_bounds__(WG) void k_sell_vidx(const double* __restrict__ val,
                                                   const int64_t* __restrict__ off,
                                                   const int32_t* __restrict__ width, int nslices,
@@ -150,29 +175,12 @@ __global__ __launch_bounds__(WG) void k_sell_vidx(const double* __restrict__ val
   const int lane = threadIdx.x & (SSCG_WAVE - 1);
   const int64_t o = off[slice] + lane;
   const int w = width[slice];
-  long long tb = 0;  // lane l < m holds table entry l (as bits)
+  long long tb = 0;
   int m = 0;
   bool over = false;
   for (int j = 0; j < w; ++j) {
     const int64_t k = o + (int64_t)j * SSCG_WAVE;
-    const long long bits = __double_as_longlong(val[k]);
-    int idx = -1;
-    for (int i = 0; i < m; ++i)
-      if (__shfl(tb, i, SSCG_WAVE) == bits && idx < 0) idx = i;
-    for (;;) {  // append the lanes' new values, lowest lane first
-      const unsigned long long need = __ballot(idx < 0);
-      if (need == 0) break;
-      if (m == VTAB) {
-        over = true;
-        if (idx < 0) idx = 0;
-        break;
-      }
-      const long long nb = __shfl(bits, __ffsll((long long)need) - 1, SSCG_WAVE);
-      if (lane == m) tb = nb;
-      if (idx < 0 && bits == nb) idx = m;
-      ++m;
-    }
-    vidx[k] = (uint8_t)idx;
+    vidx[k] = (uint8_t)vtab_index(val[k], lane, tb, m, over);
   }
   if (lane < VTAB) vtab[(int64_t)slice * VTAB + lane] = __longlong_as_double(lane < m ? tb : 0);
   if (over && lane == 0) *flag = 1;
@@ -310,7 +318,9 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
 
 // Batched pass j: every 256-row block belongs to one system (blk_sys), whose
 // basis parameters and state come from the system table; blocks of finished
-// systems (or of no system, -1) return at once.
+// systems (or of no system, -1) return at once.  A system flagged vt reads
+// the value tables and 16-bit offsets of k_sell_forms_batch, one flagged il
+// the (P, R) pairs.
 template <int NRHS, bool CHEB, bool RES>
 __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, MpkSeq s1,
                                                   const BatchSys* __restrict__ sys,
@@ -338,6 +348,13 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
     else
       r2 = mpk_slice<NRHS, CHEB, false, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
                                                           xres, bres, tg, tw);
+  } else if (sys[q].vt) {  // value tables and 16-bit offsets (k_sell_forms_batch)
+    if (j >= 2)
+      r2 = mpk_slice<NRHS, CHEB, CHEB, RES, true, false, true>(A, slice, theta, sigma, gamma, s0,
+                                                               s1, xres, bres);
+    else
+      r2 = mpk_slice<NRHS, CHEB, false, RES, true, false, true>(A, slice, theta, sigma, gamma, s0,
+                                                                s1, xres, bres);
   } else {
     if (j >= 2)
       r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
@@ -679,6 +696,48 @@ __global__ void k_set_il(BatchSys* __restrict__ sys, const unsigned long long* _
   sys[q].il = cnt[2 * q + 1] * 4 > cnt[2 * q] ? 1 : 0;
 }
 
+// Compact forms of the batched matrix over slices [sl0, sl0 + count), one
+// wavefront per slice: 16-bit column offsets (as k_sell_compact) and the
+// value table with one-byte indices (as k_sell_vidx).  A slice with an
+// offset beyond 16 bits or more than VTAB values adds one to its system's
+// count; k_set_vt then lets a system's passes read the compact forms only if
+// none of its slices did.
+__global__ __launch_bounds__(WG) void k_sell_forms_batch(
+    const int32_t* __restrict__ scol, const double* __restrict__ val,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ width, int sl0, int count,
+    const int32_t* __restrict__ blk_sys, int16_t* __restrict__ col16, double* __restrict__ vtab,
+    uint8_t* __restrict__ vidx, int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (i >= count) return;  // whole wavefronts
+  const int slice = sl0 + i;
+  const int q = blk_sys[slice / SLICES_PER_WG];
+  if (q < 0) return;
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  const int64_t o = off[slice] + lane;
+  const int w = width[slice];
+  const int base = slice * SSCG_WAVE;
+  long long tb = 0;
+  int m = 0;
+  bool over = false, far = false;
+  for (int j = 0; j < w; ++j) {
+    const int64_t k = o + (int64_t)j * SSCG_WAVE;
+    const int d = scol[k] - base;
+    far |= d < -32768 || d > 32767;
+    col16[k] = (int16_t)d;
+    vidx[k] = (uint8_t)vtab_index(val[k], lane, tb, m, over);
+  }
+  if (lane < VTAB) vtab[(int64_t)slice * VTAB + lane] = __longlong_as_double(lane < m ? tb : 0);
+  if (__ballot(far || over) != 0 && lane == 0) atomicAdd(cnt + q, 1);
+}
+
+__global__ void k_set_vt(BatchSys* __restrict__ sys, const int32_t* __restrict__ cnt, int q0,
+                         int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int q = q0 + i;
+  sys[q].vt = cnt[q] == 0 ? 1 : 0;
+}
+
 // dst[p] = src[perm[p]] (0 for padding), p < npad.
 __global__ __launch_bounds__(WG) void k_gather_perm(const double* __restrict__ src,
                                                     const int32_t* __restrict__ perm, int npad,
@@ -821,6 +880,21 @@ hipError_t launch_sell_fill_perm(const int32_t* rowptr, const int32_t* col, cons
 hipError_t launch_set_il(BatchSys* sys, const unsigned long long* cnt, int q0, int count,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_set_il, dim3((count + 63) / 64), dim3(64), 0, st, sys, cnt, q0, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_forms_batch(const int32_t* scol, const double* val, const int64_t* off,
+                                   const int32_t* width, int sl0, int count,
+                                   const int32_t* blk_sys, int16_t* col16, double* vtab,
+                                   uint8_t* vidx, int32_t* cnt, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sell_forms_batch, dim3(wg_count(count)), dim3(WG), 0, st, scol, val, off,
+                     width, sl0, count, blk_sys, col16, vtab, vidx, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_vt(BatchSys* sys, const int32_t* cnt, int q0, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_vt, dim3((count + 63) / 64), dim3(64), 0, st, sys, cnt, q0, count);
   return hipGetLastError();
 }
 
