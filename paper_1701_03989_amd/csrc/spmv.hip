@@ -501,7 +501,9 @@ inline int wg_count(int nslices) { return (nslices + SLICES_PER_WG - 1) / SLICES
 
 
 // ---------------------------------------------------------------- FP32 pass
-template <int NRHS, bool CHEB, bool HASW, bool C16>
+// VI: the values come from the FP64 value tables rounded to FP32, the same
+// bits as val32 (which is the FP64 copy rounded entry by entry).
+template <int NRHS, bool CHEB, bool HASW, bool C16, bool VI = false>
 __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict__ val32,
                                               double theta, double sigma, double gamma,
                                               MpkSeq32 s0, MpkSeq32 s1) {
@@ -517,6 +519,12 @@ __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict_
   const float* __restrict__ u0 = s0.u;
   const float* __restrict__ u1 = s1.u;
   double a0 = 0.0, a1 = 0.0;
+  float tv[VTAB];
+  if (VI) {
+    const int us = __builtin_amdgcn_readfirstlane(slice);
+#pragma unroll
+    for (int i = 0; i < VTAB; ++i) tv[i] = (float)A.vtab[(int64_t)us * VTAB + i];
+  }
   constexpr int CH = 4;
   for (int j0 = 0; j0 < w; j0 += CH) {
     float v[CH], g0[CH], g1[CH];
@@ -525,7 +533,15 @@ __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict_
     for (int u = 0; u < CH; ++u) {
       int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
       bool in = j0 + u < w;
-      v[u] = in ? val32[k] : 0.0f;
+      if (VI) {
+        const int ix = in ? (int)A.vidx[k] : 0;
+        float t = tv[VTAB - 1];
+#pragma unroll
+        for (int i = VTAB - 2; i >= 0; --i) t = ix == i ? tv[i] : t;
+        v[u] = in ? t : 0.0f;
+      } else {
+        v[u] = in ? val32[k] : 0.0f;
+      }
       if (C16) c[u] = in ? slice * SSCG_WAVE + (int)A.col16[k] : 0;
       else c[u] = in ? A.col[k] : 0;
     }
@@ -1022,12 +1038,15 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
 }
 
 // 16-bit column offsets (6 bytes per stored entry with the FP32 value) when
-// the matrix copy has them.
+// the matrix copy has them, and value tables as well (3 bytes) when it has those.
 template <int NRHS, bool CHEB, bool HASW>
 static void mpk32_launch(const DevMat& A, const float* val32, double th, double sg, double gm,
                          MpkSeq32 s0, MpkSeq32 s1, hipStream_t st) {
   dim3 grid(xcd_grid(wg_count(A.nslices)));
-  if (A.col16)
+  if (A.col16 && A.vidx)
+    hipLaunchKernelGGL((k_mpk32<NRHS, CHEB, HASW, true, true>), grid, dim3(WG), 0, st, A, val32,
+                       th, sg, gm, s0, s1);
+  else if (A.col16)
     hipLaunchKernelGGL((k_mpk32<NRHS, CHEB, HASW, true>), grid, dim3(WG), 0, st, A, val32, th, sg,
                        gm, s0, s1);
   else

@@ -217,3 +217,31 @@ def test_solve_on_per_slice_coefficients_matches_oracle(ctx, basis):
     assert rc == ref.status == sscg.OK
     assert hist.schedule == ref.schedule
     assert np.linalg.norm(xh - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+def test_fp32_pass_table_form_matches_wider_forms_bitwise(ctx):
+    """The FP32 matrix-powers pass of the mixed-precision solve reads the same
+    three forms (its values rounded from the FP64 tables or from the stored
+    values): the rows of the first block agree to the last bit."""
+    A = slice_valued(64 * 48, 11, np.full(64 * 48, 6), 60, 4)
+    B = slice_valued(64 * 4, 12, np.full(64 * 4, 6), 20, 5)
+    pa, ra = vecs(A.n, 21)
+    outs = []
+    for M in (A, block_diag(A, B), block_diag(A, far_ring())):
+        n = M.n
+        ld = (n + 63) // 64 * 64
+        rcol = S + 1
+        p, r = vecs(n, 31)
+        p[:A.n], r[:A.n] = pa, ra
+        Y = torch.zeros((2 * S + 1) * ld, dtype=torch.float32, device=DEV)
+        Y[:n] = torch.as_tensor(p.astype(np.float32), device=DEV)
+        Y[rcol * ld: rcol * ld + n] = torch.as_tensor(r.astype(np.float32), device=DEV)
+        sscg.sscg_mpk32(ctx, sscg.DeviceCsr.from_host(M, DEV), S, False, sscg.BASIS_CHEBYSHEV,
+                        LMIN, LMAX, Y, ld, rcol)
+        Yh = host(Y)
+        outs.append([Yh[c * ld: c * ld + A.n] for c in range(2 * S + 1)])
+    assert all(np.isfinite(c).all() for c in outs[0])
+    for k, other in enumerate(outs[1:]):
+        for c in range(2 * S + 1):
+            assert np.array_equal(other[c], outs[0][c]), (k, c)
+    say("FP32 pass: table, 16-bit and 32-bit forms bit-identical on the first block")
