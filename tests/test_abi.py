@@ -70,6 +70,7 @@ def test_errors_without_a_device_or_context(lib):
     # NULL context: argument error, no crash
     assert lib.sscg_solve(None, None, None, None, None, None) == -1
     assert lib.sscg_set_timing(None, 1) == -1
+    assert lib.sscg_matrix_format(None, None, None, None) == -1
     from paper_1701_03989_amd import sscg
 
     o = sscg.Opts()
