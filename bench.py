@@ -623,8 +623,8 @@ def main():
         bench_precision(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
