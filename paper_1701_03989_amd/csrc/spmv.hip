@@ -448,8 +448,9 @@ __global__ __launch_bounds__(WG) void k_gershgorin(DevMat A, double* __restrict_
   }
 }
 
-// Lanczos: w_i = RN((A v)_i - beta_prev vprev_i); partials of w.v.
-template <bool C16>
+// Lanczos: w_i = RN((A v)_i - beta_prev vprev_i); partials of w.v.  VI: the
+// values come from the slice's value table (same bits), as in the passes.
+template <bool C16, bool VI = false>
 __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __restrict__ v,
                                                      const double* __restrict__ vprev,
                                                      const double* __restrict__ beta_prev,
@@ -466,6 +467,12 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
     int64_t o = A.off[slice] + lane;
     int wd = A.width[slice];
     dd a = dd_zero();
+    double tv[VTAB];
+    if (VI) {
+      const int us = __builtin_amdgcn_readfirstlane(slice);
+#pragma unroll
+      for (int i = 0; i < VTAB; ++i) tv[i] = A.vtab[(int64_t)us * VTAB + i];
+    }
     // chunks of CH entries, every load of a chunk issued before its first use
     // (the terms are added in entry order, as one at a time)
     constexpr int CH = 4;
@@ -476,7 +483,15 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
       for (int u = 0; u < CH; ++u) {
         const int64_t k = o + (int64_t)(j0 + u) * SSCG_WAVE;
         const bool in = j0 + u < wd;
-        av[u] = in ? A.val[k] : 0.0;
+        if (VI) {
+          const int ix = in ? (int)A.vidx[k] : 0;
+          double t = tv[VTAB - 1];
+#pragma unroll
+          for (int i = VTAB - 2; i >= 0; --i) t = ix == i ? tv[i] : t;
+          av[u] = in ? t : 0.0;
+        } else {
+          av[u] = in ? A.val[k] : 0.0;
+        }
         if (C16) c[u] = in ? slice * SSCG_WAVE + (int)A.col16[k] : 0;
         else c[u] = in ? A.col[k] : 0;
       }
@@ -1028,7 +1043,10 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
                                hipStream_t st) {
   int nb = wg_count(A.nslices);
   *nparts = nb;
-  if (A.col16)
+  if (A.col16 && A.vidx)
+    hipLaunchKernelGGL((k_lanczos_spmv<true, true>), dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v,
+                       vprev, beta_prev, w, part);
+  else if (A.col16)
     hipLaunchKernelGGL(k_lanczos_spmv<true>, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v, vprev,
                        beta_prev, w, part);
   else
