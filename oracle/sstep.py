@@ -54,7 +54,7 @@ from typing import Optional
 
 import numpy as np
 
-from .arith import CR
+from .arith import CR, ieee_div, ieee_sqrt
 from .kappa import kappa_spd
 
 EPS = 2.0 ** -53  # R1
@@ -102,6 +102,7 @@ class Block:
     res_updated: float  # sqrt(r'^T G r') after the last inner iteration
     relres_true: float  # ||b - A x|| / ||b|| after the block
     status: int = OK
+    rr_trace: list = field(default_factory=list)  # r'^T G r' after inner iteration j = 1..s_k
 
 
 @dataclass
@@ -214,12 +215,13 @@ def quad(ar, G, v):
     return ar.sdot(v, ar.smatvec(G, v))
 
 
-def inner_loop(ar, G, B, s: int, first: bool, check=None, iters=None):
+def inner_loop(ar, G, B, s: int, first: bool, check=None, iters=None, trace=None):
     """Run up to s iterations (or `iters` <= s) of the coordinate recurrence
     in the s-step basis (dimension 2s+1; s+1 in block 0).
 
     check: None (Algs. 2/3) or a function (j, rr1) -> bool that is True when
     the in-loop test of Alg. 4 (eq. check) says to break after iteration j.
+    trace: optional list; r'^T G r' after each iteration is appended to it.
     Returns (s_k, x', r', p', alphas, betas, rr, status)."""
     d = len(G)
     zero = ar.scalar(0)
@@ -253,6 +255,8 @@ def inner_loop(ar, G, B, s: int, first: bool, check=None, iters=None):
         p = [a + beta * b for a, b in zip(r, p)]
         alphas.append(alpha)
         betas.append(beta)
+        if trace is not None:
+            trace.append(rr1)
         rr = rr1
         if check is not None and check(j, rr1):
             break
@@ -327,6 +331,20 @@ def c_theory(j: int, n_a: int, bnorm: float, norm_a: float, kappa_a: float) -> f
     tau = bnorm / norm_a
     nk = (7.0 + 2.0 * n_a) + 14.0 * tau
     return ((6.0 * nk) * j) * kappa_a
+
+
+def condy_accepts(kappa_i: float, thr: float) -> bool:
+    """eq. condy for one sub-basis: sqrt(kappa(G_{k,i})) <= thr, accepted on
+    equality (R7)."""
+    return ieee_sqrt(kappa_i) <= thr
+
+
+def check_breaks(gam: float, eps_star: float, c_j: float, rr1: float) -> bool:
+    """eq. check after inner iteration j: break when
+    gamma >= eps* / (c_{k,j} eps (r'^T G r')^(1/2)), with r' the coordinates
+    after iteration j's update and its quadratic form clamped at 0 (R7, R10)."""
+    rhs = ieee_div(eps_star, (c_j * EPS) * ieee_sqrt(max(rr1, 0.0)))
+    return gam >= rhs
 
 
 def max_row_nnz(A) -> int:
@@ -418,15 +436,14 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
             for i in range(1, imax + 1):  # R7
                 kap = kappa_spd(principal(G, sub_indices(s_built, i, first)))
                 kappas.append(kap)
-                if ar.sqrt(kap) <= thr:
+                if condy_accepts(kap, thr):
                     s_tilde = i
                 else:
                     break
             gam = ar.sqrt(kappas[s_tilde - 1])
             if opts.inner_check:
                 def check(j, rr1, _gam=gam, _c=cfun):
-                    rhs = ar.div(eps_star, (_c(j) * EPS) * ar.sqrt(max(rr1, 0.0)))
-                    return _gam >= rhs
+                    return check_breaks(_gam, eps_star, _c(j), rr1)
         else:
             s_tilde = s_built
         idx = sub_indices(s_built, s_tilde, first)
@@ -434,7 +451,9 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
         Bs = assemble_B(ar, s_tilde, first,
                         basis_params(opts.basis, s_tilde, opts.lmin, opts.lmax, ar, opts.shifts))
         ys = [cols[a] for a in idx]
-        s_k, xc, rc, pc, alphas, betas, rr, st = inner_loop(ar, Gs, Bs, s_tilde, first, check)
+        rr_trace = []
+        s_k, xc, rc, pc, alphas, betas, rr, st = inner_loop(ar, Gs, Bs, s_tilde, first, check,
+                                                            trace=rr_trace)
         if diag is not None:
             _diag_block(ar, diag, ys, Gs, Bs, s_tilde, first, x, check, k, m)
         if s_k == 0:
@@ -448,7 +467,7 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
                     gamma=gam, thr=thr, rnorm=rnorm, kappas=kappas, alphas=alphas, betas=betas,
                     res_updated=(ar.sqrt(max(rr, 0.0)) if not ar.exact else rr),
                     relres_true=(relres_of(ar, A, b, x, nb) if not ar.exact else math.nan),
-                    status=st)
+                    status=st, rr_trace=rr_trace)
         res.blocks.append(blk)
         k += 1
         if not ar.exact and blk.relres_true <= opts.tol:
