@@ -64,10 +64,12 @@ typedef struct sscg_ctx sscg_ctx;
 /* Sparse SPD matrix in CSR form (device arrays).  rowptr[0] = 0, rowptr
  * non-decreasing, rowptr[n] = nnz; col entries in [0, n).  Only the values
  * are read as given: symmetry and positive definiteness are the caller's
- * promise (a violation shows up as SSCG_BREAKDOWN or SSCG_NOT_CONVERGED). */
+ * promise (a violation shows up as SSCG_BREAKDOWN or SSCG_NOT_CONVERGED).
+ * nnz is 64-bit; with the 32-bit rowptr of this form it must stay below 2^31
+ * (larger values are rejected with SSCG_ERR_ARG). */
 typedef struct {
   int32_t n;
-  int32_t nnz;
+  int64_t nnz;
   const int32_t* rowptr; /* n+1 */
   const int32_t* col;    /* nnz */
   const double* val;     /* nnz */
@@ -110,7 +112,10 @@ typedef struct {
  * exact products and rounded once to FP32), the Gram matrix of the FP32 basis
  * from exact products accumulated in FP64, and the coefficient recurrence,
  * kappa estimates (unit round-off 2^-24 in eqs. condy and check) and d_j in
- * FP64.  Stops when ||r_j|| / ||b|| <= tol.  The result field `iters` counts
+ * FP64.  Stops when ||r_j|| / ||b|| <= tol, measured on the caller's system
+ * A x = b also when equilibrating (the refinement is not part of Algorithm 4,
+ * so the scaled-system reading of Section 5 does not apply to its stopping
+ * test).  Supported by sscg_solve only.  The result field `iters` counts
  * inner iterations of all refinement steps, `blocks` their outer blocks. */
 enum { SSCG_PREC_FP64 = 0, SSCG_PREC_MIXED = 1 };
 
@@ -370,6 +375,13 @@ int sscg_server_step(sscg_server* server, int32_t* running, int32_t* queued, int
  * found malformed at admission). */
 int sscg_server_poll(sscg_server* server, int64_t id, int32_t* state, int32_t* status,
                      int32_t* blocks, int32_t* iters, double* relres);
+/* Per-block history of a finished request (Algorithm 4's s_k schedule, the
+ * s~_k of eq. condy and the true relative residual after each block): HOST
+ * arrays of `cap` entries (any may be NULL); *rows gets the number of entries
+ * written, min(cap, blocks, the server's history depth max_iters + 2 capped at
+ * 4096).  SSCG_ERR_ARG for an unknown request or one that is not done. */
+int sscg_server_history(sscg_server* server, int64_t id, int32_t cap, int32_t* s_k,
+                        int32_t* s_tilde, double* relres_true, int32_t* rows);
 
 /* ---------------------------------------------------------------- timing */
 

@@ -139,7 +139,9 @@ hipError_t ev_collect(sscg_ctx* c) {
 int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
   if (!A) return fail(ctx, SSCG_ERR_ARG, "A is NULL");
   if (A->n < 1) return fail(ctx, SSCG_ERR_ARG, "n = %d must be >= 1", A->n);
-  if (A->nnz < 0) return fail(ctx, SSCG_ERR_ARG, "nnz = %d must be >= 0", A->nnz);
+  if (A->nnz < 0 || A->nnz > INT32_MAX)
+    return fail(ctx, SSCG_ERR_ARG, "nnz = %lld outside [0, 2^31) (rowptr is 32-bit)",
+                (long long)A->nnz);
   if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val)))
     return fail(ctx, SSCG_ERR_ARG, "CSR arrays must not be NULL");
   int32_t ends[2] = {-1, -1};
@@ -148,8 +150,8 @@ int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
                         ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (ends[0] != 0 || ends[1] != A->nnz)
-    return fail(ctx, SSCG_ERR_ARG, "rowptr[0] = %d, rowptr[n] = %d (nnz = %d)", ends[0], ends[1],
-                A->nnz);
+    return fail(ctx, SSCG_ERR_ARG, "rowptr[0] = %d, rowptr[n] = %d (nnz = %lld)", ends[0], ends[1],
+                (long long)A->nnz);
   return SSCG_OK;
 }
 
@@ -525,7 +527,7 @@ void sscg_destroy(sscg_ctx* c) {
   Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y,    &c->part,
                  &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
                  &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran,   &c->scol16, &c->svidx, &c->svtab,
-                 &c->sval32, &c->Y32, &c->dx,  &c->r64};
+                 &c->sval32, &c->Y32, &c->dx,  &c->r64, &c->xu, &c->upart};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   BatchWs& w = c->batch;

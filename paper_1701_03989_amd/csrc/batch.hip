@@ -84,6 +84,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   if (o.equilibrate) return fail(ctx, SSCG_ERR_ARG, "batch: equilibration is not supported");
   if (o.basis == SSCG_BASIS_NEWTON || o.c_mode != SSCG_C_CONST)
     return fail(ctx, SSCG_ERR_ARG, "batch: the Newton basis and the theoretical c are not supported");
+  if (o.precision != SSCG_PREC_FP64)
+    return fail(ctx, SSCG_ERR_ARG, "batch: only SSCG_PREC_FP64 is supported");
   const int nsys = B->nsys;
   const bool cheb = o.basis == SSCG_BASIS_CHEBYSHEV;
   if (cheb && (!B->lambda_min || !B->lambda_max))

@@ -160,7 +160,7 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
 }
 
 // Sets *flag if rowptr decreases or a column index lies outside [0, n).
-hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int nnz,
+hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int64_t nnz,
                             int32_t* flag, hipStream_t st);
 hipError_t launch_sell_widths(const int32_t* rowptr, int n, int32_t* width, hipStream_t st);
 hipError_t launch_scan_offsets(const int32_t* width, int nslices, int64_t* off, hipStream_t st);
@@ -207,6 +207,13 @@ hipError_t launch_mpk_pass(const DevMat& A, int j, BasisPrm bp, int nrhs, MpkSeq
 hipError_t launch_residual(const DevMat& A, const double* b, const double* x, double* r,
                            double* rpart, double* bpart, int* nparts, hipStream_t st);
 int residual_nparts(int n);
+// The same norms from the CSR arrays themselves (no SELL copy, one row per
+// lane): rpart gets sum (b - A x)_i^2, bpart (if not NULL) sum b_i^2, in
+// csr_residual_nparts(n) dd partials each.
+int csr_residual_nparts(int n);
+hipError_t launch_csr_residual(const int32_t* rowptr, const int32_t* col, const double* val,
+                               int n, const double* b, const double* x, double* rpart,
+                               double* bpart, hipStream_t st);
 
 // Sum dd partials (pairs) of `count` independent reductions, each with
 // nparts parts stored at part[(k * nparts + q) * 2]; out[k] = RN(sum).

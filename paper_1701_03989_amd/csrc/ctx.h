@@ -82,6 +82,7 @@ struct sscg_ctx {
   int64_t sell_total = 0;      // SELL-64 entries of the last matrix copy
   // mixed precision: FP32 values of the SELL copy, FP32 basis, FP64 correction and residual
   sscg_host::Buf sval32, Y32, dx, r64;
+  sscg_host::Buf xu, upart;  // equilibrated mixed solves: unscaled iterate, its residual partials
 };
 
 namespace sscg_host {

@@ -8,8 +8,10 @@
 //                                round-off 2^-24 and eps* = inner_tol * ||r_j||
 //   x_{j+1} = x_j + d_j          FP64 (d_j accumulated in FP64 by the recovery)
 //
-// until ||r_j|| / ||b|| <= tol.  The inner solve stops when its updated
-// residual estimate (r'^T G r')^(1/2) falls to inner_tol * ||r_j||, or makes no
+// until ||r_j|| / ||b|| <= tol.  With equilibration the refinement runs on the
+// scaled system but this test is made on the caller's system: x = D^-1/2 x~
+// and ||b - A x|| / ||b|| from the caller's CSR arrays.  The inner solve stops
+// when its updated residual estimate (r'^T G r')^(1/2) falls to inner_tol * ||r_j||, or makes no
 // step.  Bandwidth per inner pass: 8 bytes per stored entry (FP32 value, int32
 // index) and 4 per vector element, against 12 and 8 in FP64.
 #include <math.h>
@@ -66,7 +68,7 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
   double* r = as<double>(ctx->r64);
   double* G = as<double>(ctx->G);
   double* coef = as<double>(ctx->coef);
-  double* scal = as<double>(ctx->scal);  // [0] r2 [1] b2 [2] relres
+  double* scal = as<double>(ctx->scal);  // [0] r2 [1] b2 (solved system) [2] r2 [3] b2 (caller's)
   double* part = as<double>(ctx->part);
   double* gpart = as<double>(ctx->rpart);
   sscg_block_info* info = as<sscg_block_info>(ctx->info);
@@ -80,6 +82,17 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
     HIPCHK(launch_scale_vec(x_out, as<double>(ctx->scale), 0, n, as<double>(ctx->xw), st));
     b = as<double>(ctx->bw);
     x = as<double>(ctx->xw);
+  }
+
+  // equilibrated: the unscaled iterate and its residual on the caller's system
+  double* xu = nullptr;
+  double* upart = nullptr;
+  const int unp = csr_residual_nparts(n);
+  if (o.equilibrate) {
+    HIPCHK(ensure(ctx->xu, sizeof(double) * n));
+    HIPCHK(ensure(ctx->upart, sizeof(double) * 4 * (size_t)unp));
+    xu = as<double>(ctx->xu);
+    upart = as<double>(ctx->upart);
   }
 
   sscg_result dummy;
@@ -111,7 +124,13 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
     HIPCHK(launch_residual(M, b, x, r, part, outer == 0 ? part + 2 * (size_t)np : nullptr, &np,
                            st));
     HIPCHK(launch_finalize(part, np, outer == 0 ? 2 : 1, scal, st));
-    HIPCHK(hipMemcpyAsync(ctx->hscal, scal, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    if (o.equilibrate) {  // ||b - A x||^2 and ||b||^2 of the caller's system
+      HIPCHK(launch_scale_vec(x, as<double>(ctx->scale), 1, n, xu, st));
+      HIPCHK(launch_csr_residual(A->rowptr, A->col, A->val, n, b_in, xu, upart,
+                                 upart + 2 * (size_t)unp, st));
+      HIPCHK(launch_finalize(upart, unp, 2, scal + 2, st));
+    }
+    HIPCHK(hipMemcpyAsync(ctx->hscal, scal, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double r2 = ctx->hscal[0];
     if (outer == 0) {
@@ -123,7 +142,8 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
         break;
       }
     }
-    const double rel = sqrt(r2) / sqrt(b2);
+    const double rel = o.equilibrate ? sqrt(ctx->hscal[2]) / sqrt(ctx->hscal[3])
+                                     : sqrt(r2) / sqrt(b2);
     if (outer == 0) R.relres0 = rel;
     else if (R.blocks >= 1 && R.blocks - 1 < R.cap && R.relres_true)
       R.relres_true[R.blocks - 1] = rel;

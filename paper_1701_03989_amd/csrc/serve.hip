@@ -74,6 +74,7 @@ struct Req {
   int64_t row0 = 0, npad = 0, nz0 = 0, nzlen = 0;
   int status = SSCG_OK, blocks = 0, iters = 0;
   double relres = NAN;
+  std::vector<BatchHist> hist;  // per-block history, copied out at retirement
 };
 
 }  // namespace
@@ -149,6 +150,11 @@ int retire(sscg_server* s, int slot) {
   r.iters = y.m;
   r.relres = y.relres;
   r.state = 2;
+  // the block history (complete once the step's closing synchronization is done)
+  r.hist.resize(std::min(y.blocks, s->cap));
+  if (!r.hist.empty())
+    HIPCHK(hipMemcpyAsync(r.hist.data(), s->c.hist + (size_t)slot * s->cap,
+                          sizeof(BatchHist) * r.hist.size(), hipMemcpyDeviceToHost, s->st));
   s->ra.release(r.row0 / ROW_UNIT, r.npad / ROW_UNIT);
   s->na.release(r.nz0, r.nzlen);
   s->slot_req[slot] = 0;
@@ -276,6 +282,8 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
     return fail(ctx, SSCG_ERR_ARG, "server: MODE_SCHEDULE and equilibration are not supported");
   if (opts->basis == SSCG_BASIS_NEWTON || opts->c_mode != SSCG_C_CONST)
     return fail(ctx, SSCG_ERR_ARG, "server: the Newton basis and the theoretical c are not supported");
+  if (opts->precision != SSCG_PREC_FP64)
+    return fail(ctx, SSCG_ERR_ARG, "server: only SSCG_PREC_FP64 is supported");
   if (slots < 1 || slots > 65536) return fail(ctx, SSCG_ERR_ARG, "server: bad slot count %d", slots);
   const int64_t rows = (std::max<int64_t>(pool_rows, 1) + ROW_UNIT - 1) / ROW_UNIT * ROW_UNIT;
   if (rows > INT32_MAX / 2) return fail(ctx, SSCG_ERR_ARG, "server: pool_rows too large");
@@ -449,8 +457,8 @@ extern "C" int sscg_server_submit(sscg_server* s, const sscg_csr* A, const doubl
   r.lmax = cheb ? lambda_max : 1.0;
   r.npad = ((int64_t)std::max(A->n, 1) + ROW_UNIT - 1) / ROW_UNIT * ROW_UNIT;
   if (r.npad > s->rows || A->nnz > s->nnz)
-    return fail(ctx, SSCG_ERR_ARG, "server: a system of %d rows / %d nonzeros never fits the pools",
-                A->n, A->nnz);
+    return fail(ctx, SSCG_ERR_ARG, "server: a system of %d rows / %lld nonzeros never fits the pools",
+                A->n, (long long)A->nnz);
   const int64_t k = s->next_id++;
   s->reqs.emplace(k, r);
   s->queue.push_back(k);
@@ -526,5 +534,24 @@ extern "C" int sscg_server_poll(sscg_server* s, int64_t id, int32_t* state, int3
   if (blocks) *blocks = r.blocks;
   if (iters) *iters = r.iters;
   if (relres) *relres = r.relres;
+  return SSCG_OK;
+}
+
+extern "C" int sscg_server_history(sscg_server* s, int64_t id, int32_t cap, int32_t* s_k,
+                                   int32_t* s_tilde, double* relres_true, int32_t* rows) {
+  if (!s) return SSCG_ERR_ARG;
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(s->ctx, SSCG_ERR_ARG, "server: unknown request %lld",
+                                       (long long)id);
+  const Req& r = it->second;
+  if (r.state != 2) return fail(s->ctx, SSCG_ERR_ARG, "server: request %lld is not done",
+                                (long long)id);
+  const int nrec = std::min<int>((int)r.hist.size(), std::max(cap, 0));
+  for (int k = 0; k < nrec; ++k) {
+    if (s_k) s_k[k] = r.hist[k].s_k;
+    if (s_tilde) s_tilde[k] = r.hist[k].s_tilde;
+    if (relres_true) relres_true[k] = r.hist[k].relres_true;
+  }
+  if (rows) *rows = nrec;
   return SSCG_OK;
 }

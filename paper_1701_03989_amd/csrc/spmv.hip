@@ -14,8 +14,8 @@ constexpr int SLICES_PER_WG = WG / SSCG_WAVE;
 // ---------------------------------------------------------------- SELL-64
 
 __global__ __launch_bounds__(WG) void k_check_csr(const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ col, int n, int nnz,
-                                                  int32_t* __restrict__ flag) {
+                                                  const int32_t* __restrict__ col, int n,
+                                                  int64_t nnz, int32_t* __restrict__ flag) {
   int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
   int bad = 0;
   if (t < n) bad |= rowptr[t + 1] < rowptr[t];
@@ -420,6 +420,38 @@ __global__ __launch_bounds__(WG) void k_residual(DevMat A, const double* __restr
   }
 }
 
+// The residual of the caller's CSR matrix itself, one row per lane (no SELL
+// copy): per-workgroup dd partials of sum (b_i - (A x)_i)^2 and, if bpart,
+// of sum b_i^2, each res_i rounded once from its exact value.
+__global__ __launch_bounds__(WG) void k_csr_residual(const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val, int n,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ rpart,
+                                                     double* __restrict__ bpart) {
+  int nb = (n + WG - 1) / WG;
+  int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  int row = lb * WG + threadIdx.x;
+  dd r2 = dd_zero(), b2 = dd_zero();
+  if (row < n) {
+    dd a = dd_zero();
+    const int k1 = rowptr[row + 1];
+    for (int k = rowptr[row]; k < k1; ++k) dd_add_prod(a, val[k], x[col[k]]);
+    double bi = b[row];
+    dd_add(a, -bi);
+    double ri = -dd_round(a);
+    dd_add_prod(r2, ri, ri);
+    dd_add_prod(b2, bi, bi);
+  }
+  wg_store_partial(r2, rpart, lb);
+  if (bpart) {
+    __syncthreads();
+    wg_store_partial(b2, bpart, lb);
+  }
+}
+
 // Gershgorin: partial maxima of RN(sum_j |a_ij|).
 __global__ __launch_bounds__(WG) void k_gershgorin(DevMat A, double* __restrict__ part) {
   __shared__ double lm[SLICES_PER_WG];
@@ -806,7 +838,7 @@ __global__ __launch_bounds__(WG) void k_cast_f32(const double* __restrict__ in, 
 
 // ---------------------------------------------------------------- launches
 
-hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int nnz,
+hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int64_t nnz,
                             int32_t* flag, hipStream_t st) {
   int64_t m = n > nnz ? n : nnz;
   hipLaunchKernelGGL(k_check_csr, dim3((unsigned)((m + WG - 1) / WG)), dim3(WG), 0, st, rowptr, col,
@@ -1028,6 +1060,17 @@ hipError_t launch_residual(const DevMat& A, const double* b, const double* x, do
   int nb = wg_count(A.nslices);
   *nparts = nb;
   hipLaunchKernelGGL(k_residual, dim3(xcd_grid(nb)), dim3(WG), 0, st, A, b, x, r, rpart, bpart);
+  return hipGetLastError();
+}
+
+int csr_residual_nparts(int n) { return (n + WG - 1) / WG; }
+
+hipError_t launch_csr_residual(const int32_t* rowptr, const int32_t* col, const double* val,
+                               int n, const double* b, const double* x, double* rpart,
+                               double* bpart, hipStream_t st) {
+  int nb = csr_residual_nparts(n);
+  hipLaunchKernelGGL(k_csr_residual, dim3(xcd_grid(nb)), dim3(WG), 0, st, rowptr, col, val, n, b,
+                     x, rpart, bpart);
   return hipGetLastError();
 }
 

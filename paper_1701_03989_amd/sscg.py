@@ -38,7 +38,7 @@ class SscgError(RuntimeError):
 
 
 class Csr(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("rowptr", ctypes.c_void_p),
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
@@ -150,6 +150,8 @@ EXPORTS = {
     "sscg_server_step": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
     "sscg_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _ip, _ip, _ip, _ip,
                                         _dp]),
+    "sscg_server_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _ip,
+                                           _ip, _dp, _ip]),
     "sscg_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sscg_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
@@ -404,6 +406,19 @@ def sscg_server_poll(ctx: int, server: int, rid: int) -> dict:
                                        ctypes.byref(rel)))
     return dict(state=st.value, status=status.value, blocks=blocks.value, iters=iters.value,
                 relres=rel.value)
+
+
+def sscg_server_history(ctx: int, server: int, rid: int, cap: int = 4096) -> dict:
+    """Per-block s_k, s~_k and true relative residual of a finished request."""
+    sk = np.zeros(cap, np.int32)
+    st = np.zeros(cap, np.int32)
+    rel = np.full(cap, np.nan)
+    rows = ctypes.c_int32()
+    _check(ctx, lib().sscg_server_history(server, rid, cap, sk.ctypes.data_as(_ip),
+                                          st.ctypes.data_as(_ip), rel.ctypes.data_as(_dp),
+                                          ctypes.byref(rows)))
+    k = rows.value
+    return dict(s_k=sk[:k].tolist(), s_tilde=st[:k].tolist(), relres_true=rel[:k].tolist())
 
 
 def sscg_residual(ctx: int, A: DeviceCsr, b, x, r, out2) -> int:

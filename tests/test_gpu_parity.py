@@ -210,6 +210,10 @@ def _solve(ctx, A, b, x1, cap=4096, **kw):
 
 
 SOLVES = [
+    # the 32 x 32 workload exactly as stated: adaptive monomial, s_max 8, tol
+    # 1e-10, in-loop checks on, no equilibration; and its fixed s = 4 run
+    dict(mode="adaptive", s_max=8, tol=1e-10),
+    dict(mode="fixed", fixed_s=4, s_max=8, tol=1e-10),
     dict(mode="adaptive", s_max=8, tol=1e-10, equilibrate=True),
     dict(mode="adaptive", s_max=8, tol=1e-14, equilibrate=True),
     dict(mode="fixed", fixed_s=4, s_max=8, tol=1e-10, equilibrate=True),
@@ -244,6 +248,57 @@ def test_full_solve_matches_oracle_on_poisson_32(ctx, k):
     say(f"  |x - x_oracle| / |x_oracle| = {err:.2e}")
     assert err <= 1e-12
     assert hist.res.relres <= kw["tol"] or rc != sscg.OK
+
+
+@pytest.mark.parametrize("f,s_bar,s_k", [
+    (1, [2, 3, 3, 4, 5, 6, 6, 6], [2, 2, 3, 4, 5, 6, 6, 6]),
+    (2, [2, 4, 4, 6, 6, 6, 6, 6], [2, 2, 4, 6, 6, 6, 6, 6]),
+])
+def test_growth_limit_sequences_by_hand(ctx, f, s_bar, s_k):
+    """Algorithm 4's growth limit s_bar_k = min(s_{k-1} + f, s_max) with
+    s_bar_0 = 2, s_max = 6 and a threshold so large that every basis is
+    accepted: the s_bar and s_k sequences written out by hand (the same ones
+    the oracle's CPU test pins), and the oracle's iterates."""
+    A, b, x1, _ = problems.poisson2d_32_system(0)
+    kw = dict(mode="adaptive", s_max=6, s0_bar=2, f=f, c=1e-30, tol=1e-10, equilibrate=True,
+              max_iters=40)
+    ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
+    rc, x, hist = _solve(ctx, A, b, x1, **kw)
+    say(f"growth f={f}: gpu s_bar {hist.s_bar[:hist.blocks].tolist()} s_k {hist.schedule}")
+    assert hist.s_bar[:len(s_bar)].tolist() == s_bar
+    assert hist.schedule[:len(s_k)] == s_k
+    assert rc == ref.status and hist.schedule == ref.schedule
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-12
+
+
+def _graph400():
+    A = problems.graph_laplacian(400, 0)
+    return A, problems.uniform(A.n, 0), np.zeros(A.n)
+
+
+def _logdiag30():
+    d = np.logspace(0.0, 4.0, 30)
+    return problems.from_dense(np.diag(d)), np.random.default_rng(0).uniform(-1, 1, 30), np.zeros(30)
+
+
+@pytest.mark.parametrize("system,kw", [
+    (_graph400, dict(mode="adaptive", s_max=10, tol=1e-12, c=10.0)),
+    (_logdiag30, dict(mode="adaptive", s_max=8, tol=1e-10)),
+    (_logdiag30, dict(mode="adaptive", s_max=6, tol=1e-8, c=10.0, basis="chebyshev", lmin=0.9,
+                      lmax=1.1e4)),
+])
+def test_inner_check_breaks_match_oracle(ctx, system, kw):
+    """Systems on which eq. check stops some blocks short of s~ (a residual
+    grows inside the block): the device takes the same breaks."""
+    A, b, x1 = system()
+    ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
+    rc, x, hist = _solve(ctx, A, b, x1, **kw)
+    short = [k for k, blk in enumerate(ref.blocks) if blk.s_k < blk.s_tilde]
+    say(f"check breaks: oracle blocks {short[:10]} of {len(ref.blocks)}")
+    assert rc == ref.status and hist.schedule == ref.schedule
+    assert [int(hist.s_tilde[k]) for k in range(hist.blocks)] == [blk.s_tilde for blk in ref.blocks]
+    assert short, "the case must exercise the break"
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-12
 
 
 def test_schedule_replay_matches_oracle_iterates(ctx):

@@ -1,7 +1,8 @@
 """The solve server (continuous batching) through the C ABI: every request's
 result must be the one sscg_solve gives for that system alone (same bits,
 schedule length and status), whatever else shares the device with it, however
-requests arrive, and however tight the pools are."""
+requests arrive, and however tight the pools are; and, against the CPU oracle
+(Algorithm 4 in FP64), the same s_k schedule and iterates within 1e-12."""
 import sys
 
 import numpy as np
@@ -9,6 +10,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import sstep  # noqa: E402
 from paper_1701_03989_amd import problems, sscg  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -75,6 +77,23 @@ class Client:
             assert p["status"] == rc and p["blocks"] == blocks, (rid, p, rc, blocks)
             assert np.array_equal(x.cpu().numpy(), xa), (rid, s.kind)
 
+    def check_oracle(self):
+        """Each served request against the oracle's Algorithm 4 with the same
+        tolerance and interval: status, s_k schedule, s~_k, and x within 1e-12."""
+        for rid, (s, tol, _, _, x) in self.live.items():
+            p = sscg.sscg_server_poll(self.ctx, self.srv, rid)
+            h = sscg.sscg_server_history(self.ctx, self.srv, rid)
+            ref = sstep.solve(s.A, s.b, np.zeros(s.A.n),
+                              sstep.Opts(**dict(KW, tol=tol, lmin=s.lmin, lmax=s.lmax)))
+            xh = x.cpu().numpy()
+            err = np.linalg.norm(xh - ref.x) / np.linalg.norm(ref.x)
+            say(f"  request {rid} ({s.kind}, n={s.A.n}, tol {tol:g}): {len(h['s_k'])} blocks, "
+                f"oracle {len(ref.blocks)}; error vs oracle {err:.1e}")
+            assert p["status"] == ref.status
+            assert h["s_k"] == ref.schedule
+            assert h["s_tilde"] == [blk.s_tilde for blk in ref.blocks]
+            assert err <= 1e-12
+
 
 def make_server(ctx, rows=1 << 16, nnz=1 << 20, slots=64):
     return sscg.sscg_server_create(ctx, sscg.make_opts(**KW), rows, nnz, slots)
@@ -112,6 +131,7 @@ def test_server_staggered_arrivals_and_tolerances(ctx):
         cl.check_all()
         for rid, (s, tol, *_r) in cl.live.items():
             assert sscg.sscg_server_poll(ctx, srv, rid)["relres"] <= tol
+        cl.check_oracle()
     finally:
         sscg.sscg_server_destroy(srv)
 
@@ -135,6 +155,25 @@ def test_server_admission_waits_for_room(ctx):
                 break
         assert seen_queue
         cl.check_all()
+    finally:
+        sscg.sscg_server_destroy(srv)
+
+
+def test_server_history_requires_a_finished_request(ctx):
+    s = problems.batch_systems(1, seed=91, nlo=300, nhi=400)[0]
+    srv = make_server(ctx)
+    try:
+        cl = Client(ctx, srv)
+        rid = cl.submit(s, 1e-10)
+        with pytest.raises(sscg.SscgError):
+            sscg.sscg_server_history(ctx, srv, rid)
+        with pytest.raises(sscg.SscgError):
+            sscg.sscg_server_history(ctx, srv, rid + 1000)
+        cl.drain()
+        h = sscg.sscg_server_history(ctx, srv, rid)
+        assert len(h["s_k"]) == sscg.sscg_server_poll(ctx, srv, rid)["blocks"] >= 1
+        assert h["relres_true"][-1] <= 1e-10
+        cl.check_oracle()
     finally:
         sscg.sscg_server_destroy(srv)
 
