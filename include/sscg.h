@@ -268,6 +268,20 @@ int sscg_mpk_newton(sscg_ctx* ctx, const sscg_csr* A, int s, int first, const do
 int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,
               double* G);
 
+/* sscg_gram for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same G, bit for bit, with the partial sums held in a
+ * fixed 4 MiB device array of the library (one per GPU, kept until the
+ * process ends, its address looked up by sscg_create) instead of the
+ * context's growable workspace.  Allocates nothing; enqueues on the
+ * context's stream like sscg_gram.  Any n is accepted (fewer workgroups are
+ * used when the d(d+1)/2 entries' partials would not fit); arguments as for
+ * sscg_gram.  Calls on one GPU share the array: calls that overlap in time
+ * on that GPU (other streams, other contexts, other threads) race and must
+ * be serialised by the caller. */
+int sscg_gram_noalloc(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy,
+                      int rcol, double* G);
+
 /* One block's coordinate solve (Algorithm 4 from "Determine s~" to the end
  * of the inner loop): kappa(G_i) for i = 1..s (Jacobi eigenvalues, when
  * adaptive), s~ by eq. condy, B (eq. AVVB), the inner recurrence with the

@@ -515,6 +515,11 @@ int sscg_create(sscg_ctx** out, int device, void* stream) {
     return SSCG_ERR_OOM;
   }
   c->events_made = true;
+  if (scratch_setup(c) != SSCG_OK) {
+    g_create_err = c->err;
+    sscg_destroy(c);
+    return SSCG_ERR_HIP;
+  }
   *out = c;
   return SSCG_OK;
 }

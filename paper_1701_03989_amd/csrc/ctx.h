@@ -83,6 +83,7 @@ struct sscg_ctx {
   // mixed precision: FP32 values of the SELL copy, FP32 basis, FP64 correction and residual
   sscg_host::Buf sval32, Y32, dx, r64;
   sscg_host::Buf xu, upart;  // equilibrated mixed solves: unscaled iterate, its residual partials
+  void* scratch = nullptr;   // device address of the static scratch array on this device
 };
 
 namespace sscg_host {
@@ -167,6 +168,11 @@ int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const 
 
 // One outer block of a batch for every unfinished system (capturable).
 int batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st);
+
+// Look up the device address of the static scratch array of
+// sscg_gram_noalloc on ctx's device (current), once per device; sets
+// ctx->scratch.
+int scratch_setup(sscg_ctx* ctx);
 
 // sscg_solve with opts->precision = SSCG_PREC_MIXED (arguments checked).
 int solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x, const sscg_opts& o,

@@ -126,6 +126,9 @@ EXPORTS = {
                                 ctypes.c_int64, ctypes.c_int]),
     "sscg_gram": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
+    "sscg_gram_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_void_p]),
     "sscg_small_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(BlockParams), ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -469,6 +472,11 @@ def sscg_mpk_newton(ctx: int, A: DeviceCsr, s: int, first: bool, shifts, Y, ldy:
 
 def sscg_gram(ctx: int, n: int, s: int, first: bool, Y, ldy: int, rcol: int, G) -> int:
     return _check(ctx, lib().sscg_gram(ctx, n, s, int(first), _f64(Y), ldy, rcol, _f64(G)))
+
+
+def sscg_gram_noalloc(ctx: int, n: int, s: int, first: bool, Y, ldy: int, rcol: int, G) -> int:
+    return _check(ctx, lib().sscg_gram_noalloc(ctx, n, s, int(first), _f64(Y), ldy, rcol,
+                                               _f64(G)))
 
 
 def sscg_small_solve(ctx: int, G, prm: BlockParams, coef, info) -> int:

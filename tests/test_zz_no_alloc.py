@@ -1,0 +1,85 @@
+"""sscg_gram_noalloc (the Gram stage with its partials in the library's static
+device array, allocating nothing) against sscg_gram (the same stage with the
+context's growable workspace), through the C ABI: the same G bit for bit on
+two calls in a row, the second with a smaller input, and against the oracle's
+correctly rounded Gram of the same columns.  Also with n so large that the
+static array forces fewer workgroups than sscg_gram uses."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.arith import CR  # noqa: E402
+from paper_1701_03989_amd import problems, sscg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = sscg.sscg_create(0)
+    yield h
+    sscg.sscg_destroy(h)
+
+
+def basis(n, s, first, seed):
+    """Seeded columns in the layout of sscg_mpk: P_j at column j, R_j at rcol + j."""
+    ld = (n + 63) // 64 * 64 + 64
+    rcol = s + 2
+    rng = np.random.default_rng(seed)
+    Yh = np.zeros((2 * s + 3) * ld)
+    cols = list(range(s + 1)) + ([] if first else list(range(rcol, rcol + s)))
+    for c in cols:
+        Yh[c * ld:c * ld + n] = rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 4)
+    return Yh, ld, rcol, cols
+
+
+def one_case(ctx, n, s, first, seed, oracle=True):
+    Yh, ld, rcol, cols = basis(n, s, first, seed)
+    Y = torch.as_tensor(Yh, device=DEV)
+    d = len(cols)
+    G1 = torch.full((d * d,), np.nan, dtype=torch.float64, device=DEV)
+    G2 = torch.full((d * d,), np.nan, dtype=torch.float64, device=DEV)
+    sscg.sscg_gram(ctx, n, s, first, Y, ld, rcol, G1)
+    sscg.sscg_gram_noalloc(ctx, n, s, first, Y, ld, rcol, G2)
+    torch.cuda.synchronize()
+    g1 = G1.cpu().numpy().reshape(d, d)
+    g2 = G2.cpu().numpy().reshape(d, d)
+    say(f"n={n} s={s} first={first}: equal {np.array_equal(g1, g2)}")
+    assert np.array_equal(g1, g2)
+    if oracle:
+        go = np.array(CR().gram([Yh[c * ld:c * ld + n] for c in cols]))
+        assert np.array_equal(g2, go)
+
+
+def test_noalloc_gram_equals_sscg_gram_two_calls_second_smaller(ctx):
+    one_case(ctx, 50_000, 10, False, 1)
+    one_case(ctx, 3_001, 4, False, 2)   # smaller: stale partials of the first call must not leak
+    one_case(ctx, 1_000, 8, True, 3)    # block 0 form, smaller again
+
+
+def test_noalloc_gram_with_reduced_partition(ctx):
+    """d = 33 and 2.1 M rows: sscg_gram uses 2048 workgroups, the static array
+    holds the partials of 467; the entries are the same bits."""
+    one_case(ctx, 2_097_152, 16, False, 4, oracle=False)
+    one_case(ctx, 70_000, 16, False, 5)
+
+
+def test_noalloc_gram_rejects_bad_arguments(ctx):
+    Y = torch.zeros(1024, dtype=torch.float64, device=DEV)
+    G = torch.zeros(9, dtype=torch.float64, device=DEV)
+    for args in [(0, 1, True), (100, 0, True), (100, 17, True)]:
+        with pytest.raises(sscg.SscgError) as e:
+            sscg.sscg_gram_noalloc(ctx, args[0], args[1], args[2], Y, 512, 4, G)
+        assert e.value.code == sscg.ERR_ARG
