@@ -407,7 +407,12 @@ int sscg_server_history(sscg_server* server, int64_t id, int32_t cap, int32_t* s
  * launches (each pair costs a little time on the stream, so time only the
  * families you need).  sscg_kernel_stats (which waits for the streams)
  * returns, for one family id, the launches, their summed duration in ms and
- * their summed algorithmic bytes.  Every call resets the counters. */
+ * their summed algorithmic bytes: what each launch must move at least, in the
+ * form it reads.  Matrix powers: the stored SELL-64 entries of A at 3 bytes
+ * (value tables and 16-bit offsets), 10 (16-bit offsets) or 12, per slice its
+ * offset and width (and 4-entry table), plus 8 bytes per vector element read
+ * or written (sequences, three-term w, outputs, the fused residual's x and b).
+ * Gram: 8 n d.  Recovery: 8 n (d + 4).  Every call resets the counters. */
 #define SSCG_TIME_ALL 0xF
 int sscg_set_timing(sscg_ctx* ctx, int families);
 int sscg_kernel_stats(sscg_ctx* ctx, int family, int64_t* launches, double* ms, double* bytes);

@@ -9,7 +9,10 @@ written once against the small interface below, so the same code runs
   its exact value; every other operation is a single IEEE operation; and
 * in exact rational arithmetic (``Exact``), which pins the algorithms to their
   exact-arithmetic identities (s-step CG and CG produce the same iterates,
-  Section 2; CG terminates in at most n steps).
+  Section 2; CG terminates in at most n steps); and
+* in plain FP64 (``Plain``): every reduction is an ordinary FP64 library sum
+  (numpy / scipy, order unspecified), as in the paper's MATLAB runs.  Used to
+  time the oracle (no correctly rounded sums), never as a parity reference.
 
 Vectors of length n are numpy arrays (CR) or lists of Fractions (Exact);
 small coordinate vectors and matrices are Python lists in both.
@@ -178,3 +181,50 @@ class Exact:
 
     def isfinite(self, a) -> bool:
         return True
+
+
+class Plain(CR):
+    """FP64 with plain library reductions (numpy / scipy sparse): the same
+    algorithms and operation sequence as CR, but sums are not correctly
+    rounded.  For timing the CPU oracle only."""
+
+    name = "plain"
+
+    def __init__(self):
+        self._csr = {}
+
+    def _mat(self, A):
+        import scipy.sparse as sp
+
+        key = id(A)
+        hit = self._csr.get(key)
+        if hit is None or hit[0] is not A:
+            n = len(A.rowptr) - 1
+            m = sp.csr_matrix((np.asarray(A.val, dtype=np.float64), np.asarray(A.col),
+                               np.asarray(A.rowptr)), shape=(n, n))
+            hit = (A, m)
+            self._csr[key] = hit
+        return hit[1]
+
+    def csr_comb(self, A, u, extra=()):
+        out = self._mat(A) @ np.asarray(u, dtype=np.float64)
+        for c, v in extra:
+            out = out + c * v
+        return out
+
+    def dot(self, x, y) -> float:
+        return float(np.dot(x, y))
+
+    def gram(self, cols):
+        Y = np.stack(cols, axis=1)
+        return (Y.T @ Y).tolist()
+
+    def rows_comb(self, cols, coef, base=None):
+        out = np.stack(cols, axis=1) @ np.asarray(coef, dtype=np.float64)
+        return out if base is None else base + out
+
+    def sdot(self, a, b) -> float:
+        return float(np.dot(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)))
+
+    def smatvec(self, M, v):
+        return (np.asarray(M, dtype=np.float64) @ np.asarray(v, dtype=np.float64)).tolist()

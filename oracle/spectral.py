@@ -37,9 +37,9 @@ def start_vector(n: int, seed: int) -> np.ndarray:
     return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
 
 
-def gershgorin_max(A) -> float:
-    """max_i sum_j |a_ij| (each row sum correctly rounded)."""
-    ar = CR()
+def gershgorin_max(A, ar=None) -> float:
+    """max_i sum_j |a_ij| (each row sum correctly rounded with CR)."""
+    ar = ar if ar is not None else CR()
     absval = np.abs(np.asarray(A.val, dtype=np.float64))
 
     class _Abs:
@@ -49,13 +49,13 @@ def gershgorin_max(A) -> float:
     return float(np.max(ar.csr_comb(_Abs, ones)))
 
 
-def lanczos_tridiag(A, m: int, seed: int):
+def lanczos_tridiag(A, m: int, seed: int, ar=None):
     """m Lanczos steps on A from start_vector(n, seed); returns (alphas, betas).
 
     v_1 = u/||u||;  w = A v_j - beta_{j-1} v_{j-1} (one rounding per row);
     alpha_j = w.v_j;  w = w - alpha_j v_j;  beta_j = ||w||;  v_{j+1} = w / beta_j.
     Stops early if beta_j = 0 (invariant subspace)."""
-    ar = CR()
+    ar = ar if ar is not None else CR()
     n = len(A.rowptr) - 1
     u = start_vector(n, seed)
     nu = ar.sqrt(ar.dot(u, u))
@@ -91,10 +91,10 @@ def ritz_values(alphas, betas) -> np.ndarray:
     return np.sort(ev)
 
 
-def chebyshev_interval(A, m: int = 30, seed: int = 0) -> tuple[float, float]:
-    a, b = lanczos_tridiag(A, m, seed)
+def chebyshev_interval(A, m: int = 30, seed: int = 0, ar=None) -> tuple[float, float]:
+    a, b = lanczos_tridiag(A, m, seed, ar)
     rv = ritz_values(a, b)
-    return float(rv[0]), gershgorin_max(A)
+    return float(rv[0]), gershgorin_max(A, ar)
 
 
 def leja_order(points) -> list:

@@ -215,7 +215,16 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   M->col16 = wide ? nullptr : as<int16_t>(ctx->scol16);
   M->vidx = many ? nullptr : as<uint8_t>(ctx->svidx);
   M->vtab = many ? nullptr : as<double>(ctx->svtab);
+  ctx->mat_bytes = mpk_matrix_bytes(*M, total);
   return SSCG_OK;
+}
+
+double mpk_matrix_bytes(const DevMat& M, int64_t stored) {
+  // the forms the pass dispatches on: value tables only with 16-bit offsets
+  const bool c16 = M.col16 != nullptr, vt = c16 && M.vidx != nullptr;
+  const double per_entry = vt ? 1.0 + 2.0 : (c16 ? 8.0 + 2.0 : 8.0 + 4.0);
+  const double per_slice = 8.0 + 4.0 + (vt ? 8.0 * VTAB : 0.0);  // off, width, table
+  return per_entry * (double)stored + per_slice * (double)M.nslices;
 }
 
 ColPtr colptr_of(const BasisCols& bc, int s, int first) {
@@ -224,7 +233,7 @@ ColPtr colptr_of(const BasisCols& bc, int s, int first) {
 }
 
 int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
-               int64_t nnz, const int* stop, const MpkResidual& res) {
+               double mat_bytes, const int* stop, const MpkResidual& res) {
   const int n = M.n;
   // the s passes run back to back: one timed interval, a ran flag per pass
   size_t slot = 0;
@@ -239,7 +248,7 @@ int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, co
     }
     const bool withres = j == 1 && res.x;
     double vec = 2.0 * nrhs + ((bp.cheb && j >= 2) ? nrhs : 0) + (withres ? 2 : 0);
-    double bytes = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n * vec;
+    double bytes = mat_bytes + 8.0 * n * vec;
     HIPCHK(launch_mpk_pass(M, j, bp, nrhs, sp, sr, Gate{stop, ev_sub(ctx, slot, bytes)},
                            withres ? res : MpkResidual{}, ctx->stream));
   }
@@ -678,7 +687,7 @@ int sscg_mpk_newton(sscg_ctx* ctx, const sscg_csr* A, int s, int first, const do
   if ((rc = build_mat(ctx, A, 0, &M))) return rc;
   BasisCols bc{Y, Y + (int64_t)rcol * ldy, Y, ldy, rcol};
   return mpk_passes(ctx, M, s, first ? 1 : 0, make_basis(SSCG_BASIS_NEWTON, 0.0, 1.0, th), bc,
-                    A->nnz, nullptr, MpkResidual{});
+                    ctx->mat_bytes, nullptr, MpkResidual{});
 }
 
 int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, double lambda_min,
@@ -701,7 +710,7 @@ int sscg_mpk(sscg_ctx* ctx, const sscg_csr* A, int s, int first, int basis, doub
   if ((rc = build_mat(ctx, A, 0, &M))) return rc;
   BasisCols bc{Y, Y + (int64_t)rcol * ldy, Y, ldy, rcol};
   return mpk_passes(ctx, M, s, first ? 1 : 0, make_basis(basis, lambda_min, lambda_max), bc,
-                    A->nnz, nullptr, MpkResidual{});
+                    ctx->mat_bytes, nullptr, MpkResidual{});
 }
 
 int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy, int rcol,

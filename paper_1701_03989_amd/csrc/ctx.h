@@ -80,6 +80,7 @@ struct sscg_ctx {
   sscg_host::BatchWs batch;
   int32_t* hactive = nullptr;  // pinned
   int64_t sell_total = 0;      // SELL-64 entries of the last matrix copy
+  double mat_bytes = 0.0;      // bytes of it one matrix-powers pass reads (mpk_matrix_bytes)
   // mixed precision: FP32 values of the SELL copy, FP32 basis, FP64 correction and residual
   sscg_host::Buf sval32, Y32, dx, r64;
   sscg_host::Buf xu, upart;  // equilibrated mixed solves: unscaled iterate, its residual partials
@@ -162,7 +163,12 @@ ColPtr colptr_of(const BasisCols& bc, int s, int first);
 // The s passes of the matrix powers kernel of one block (res: fused residual
 // of the block's start, may be {NULL}); stop may be NULL.
 int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
-               int64_t nnz, const int* stop, const MpkResidual& res);
+               double mat_bytes, const int* stop, const MpkResidual& res);
+// Bytes of A one matrix-powers pass reads in the form it dispatches on: per
+// stored SELL-64 entry 3 (one-byte value index, 16-bit column offset), 10
+// (value, 16-bit offset) or 12 (value, 32-bit index), plus per slice its
+// offset, width and (value tables) its 4-entry table.
+double mpk_matrix_bytes(const DevMat& M, int64_t stored);
 // Gram of the block's basis into G (device, d x d).
 int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const int* stop);
 

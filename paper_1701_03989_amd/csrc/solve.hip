@@ -196,7 +196,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
     BasisCols bc{P0[par], R0[par], Y, ld, rcol};
     MpkResidual rres{};
     if (!first) rres = MpkResidual{X[par], bw, as<double>(ctx->rpart)};
-    int rc2 = mpk_passes(ctx, M, s, first, bp, bc, A->nnz, stop, rres);
+    int rc2 = mpk_passes(ctx, M, s, first, bp, bc, ctx->mat_bytes, stop, rres);
     if (rc2) return rc2;
     if (!first)
       HIPCHK(launch_res_finalize(as<double>(ctx->rpart), np_res, scal + 1, o.tol, info, stop, S1));

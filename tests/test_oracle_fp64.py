@@ -390,3 +390,35 @@ def test_fixed_large_s_loses_accuracy_where_adaptive_does_not():
     ad4 = sstep.solve(A, b, x1, sstep.Opts(mode="adaptive", s_max=4, tol=tol, equilibrate=True))
     assert fx4.status == sstep.OK and ad4.status == sstep.OK
     assert len(ad4.blocks) <= len(fx4.blocks) + 2
+
+
+def test_plain_arithmetic_within_summation_bounds_and_solves():
+    """The plain-FP64 back-end (timing only): every reduction within the
+    recursive-summation bound n eps sum|terms| of the correctly rounded one,
+    and an adaptive solve with it reaches the tolerance near CR's solution."""
+    from oracle.arith import Plain
+
+    rng = np.random.default_rng(2)
+    ar, cr = Plain(), CR()
+    A = poisson2d(20)
+    u = rng.standard_normal(A.n)
+    w = rng.standard_normal(A.n)
+    eps = 2.0 ** -53
+    got = ar.csr_comb(A, u, [(-0.5, w)])
+    ref = cr.csr_comb(A, u, [(-0.5, w)])
+    mag = np.abs(A.to_scipy()) @ np.abs(u) + 0.5 * np.abs(w)
+    assert np.all(np.abs(got - ref) <= 8 * eps * mag)
+    cols = [rng.standard_normal(500) * 10.0 ** k for k in range(-2, 3)]
+    G, Gc = np.array(ar.gram(cols)), np.array(cr.gram(cols))
+    Y = np.abs(np.stack(cols))
+    assert np.all(np.abs(G - Gc) <= 500 * eps * (Y @ Y.T))
+    A2, b, x1, _ = poisson2d_32_system(0)
+    opts = sstep.Opts(mode="adaptive", s_max=8, tol=1e-10, equilibrate=True)
+    rp = sstep.solve(A2, b, x1, opts, ar=Plain())
+    rc = sstep.solve(A2, b, x1, opts)
+    assert rp.status == sstep.OK and rp.relres <= 1e-10
+    M = A2.to_scipy().toarray()
+    assert np.linalg.norm(rp.x - rc.x) / np.linalg.norm(rc.x) <= np.linalg.cond(M) * 2e-10
+    lo, hi = spectral.chebyshev_interval(A2, 30, 0, ar=Plain())
+    lo_c, hi_c = spectral.chebyshev_interval(A2, 30, 0)
+    assert lo == pytest.approx(lo_c, rel=1e-8) and hi == pytest.approx(hi_c, rel=1e-14)
