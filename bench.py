@@ -719,6 +719,9 @@ def main():
                     help="basis of the single-solve workloads (default: the workload's)")
     ap.add_argument("--c-mode", choices=["const", "theory"], default="const",
                     help="c_{k,j}: the constant 1, or 6 N_k j kappa(A) of Section 4.1")
+    ap.add_argument("--forms", type=int, default=7,
+                    help="compact forms of A the library may use (bits: 1 16-bit offsets, "
+                         "2 value tables, 4 slice-diagonal; default all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-classical", action="store_true",
                     help="skip timing classical CG (s = 1) beside the s-step solve")
@@ -783,7 +786,7 @@ def main():
     from paper_1701_03989_amd import problems, sscg
 
     wl = dict(WORKLOADS[args.workload])
-    variant = args.basis not in (None, wl["basis"]) or args.c_mode != "const"
+    variant = args.basis not in (None, wl["basis"]) or args.c_mode != "const" or args.forms != 7
     if args.basis:
         wl["basis"] = args.basis
     A, b, x1 = problems.poisson3d_128_system(0, N=wl["N"])
@@ -796,6 +799,7 @@ def main():
     opts = sscg.make_opts(mode="adaptive", basis=wl["basis"], s_max=wl["s_max"], tol=wl["tol"],
                           c_mode=args.c_mode)
     ctx = sscg.sscg_create(0)
+    sscg.sscg_set_forms(ctx, args.forms)
     hist = sscg.History(4096, wl["s_max"])
 
     def one_solve():

@@ -244,7 +244,21 @@ int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, d
  * either may be NULL. */
 #define SSCG_FMT_COL16 1
 #define SSCG_FMT_VTAB 2
+/* SSCG_FMT_SDIA: every slice couples its rows to at most 8 column distances
+ * d = col - row and holds at most 3 distinct values (padding excluded), and
+ * no row has two entries at one distance (stencils): the matrix-powers pass
+ * then reads, per slice, the distances and values, and per row one 16-bit
+ * word with a 2-bit value code per distance (2 bytes of A per row), and
+ * gathers row i's inputs at i + d without loading an index.  It takes
+ * precedence over the other forms; the same bits result. */
+#define SSCG_FMT_SDIA 4
 int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* stored);
+/* Which of the compact forms above the context's later calls may build and
+ * read (bit mask of SSCG_FMT_*, default all three; 0 = the stored FP64 values
+ * with 32-bit indices).  For timing and testing the forms against each
+ * other: every form gives the same bits.  Value tables are only used together
+ * with 16-bit offsets. */
+int sscg_set_forms(sscg_ctx* ctx, int forms);
 
 /* Matrix powers (eqs. cg-krylovbasis, polybasiscg): Y is n x ncol, column-major
  * with leading dimension ldy >= n.  On entry column 0 holds p (P_0) and, unless

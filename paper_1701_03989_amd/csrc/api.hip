@@ -159,7 +159,7 @@ int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
 int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   const int n = A->n;
   const int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
-  HIPCHK(ensure(ctx->width, sizeof(int32_t) * (nslices + 2)));
+  HIPCHK(ensure(ctx->width, sizeof(int32_t) * (nslices + 4)));
   HIPCHK(ensure(ctx->off, sizeof(int64_t) * (nslices + 1)));
   // every later kernel gathers through col[]
   int32_t* flag = as<int32_t>(ctx->width) + nslices;
@@ -202,10 +202,24 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   HIPCHK(launch_sell_vidx(as<double>(ctx->sval), as<int64_t>(ctx->off), as<int32_t>(ctx->width),
                           nslices, as<double>(ctx->svtab), as<uint8_t>(ctx->svidx), flag + 1,
                           ctx->stream));
-  int32_t fl[2] = {1, 1};
+  // slice-diagonal form when every slice has few distances and values (stencils)
+  HIPCHK(ensure(ctx->sd_nd, sizeof(int32_t) * std::max(nslices, 1)));
+  HIPCHK(ensure(ctx->sd_delta, sizeof(int32_t) * SD_DIAG * std::max(nslices, 1)));
+  HIPCHK(ensure(ctx->sd_tab, sizeof(double) * 4 * std::max(nslices, 1)));
+  HIPCHK(ensure(ctx->sd_code, sizeof(uint16_t) * SSCG_WAVE * std::max(nslices, 1)));
+  HIPCHK(hipMemsetAsync(flag + 2, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_sell_sdia(A->rowptr, n, as<int32_t>(ctx->scol), as<double>(ctx->sval),
+                          as<int64_t>(ctx->off), as<int32_t>(ctx->width), nslices,
+                          as<int32_t>(ctx->sd_nd), as<int32_t>(ctx->sd_delta),
+                          as<double>(ctx->sd_tab), as<uint16_t>(ctx->sd_code), flag + 2,
+                          ctx->stream));
+  int32_t fl[3] = {1, 1, 1};
   HIPCHK(hipMemcpyAsync(fl, flag, sizeof fl, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  const int32_t wide = fl[0], many = fl[1];
+  // forms the caller allowed (sscg_set_forms); tables only with 16-bit offsets
+  const int32_t wide = fl[0] || !(ctx->forms & SSCG_FMT_COL16);
+  const int32_t many = fl[1] || !(ctx->forms & SSCG_FMT_VTAB);
+  const int32_t nosd = fl[2] || !(ctx->forms & SSCG_FMT_SDIA);
   M->n = n;
   M->nslices = nslices;
   M->off = as<int64_t>(ctx->off);
@@ -215,12 +229,19 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   M->col16 = wide ? nullptr : as<int16_t>(ctx->scol16);
   M->vidx = many ? nullptr : as<uint8_t>(ctx->svidx);
   M->vtab = many ? nullptr : as<double>(ctx->svtab);
+  M->sd_nd = nosd ? nullptr : as<int32_t>(ctx->sd_nd);
+  M->sd_delta = nosd ? nullptr : as<int32_t>(ctx->sd_delta);
+  M->sd_tab = nosd ? nullptr : as<double>(ctx->sd_tab);
+  M->sd_code = nosd ? nullptr : as<uint16_t>(ctx->sd_code);
   ctx->mat_bytes = mpk_matrix_bytes(*M, total);
   return SSCG_OK;
 }
 
 double mpk_matrix_bytes(const DevMat& M, int64_t stored) {
-  // the forms the pass dispatches on: value tables only with 16-bit offsets
+  // slice-diagonal: a 16-bit code word per row, per slice its count,
+  // distances and 4-entry table
+  if (M.sd_code) return 2.0 * SSCG_WAVE * M.nslices + (4.0 + 4.0 * SD_DIAG + 32.0) * M.nslices;
+  // the other forms: value tables only with 16-bit offsets
   const bool c16 = M.col16 != nullptr, vt = c16 && M.vidx != nullptr;
   const double per_entry = vt ? 1.0 + 2.0 : (c16 ? 8.0 + 2.0 : 8.0 + 4.0);
   const double per_slice = 8.0 + 4.0 + (vt ? 8.0 * VTAB : 0.0);  // off, width, table
@@ -541,7 +562,8 @@ void sscg_destroy(sscg_ctx* c) {
   Buf* bufs[] = {&c->width, &c->off, &c->scol, &c->sval, &c->scale, &c->Y,    &c->part,
                  &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
                  &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran,   &c->scol16, &c->svidx, &c->svtab,
-                 &c->sval32, &c->Y32, &c->dx,  &c->r64, &c->xu, &c->upart};
+                 &c->sval32, &c->Y32, &c->dx,  &c->r64, &c->xu, &c->upart,
+                 &c->sd_nd, &c->sd_delta, &c->sd_tab, &c->sd_code};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   BatchWs& w = c->batch;
@@ -646,9 +668,19 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
   DevMat M;
   if ((rc = build_mat(ctx, A, 0, &M))) return rc;
   // the forms the matrix-powers pass dispatches on: tables only with 16-bit offsets
-  const int f = (M.col16 ? SSCG_FMT_COL16 : 0) | (M.col16 && M.vidx ? SSCG_FMT_VTAB : 0);
+  const int f = (M.col16 ? SSCG_FMT_COL16 : 0) | (M.col16 && M.vidx ? SSCG_FMT_VTAB : 0) |
+                (M.sd_code ? SSCG_FMT_SDIA : 0);
   if (format) *format = f;
   if (stored) *stored = ctx->sell_total;
+  return SSCG_OK;
+}
+
+int sscg_set_forms(sscg_ctx* ctx, int forms) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  if (forms & ~(SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA))
+    return fail(ctx, SSCG_ERR_ARG, "forms = %d: bits SSCG_FMT_COL16 | VTAB | SDIA only", forms);
+  ctx->forms = forms;
   return SSCG_OK;
 }
 

@@ -113,8 +113,22 @@ struct DevMat {
   // col16 the matrix-powers pass then reads 3 bytes per entry.
   const uint8_t* vidx = nullptr;
   const double* vtab = nullptr;
+  // Optional slice-diagonal form, present when every slice couples its rows
+  // to at most SD_DIAG column distances d = col - row and holds at most
+  // SD_VALS distinct stored values (bitwise, padding excluded), and no row has
+  // two entries at one distance: per slice the number of distances sd_nd, the
+  // distances sd_delta[SD_DIAG t + k] and values sd_tab[4 t + c]; per row
+  // (padded to the slices) a 16-bit word whose bits 2k, 2k+1 give the value
+  // code of the row's entry at distance k, SD_ABSENT for none.  The
+  // matrix-powers pass then reads 2 bytes of A per row and gathers from
+  // addresses known without an index load.
+  const int32_t* sd_nd = nullptr;
+  const int32_t* sd_delta = nullptr;
+  const double* sd_tab = nullptr;
+  const uint16_t* sd_code = nullptr;
 };
 constexpr int VTAB = 4;  // values in the table of a slice
+constexpr int SD_DIAG = 8, SD_VALS = 3, SD_ABSENT = 3;
 
 // Basis parameters of the three-term recurrence (monomial: theta = 0,
 // gamma = sigma = 1 unused).  Chebyshev on [lmin, lmax]:
@@ -184,6 +198,12 @@ hipError_t launch_sell_vidx(const double* val, const int64_t* off, const int32_t
 hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
                                const int32_t* width, int16_t* col16, int32_t* flag,
                                hipStream_t st);
+// The slice-diagonal form of the SELL copy (DevMat::sd_*; sd_code has one
+// word per row of the padded slices); *flag = 1 if some slice does not fit it.
+hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, const double* sval,
+                            const int64_t* off, const int32_t* width, int nslices, int32_t* sd_nd,
+                            int32_t* sd_delta, double* sd_tab, uint16_t* sd_code, int32_t* flag,
+                            hipStream_t st);
 
 // One matrix-powers pass: for each of nrhs (1 or 2) sequences v,
 // out = RN(A u - theta u - sigma w) / gamma_{j-1}, j >= 1 (w unused for j = 1).

@@ -186,6 +186,82 @@ __global__ __launch_bounds__(WG) void k_sell_vidx(const double* __restrict__ val
   if (over && lane == 0) *flag = 1;
 }
 
+// The slice-diagonal form (DevMat::sd_*), one wavefront per slice.  The
+// distances and values are collected in order of first appearance (entry j,
+// then lane), like the value table; padding entries (j >= the row's length)
+// are left out.  A slice with more than SD_DIAG distances or SD_VALS values,
+// or a row with two entries at one distance, sets *flag (the form is then
+// not used for the matrix).
+__global__ __launch_bounds__(WG) void k_sell_sdia(const int32_t* __restrict__ rowptr, int n,
+                                                  const int32_t* __restrict__ scol,
+                                                  const double* __restrict__ sval,
+                                                  const int64_t* __restrict__ off,
+                                                  const int32_t* __restrict__ width, int nslices,
+                                                  int32_t* __restrict__ sd_nd,
+                                                  int32_t* __restrict__ sd_delta,
+                                                  double* __restrict__ sd_tab,
+                                                  uint16_t* __restrict__ sd_code,
+                                                  int32_t* __restrict__ flag) {
+  const int slice = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= nslices) return;  // whole wavefronts
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  const int row = slice * SSCG_WAVE + lane;
+  const int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+  const int64_t o = off[slice] + lane;
+  const int w = width[slice];
+  int ds = 0, nd = 0;      // lane k < nd holds distance k
+  long long tb = 0;        // lane c < m holds value c (bits)
+  int m = 0;
+  bool over = false, dup = false;
+  unsigned code = 0xFFFFu;  // every distance absent
+  for (int j = 0; j < w && !over; ++j) {
+    const int64_t e = o + (int64_t)j * SSCG_WAVE;
+    const bool real = j < len;
+    const int d = real ? scol[e] - row : 0;
+    const long long bits = real ? __double_as_longlong(sval[e]) : 0;
+    int di = -1, vi = -1;
+    for (int i = 0; i < nd; ++i)
+      if (__shfl(ds, i, SSCG_WAVE) == d && di < 0) di = i;
+    for (int i = 0; i < m; ++i)
+      if (__shfl(tb, i, SSCG_WAVE) == bits && vi < 0) vi = i;
+    for (;;) {  // new distances, lowest lane first
+      const unsigned long long need = __ballot(real && di < 0);
+      if (need == 0) break;
+      if (nd == SD_DIAG) {
+        over = true;
+        break;
+      }
+      const int nb = __shfl(d, __ffsll((long long)need) - 1, SSCG_WAVE);
+      if (lane == nd) ds = nb;
+      if (real && di < 0 && d == nb) di = nd;
+      ++nd;
+    }
+    for (;;) {  // new values
+      const unsigned long long need = __ballot(real && vi < 0);
+      if (need == 0 || over) break;
+      if (m == SD_VALS) {
+        over = true;
+        break;
+      }
+      const long long nb = __shfl(bits, __ffsll((long long)need) - 1, SSCG_WAVE);
+      if (lane == m) tb = nb;
+      if (real && vi < 0 && bits == nb) vi = m;
+      ++m;
+    }
+    if (real && di >= 0 && vi >= 0) {
+      const unsigned sh = 2u * (unsigned)di;
+      dup |= ((code >> sh) & 3u) != (unsigned)SD_ABSENT;
+      code = (code & ~(3u << sh)) | ((unsigned)vi << sh);
+    }
+  }
+  over |= __ballot(dup) != 0;
+  if (lane < SD_DIAG) sd_delta[(int64_t)slice * SD_DIAG + lane] = lane < nd ? ds : 0;
+  if (lane < 4) sd_tab[(int64_t)slice * 4 + lane] = lane < m ? __longlong_as_double(tb) : 0.0;
+  if (lane == 0) sd_nd[slice] = nd;
+  sd_code[row] = (uint16_t)code;
+  if (over && lane == 0) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------- MPK pass
 //
 // Pass j of the matrix-powers kernel for one or two sequences (P and R of
@@ -205,7 +281,7 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 // s1.u[c]), one 16-byte load instead of two 8-byte ones on different cache
 // lines (random gathers), and tw, if given, receives the pairs of the outputs.
 template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false,
-          bool VI = false>
+          bool VI = false, bool SD = false>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeq& s0, const MpkSeq& s1,
                                         const double* __restrict__ xres,
@@ -216,10 +292,58 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   int row = slice * SSCG_WAVE + lane;
   dd r2 = dd_zero();
   if (slice < A.nslices) {
-    int64_t o = A.off[slice] + lane;
-    int w = A.width[slice];
     const double* __restrict__ u0 = s0.u;
     const double* __restrict__ u1 = s1.u;
+    dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
+    if constexpr (SD) {
+      // slice-diagonal form: distances and values of the slice (wave-uniform,
+      // scalar registers), one 16-bit code word per row; every gather address
+      // is row + distance, so all of a chunk's loads issue at once
+      const int us = __builtin_amdgcn_readfirstlane(slice);
+      const int nd = A.sd_nd[us];
+      int dl[SD_DIAG];
+      double tv[SD_VALS];
+#pragma unroll
+      for (int k = 0; k < SD_DIAG; ++k) dl[k] = A.sd_delta[(int64_t)us * SD_DIAG + k];
+#pragma unroll
+      for (int i = 0; i < SD_VALS; ++i) tv[i] = A.sd_tab[(int64_t)us * 4 + i];
+      const unsigned code = A.sd_code[row];
+      constexpr int CH = 4;
+#pragma unroll
+      for (int k0 = 0; k0 < SD_DIAG; k0 += CH) {
+        if (k0 < nd) {
+          double v[CH], g0[CH], g1[CH], gx[CH];
+          bool pr[CH];
+          int c[CH];
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int k = k0 + u;
+            const unsigned cd = k < nd ? (code >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
+            pr[u] = cd != (unsigned)SD_ABSENT;
+            v[u] = cd == 0u ? tv[0] : (cd == 1u ? tv[1] : tv[2]);
+            c[u] = row + dl[k];
+          }
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            if (pr[u]) {
+              g0[u] = u0[c[u]];
+              if (NRHS == 2) g1[u] = u1[c[u]];
+              if (RES) gx[u] = xres[c[u]];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            if (pr[u]) {
+              dd_add_prod(a0, v[u], g0[u]);
+              if (NRHS == 2) dd_add_prod(a1, v[u], g1[u]);
+              if (RES) dd_add_prod(ax, v[u], gx[u]);
+            }
+          }
+        }
+      }
+    } else {
+    int64_t o = A.off[slice] + lane;
+    int w = A.width[slice];
     // VI: the slice's value table (wave-uniform) in scalar registers
     double tv[VTAB];
     if (VI) {
@@ -227,7 +351,6 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
 #pragma unroll
       for (int i = 0; i < VTAB; ++i) tv[i] = A.vtab[(int64_t)us * VTAB + i];
     }
-    dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
     // chunks of CH entries: every load of a chunk is issued before its first
     // use (w is uniform over the wave, so the guards do not diverge)
     constexpr int CH = 4;
@@ -272,6 +395,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
         }
       }
     }
+    }  // SELL forms
     if (row < A.n) {
       double o0, o1 = 0.0;
       if (CHEB) {
@@ -300,7 +424,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   return r2;
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16, bool VI>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16, bool VI, bool SD>
 __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
                                             MpkSeq s0, MpkSeq s1, Gate gate,
                                             const double* __restrict__ xres,
@@ -311,8 +435,8 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   int lb = xcd_block(nb);
   if (lb >= nb) return;
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI>(A, slice, theta, sigma, gamma, s0, s1,
-                                                            xres, bres);
+  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD>(A, slice, theta, sigma, gamma, s0,
+                                                                s1, xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
 }
 
@@ -889,6 +1013,15 @@ hipError_t launch_sell_vidx(const double* val, const int64_t* off, const int32_t
   return hipGetLastError();
 }
 
+hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, const double* sval,
+                            const int64_t* off, const int32_t* width, int nslices, int32_t* sd_nd,
+                            int32_t* sd_delta, double* sd_tab, uint16_t* sd_code, int32_t* flag,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_sdia, dim3(wg_count(nslices)), dim3(WG), 0, st, rowptr, n, scol, sval,
+                     off, width, nslices, sd_nd, sd_delta, sd_tab, sd_code, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
                                const int32_t* width, int16_t* col16, int32_t* flag,
                                hipStream_t st) {
@@ -999,23 +1132,26 @@ hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s
   return hipGetLastError();
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool C16, bool VI>
+template <int NRHS, bool CHEB, bool HASW, bool C16, bool VI, bool SD = false>
 void mpk_launch_c(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                   MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
   if (res.x)
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16, VI>), grid, dim3(WG), 0, st, A, theta,
-                       sigma, gamma, s0, s1, g, res.x, res.b, res.part);
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16, VI, SD>), grid, dim3(WG), 0, st, A,
+                       theta, sigma, gamma, s0, s1, g, res.x, res.b, res.part);
   else
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16, VI>), grid, dim3(WG), 0, st, A, theta,
-                       sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16, VI, SD>), grid, dim3(WG), 0, st, A,
+                       theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
 }
 
-// The compact forms the copy has: 16-bit column offsets, and value indices
-// with them.
+// The compact forms the copy has: the slice-diagonal form, else 16-bit
+// column offsets, and value indices with them.
 template <int NRHS, bool CHEB, bool HASW>
 void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                 MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
-  if (A.col16 && A.vidx)
+  if (A.sd_code)
+    mpk_launch_c<NRHS, CHEB, HASW, false, false, true>(grid, A, theta, sigma, gamma, s0, s1, g,
+                                                       res, st);
+  else if (A.col16 && A.vidx)
     mpk_launch_c<NRHS, CHEB, HASW, true, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
   else if (A.col16)
     mpk_launch_c<NRHS, CHEB, HASW, true, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);

@@ -21,7 +21,7 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_OOM = -1, -2, -3
 MODE_ADAPTIVE, MODE_FIXED, MODE_SCHEDULE = 0, 1, 2
 BASIS_MONOMIAL, BASIS_CHEBYSHEV, BASIS_NEWTON = 0, 1, 2
-FMT_COL16, FMT_VTAB = 1, 2
+FMT_COL16, FMT_VTAB, FMT_SDIA = 1, 2, 4
 C_CONST, C_THEORY = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 S_LIMIT = 16
@@ -118,6 +118,7 @@ EXPORTS = {
     "sscg_matrix_format": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr),
                                           ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int64)]),
+    "sscg_set_forms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sscg_mpk_newton": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Csr), ctypes.c_int,
                                        ctypes.c_int, _dp, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.c_int]),
@@ -447,12 +448,17 @@ def sscg_mpk(ctx: int, A: DeviceCsr, s: int, first: bool, basis: int, lmin: floa
 
 
 def sscg_matrix_format(ctx: int, A: DeviceCsr):
-    """(format bits FMT_COL16 | FMT_VTAB, padded SELL-64 entry count)."""
+    """(format bits FMT_COL16 | FMT_VTAB | FMT_SDIA, padded SELL-64 entry count)."""
     c = A.cstruct()
     f = ctypes.c_int()
     st = ctypes.c_int64()
     _check(ctx, lib().sscg_matrix_format(ctx, ctypes.byref(c), ctypes.byref(f), ctypes.byref(st)))
     return f.value, st.value
+
+
+def sscg_set_forms(ctx: int, forms: int) -> int:
+    """Allowed compact forms of A (FMT_COL16 | FMT_VTAB | FMT_SDIA bits)."""
+    return _check(ctx, lib().sscg_set_forms(ctx, forms))
 
 
 def sscg_newton_shifts(ctx: int, A: DeviceCsr, m: int, seed: int = 0) -> list:

@@ -1,9 +1,11 @@
 """GPU parity of the device forms of the matrix.
 
-The matrix-powers pass reads A in one of three forms: per-slice value tables
-with one-byte indices and 16-bit column offsets (no 64-row slice holds more
-than four distinct values), 16-bit offsets with the stored values, or 32-bit
-indices with the stored values.  Each form must give the oracle's row sums
+The matrix-powers pass reads A in one of four forms: the slice-diagonal form
+(every 64-row slice couples its rows to at most 8 column distances with at
+most 3 distinct values: per-slice distances and values, a 2-bit code per row
+and distance), per-slice value tables with one-byte indices and 16-bit column
+offsets (no 64-row slice holds more than four distinct values), 16-bit offsets
+with the stored values, or 32-bit indices with the stored values.  Each form must give the oracle's row sums
 (eq. cg-krylovbasis, every row rounded once), and since a table entry carries
 the stored value's bits, the three forms must agree with each other to the last
 bit on the same rows.  Block-diagonal matrices put the same block into each
@@ -26,6 +28,8 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 FULL = sscg.FMT_COL16 | sscg.FMT_VTAB
+SDIA = FULL | sscg.FMT_SDIA
+ALL_FORMS = sscg.FMT_COL16 | sscg.FMT_VTAB | sscg.FMT_SDIA
 
 
 def say(*a):
@@ -99,6 +103,45 @@ def block_diag(A, B):
                   np.concatenate([A.val, B.val]))
 
 
+def nine_point(N):
+    """2-D 9-point stencil on N x N (Dirichlet): 9 column distances per row."""
+    rows, cols, vals = [], [], []
+    for y in range(N):
+        for x in range(N):
+            i = y * N + x
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if 0 <= x + dx < N and 0 <= y + dy < N:
+                        rows.append(i)
+                        cols.append((y + dy) * N + x + dx)
+                        vals.append(8.0 if dx == dy == 0 else -1.0)
+    return csr_of(N * N, rows, cols, vals)
+
+
+def with_duplicate(A):
+    """A with row 70's diagonal split into two entries of the same column (the
+    CSR sum is unchanged in exact arithmetic; both entries are products)."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    k = int(A.rowptr[70]) + int(np.nonzero(A.col[A.rowptr[70]:A.rowptr[71]] == 70)[0][0])
+    half = A.val[k] / 2.0
+    val = A.val.copy()
+    val[k] = half
+    rowptr = A.rowptr.copy()
+    rowptr[71:] += 1
+    col = np.insert(A.col, k + 1, 70)
+    val = np.insert(val, k + 1, half)
+    del rows
+    return problems.CSR(rowptr, col.astype(np.int32), val)
+
+
+def with_explicit_zero(A, i):
+    """A with an explicitly stored 0.0 at (i, i + 2) and (i + 2, i)."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr)).tolist() + [i, i + 2]
+    cols = A.col.tolist() + [i + 2, i]
+    vals = A.val.tolist() + [0.0, 0.0]
+    return csr_of(A.n, rows, cols, vals)
+
+
 def far_ring(n=33000):
     """Cyclic tridiagonal block: row 0 holds column n - 1, beyond 16 bits."""
     A, _, _ = ring(n, 5)
@@ -151,7 +194,10 @@ def test_forms_chosen_as_documented(ctx):
         ("5 values in a slice", slice_valued(n, 3, np.full(n, 6), 40, 5), sscg.FMT_COL16),
         ("column 32999 rows away", far_ring(), 0),
         ("ring, per-slice weights", ring(64 * 8, 4)[0], FULL),
-        ("3-D Poisson", problems.poisson3d(12), FULL),
+        ("3-D Poisson", problems.poisson3d(12), SDIA),
+        ("2-D Poisson, ragged n", problems.poisson2d(25, 41), SDIA),
+        ("9-point stencil: 9 distances", nine_point(20), FULL),
+        ("a repeated column in a row", with_duplicate(problems.poisson2d(16)), FULL),
         ("graph Laplacian", problems.graph_laplacian(3001, 7), sscg.FMT_COL16),
     ]
     for what, A, want in cases:
@@ -245,3 +291,62 @@ def test_fp32_pass_table_form_matches_wider_forms_bitwise(ctx):
         for c in range(2 * S + 1):
             assert np.array_equal(other[c], outs[0][c]), (k, c)
     say("FP32 pass: table, 16-bit and 32-bit forms bit-identical on the first block")
+
+
+@pytest.mark.parametrize("name", ["poisson3d_12", "poisson2d_25x41", "poisson2d_explicit_zero",
+                                  "poisson3d_9"])
+def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
+    """The slice-diagonal form against the oracle's row sums and against the
+    value-table, 16-bit and 32-bit forms of the same matrix (sscg_set_forms),
+    bit for bit: two-sequence Chebyshev passes, ragged last slice, a stored
+    explicit zero among three values."""
+    A = {"poisson3d_12": lambda: problems.poisson3d(12),
+         "poisson2d_25x41": lambda: problems.poisson2d(25, 41),
+         "poisson2d_explicit_zero": lambda: with_explicit_zero(problems.poisson2d(24), 100),
+         "poisson3d_9": lambda: problems.poisson3d(9)}[name]()
+    p, r = vecs(A.n, 61)
+    outs = {}
+    try:
+        for forms in (ALL_FORMS, sscg.FMT_COL16 | sscg.FMT_VTAB, sscg.FMT_COL16, 0):
+            sscg.sscg_set_forms(ctx, forms)
+            f, _ = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
+            outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX)
+    finally:
+        sscg.sscg_set_forms(ctx, ALL_FORMS)
+    assert sorted(outs) == [0, sscg.FMT_COL16, FULL, SDIA] or (
+        name == "poisson2d_explicit_zero" and sorted(outs) == [0, sscg.FMT_COL16, SDIA]), sorted(outs)
+    check_against_oracle(outs[SDIA], A, S, p, r, LMIN, LMAX, f"slice-diagonal {name}")
+    for f, y in outs.items():
+        for c in range(2 * S + 1):
+            assert np.array_equal(y[c], outs[SDIA][c]), (name, f, c)
+    say(f"{name}: slice-diagonal form bit-identical to forms {sorted(outs)}")
+
+
+def test_slice_diagonal_whole_solve_with_fused_residual(ctx):
+    """Whole adaptive solves (the first pass of every block also forms the
+    true residual through the form) with and without the slice-diagonal
+    form: same schedule, same bits, and the oracle's iterates."""
+    A = problems.poisson3d(14)
+    b = problems.uniform(A.n, 71)
+    x1 = np.zeros(A.n)
+    kw = dict(mode="adaptive", s_max=10, tol=1e-12, basis="chebyshev", lmin=0.05, lmax=12.0)
+    ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
+    xs = []
+    try:
+        for forms in (ALL_FORMS, sscg.FMT_COL16 | sscg.FMT_VTAB):
+            sscg.sscg_set_forms(ctx, forms)
+            x = dvec(x1)
+            hist = sscg.History(4096, 10)
+            rc = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(A, DEV), dvec(b), x,
+                                 sscg.make_opts(**kw), hist)
+            assert rc == ref.status == sscg.OK and hist.schedule == ref.schedule
+            xs.append(host(x))
+    finally:
+        sscg.sscg_set_forms(ctx, ALL_FORMS)
+    assert np.array_equal(xs[0], xs[1])
+    assert np.linalg.norm(xs[0] - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+def test_set_forms_rejects_unknown_bits(ctx):
+    with pytest.raises(sscg.SscgError):
+        sscg.sscg_set_forms(ctx, 8)
