@@ -285,14 +285,15 @@ int sscg_gram(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t l
 /* sscg_gram for callers that cannot allocate device memory during the call
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same G, bit for bit, with the partial sums held in a
- * fixed 4 MiB device array of the library (one per GPU, kept until the
+ * fixed 8 MiB device array of the library (one per GPU, kept until the
  * process ends, its address looked up by sscg_create) instead of the
  * context's growable workspace.  Allocates nothing; enqueues on the
- * context's stream like sscg_gram.  Any n is accepted (fewer workgroups are
- * used when the d(d+1)/2 entries' partials would not fit); arguments as for
- * sscg_gram.  Calls on one GPU share the array: calls that overlap in time
- * on that GPU (other streams, other contexts, other threads) race and must
- * be serialised by the caller. */
+ * context's stream like sscg_gram.  Limit: d(d+1)/2 * ceil(n / 1024) <= 2^20
+ * (d = 2s+1, or s+1 when first; e.g. n <= 4.6 M rows at s = 10, 1.9 M at
+ * s = 16); larger calls return SSCG_ERR_ARG.  Arguments as for sscg_gram.
+ * Calls on one GPU share the array: calls that overlap in time on that GPU
+ * (other streams, other contexts, other threads) race and must be
+ * serialised by the caller. */
 int sscg_gram_noalloc(sscg_ctx* ctx, int n, int s, int first, const double* Y, int64_t ldy,
                       int rcol, double* G);
 

@@ -6,7 +6,10 @@ written once against the small interface below, so the same code runs
 * in FP64 with correctly rounded reductions (``CR``), the reading this oracle
   takes of the paper's plain double-precision arithmetic (Section 5): every row
   sum, inner product and row-wise linear combination is the double nearest to
-  its exact value; every other operation is a single IEEE operation; and
+  its exact value, except the Gram matrix, whose entries are plain FP64 fused
+  multiply-add chains in a stated order (fma over the rows of each 1024-row
+  group in order, then pairwise summation of the group partials); every other
+  operation is a single IEEE operation; and
 * in exact rational arithmetic (``Exact``), which pins the algorithms to their
   exact-arithmetic identities (s-step CG and CG produce the same iterates,
   Section 2; CG terminates in at most n steps); and
@@ -81,7 +84,10 @@ class CR:
         return native.cr_dot(x, y)
 
     def gram(self, cols):
-        return native.cr_gram(cols).tolist()
+        """G = Y^T Y with the stated order of R9 for Gram matrices: IEEE fma
+        chains over groups of 1024 rows, group partials added pairwise (the
+        reduction a device's FP64 matrix instructions reproduce)."""
+        return native.ord_gram(cols).tolist()
 
     def rows_comb(self, cols, coef, base=None):
         return native.cr_rows_comb(cols, coef, base)

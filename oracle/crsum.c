@@ -14,11 +14,17 @@
  * precision floating-point arithmetic", 1997), and the final rounding uses the
  * half-way correction of the same published msum/fsum procedure.
  *
+ * Gram matrices are the exception (ord_gram below): they are read as plain
+ * FP64 fused multiply-add chains in a stated order, which a device reproduces
+ * bit for bit with its FP64 matrix instructions.
+ *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -shared -fPIC
- * (no fast-math: every + - * must be an IEEE double operation).
+ * (no fast-math: every + - * must be an IEEE double operation; fma() is the
+ * C library's correctly rounded fused multiply-add).
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define CR_MAXP 64 /* a double expansion never needs more than ~40 parts */
@@ -180,6 +186,54 @@ void cr_gram(int64_t n, int32_t d, const double* Y, int64_t ld, double* G) {
     double g = cr_dot(Y + (int64_t)a * ld, Y + (int64_t)b * ld, n);
     G[a * d + b] = g;
     G[b * d + a] = g;
+  }
+}
+
+/*
+ * Gram matrix in the oracle's order for Gram matrices (reading R9, Gram
+ * part): the rows, zero-padded to a multiple of ORD_GROUP, fall into groups of
+ * ORD_GROUP consecutive rows; a group's partial is the chain of IEEE fused
+ * multiply-adds s <- fma(y_ra, y_rb, s) over its rows in order, from s = +0;
+ * the partials of the groups, zero-padded to the next power of two P, are
+ * added by pairwise summation: PT(v[0..P)) = PT(v[0..P/2)) + PT(v[P/2..P)),
+ * PT of one value = that value.  Written to G[a*d+b] and G[b*d+a].
+ */
+#define ORD_GROUP 1024
+
+static double ord_pt(const double* v, int64_t lo, int64_t len, int64_t count) {
+  if (len == 1) return lo < count ? v[lo] : 0.0;
+  const int64_t h = len / 2;
+  const double left = ord_pt(v, lo, h, count);
+  const double right = ord_pt(v, lo + h, h, count);
+  return left + right;
+}
+
+void ord_gram(int64_t n, int32_t d, const double* Y, int64_t ld, double* G) {
+  const int64_t ng = (n + ORD_GROUP - 1) / ORD_GROUP;
+  int64_t P = 1;
+  while (P < ng) P <<= 1;
+  int32_t npair = d * (d + 1) / 2;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t q = 0; q < npair; ++q) {
+    int32_t a = 0, rem = q;
+    while (rem >= d - a) {
+      rem -= d - a;
+      ++a;
+    }
+    int32_t b = a + rem;
+    const double* ya = Y + (int64_t)a * ld;
+    const double* yb = Y + (int64_t)b * ld;
+    double* part = (double*)malloc(sizeof(double) * (size_t)(ng > 0 ? ng : 1));
+    for (int64_t g = 0; g < ng; ++g) {
+      double s = 0.0;
+      for (int64_t r = g * ORD_GROUP; r < (g + 1) * ORD_GROUP; ++r)
+        s = r < n ? fma(ya[r], yb[r], s) : fma(0.0, 0.0, s);
+      part[g] = s;
+    }
+    double gab = ng > 0 ? ord_pt(part, 0, P, ng) : 0.0;
+    free(part);
+    G[a * d + b] = gab;
+    G[b * d + a] = gab;
   }
 }
 

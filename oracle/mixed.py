@@ -15,10 +15,9 @@ fixes what the inner stages compute:
     gamma are single FP64 operations, and the result is rounded once to FP32
     (eq. polybasiscg with FP32 storage);
   * the Gram matrix of the FP32 basis (``gram32``): G = Y^T Y of the FP32
-    columns, defined here as the correctly rounded FP64 value of each entry
-    (the products of FP32 values are exact in FP64).  A device that adds the
-    exact products in FP64 in any order is within n eps sum|y_ia y_ib| of it;
-    that is the stated tolerance, not a bitwise match.
+    columns widened to FP64, in the stated order of the FP64 Gram (fma chains
+    over 1024-row groups, group partials added pairwise; the products of FP32
+    values are exact in FP64, so each fma is one rounding of a sum).
 
 Everything else of the inner solve (kappa, eqs. condy and check with the FP32
 unit round-off 2^-24, the coefficient recurrence, d_j) is the FP64 algorithm of
@@ -86,14 +85,15 @@ def mpk32_basis(A, s: int, first: bool, basis: str, p0, r0, lmin=None, lmax=None
 
 
 def gram32(cols) -> np.ndarray:
-    """Correctly rounded Gram matrix of FP32 columns (FP64 result)."""
+    """Gram matrix of FP32 columns (FP64 result), in the stated order."""
     return np.array(CR().gram([np.asarray(c, dtype=np.float32).astype(np.float64)
                                for c in cols]))
 
 
 def gram32_tolerance(cols) -> np.ndarray:
     """n eps64 sum_i |y_ia y_ib|: how far any FP64 summation order of the exact
-    products may lie from gram32 (standard bound for recursive summation)."""
+    products may lie from the exact Gram (standard bound for recursive
+    summation)."""
     Y = np.abs(np.stack([np.asarray(c, dtype=np.float32).astype(np.float64) for c in cols]))
     n = Y.shape[1]
     return n * 2.0 ** -53 * (Y @ Y.T)

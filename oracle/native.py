@@ -47,6 +47,8 @@ def lib():
         L.cr_rows_comb.argtypes = [ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64, dp, dp, dp]
         L.cr_gram.restype = None
         L.cr_gram.argtypes = [ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64, dp]
+        L.ord_gram.restype = None
+        L.ord_gram.argtypes = [ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64, dp]
         L.cr_num_threads.restype = ctypes.c_int
         L.cr_num_threads.argtypes = []
         _lib = L
@@ -114,6 +116,16 @@ def cr_gram(cols) -> np.ndarray:
     d, n = Y.shape
     G = np.empty((d, d), dtype=np.float64)
     lib().cr_gram(n, d, _dp(Y), n, _dp(G))
+    return G
+
+
+def ord_gram(cols) -> np.ndarray:
+    """G = Y^T Y in the stated order: fma chains over 1024-row groups, pairwise
+    summation of the group partials (see crsum.c)."""
+    Y = np.ascontiguousarray(np.stack([_f64(c) for c in cols]), dtype=np.float64)
+    d, n = Y.shape
+    G = np.empty((d, d), dtype=np.float64)
+    lib().ord_gram(n, d, _dp(Y), n, _dp(G))
     return G
 
 

@@ -30,7 +30,10 @@ notes of the repository):
       condy (accept on equality); none -> s~ = 1 (Section 4.2's default).  The
       in-loop check breaks on '>=' after the updates of that iteration.
   R8  ||r_{m+1}|| in eq. condy is sqrt(G[R_0, R_0]) (sqrt(G[P_0,P_0]) in block 0).
-  R9  quadratic forms: v^T G v = RN(v . RN(G v)); p'^T G B p' = RN(p' . RN(G RN(B p'))).
+  R9  reductions are order independent (correctly rounded), except the Gram
+      matrix G = Y^T Y, whose entries are fma chains over 1024-row groups in row
+      order with the group partials added pairwise (``oracle.arith``);
+      quadratic forms: v^T G v = RN(v . RN(G v)); p'^T G B p' = RN(p' . RN(G RN(B p'))).
   R10 breakdown: if p'^T G B p' is not positive and finite, or alpha is not
       finite, the block ends after the previous iteration (status BREAKDOWN if
       that leaves no iteration).

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsscg.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["spmv.hip", "dense.hip", "small.hip", "api.hip", "solve.hip", "batch.hip", "serve.hip",
-           "mixed.hip", "noalloc.hip"]
+           "mixed.hip", "noalloc.hip", "gram.hip"]
 ARCH = os.environ.get("SSCG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

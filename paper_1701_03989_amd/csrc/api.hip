@@ -278,14 +278,14 @@ int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, co
 }
 
 int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const int* stop) {
-  int np = gram_nparts(n);
-  HIPCHK(ensure(ctx->part, sizeof(double) * 2 * (size_t)np * (d * (d + 1) / 2)));
+  const int ng = gram_ngroups(n);
+  HIPCHK(ensure(ctx->part, sizeof(double) * (size_t)ng * (d * (d + 1) / 2)));
   size_t slot = 0;
   HIPCHK(ev_begin(ctx, 1, 8.0 * n * d, ctx->stream, &slot));
-  HIPCHK(launch_gram(cols, n, d, as<double>(ctx->part), np, Gate{stop, ev_ran(ctx, slot)},
+  HIPCHK(launch_gram(cols, n, d, as<double>(ctx->part), Gate{stop, ev_ran(ctx, slot)},
                      ctx->stream));
   HIPCHK(ev_end(ctx, slot, ctx->stream));
-  HIPCHK(launch_gram_finalize(as<double>(ctx->part), np, d, G, stop, ctx->stream));
+  HIPCHK(launch_gram_finalize(as<double>(ctx->part), ng, d, G, stop, ctx->stream));
   return SSCG_OK;
 }
 

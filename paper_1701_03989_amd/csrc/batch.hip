@@ -239,6 +239,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   c.gpart = as<double>(w.gpart);
   c.active = as<int32_t>(w.active);
   c.T[0] = as<double2>(w.T);
+  c.inv = as<int32_t>(w.inv);
   c.T[1] = c.T[0] + N;
   HIPCHK(hipMemsetAsync(c.Y, 0, sizeof(double) * (size_t)N * ncols, st));
   HIPCHK(hipMemsetAsync(c.x, 0, sizeof(double) * (size_t)N, st));

@@ -261,12 +261,21 @@ struct ColPtr {
   }
 };
 
-// Gram of the d columns; partials then the finalize.  stop may be NULL.
-int gram_nparts(int n);
-hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts, Gate g,
-                       hipStream_t st);
-hipError_t launch_gram_finalize(const double* part, int nparts, int d, double* G,
-                                const int* stop, hipStream_t st);
+// Gram matrix G = Y^T Y of d <= 2 SSCG_S_LIMIT + 1 columns, in the stated
+// order (reading R9 for Gram matrices): the rows, zero-padded to a multiple
+// of GRAM_GROUP, fall into groups of GRAM_GROUP consecutive rows; a group's
+// partial of entry (a, b) is the chain of IEEE fused multiply-adds
+// s <- fma(y_ra, y_rb, s) over its rows in order from +0; the partials of the
+// groups, zero-padded to the next power of two, are added by pairwise
+// summation (left half + right half, recursively).  launch_gram writes the
+// partials, part[q * ng + g] for the upper-triangle entry q (row-major,
+// a <= b) and group g < ng = gram_ngroups(n); launch_gram_finalize sums them
+// into both triangles of G (d x d).  stop may be NULL.
+constexpr int GRAM_GROUP = 1024;
+__host__ __device__ inline int gram_ngroups(int n) { return (n + GRAM_GROUP - 1) / GRAM_GROUP; }
+hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, Gate g, hipStream_t st);
+hipError_t launch_gram_finalize(const double* part, int ng, int d, double* G, const int* stop,
+                                hipStream_t st);
 
 // Coordinate solve.  stop may be NULL.
 hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_info* info,
@@ -357,7 +366,7 @@ struct BatchHist {  // one committed block of one system
   double relres_true;  // true relative residual of the iterate after the block
 };
 
-struct BatchChunk {  // Gram work item: rows [r0, r1) of system sys
+struct BatchChunk {  // Gram work item: rows [r0, r1) of system sys, one GRAM_GROUP-row group
   int32_t sys, r0, r1, pad_;
 };
 
@@ -379,14 +388,31 @@ struct BatchCfg {
   const BatchChunk* chunks;   // Gram work items, grouped by system
   double* rpart;              // dd partial per 256-row block (residual of x)
   double* bpart;              // dd partial per 256-row block (||b||^2, set-up)
-  double* gpart;              // Gram partials: (pair * nchunks + chunk) * 2
+  double* gpart;              // Gram partials: pair * nchunks + chunk
   int32_t* active;            // systems not done (after each block)
   double2* T[2];              // (P_j, R_j) pairs for the gathers of pass j + 1 (T[j & 1])
+  const int32_t* inv;         // inv[row0 + r]: position of row r of the system (row order)
 };
 
 // P_j / R_j column of a batch (global row index applies on top).
 __host__ __device__ inline double* batch_col(const BatchCfg& c, int col) {
   return c.Y + (int64_t)col * c.ld;
+}
+
+// The d columns of a batched block in G's order: P_0..P_s at 0..s, R_0.. at
+// S+1.. (s: the system's built steps, S: the batch's column layout).
+struct BatchCols {
+  double* Y;
+  int64_t ld;
+  int s, S;
+  __device__ __forceinline__ const double* at(int a) const {
+    return Y + (int64_t)(a <= s ? a : S + 1 + (a - s - 1)) * ld;
+  }
+};
+
+__device__ __forceinline__ BatchCols batch_cols(const BatchCfg& c, int s, int first) {
+  (void)first;  // block 0 uses P_0..P_s only: d = s + 1 never reaches the R columns
+  return BatchCols{c.Y, c.ld, s, c.S};
 }
 
 hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32_t* width,
@@ -444,6 +470,8 @@ hipError_t launch_batch_init_range(const BatchCfg& c, int q0, int count, hipStre
 hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st);
 // Residual of each system's starting iterate; convergence / iteration cap.
 hipError_t launch_batch_res_finalize(const BatchCfg& c, hipStream_t st);
+// Gram of every unfinished system's block (its chunks are its GRAM_GROUP-row
+// groups, counted from its first row), then each system's G.
 hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st);
 hipError_t launch_gram_finalize_batch(const BatchCfg& c, hipStream_t st);
 hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st);
@@ -473,12 +501,10 @@ struct Cols32 {
 // FP64) - theta u_i - sigma w_i) / gamma), FP64 in between.
 hipError_t launch_mpk32_pass(const DevMat& A, const float* val32, int j, BasisPrm bp, int nrhs,
                              MpkSeq32 s0, MpkSeq32 s1, hipStream_t st);
-// Gram of d FP32 columns: exact products, FP64 sums per workgroup (partials
-// in the layout of launch_gram, finished by launch_gram_finalize).
-// Partials of launch_gram32 for n rows (<= gram_nparts(n)).
-int gram32_nparts(int n);
-hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, int nparts,
-                         hipStream_t st);
+// Gram of d FP32 columns widened to FP64, in the order of launch_gram (the
+// products of FP32 values are exact in FP64); same partial layout and
+// finalize.
+hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, hipStream_t st);
 // dx += Y x' (FP64), r = RN32(Y r'), p = RN32(Y p') (r, p may alias columns).
 hipError_t launch_recover32(const Cols32& cols, int n, int d, const double* coef, double* dx,
                             float* r, float* p, hipStream_t st);

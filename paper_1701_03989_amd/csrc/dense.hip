@@ -1,107 +1,18 @@
-// Tall-skinny kernels: the Gram matrix G = Y^T Y, the recovery Y*coef, the
-// reductions that finish them, and small vector helpers.
+// Tall-skinny kernels: the recovery Y*coef, the reductions that finish the
+// partial sums of the other kernels, and small vector helpers.  (The Gram
+// matrix is in gram.hip.)
 #include "common.h"
 
 namespace {
 
 constexpr int WG = 256;
-constexpr int GT = 32;            // rows of Y per LDS tile
 constexpr int MAXD = 2 * SSCG_S_LIMIT + 1;
-constexpr int MAXPAIRS = MAXD * (MAXD + 1) / 2;
-constexpr int PAIRS_PER_THREAD = (MAXPAIRS + WG - 1) / WG;
 
 
-// ---------------------------------------------------------------- Gram
+// ---------------------------------------------------------------- finalizers
 //
-// Each workgroup owns a contiguous range of row tiles (XCD-aware) and keeps
-// one dd accumulator per upper-triangle entry (a <= b) it is assigned; tiles
-// of GT rows x d columns are staged in LDS (row-major, so the lanes of a wave
-// reading different columns of one row hit different banks).  Output: one dd
-// partial per (entry, workgroup), entry-major.
-//
-// Upper-triangle dd partials of the Gram matrix of columns cols[0..d) over
-// rows [rb, re): entry q (a <= b, row-major over the triangle) goes to
-// part[(q * nparts + slot) * 2].
-template <int PPT, class Cols>
-__device__ __forceinline__ void gram_rows(const Cols& cols, int d, int rb, int re,
-                                          double* __restrict__ part, int nparts, int slot) {
-  // two LDS tiles: tile t+1 is loaded into registers while tile t is used
-  __shared__ double tile[2][GT][MAXD + 1];
-  constexpr int LPT = (GT * MAXD + WG - 1) / WG;  // tile elements per thread
-  const int npairs = d * (d + 1) / 2;
-  const int nel = GT * d;
-  int pa[PPT], pb[PPT];
-  dd acc[PPT];
-#pragma unroll
-  for (int u = 0; u < PPT; ++u) {
-    int q = threadIdx.x + u * WG;
-    int a = 0, rem = q;
-    while (a < d && rem >= d - a) {
-      rem -= d - a;
-      ++a;
-    }
-    pa[u] = a < d ? a : 0;
-    pb[u] = a < d ? a + rem : 0;
-    acc[u] = dd_zero();
-  }
-  // element e of a tile: column e / GT, row e % GT (a wave reads whole column runs)
-  double nx[LPT];
-  auto fetch = [&](int r0) {
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int e = threadIdx.x + k * WG;
-      const int a = e / GT, row = r0 + (e - a * GT);
-      nx[k] = (e < nel && row < re) ? cols.at(a)[row] : 0.0;
-    }
-  };
-  if (rb < re) fetch(rb);
-  int buf = 0;
-  for (int r0 = rb; r0 < re; r0 += GT) {
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int e = threadIdx.x + k * WG;
-      const int a = e / GT;
-      if (e < nel) tile[buf][e - a * GT][a] = nx[k];
-    }
-    // one barrier per tile: a thread writes tile[buf] again two tiles later,
-    // after every thread has passed the next barrier, i.e. finished this tile
-    __syncthreads();
-    if (r0 + GT < re) fetch(r0 + GT);
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      if (threadIdx.x + u * WG < npairs) {
-        const int a = pa[u], b = pb[u];
-#pragma unroll 4
-        for (int r = 0; r < GT; ++r) dd_add_prod(acc[u], tile[buf][r][a], tile[buf][r][b]);
-      }
-    }
-    buf ^= 1;
-  }
-#pragma unroll
-  for (int u = 0; u < PPT; ++u) {
-    int q = threadIdx.x + u * WG;
-    if (q < npairs) {
-      part[((int64_t)q * nparts + slot) * 2] = acc[u].s;
-      part[((int64_t)q * nparts + slot) * 2 + 1] = acc[u].e;
-    }
-  }
-}
-
-// PPT: upper-triangle entries per thread (1 covers d <= 22)
-template <int PPT>
-__global__ __launch_bounds__(WG) void k_gram(ColPtr cols, int n, int d, double* __restrict__ part,
-                                             int nparts, Gate gate) {
-  if (gate_closed(gate)) return;
-  int lb = xcd_block(nparts);
-  if (lb >= nparts) return;
-  int ntiles = (n + GT - 1) / GT;
-  int per = (ntiles + nparts - 1) / nparts;
-  int t0 = lb * per, t1 = min(t0 + per, ntiles);
-  gram_rows<PPT>(cols, d, t0 * GT, min(t1 * GT, n), part, nparts, lb);
-}
-
 // Sum `nparts` dd partials of reduction blockIdx.x in a fixed order and
-// round once.  Gram variant writes both triangles of G.
+// round once.
 __device__ __forceinline__ dd reduce_parts(const double* __restrict__ p, int nparts) {
   __shared__ double ls[WG / SSCG_WAVE], le[WG / SSCG_WAVE];
   dd a = dd_zero();
@@ -126,25 +37,6 @@ __device__ __forceinline__ dd reduce_parts(const double* __restrict__ p, int npa
   dd t{ls[0], le[0]};
   for (int q = 1; q < WG / SSCG_WAVE; ++q) dd_merge(t, dd{ls[q], le[q]});
   return t;
-}
-
-__global__ __launch_bounds__(WG) void k_gram_finalize(const double* __restrict__ part, int nparts,
-                                                      int d, double* __restrict__ G,
-                                                      const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  int q = blockIdx.x;
-  dd t = reduce_parts(part + (int64_t)q * nparts * 2, nparts);
-  if (threadIdx.x == 0) {
-    int a = 0, rem = q;
-    while (rem >= d - a) {
-      rem -= d - a;
-      ++a;
-    }
-    int b = a + rem;
-    double g = dd_round(t);
-    G[a * d + b] = g;
-    G[b * d + a] = g;
-  }
 }
 
 __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int nparts,
@@ -383,55 +275,6 @@ __global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
 
 // Gram columns of a system in this block: P_0..P_s, then R_0..R_{s-1}; the
 // address is computed (an array of pointers would live in scratch memory).
-struct BatchCols {
-  double* Y;
-  int64_t ld;
-  int s, S;
-  __device__ __forceinline__ const double* at(int a) const {
-    return Y + (int64_t)(a <= s ? a : S + 1 + (a - s - 1)) * ld;
-  }
-};
-
-__device__ __forceinline__ BatchCols batch_cols(const BatchCfg& c, int s, int first) {
-  (void)first;  // block 0 uses P_0..P_s only: d = s + 1 never reaches the R columns
-  return BatchCols{c.Y, c.ld, s, c.S};
-}
-
-template <int PPT>
-__global__ __launch_bounds__(WG) void k_gram_batch(BatchCfg c) {
-  int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
-  if (lb >= c.nchunks) return;
-  const BatchChunk ch = c.chunks[lb];
-  const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
-  if (q < 0 || c.sys[q].done) return;
-  const sscg_block_params prm = c.prm[q];
-  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  gram_rows<PPT>(batch_cols(c, prm.s, prm.first), d, ch.r0, ch.r1, c.gpart, c.nchunks, lb);
-}
-
-// grid (pairs, systems): entry blockIdx.x of system blockIdx.y.
-__global__ __launch_bounds__(WG) void k_gram_finalize_batch(BatchCfg c) {
-  const int q = blockIdx.y, e = blockIdx.x;
-  const BatchSys& sy = c.sys[q];
-  if (sy.done) return;
-  const sscg_block_params prm = c.prm[q];
-  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  if (e >= d * (d + 1) / 2) return;
-  dd t = reduce_parts(c.gpart + ((int64_t)e * c.nchunks + sy.ch0) * 2, sy.ch1 - sy.ch0);
-  if (threadIdx.x == 0) {
-    int a = 0, rem = e;
-    while (rem >= d - a) {
-      rem -= d - a;
-      ++a;
-    }
-    int b = a + rem;
-    double g = dd_round(t);
-    double* G = c.G + (int64_t)q * BATCH_GSZ;
-    G[a * d + b] = g;
-    G[b * d + a] = g;
-  }
-}
-
 // x <- x + Y x', r = Y r' (into R_0), p = Y p' (into P_0), per system.
 __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
   int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
@@ -519,143 +362,7 @@ __global__ __launch_bounds__(WG) void k_batch_count(BatchCfg c) {
 
 
 // ---------------------------------------------------------------- FP32 basis
-// Gram of FP32 columns: the products are exact in FP64 and summed in FP64 per
-// thread (tiles of GT rows in LDS as before); partials as dd pairs (lo = 0).
-__global__ __launch_bounds__(WG) void k_gram32(Cols32 cols, int n, int d,
-                                               double* __restrict__ part, int nparts) {
-  __shared__ double tile[GT][MAXD + 1];
-  int lb = xcd_block(nparts);
-  if (lb >= nparts) return;
-  const int npairs = d * (d + 1) / 2;
-  int pa[PAIRS_PER_THREAD], pb[PAIRS_PER_THREAD];
-  double acc[PAIRS_PER_THREAD];
-#pragma unroll
-  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
-    int q = threadIdx.x + u * WG;
-    int a = 0, rem = q;
-    while (a < d && rem >= d - a) {
-      rem -= d - a;
-      ++a;
-    }
-    pa[u] = a < d ? a : 0;
-    pb[u] = a < d ? a + rem : 0;
-    acc[u] = 0.0;
-  }
-  int ntiles = (n + GT - 1) / GT;
-  int per = (ntiles + nparts - 1) / nparts;
-  int t0 = lb * per, t1 = min(t0 + per, ntiles);
-  for (int t = t0; t < t1; ++t) {
-    int r0 = t * GT;
-    for (int e = threadIdx.x; e < GT * d; e += WG) {
-      int a = e / GT, r = e - a * GT;
-      int row = r0 + r;
-      tile[r][a] = row < n ? (double)cols.at(a)[row] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
-      if (threadIdx.x + u * WG < npairs) {
-        int a = pa[u], b = pb[u];
-#pragma unroll 8
-        for (int r = 0; r < GT; ++r) acc[u] = acc[u] + tile[r][a] * tile[r][b];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < PAIRS_PER_THREAD; ++u) {
-    int q = threadIdx.x + u * WG;
-    if (q < npairs) {
-      part[((int64_t)q * nparts + lb) * 2] = acc[u];
-      part[((int64_t)q * nparts + lb) * 2 + 1] = 0.0;
-    }
-  }
-}
-
 // dx_i += sum_a Y_ia x'_a; r_i = RN32(sum_a Y_ia r'_a); p_i likewise (FP64 sums).
-// Gram of FP32 columns for d <= D, one row per lane: wavefront w of the W
-// accumulates the entries [w NP / W, (w + 1) NP / W) of the row-major upper
-// triangle over the workgroup's rows from registers (no LDS, no barrier).
-// Products are exact in FP64 and summed with fma per lane (the same roundings
-// as sum + product), the 64 lane sums added in a fixed tree; partials as dd
-// pairs (lo = 0).
-template <int D>
-constexpr int g32_waves() {
-  return D <= 11 ? 4 : 8;  // at most 29 entries (58 VGPRs of sums) per wavefront
-}
-
-template <int D, int w>
-__device__ __forceinline__ void gram32_lr_wave(const Cols32& cols, int d, int r0, int r1,
-                                               double* __restrict__ part, int nparts, int slot) {
-  constexpr int NP = D * (D + 1) / 2;
-  constexpr int W = g32_waves<D>();
-  constexpr int Q0 = w * NP / W, Q1 = (w + 1) * NP / W;
-  const int lane = threadIdx.x & (SSCG_WAVE - 1);
-  const float* cp[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) cp[a] = a < d ? cols.at(a) : cols.Y;
-  double acc[Q1 - Q0];
-#pragma unroll
-  for (int q = 0; q < Q1 - Q0; ++q) acc[q] = 0.0;
-  float nx[D];
-  auto fetch = [&](int r) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) nx[a] = (a < d && r < r1) ? cp[a][r] : 0.0f;
-  };
-  fetch(r0 + lane);
-  for (int base = r0; base < r1; base += SSCG_WAVE) {
-    double v[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) v[a] = (double)nx[a];
-    if (base + SSCG_WAVE < r1) fetch(base + SSCG_WAVE + lane);
-    // (a, b) and the entry index q are constants after unrolling, so v stays in registers
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-#pragma unroll
-      for (int b = a; b < D; ++b) {
-        const int q = a * D - a * (a - 1) / 2 + (b - a);
-        if (q >= Q0 && q < Q1) acc[q - Q0] = __builtin_fma(v[a], v[b], acc[q - Q0]);
-      }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-#pragma unroll
-    for (int b = a; b < D; ++b) {
-      const int q = a * D - a * (a - 1) / 2 + (b - a);
-      if (q < Q0 || q >= Q1) continue;
-      double t = acc[q - Q0];
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) t = t + shfl_xor_d(t, m);
-      if (lane == 0 && b < d) {
-        const int qd = a * d - a * (a - 1) / 2 + (b - a);  // the entry's index for dimension d
-        part[((int64_t)qd * nparts + slot) * 2] = t;
-        part[((int64_t)qd * nparts + slot) * 2 + 1] = 0.0;
-      }
-    }
-  }
-}
-
-template <int D>
-__global__ __launch_bounds__(g32_waves<D>() * SSCG_WAVE) void k_gram32_lr(Cols32 cols, int n, int d,
-                                                                double* __restrict__ part,
-                                                                int nparts) {
-  const int lb = xcd_block(nparts);
-  if (lb >= nparts) return;
-  const int nb = (n + SSCG_WAVE - 1) / SSCG_WAVE, per = (nb + nparts - 1) / nparts;
-  const int r0 = min(lb * per, nb) * SSCG_WAVE, r1 = min((lb + 1) * per * SSCG_WAVE, n);
-  switch (threadIdx.x / SSCG_WAVE) {
-    case 0: gram32_lr_wave<D, 0>(cols, d, r0, r1, part, nparts, lb); break;
-    case 1: gram32_lr_wave<D, 1>(cols, d, r0, r1, part, nparts, lb); break;
-    case 2: gram32_lr_wave<D, 2>(cols, d, r0, r1, part, nparts, lb); break;
-    case 3: gram32_lr_wave<D, 3>(cols, d, r0, r1, part, nparts, lb); break;
-    case 4: if constexpr (g32_waves<D>() > 4) gram32_lr_wave<D, 4>(cols, d, r0, r1, part, nparts, lb); break;
-    case 5: if constexpr (g32_waves<D>() > 5) gram32_lr_wave<D, 5>(cols, d, r0, r1, part, nparts, lb); break;
-    case 6: if constexpr (g32_waves<D>() > 6) gram32_lr_wave<D, 6>(cols, d, r0, r1, part, nparts, lb); break;
-    default: if constexpr (g32_waves<D>() > 7) gram32_lr_wave<D, 7>(cols, d, r0, r1, part, nparts, lb); break;
-  }
-}
-
 __global__ __launch_bounds__(WG) void k_recover32(Cols32 cols, int n, int d,
                                                   const double* __restrict__ coef, double* dx,
                                                   float* r, float* p) {
@@ -704,32 +411,6 @@ __global__ __launch_bounds__(WG) void k_add(double* __restrict__ x, const double
 }  // namespace
 
 // ---------------------------------------------------------------- launches
-
-int gram_nparts(int n) {
-  int ntiles = (n + GT - 1) / GT;
-  // about 8 tiles per workgroup, at most 2048 workgroups
-  int np = (ntiles + 7) / 8;
-  if (np > 2048) np = 2048;
-  return np < 1 ? 1 : np;
-}
-
-hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, int nparts, Gate g,
-                       hipStream_t st) {
-  if (d * (d + 1) / 2 <= WG)
-    hipLaunchKernelGGL(k_gram<1>, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part,
-                       nparts, g);
-  else
-    hipLaunchKernelGGL(k_gram<PAIRS_PER_THREAD>, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n,
-                       d, part, nparts, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_gram_finalize(const double* part, int nparts, int d, double* G,
-                                const int* stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_finalize, dim3(d * (d + 1) / 2), dim3(WG), 0, st, part, nparts, d, G,
-                     stop);
-  return hipGetLastError();
-}
 
 hipError_t launch_res_finalize(const double* part, int nparts, const double* b2, double tol,
                                sscg_block_info* info, int* stop, hipStream_t st) {
@@ -814,22 +495,6 @@ hipError_t launch_div_vec(const double* w, const double* beta, int n, double* ou
   return hipGetLastError();
 }
 
-hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
-  const int dmax = 2 * c.S + 1;  // the largest basis of any system
-  if (dmax * (dmax + 1) / 2 <= WG)
-    hipLaunchKernelGGL(k_gram_batch<1>, dim3(xcd_grid(c.nchunks)), dim3(WG), 0, st, c);
-  else
-    hipLaunchKernelGGL(k_gram_batch<PAIRS_PER_THREAD>, dim3(xcd_grid(c.nchunks)), dim3(WG), 0, st,
-                       c);
-  return hipGetLastError();
-}
-
-hipError_t launch_gram_finalize_batch(const BatchCfg& c, hipStream_t st) {
-  const int dm = 2 * c.S + 1;
-  hipLaunchKernelGGL(k_gram_finalize_batch, dim3(dm * (dm + 1) / 2, c.nsys), dim3(WG), 0, st, c);
-  return hipGetLastError();
-}
-
 hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st) {
   hipLaunchKernelGGL(k_recover_batch, dim3(xcd_grid(c.nblk)), dim3(WG), 0, st, c);
   return hipGetLastError();
@@ -852,28 +517,6 @@ hipError_t launch_batch_res_finalize(const BatchCfg& c, hipStream_t st) {
 
 hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(WG), 0, st, c);
-  return hipGetLastError();
-}
-
-int gram32_nparts(int n) {
-  // at least 32 row blocks of 64 per workgroup (the lane sums stay cheap), at most 512
-  int nb = (n + SSCG_WAVE - 1) / SSCG_WAVE;
-  int np = (nb + 31) / 32;
-  if (np > 512) np = 512;
-  return np < 1 ? 1 : np;
-}
-
-hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, int nparts,
-                         hipStream_t st) {
-  if (d <= 11)
-    hipLaunchKernelGGL(k_gram32_lr<11>, dim3(xcd_grid(nparts)), dim3(g32_waves<11>() * SSCG_WAVE),
-                       0, st, cols, n, d, part, nparts);
-  else if (d <= 21)
-    hipLaunchKernelGGL(k_gram32_lr<21>, dim3(xcd_grid(nparts)), dim3(g32_waves<21>() * SSCG_WAVE),
-                       0, st, cols, n, d, part, nparts);
-  else
-    hipLaunchKernelGGL(k_gram32, dim3(xcd_grid(nparts)), dim3(WG), 0, st, cols, n, d, part,
-                       nparts);
   return hipGetLastError();
 }
 

@@ -59,8 +59,8 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
   HIPCHK(ensure(ctx->info, sizeof(sscg_block_info)));
   HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
   if ((rc = ensure_parts(ctx, n, 2))) return rc;
-  const int npg = gram32_nparts(n);
-  HIPCHK(ensure(ctx->rpart, sizeof(double) * 2 * (size_t)npg * (dmax * (dmax + 1) / 2)));
+  const int npg = gram_ngroups(n);
+  HIPCHK(ensure(ctx->rpart, sizeof(double) * (size_t)npg * (dmax * (dmax + 1) / 2)));
   float* Y = as<float>(ctx->Y32);
   float* P0 = Y;
   float* R0 = Y + (int64_t)rcol * ld;
@@ -189,7 +189,7 @@ int sscg_host::solve_mixed(sscg_ctx* ctx, const sscg_csr* A, const double* b, do
         HIPCHK(launch_mpk32_pass(M, val32, j, bp, nrhs, sp, sr, st));
       }
       const Cols32 cols{Y, ld, s, rcol};
-      HIPCHK(launch_gram32(cols, n, d, gpart, npg, st));
+      HIPCHK(launch_gram32(cols, n, d, gpart, st));
       HIPCHK(launch_gram_finalize(gpart, npg, d, G, nullptr, st));
       sscg_block_params prm;
       prm.s = s;
@@ -292,10 +292,10 @@ extern "C" int sscg_gram32(sscg_ctx* ctx, int n, int s, int first, const float* 
     return fail(ctx, SSCG_ERR_ARG, "bad Gram arguments");
   if (!first && rcol < s + 1) return fail(ctx, SSCG_ERR_ARG, "rcol must be >= s+1");
   const int d = first ? s + 1 : 2 * s + 1;
-  const int np = gram32_nparts(n);
-  HIPCHK(ensure(ctx->part, sizeof(double) * 2 * (size_t)np * (d * (d + 1) / 2)));
+  const int np = gram_ngroups(n);
+  HIPCHK(ensure(ctx->part, sizeof(double) * (size_t)np * (d * (d + 1) / 2)));
   const Cols32 cols{Y, ldy, s, rcol};
-  HIPCHK(launch_gram32(cols, n, d, as<double>(ctx->part), np, ctx->stream));
+  HIPCHK(launch_gram32(cols, n, d, as<double>(ctx->part), ctx->stream));
   HIPCHK(launch_gram_finalize(as<double>(ctx->part), np, d, G, nullptr, ctx->stream));
   return SSCG_OK;
 }

@@ -2,19 +2,17 @@
 // allocate device memory during the call (code under HIP graph capture,
 // tight serving loops, harnesses that forbid hipMalloc).
 //
-// sscg_gram keeps its per-workgroup partial sums in the context's workspace,
-// which grows with hipMalloc on demand.  This variant keeps them in the
-// file-scope device array `scratch` below instead: a fixed SCRATCH_DD
-// double-double partials (4 MiB) that every GPU the library runs on holds
-// until the process ends.  Its device address is looked up once per device
-// when the first context on that device is created (sscg_create) and kept in
-// a per-device table; host code uses only that address, never the array's
-// name (which on the host is a stand-in, not a device address).
-//
-// The number of workgroups is reduced, when needed, so that the partials of
-// d(d+1)/2 entries fit the array: min(gram_nparts(n), SCRATCH_DD / (d(d+1)/2)).
-// Every Gram entry is rounded once from its exact value, so the result does
-// not depend on that partition and equals sscg_gram's.
+// sscg_gram keeps its per-group partial sums (one double per upper-triangle
+// entry and 1024-row group) in the context's workspace, which grows with
+// hipMalloc on demand.  This variant keeps them in the file-scope device
+// array `scratch` below instead: SCRATCH_PARTS doubles (8 MiB) that every
+// GPU the library runs on holds until the process ends.  Its device address
+// is looked up once per device when the first context on that device is
+// created (sscg_create) and kept in a per-device table; host code uses only
+// that address, never the array's name (which on the host is a stand-in, not
+// a device address).  The partials follow the stated order of the Gram
+// matrix, so the same kernels give the same bits as sscg_gram; a Gram whose
+// d(d+1)/2 entries x ceil(n / 1024) groups exceed the array is refused.
 #include <mutex>
 
 #include "ctx.h"
@@ -23,10 +21,10 @@ using namespace sscg_host;
 
 namespace {
 
-constexpr int64_t SCRATCH_DD = int64_t(1) << 18;  // double-double partials (2 doubles each)
+constexpr int64_t SCRATCH_PARTS = int64_t(1) << 20;  // doubles (8 MiB)
 constexpr int MAX_DEVICES = 64;
 
-__device__ __align__(256) double scratch[2 * SCRATCH_DD];
+__device__ __align__(256) double scratch[SCRATCH_PARTS];
 
 std::mutex g_mu;
 void* g_ptr[MAX_DEVICES] = {};  // device address of `scratch` on each device (NULL: not looked up)
@@ -61,18 +59,18 @@ extern "C" int sscg_gram_noalloc(sscg_ctx* ctx, int n, int s, int first, const d
   if (!ctx->scratch) return fail(ctx, SSCG_ERR_HIP, "static scratch not set up on this context");
   const int d = first ? s + 1 : 2 * s + 1;
   const int64_t pairs = (int64_t)d * (d + 1) / 2;
-  if (pairs > SCRATCH_DD)
-    return fail(ctx, SSCG_ERR_ARG, "Gram of %d columns needs %lld partials, the scratch holds %lld",
-                d, (long long)pairs, (long long)SCRATCH_DD);
-  int np = gram_nparts(n);
-  if ((int64_t)np * pairs > SCRATCH_DD) np = (int)(SCRATCH_DD / pairs);
+  const int ng = gram_ngroups(n);
+  if (pairs * ng > SCRATCH_PARTS)
+    return fail(ctx, SSCG_ERR_ARG,
+                "Gram of %d columns x %d rows needs %lld partials; the static scratch holds %lld "
+                "(use sscg_gram)", d, n, (long long)(pairs * ng), (long long)SCRATCH_PARTS);
   double* part = static_cast<double*>(ctx->scratch);
   double* Yw = const_cast<double*>(Y);
   BasisCols bc{Y, Y + (int64_t)rcol * ldy, Yw, ldy, rcol};
   const ColPtr cols = colptr_of(bc, s, first ? 1 : 0);
-  // every partial slot [0, np * pairs) is written by the first kernel before
+  // every partial slot [0, ng * pairs) is written by the first kernel before
   // the second reads it: nothing needs clearing between calls
-  HIPCHK(launch_gram(cols, n, d, part, np, Gate{nullptr, nullptr}, ctx->stream));
-  HIPCHK(launch_gram_finalize(part, np, d, G, nullptr, ctx->stream));
+  HIPCHK(launch_gram(cols, n, d, part, Gate{nullptr, nullptr}, ctx->stream));
+  HIPCHK(launch_gram_finalize(part, ng, d, G, nullptr, ctx->stream));
   return SSCG_OK;
 }

@@ -388,6 +388,7 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   c.gpart = as<double>(w.gpart);
   c.active = as<int32_t>(w.active);
   c.T[0] = as<double2>(w.T);
+  c.inv = as<int32_t>(w.inv);
   c.T[1] = c.T[0] + N;
   s->M.n = N;
   s->M.nslices = nslices;

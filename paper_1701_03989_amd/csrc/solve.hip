@@ -80,7 +80,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   HIPCHK(ensure(ctx->scal, sizeof(double) * 16));
   HIPCHK(ensure(ctx->ctl, sizeof(int) * 4));
   if ((rc = ensure_parts(ctx, n, 2))) return rc;
-  HIPCHK(ensure(ctx->part, std::max(ctx->part.cap, sizeof(double) * 2 * (size_t)gram_nparts(n) *
+  HIPCHK(ensure(ctx->part, std::max(ctx->part.cap, sizeof(double) * (size_t)gram_ngroups(n) *
                                                         (dmax * (dmax + 1) / 2))));
   const int np_res = residual_nparts(n);
   HIPCHK(ensure(ctx->rpart, sizeof(double) * 2 * (size_t)np_res));

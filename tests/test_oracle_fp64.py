@@ -169,19 +169,64 @@ def test_chebyshev_basis_closed_form_on_diagonal_matrix():
         assert np.allclose(Y[:, j], Tj * u, rtol=1e-12, atol=1e-13)
 
 
-def test_gram_equals_explicit_YtY():
-    A = poisson2d(12)
-    Y, _ = _basis(A, 5, False, "monomial")
+def _fma(a, b, s):
+    """IEEE fused multiply-add by its definition: a * b + s exact, one rounding."""
+    from fractions import Fraction
+
+    return float(Fraction(a) * Fraction(b) + Fraction(s))
+
+
+def _gram_by_definition(Y, group=1024):
+    """G = Y^T Y in the stated order, written out with an exact-rational fma:
+    per group of `group` rows (zero-padded) s = fma(y_ra, y_rb, s) from +0 in
+    row order; the group partials zero-padded to a power of two and added by
+    recursive halves."""
+    n, d = Y.shape
+    ng = -(-n // group)
+
+    def halves(v):
+        return v[0] if len(v) == 1 else halves(v[:len(v) // 2]) + halves(v[len(v) // 2:])
+
+    G = np.zeros((d, d))
+    for a in range(d):
+        for b in range(a, d):
+            parts = []
+            for g in range(ng):
+                s = 0.0
+                for r in range(g * group, (g + 1) * group):
+                    s = _fma(Y[r, a], Y[r, b], s) if r < n else _fma(0.0, 0.0, s)
+                parts.append(s)
+            P = 1
+            while P < len(parts):
+                P *= 2
+            G[a, b] = G[b, a] = halves(parts + [0.0] * (P - len(parts)))
+    return G
+
+
+def test_gram_equals_explicit_YtY_in_the_stated_order():
+    """The oracle's Gram (C helper) against its definition evaluated with
+    rational fma (3 groups, the last one ragged, so the pairwise step pads to
+    4), and against the exact inner products within the fma-chain bound."""
+    from fractions import Fraction
+
+    A = poisson2d(48)  # n = 2304: groups of 1024, 1024, 256
+    Y, _ = _basis(A, 3, False, "monomial")
     G = np.array(CR().gram([Y[:, a] for a in range(Y.shape[1])]))
-    import math as m
+    assert np.array_equal(G, _gram_by_definition(Y))
+    absb = np.abs(Y).T @ np.abs(Y)
+    gam = (1024 + 2) * sstep.EPS / (1 - (1024 + 2) * sstep.EPS)  # chain of 1024 + 2 tree levels
     for a in range(Y.shape[1]):
         for b in range(Y.shape[1]):
-            from fractions import Fraction
-            ex = float(sum((Fraction(x) * Fraction(y) for x, y in zip(Y[:, a], Y[:, b])), Fraction(0)))
-            assert G[a, b] == ex
-    absb = np.abs(Y).T @ np.abs(Y)
-    gam = Y.shape[0] * sstep.EPS / (1 - Y.shape[0] * sstep.EPS)
-    assert np.all(np.abs(G - Y.T @ Y) <= gam * absb)
+            ex = float(sum((Fraction(x) * Fraction(y) for x, y in zip(Y[:, a], Y[:, b])),
+                           Fraction(0)))
+            assert abs(G[a, b] - ex) <= gam * absb[a, b]
+    # the stated order is not just any order: a column pair whose sum depends on it
+    big, tiny = 1.0, 2.0 ** -60
+    col = np.zeros(2048)
+    col[0], col[1], col[1024] = big, tiny, -big  # 1 + tiny in group 0, -1 in group 1
+    G2 = np.array(CR().gram([col, np.ones(2048)]))
+    assert G2[0, 1] == 0.0  # (1 + 2^-60) rounds to 1 inside group 0; then 1 + (-1)
+    assert _gram_by_definition(np.stack([col, np.ones(2048)], 1))[0, 1] == 0.0
 
 
 def test_sqrt_kappa_G_equals_kappa_Y_and_interlacing():

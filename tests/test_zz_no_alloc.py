@@ -2,8 +2,7 @@
 device array, allocating nothing) against sscg_gram (the same stage with the
 context's growable workspace), through the C ABI: the same G bit for bit on
 two calls in a row, the second with a smaller input, and against the oracle's
-correctly rounded Gram of the same columns.  Also with n so large that the
-static array forces fewer workgroups than sscg_gram uses."""
+Gram of the same columns; and the size limit of the static array."""
 import sys
 
 import numpy as np
@@ -69,11 +68,20 @@ def test_noalloc_gram_equals_sscg_gram_two_calls_second_smaller(ctx):
     one_case(ctx, 1_000, 8, True, 3)    # block 0 form, smaller again
 
 
-def test_noalloc_gram_with_reduced_partition(ctx):
-    """d = 33 and 2.1 M rows: sscg_gram uses 2048 workgroups, the static array
-    holds the partials of 467; the entries are the same bits."""
-    one_case(ctx, 2_097_152, 16, False, 4, oracle=False)
+def test_noalloc_gram_at_and_beyond_its_limit(ctx):
+    """2.1 M rows x 21 columns (231 entries x 2048 groups of partials, within
+    the 2^20 of the static array) gives sscg_gram's bits; 33 columns of the
+    same length (561 x 2048) is refused with SSCG_ERR_ARG and leaves G alone."""
+    one_case(ctx, 2_097_152, 10, False, 4, oracle=False)
     one_case(ctx, 70_000, 16, False, 5)
+    n, s = 2_097_152, 16
+    Y = torch.zeros((2 * s + 3) * n, dtype=torch.float64, device=DEV)
+    G = torch.full((33 * 33,), 7.0, dtype=torch.float64, device=DEV)
+    with pytest.raises(sscg.SscgError) as e:
+        sscg.sscg_gram_noalloc(ctx, n, s, False, Y, n, s + 2, G)
+    assert e.value.code == sscg.ERR_ARG and "static scratch" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((G == 7.0).all())
 
 
 def test_noalloc_gram_rejects_bad_arguments(ctx):
