@@ -570,7 +570,8 @@ void sscg_destroy(sscg_ctx* c) {
   Buf* bbufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag,    &w.Y,      &w.x,     &w.b,
                   &w.sys,   &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,   &w.blk_sys,
                   &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active, &w.perm, &w.inv, &w.T, &w.ilcnt,
-                  &w.scol16, &w.svidx, &w.svtab, &w.vtcnt};
+                  &w.scol16, &w.svidx, &w.svtab, &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab,
+                  &w.sd_code, &w.sdcnt};
   for (Buf* b : bbufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {

@@ -269,6 +269,26 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   M.col16 = as<int16_t>(w.scol16);
   M.vidx = as<uint8_t>(w.svidx);
   M.vtab = as<double>(w.svtab);
+  // slice-diagonal form, read by the systems all of whose slices fit it
+  HIPCHK(ensure(w.sd_nd, sizeof(int32_t) * (size_t)nslices));
+  HIPCHK(ensure(w.sd_delta, sizeof(int32_t) * SD_DIAG * (size_t)nslices));
+  HIPCHK(ensure(w.sd_tab, sizeof(double) * 4 * (size_t)nslices));
+  HIPCHK(ensure(w.sd_code, sizeof(uint16_t) * (size_t)N));
+  HIPCHK(ensure(w.sdcnt, sizeof(int32_t) * nsys));
+  int32_t* sdcnt = as<int32_t>(w.sdcnt);
+  HIPCHK(hipMemsetAsync(sdcnt, 0, sizeof(int32_t) * nsys, st));
+  for (int q = 0; q < nsys; ++q) {
+    const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
+    HIPCHK(launch_sell_sdia_sys(B->A[q].rowptr, perm + hs[q].row0, hs[q].row0 / SSCG_WAVE,
+                                npad / SSCG_WAVE, M.col, M.val, off, width,
+                                as<int32_t>(w.sd_nd), as<int32_t>(w.sd_delta),
+                                as<double>(w.sd_tab), as<uint16_t>(w.sd_code), sdcnt + q, st));
+  }
+  HIPCHK(launch_set_sd(c.sys, sdcnt, 0, nsys, st));
+  M.sd_nd = as<int32_t>(w.sd_nd);
+  M.sd_delta = as<int32_t>(w.sd_delta);
+  M.sd_tab = as<double>(w.sd_tab);
+  M.sd_code = as<uint16_t>(w.sd_code);
   HIPCHK(hipMemsetAsync(c.hist, 0, sizeof(BatchHist) * (size_t)cap * nsys, st));
   int np = 0;
   HIPCHK(launch_residual(M, c.b, c.x, batch_col(c, 0), c.rpart, c.bpart, &np, st));

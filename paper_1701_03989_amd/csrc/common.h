@@ -353,6 +353,7 @@ struct BatchSys {
   int32_t ch0, ch1;    // Gram chunks [ch0, ch1)
   int32_t il;          // 1: two-sequence passes gather (P, R) pairs (scattered columns)
   int32_t vt;          // 1: passes read value tables and 16-bit offsets (all slices fit)
+  int32_t sd;          // 1: passes read the slice-diagonal form (all slices fit; not il)
   double tol;          // target relative residual
   double eps_star;     // tol * ||b||
   double b2;           // ||b||^2
@@ -449,6 +450,14 @@ hipError_t launch_sell_forms_batch(const int32_t* scol, const double* val, const
                                    const int32_t* blk_sys, int16_t* col16, double* vtab,
                                    uint8_t* vidx, int32_t* cnt, hipStream_t st);
 hipError_t launch_set_vt(BatchSys* sys, const int32_t* cnt, int q0, int count, hipStream_t st);
+// Slice-diagonal form of one batched system's slices [slice0, slice0 + nsl)
+// (perm: the system's positions -> rows, rowptr: its CSR); *cnt gains one per
+// slice that does not fit.  Then sys[q].sd = (cnt[q] == 0) (and il = 0 then).
+hipError_t launch_sell_sdia_sys(const int32_t* rowptr, const int32_t* perm, int slice0, int nsl,
+                                const int32_t* scol, const double* sval, const int64_t* off,
+                                const int32_t* width, int32_t* sd_nd, int32_t* sd_delta,
+                                double* sd_tab, uint16_t* sd_code, int32_t* cnt, hipStream_t st);
+hipError_t launch_set_sd(BatchSys* sys, const int32_t* cnt, int q0, int count, hipStream_t st);
 // dst[p] = src[perm[p]] (0 for padding) and dst[perm[p]] = src[p], p < npad.
 hipError_t launch_gather_perm(const double* src, const int32_t* perm, int npad, double* dst,
                               hipStream_t st);

@@ -35,6 +35,7 @@ struct BatchWs {
   Buf T;                             // (P_j, R_j) pairs for the gathers (two N-row halves)
   Buf ilcnt;                         // per system: stored and scattered SELL entries
   Buf scol16, svidx, svtab, vtcnt;   // compact forms; per system: slices that miss them
+  Buf sd_nd, sd_delta, sd_tab, sd_code, sdcnt;  // slice-diagonal form; per system: misses
 };
 
 // One timed interval on a stream: a single launch, or a group of launches

@@ -121,7 +121,7 @@ void server_free(sscg_server* s) {
                  &w.b,     &w.sys,  &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,
                  &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active,
                  &w.perm,  &w.inv,  &w.T,    &w.ilcnt, &w.scol16, &w.svidx, &w.svtab,
-                 &w.vtcnt};
+                 &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab, &w.sd_code, &w.sdcnt};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (s->hsys) (void)hipHostFree(s->hsys);
@@ -248,6 +248,16 @@ int admit(sscg_server* s, int64_t id) {
                                  as<int32_t>(s->w.blk_sys), as<int16_t>(s->w.scol16),
                                  as<double>(s->w.svtab), as<uint8_t>(s->w.svidx), vtcnt, s->st));
   HIPCHK(launch_set_vt(c.sys, vtcnt, slot, 1, s->st));
+  // its slice-diagonal form, read (in place of the above and the pairs) if
+  // all of its slices fit
+  int32_t* sdcnt = as<int32_t>(s->w.sdcnt);
+  HIPCHK(hipMemsetAsync(sdcnt + slot, 0, sizeof(int32_t), s->st));
+  HIPCHK(launch_sell_sdia_sys(r.A.rowptr, perm + row0, (int)slice0, ns, as<int32_t>(s->w.scol),
+                              as<double>(s->w.sval), as<int64_t>(s->w.off),
+                              as<int32_t>(s->w.width), as<int32_t>(s->w.sd_nd),
+                              as<int32_t>(s->w.sd_delta), as<double>(s->w.sd_tab),
+                              as<uint16_t>(s->w.sd_code), sdcnt + slot, s->st));
+  HIPCHK(launch_set_sd(c.sys, sdcnt, slot, 1, s->st));
   HIPCHK(hipMemsetAsync(c.hist + (size_t)slot * s->cap, 0, sizeof(BatchHist) * s->cap, s->st));
   // r_1 = b - A x_1 into P_0 over the request's slices, then its set-up
   DevMat V = s->M;
@@ -329,7 +339,12 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
       {&w.ilcnt, sizeof(unsigned long long) * 2 * (size_t)slots},
       {&w.scol16, sizeof(int16_t) * pool_nnz},     {&w.svidx, sizeof(uint8_t) * pool_nnz},
       {&w.svtab, sizeof(double) * VTAB * (size_t)nslices},
-      {&w.vtcnt, sizeof(int32_t) * (size_t)slots}};
+      {&w.vtcnt, sizeof(int32_t) * (size_t)slots},
+      {&w.sd_nd, sizeof(int32_t) * (size_t)nslices},
+      {&w.sd_delta, sizeof(int32_t) * SD_DIAG * (size_t)nslices},
+      {&w.sd_tab, sizeof(double) * 4 * (size_t)nslices},
+      {&w.sd_code, sizeof(uint16_t) * (size_t)N},
+      {&w.sdcnt, sizeof(int32_t) * (size_t)slots}};
   for (const auto& p : sizes)
     if (e == hipSuccess) e = ensure(*p.first, p.second);
   if (e != hipSuccess) return bad(e);
@@ -399,6 +414,10 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   s->M.col16 = as<int16_t>(w.scol16);
   s->M.vidx = as<uint8_t>(w.svidx);
   s->M.vtab = as<double>(w.svtab);
+  s->M.sd_nd = as<int32_t>(w.sd_nd);
+  s->M.sd_delta = as<int32_t>(w.sd_delta);
+  s->M.sd_tab = as<double>(w.sd_tab);
+  s->M.sd_code = as<uint16_t>(w.sd_code);
   // one outer block over the first g/NG of the pool, captured once per g: a
   // step replays the smallest one that covers every admitted system (the
   // allocator is first-fit, so admitted rows stay low), so an idle tail of

@@ -186,27 +186,23 @@ __global__ __launch_bounds__(WG) void k_sell_vidx(const double* __restrict__ val
   if (over && lane == 0) *flag = 1;
 }
 
-// The slice-diagonal form (DevMat::sd_*), one wavefront per slice.  The
-// distances and values are collected in order of first appearance (entry j,
-// then lane), like the value table; padding entries (j >= the row's length)
-// are left out.  A slice with more than SD_DIAG distances or SD_VALS values,
-// or a row with two entries at one distance, sets *flag (the form is then
-// not used for the matrix).
-__global__ __launch_bounds__(WG) void k_sell_sdia(const int32_t* __restrict__ rowptr, int n,
-                                                  const int32_t* __restrict__ scol,
-                                                  const double* __restrict__ sval,
-                                                  const int64_t* __restrict__ off,
-                                                  const int32_t* __restrict__ width, int nslices,
-                                                  int32_t* __restrict__ sd_nd,
-                                                  int32_t* __restrict__ sd_delta,
-                                                  double* __restrict__ sd_tab,
-                                                  uint16_t* __restrict__ sd_code,
-                                                  int32_t* __restrict__ flag) {
-  const int slice = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  if (slice >= nslices) return;  // whole wavefronts
+// The slice-diagonal form (DevMat::sd_*) of one slice, called by its whole
+// wavefront: lane = the row at position `row` (absolute), len = its number of
+// stored entries (the rest of the slice's width is padding).  The distances
+// and values are collected in order of first appearance (entry j, then lane),
+// like the value table.  Returns true (on every lane) if the slice does not
+// fit the form: more than SD_DIAG distances or SD_VALS values, or a row with
+// two entries at one distance.
+__device__ __forceinline__ bool sdia_slice(int slice, int row, int len,
+                                           const int32_t* __restrict__ scol,
+                                           const double* __restrict__ sval,
+                                           const int64_t* __restrict__ off,
+                                           const int32_t* __restrict__ width,
+                                           int32_t* __restrict__ sd_nd,
+                                           int32_t* __restrict__ sd_delta,
+                                           double* __restrict__ sd_tab,
+                                           uint16_t* __restrict__ sd_code) {
   const int lane = threadIdx.x & (SSCG_WAVE - 1);
-  const int row = slice * SSCG_WAVE + lane;
-  const int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
   const int64_t o = off[slice] + lane;
   const int w = width[slice];
   int ds = 0, nd = 0;      // lane k < nd holds distance k
@@ -259,7 +255,65 @@ __global__ __launch_bounds__(WG) void k_sell_sdia(const int32_t* __restrict__ ro
   if (lane < 4) sd_tab[(int64_t)slice * 4 + lane] = lane < m ? __longlong_as_double(tb) : 0.0;
   if (lane == 0) sd_nd[slice] = nd;
   sd_code[row] = (uint16_t)code;
-  if (over && lane == 0) atomicOr(flag, 1);
+  return over;
+}
+
+// Single matrix: *flag = 1 if some slice does not fit (the form is then not
+// used for the matrix).
+__global__ __launch_bounds__(WG) void k_sell_sdia(const int32_t* __restrict__ rowptr, int n,
+                                                  const int32_t* __restrict__ scol,
+                                                  const double* __restrict__ sval,
+                                                  const int64_t* __restrict__ off,
+                                                  const int32_t* __restrict__ width, int nslices,
+                                                  int32_t* __restrict__ sd_nd,
+                                                  int32_t* __restrict__ sd_delta,
+                                                  double* __restrict__ sd_tab,
+                                                  uint16_t* __restrict__ sd_code,
+                                                  int32_t* __restrict__ flag) {
+  const int slice = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (slice >= nslices) return;  // whole wavefronts
+  const int row = slice * SSCG_WAVE + (threadIdx.x & (SSCG_WAVE - 1));
+  const int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+  const bool over = sdia_slice(slice, row, len, scol, sval, off, width, sd_nd, sd_delta, sd_tab,
+                               sd_code);
+  if (over && (threadIdx.x & (SSCG_WAVE - 1)) == 0) atomicOr(flag, 1);
+}
+
+// One batched system's slices [slice0, slice0 + nsl): position p of the
+// system holds its row perm[p] (-1: padding); *cnt gains one per slice that
+// does not fit.
+__global__ __launch_bounds__(WG) void k_sell_sdia_sys(const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ perm,
+                                                      int slice0, int nsl,
+                                                      const int32_t* __restrict__ scol,
+                                                      const double* __restrict__ sval,
+                                                      const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ width,
+                                                      int32_t* __restrict__ sd_nd,
+                                                      int32_t* __restrict__ sd_delta,
+                                                      double* __restrict__ sd_tab,
+                                                      uint16_t* __restrict__ sd_code,
+                                                      int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  if (i >= nsl) return;  // whole wavefronts
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  const int r = perm[i * SSCG_WAVE + lane];
+  const int len = r >= 0 ? rowptr[r + 1] - rowptr[r] : 0;
+  const int slice = slice0 + i;
+  const bool over = sdia_slice(slice, slice * SSCG_WAVE + lane, len, scol, sval, off, width,
+                               sd_nd, sd_delta, sd_tab, sd_code);
+  if (over && lane == 0) atomicAdd(cnt, 1);
+}
+
+// sys[q].sd = 1 when none of system q's slices missed the slice-diagonal
+// form (cnt[q] == 0); such a system's passes read it (and not the pairs).
+__global__ void k_set_sd(BatchSys* __restrict__ sys, const int32_t* __restrict__ cnt, int q0,
+                         int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int q = q0 + i;
+  sys[q].sd = cnt[q] == 0 ? 1 : 0;
+  if (sys[q].sd) sys[q].il = 0;
 }
 
 // ---------------------------------------------------------------- MPK pass
@@ -442,9 +496,9 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
 
 // Batched pass j: every 256-row block belongs to one system (blk_sys), whose
 // basis parameters and state come from the system table; blocks of finished
-// systems (or of no system, -1) return at once.  A system flagged vt reads
-// the value tables and 16-bit offsets of k_sell_forms_batch, one flagged il
-// the (P, R) pairs.
+// systems (or of no system, -1) return at once.  A system flagged sd reads
+// the slice-diagonal form, one flagged vt the value tables and 16-bit offsets
+// of k_sell_forms_batch, one flagged il the (P, R) pairs.
 template <int NRHS, bool CHEB, bool RES>
 __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, MpkSeq s1,
                                                   const BatchSys* __restrict__ sys,
@@ -465,7 +519,14 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
   const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
   dd r2;
-  if (il) {
+  if (sys[q].sd) {  // slice-diagonal form (stencils)
+    if (j >= 2)
+      r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true>(A, slice, theta, sigma,
+                                                                       gamma, s0, s1, xres, bres);
+    else
+      r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, true>(A, slice, theta, sigma,
+                                                                        gamma, s0, s1, xres, bres);
+  } else if (il) {
     if (j >= 2)
       r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
                                                          xres, bres, tg, tw);
@@ -1019,6 +1080,20 @@ hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, c
                             hipStream_t st) {
   hipLaunchKernelGGL(k_sell_sdia, dim3(wg_count(nslices)), dim3(WG), 0, st, rowptr, n, scol, sval,
                      off, width, nslices, sd_nd, sd_delta, sd_tab, sd_code, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_sdia_sys(const int32_t* rowptr, const int32_t* perm, int slice0, int nsl,
+                                const int32_t* scol, const double* sval, const int64_t* off,
+                                const int32_t* width, int32_t* sd_nd, int32_t* sd_delta,
+                                double* sd_tab, uint16_t* sd_code, int32_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_sdia_sys, dim3(wg_count(nsl)), dim3(WG), 0, st, rowptr, perm, slice0,
+                     nsl, scol, sval, off, width, sd_nd, sd_delta, sd_tab, sd_code, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_sd(BatchSys* sys, const int32_t* cnt, int q0, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_sd, dim3((count + 255) / 256), dim3(256), 0, st, sys, cnt, q0, count);
   return hipGetLastError();
 }
 
