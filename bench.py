@@ -633,6 +633,7 @@ def bench_serve(args) -> None:
                     pending.discard(r)
     makespan = float(np.nanmax(done_at))
     lat = done_at - arrive
+    occ = sscg.sscg_server_stats(ctx, srv)
     sscg.sscg_server_destroy(srv)
     # accuracy of every served result, recomputed in FP64 on the host
     worst = 0.0
@@ -686,6 +687,8 @@ def bench_serve(args) -> None:
             "basis": "chebyshev", "s_max": 8, "pool_rows": pool_rows, "slots": args.serve_slots,
         },
         "offered_rate": args.serve_rate,
+        "replays": occ["replays"],
+        "mean_rows_per_replay": occ["rows_active"] / max(occ["replays"], 1),
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "worst_relres_over_tol": worst,

@@ -375,9 +375,12 @@ int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* batch, const sscg_opts* op
  * its rows, padded to 1024, in the row pool, which holds the 2 s_max + 3
  * vectors of every row).  Each sscg_server_step runs one outer block for all
  * admitted systems (the same batched launches as sscg_batch_solve, replayed
- * from one HIP graph over the whole pool), retires finished systems (x is
+ * from one HIP graph; its row launches take the admitted systems' rows only,
+ * wherever they sit in the pool), retires finished systems (x is
  * copied back to the caller's buffer before the step returns) and admits
- * waiting ones; their work overlaps on the device.  Each result is the one
+ * waiting ones; their work overlaps on the device.  A step returns while its
+ * block still runs (at most two blocks are in flight), so a system is seen
+ * finished, and retired, one or two steps after the block that finished it.  Each result is the one
  * sscg_solve gives for that system alone.  Options as for batches
  * (MODE_SCHEDULE and equilibration are not supported). */
 typedef struct sscg_server sscg_server;
@@ -411,6 +414,10 @@ int sscg_server_poll(sscg_server* server, int64_t id, int32_t* state, int32_t* s
  * 4096).  SSCG_ERR_ARG for an unknown request or one that is not done. */
 int sscg_server_history(sscg_server* server, int64_t id, int32_t cap, int32_t* s_k,
                         int32_t* s_tilde, double* relres_true, int32_t* rows);
+/* Counters since creation (any output may be NULL): outer-block replays
+ * launched, and the sum over replays of the admitted systems' rows (each
+ * padded to 1024); rows_active / replays is the mean rows per block. */
+int sscg_server_stats(sscg_server* server, int64_t* replays, int64_t* rows_active);
 
 /* ---------------------------------------------------------------- timing */
 

@@ -571,7 +571,7 @@ void sscg_destroy(sscg_ctx* c) {
                   &w.sys,   &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,   &w.blk_sys,
                   &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active, &w.perm, &w.inv, &w.T, &w.ilcnt,
                   &w.scol16, &w.svidx, &w.svtab, &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab,
-                  &w.sd_code, &w.sdcnt};
+                  &w.sd_code, &w.sdcnt, &w.ablk, &w.achk, &w.loff};
   for (Buf* b : bbufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {

@@ -29,16 +29,51 @@ namespace {
 constexpr int CHUNK_ROWS = 1024;  // rows per Gram work item
 constexpr int GROUP = 4;          // blocks replayed between checks of the active count
 
-struct GraphGuard {
-  hipGraph_t g = nullptr;
-  hipGraphExec_t e = nullptr;
-  ~GraphGuard() {
-    if (e) (void)hipGraphExecDestroy(e);
-    if (g) (void)hipGraphDestroy(g);
-  }
-};
-
 }  // namespace
+
+void sscg_host::BlockGraphs::clear() {
+  for (hipGraphExec_t x : e)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t x : g)
+    if (x) (void)hipGraphDestroy(x);
+  e.clear();
+  g.clear();
+  gblk.clear();
+  gchk.clear();
+}
+
+int sscg_host::BlockGraphs::capture(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c0,
+                                    hipStream_t st) {
+  clear();
+  int64_t nb = c0.nblk, nc = c0.nchunks;
+  for (;;) {
+    BatchCfg c = c0;
+    c.gblk = (int)nb;
+    c.gchk = (int)nc;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue_block(ctx, M, c, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (graph) g.push_back(graph);
+    if (rc) return rc;
+    HIPCHK(ce);
+    hipGraphExec_t x = nullptr;
+    HIPCHK(hipGraphInstantiate(&x, graph, nullptr, nullptr, 0));
+    e.push_back(x);
+    gblk.push_back((int)nb);
+    gchk.push_back((int)nc);
+    if (nb <= 1024) break;
+    nb = (nb + 3) / 4;
+    nc = (nc + 3) / 4;
+  }
+  return SSCG_OK;
+}
+
+hipGraphExec_t sscg_host::BlockGraphs::pick(int64_t nb, int64_t nc) const {
+  size_t k = e.size() - 1;
+  while (k > 0 && (gblk[k] < nb || gchk[k] < nc)) --k;
+  return e[k];
+}
 
 // One outer block for every unfinished system (enqueued on st; capturable).
 int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c,
@@ -56,7 +91,8 @@ int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCf
     // two-sequence passes gather (P_{j-1}, R_{j-1}) pairs from T[(j-1) & 1] and
     // leave theirs in T[j & 1] when the next pass gathers pairs too
     double2* tw = j + 1 <= c.S - 1 ? c.T[j & 1] : nullptr;
-    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, res, c.T[(j - 1) & 1], tw,
+    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, c.ablk, c.active + 1,
+                            c.gblk, res, c.T[(j - 1) & 1], tw,
                             st));
     if (j == 1) HIPCHK(launch_batch_res_finalize(c, st));
   }
@@ -155,6 +191,9 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(ensure(w.bpart, sizeof(double) * 2 * (size_t)nblk));
   HIPCHK(ensure(w.gpart, sizeof(double) * 2 * (size_t)npairs * nchunks));
   HIPCHK(ensure(w.active, sizeof(int32_t) * 4));
+  HIPCHK(ensure(w.ablk, sizeof(int32_t) * nblk));
+  HIPCHK(ensure(w.achk, sizeof(int32_t) * nchunks));
+  HIPCHK(ensure(w.loff, sizeof(int32_t) * 2 * nsys));
   HIPCHK(ensure(w.perm, sizeof(int32_t) * (size_t)N));
   HIPCHK(ensure(w.T, sizeof(double2) * 2 * (size_t)N));
   HIPCHK(ensure(w.ilcnt, sizeof(unsigned long long) * 2 * nsys));
@@ -238,6 +277,11 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   c.bpart = as<double>(w.bpart);
   c.gpart = as<double>(w.gpart);
   c.active = as<int32_t>(w.active);
+  c.ablk = as<int32_t>(w.ablk);
+  c.achk = as<int32_t>(w.achk);
+  c.loff = as<int32_t>(w.loff);
+  c.gblk = nblk;
+  c.gchk = nchunks;
   c.T[0] = as<double2>(w.T);
   c.inv = as<int32_t>(w.inv);
   c.T[1] = c.T[0] + N;
@@ -297,26 +341,23 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(launch_batch_init(c, st));
   HIPCHK(launch_batch_count(c, st));
 
-  // ---- one outer block as a graph, replayed
-  GraphGuard gg;
-  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  rc = batch_enqueue_block(ctx, M, c, st);
-  hipGraph_t graph = nullptr;
-  hipError_t ce = hipStreamEndCapture(st, &graph);
-  gg.g = graph;
-  if (rc) return rc;
-  HIPCHK(ce);
-  HIPCHK(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+  // ---- one outer block as a graph (grids in steps of 4), replayed; the
+  // lists only shrink, so the grids picked after a check cover them until
+  // the next one
+  BlockGraphs gg;
+  if ((rc = gg.capture(ctx, M, c, st))) return rc;
   // every replay adds >= 1 iteration to each unfinished system or finishes it
   const int64_t limit = (int64_t)o.max_iters + 2;
   int launches = 0;
-  HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   while (ctx->hactive[0] > 0 && launches < limit) {
     const int g = (int)std::min<int64_t>(GROUP, limit - launches);
-    for (int i = 0; i < g; ++i) HIPCHK(hipGraphLaunch(gg.e, st));
+    hipGraphExec_t ge = gg.pick(ctx->hactive[1], ctx->hactive[2]);
+    for (int i = 0; i < g; ++i) HIPCHK(hipGraphLaunch(ge, st));
     launches += g;
-    HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t) * 3, hipMemcpyDeviceToHost,
+                          st));
     HIPCHK(hipStreamSynchronize(st));
   }
 

@@ -390,10 +390,22 @@ struct BatchCfg {
   double* rpart;              // dd partial per 256-row block (residual of x)
   double* bpart;              // dd partial per 256-row block (||b||^2, set-up)
   double* gpart;              // Gram partials: pair * nchunks + chunk
-  int32_t* active;            // systems not done (after each block)
+  int32_t* active;            // [0] systems not done (after each block), [1] blocks and
+                              // [2] chunks of those systems (lengths of ablk / achk)
+  int32_t* ablk;              // 256-row blocks of the systems not done, by system
+  int32_t* achk;              // Gram chunks of the systems not done, by system
+  int32_t* loff;              // per system: its first entry in ablk, in achk
+  int32_t gblk, gchk;         // grids of the row launches: blocks (one per workgroup) and
+                              // chunks (one per wavefront) covered at once
   double2* T[2];              // (P_j, R_j) pairs for the gathers of pass j + 1 (T[j & 1])
   const int32_t* inv;         // inv[row0 + r]: position of row r of the system (row order)
 };
+
+// The row launches of a batched block (matrix powers, Gram, recovery) stride
+// over the lists of the systems not done with the grid the captured graph
+// was given (BatchCfg::gblk, gchk: blocks / chunks covered at once), so
+// finished systems and empty pool rows cost no work beyond that grid.
+inline int batch_grid(int units) { return units < 1 ? 1 : units; }
 
 // P_j / R_j column of a batch (global row index applies on top).
 __host__ __device__ inline double* batch_col(const BatchCfg& c, int col) {
@@ -465,8 +477,11 @@ hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad,
                                hipStream_t st);
 // Batched pass j; with two sequences the gathers read the pairs tg and the
 // outputs' pairs go to tw (if not NULL).
+// Batched pass over the blocks listed in ablk[0, *nl) (grid: gblk workgroups
+// striding over the list).
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
-                            const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
+                            const BatchSys* sys, const int32_t* blk_sys, const int32_t* ablk,
+                            const int32_t* nl, int gblk, const MpkResidual& res,
                             const double2* tg, double2* tw, hipStream_t st);
 // t[i] = (a[i], b[i]), i < n.
 hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, hipStream_t st);

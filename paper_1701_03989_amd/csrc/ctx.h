@@ -36,6 +36,7 @@ struct BatchWs {
   Buf ilcnt;                         // per system: stored and scattered SELL entries
   Buf scol16, svidx, svtab, vtcnt;   // compact forms; per system: slices that miss them
   Buf sd_nd, sd_delta, sd_tab, sd_code, sdcnt;  // slice-diagonal form; per system: misses
+  Buf ablk, achk, loff;                         // lists of the systems not done
 };
 
 // One timed interval on a stream: a single launch, or a group of launches
@@ -177,6 +178,24 @@ int gram_into(sscg_ctx* ctx, const ColPtr& cols, int n, int d, double* G, const 
 
 // One outer block of a batch for every unfinished system (capturable).
 int batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st);
+
+// Graphs of one outer block (batch_enqueue_block) whose row launches have
+// grids of 1/4^k of the full lists (k = 0, 1, ...; down to about 256 blocks),
+// so that a replay launches about as many workgroups as the systems not done
+// have blocks (the launches stride over the lists, so any grid is correct).
+struct BlockGraphs {
+  std::vector<hipGraph_t> g;
+  std::vector<hipGraphExec_t> e;
+  std::vector<int> gblk, gchk;
+  BlockGraphs() = default;
+  BlockGraphs(const BlockGraphs&) = delete;
+  BlockGraphs& operator=(const BlockGraphs&) = delete;
+  ~BlockGraphs() { clear(); }
+  void clear();
+  int capture(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st);
+  // the smallest grids that cover nb blocks and nc chunks
+  hipGraphExec_t pick(int64_t nb, int64_t nc) const;
+};
 
 // Look up the device address of the static scratch array of
 // sscg_gram_noalloc on ctx's device (current), once per device; sets

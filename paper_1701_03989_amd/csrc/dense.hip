@@ -275,21 +275,25 @@ __global__ __launch_bounds__(WG) void k_div_vec(const double* __restrict__ w,
 
 // Gram columns of a system in this block: P_0..P_s, then R_0..R_{s-1}; the
 // address is computed (an array of pointers would live in scratch memory).
-// x <- x + Y x', r = Y r' (into R_0), p = Y p' (into P_0), per system.
+// x <- x + Y x', r = Y r' (into R_0), p = Y p' (into P_0), per system; over
+// the blocks listed in ablk (a workgroup takes every gridDim.x-th entry).
 __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
-  int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
-  if (lb >= c.nblk) return;
-  const int q = c.blk_sys[lb];
-  if (q < 0 || c.sys[q].done) return;
-  const sscg_block_params prm = c.prm[q];
-  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  const int i = lb * BATCH_ROWS + threadIdx.x;
   __shared__ double cf[3 * MAXD];
-  stage_coef(c.coef + (int64_t)q * BATCH_CSZ, d, cf);
-  recover_row(batch_cols(c, prm.s, prm.first), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
-              batch_col(c, 0));
-  // the (p, r) pairs the next block's first pass gathers (each thread its own row)
-  if (c.sys[q].il) c.T[0][i] = make_double2(batch_col(c, 0)[i], batch_col(c, c.S + 1)[i]);
+  const int nl = c.active[1];
+  for (int li = blockIdx.x; li < nl; li += gridDim.x) {  // uniform over the workgroup
+    const int lb = c.ablk[li];
+    const int q = c.blk_sys[lb];
+    if (q < 0 || c.sys[q].done) continue;
+    const sscg_block_params prm = c.prm[q];
+    const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
+    const int i = lb * BATCH_ROWS + threadIdx.x;
+    stage_coef(c.coef + (int64_t)q * BATCH_CSZ, d, cf);
+    recover_row(batch_cols(c, prm.s, prm.first), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
+                batch_col(c, 0));
+    // the (p, r) pairs the next block's first pass gathers (each thread its own row)
+    if (c.sys[q].il) c.T[0][i] = make_double2(batch_col(c, 0)[i], batch_col(c, c.S + 1)[i]);
+    __syncthreads();  // cf is read before the next block's system rewrites it
+  }
 }
 
 // Set-up per system from the residual and ||b||^2 partials of its blocks.
@@ -347,17 +351,66 @@ __global__ __launch_bounds__(WG) void k_batch_res_finalize(BatchCfg c) {
   }
 }
 
+// The systems not done: their number (active[0]), and the offsets (loff) and
+// lengths (active[1], active[2]) of their entries in the block and chunk
+// lists, in system order.  One workgroup; thread t takes a contiguous run of
+// systems.
 __global__ __launch_bounds__(WG) void k_batch_count(BatchCfg c) {
-  __shared__ int ls[WG];
-  int a = 0;
-  for (int q = threadIdx.x; q < c.nsys; q += WG) a += c.sys[q].done ? 0 : 1;
-  ls[threadIdx.x] = a;
+  __shared__ int ls[3][WG];
+  const int t = threadIdx.x;
+  const int per = (c.nsys + WG - 1) / WG;
+  const int q0 = min(t * per, c.nsys), q1 = min(q0 + per, c.nsys);
+  int a = 0, nb = 0, nc = 0;
+  for (int q = q0; q < q1; ++q) {
+    const BatchSys& y = c.sys[q];
+    if (y.done) continue;
+    ++a;
+    nb += y.blk1 - y.blk0;
+    nc += y.ch1 - y.ch0;
+  }
+  ls[0][t] = a;
+  ls[1][t] = nb;
+  ls[2][t] = nc;
   __syncthreads();
-  for (int h = WG / 2; h >= 1; h >>= 1) {
-    if (threadIdx.x < h) ls[threadIdx.x] += ls[threadIdx.x + h];
+  for (int h = 1; h < WG; h <<= 1) {  // inclusive scans
+    int v0 = 0, v1 = 0, v2 = 0;
+    if (t >= h) {
+      v0 = ls[0][t - h];
+      v1 = ls[1][t - h];
+      v2 = ls[2][t - h];
+    }
+    __syncthreads();
+    ls[0][t] += v0;
+    ls[1][t] += v1;
+    ls[2][t] += v2;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *c.active = ls[0];
+  int ob = ls[1][t] - nb, oc = ls[2][t] - nc;
+  for (int q = q0; q < q1; ++q) {
+    const BatchSys& y = c.sys[q];
+    if (y.done) continue;
+    c.loff[2 * q] = ob;
+    c.loff[2 * q + 1] = oc;
+    ob += y.blk1 - y.blk0;
+    oc += y.ch1 - y.ch0;
+  }
+  if (t == WG - 1) {
+    c.active[0] = ls[0][t];
+    c.active[1] = ls[1][t];
+    c.active[2] = ls[2][t];
+  }
+}
+
+// The lists themselves: the blocks and chunks of each system not done, at its
+// offsets (after k_batch_count).
+__global__ __launch_bounds__(WG) void k_batch_lists(BatchCfg c) {
+  for (int q = blockIdx.x; q < c.nsys; q += gridDim.x) {
+    const BatchSys& y = c.sys[q];
+    if (y.done) continue;
+    const int ob = c.loff[2 * q], oc = c.loff[2 * q + 1];
+    for (int k = threadIdx.x; k < y.blk1 - y.blk0; k += WG) c.ablk[ob + k] = y.blk0 + k;
+    for (int k = threadIdx.x; k < y.ch1 - y.ch0; k += WG) c.achk[oc + k] = y.ch0 + k;
+  }
 }
 
 
@@ -496,7 +549,7 @@ hipError_t launch_div_vec(const double* w, const double* beta, int n, double* ou
 }
 
 hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_recover_batch, dim3(xcd_grid(c.nblk)), dim3(WG), 0, st, c);
+  hipLaunchKernelGGL(k_recover_batch, dim3(batch_grid(c.gblk)), dim3(WG), 0, st, c);
   return hipGetLastError();
 }
 
@@ -517,6 +570,7 @@ hipError_t launch_batch_res_finalize(const BatchCfg& c, hipStream_t st) {
 
 hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(WG), 0, st, c);
+  hipLaunchKernelGGL(k_batch_lists, dim3(c.nsys < 1024 ? c.nsys : 1024), dim3(WG), 0, st, c);
   return hipGetLastError();
 }
 

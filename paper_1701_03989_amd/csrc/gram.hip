@@ -155,23 +155,27 @@ struct BatchRow {
   __device__ __forceinline__ int64_t operator()(int64_t r) const { return inv[row0 + r]; }
 };
 
-// Batched: wavefront w of workgroup b takes chunk b GW + w, one group of the
-// system that owns its rows (rows of the system past its n read as 0).
+// Batched: over the chunks listed in achk, wavefront w of workgroup b takes
+// entries b GW + w, then every gridDim.x GW-th after it; a chunk is one group
+// of the system that owns its rows (rows of the system past its n read as 0).
+// The partials go to the chunk's own slot, whatever its place in the list.
 template <int NB>
 __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
   __shared__ double lds[GW * GTR * (16 * NB + 1)];
   const int w = threadIdx.x / SSCG_WAVE;
-  const int ci = blockIdx.x * GW + w;
-  if (ci >= c.nchunks) return;
-  const BatchChunk ch = c.chunks[ci];
-  const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
-  if (q < 0 || c.sys[q].done) return;
-  const sscg_block_params prm = c.prm[q];
-  const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  const int64_t row0 = c.sys[q].row0;
-  const int64_t rend = min((int64_t)ch.r1 - row0, (int64_t)c.sys[q].n);  // system-local rows
-  gram_group<NB>(batch_cols(c, prm.s, prm.first), d, ch.r0 - row0, rend, BatchRow{c.inv, row0},
-                 c.gpart, c.nchunks, ci, lds + w * GTR * (16 * NB + 1));
+  const int nl = c.active[2];
+  for (int li = blockIdx.x * GW + w; li < nl; li += gridDim.x * GW) {  // whole wavefronts
+    const int ci = c.achk[li];
+    const BatchChunk ch = c.chunks[ci];
+    const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
+    if (q < 0 || c.sys[q].done) continue;
+    const sscg_block_params prm = c.prm[q];
+    const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
+    const int64_t row0 = c.sys[q].row0;
+    const int64_t rend = min((int64_t)ch.r1 - row0, (int64_t)c.sys[q].n);  // system-local rows
+    gram_group<NB>(batch_cols(c, prm.s, prm.first), d, ch.r0 - row0, rend, BatchRow{c.inv, row0},
+                   c.gpart, c.nchunks, ci, lds + w * GTR * (16 * NB + 1));
+  }
 }
 
 // ---------------------------------------------------------------- pairwise sums
@@ -301,7 +305,7 @@ hipError_t launch_gram_finalize(const double* part, int ng, int d, double* G, co
 }
 
 hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
-  const dim3 grid((c.nchunks + GW - 1) / GW), block(GW * SSCG_WAVE);
+  const dim3 grid((batch_grid(c.gchk) + GW - 1) / GW), block(GW * SSCG_WAVE);
   switch (column_blocks(2 * c.S + 1)) {
     case 1: hipLaunchKernelGGL(k_gram_batch<1>, grid, block, 0, st, c); break;
     case 2: hipLaunchKernelGGL(k_gram_batch<2>, grid, block, 0, st, c); break;

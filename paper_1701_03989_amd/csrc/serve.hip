@@ -6,11 +6,21 @@
 // One outer block over the whole pool is captured once as a HIP graph; a pool
 // block that belongs to no admitted system has system -1 and its workgroups
 // return at once, so admitting and retiring systems only rewrites tables and
-// pool regions, never the graph.  A step: wait for the previous block's
+// pool regions, never the graph.  The row launches of the block stride over
+// device-side lists of the blocks of the systems not done (k_batch_count, at
+// the end of every block and after admissions), so their cost follows the
+// admitted rows, not the pool's size or where in it the systems sit.  A step: wait for the previous block's
 // system table, retire the systems it finished (copy x out, free their
 // ranges), admit queued requests first come first served while a slot and
 // room in both pools are free (matrix copy, set-up residual, table entries),
 // then replay the graph for one more block.
+//
+// Up to PIPE replays are in flight: a step launches the next block before it
+// has seen the system table of the last one, so the device never waits for
+// the host's retire/admit work.  A replay of a system that is already done
+// changes nothing (every batched kernel skips done systems), so a retirement
+// seen one block late costs only that block's empty workgroups; a slot's
+// table copies older than its admission are ignored.
 #include <math.h>
 #include <string.h>
 
@@ -27,7 +37,7 @@ using namespace sscg_host;
 namespace {
 
 constexpr int64_t ROW_UNIT = 1024;  // row allocation unit: one Gram chunk
-constexpr int NG = 8;               // graphs over the first 1/8, 2/8, ... of the row pool
+constexpr int PIPE = 2;             // outer blocks in flight
 
 // First-fit allocator of ranges in [0, size).
 struct RangeAlloc {
@@ -88,19 +98,19 @@ struct sscg_server {
   BatchWs w;
   BatchCfg c;
   DevMat M;
-  hipGraph_t graph[NG] = {};
-  hipGraphExec_t exec[NG] = {};
-  int64_t extent[NG] = {};  // rows covered by graph g
+  BlockGraphs graphs;
   RangeAlloc ra, na;
   std::vector<int> free_slots;
   std::vector<int64_t> slot_req;
   std::deque<int64_t> queue;
   std::unordered_map<int64_t, Req> reqs;
-  BatchSys* hsys = nullptr;  // pinned copy of the system table after the last block
+  BatchSys* hsys = nullptr;  // pinned copies of the system table after replays k % PIPE
   int64_t* hscan = nullptr;  // pinned scratch
-  hipEvent_t ev = nullptr;      // after the system table copy of the last block
+  hipEvent_t ev[PIPE] = {};     // after the system table copy of replay k % PIPE
   hipEvent_t ev_ret = nullptr;  // after the x copies of the last retirements
-  bool pending = false;
+  int64_t launched = 0, seen = 0;  // replays launched; replays whose table was read
+  std::vector<int64_t> adm_at;     // per slot: the first replay its request takes part in
+  int64_t st_rows_active = 0;      // sum over replays of the admitted rows
   int64_t next_id = 1;
   int running = 0;
   std::vector<int32_t> hblk;  // staging for block -> system entries
@@ -112,31 +122,30 @@ namespace {
 void server_free(sscg_server* s) {
   if (!s) return;
   if (s->st) (void)hipStreamSynchronize(s->st);
-  for (int g = 0; g < NG; ++g) {
-    if (s->exec[g]) (void)hipGraphExecDestroy(s->exec[g]);
-    if (s->graph[g]) (void)hipGraphDestroy(s->graph[g]);
-  }
+  s->graphs.clear();
   BatchWs& w = s->w;
   Buf* bufs[] = {&w.width, &w.off,  &w.scol, &w.sval, &w.flag, &w.Y,       &w.x,
                  &w.b,     &w.sys,  &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,
                  &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active,
                  &w.perm,  &w.inv,  &w.T,    &w.ilcnt, &w.scol16, &w.svidx, &w.svtab,
-                 &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab, &w.sd_code, &w.sdcnt};
+                 &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab, &w.sd_code, &w.sdcnt,
+                 &w.ablk,  &w.achk, &w.loff};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (s->hsys) (void)hipHostFree(s->hsys);
   if (s->hscan) (void)hipHostFree(s->hscan);
-  if (s->ev) (void)hipEventDestroy(s->ev);
+  for (hipEvent_t e : s->ev)
+    if (e) (void)hipEventDestroy(e);
   if (s->ev_ret) (void)hipEventDestroy(s->ev_ret);
   if (s->st) (void)hipStreamDestroy(s->st);
   delete s;
 }
 
-// Copy x out and free the ranges of the system in `slot` (it is done).
-int retire(sscg_server* s, int slot) {
+// Copy x out and free the ranges of the system in `slot` (it is done; y: its
+// table entry).
+int retire(sscg_server* s, int slot, const BatchSys& y) {
   sscg_ctx* ctx = s->ctx;
   Req& r = s->reqs[s->slot_req[slot]];
-  const BatchSys& y = s->hsys[slot];
   if (y.b2 == 0.0)
     HIPCHK(launch_fill(r.x, r.A.n, 0.0, s->st));
   else
@@ -204,6 +213,7 @@ int admit(sscg_server* s, int64_t id) {
   const int slot = s->free_slots.back();
   s->free_slots.pop_back();
   r.slot = slot;
+  s->adm_at[slot] = s->launched;
   r.row0 = row0;
   r.nz0 = nz0;
   r.nzlen = total;
@@ -317,9 +327,10 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
     return e == hipErrorOutOfMemory ? SSCG_ERR_OOM : SSCG_ERR_HIP;
   };
   hipError_t e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+  for (hipEvent_t& v : s->ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&v, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_ret, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&s->hsys, sizeof(BatchSys) * slots);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->hsys, sizeof(BatchSys) * slots * PIPE);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->hscan, sizeof(int64_t) * 4);
   const std::pair<Buf*, size_t> sizes[] = {
       {&w.width, sizeof(int32_t) * (nslices + 1)}, {&w.off, sizeof(int64_t) * (nslices + 1)},
@@ -344,7 +355,9 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
       {&w.sd_delta, sizeof(int32_t) * SD_DIAG * (size_t)nslices},
       {&w.sd_tab, sizeof(double) * 4 * (size_t)nslices},
       {&w.sd_code, sizeof(uint16_t) * (size_t)N},
-      {&w.sdcnt, sizeof(int32_t) * (size_t)slots}};
+      {&w.sdcnt, sizeof(int32_t) * (size_t)slots},
+      {&w.ablk, sizeof(int32_t) * (size_t)nblk},   {&w.achk, sizeof(int32_t) * (size_t)nchunks},
+      {&w.loff, sizeof(int32_t) * 2 * (size_t)slots}};
   for (const auto& p : sizes)
     if (e == hipSuccess) e = ensure(*p.first, p.second);
   if (e != hipSuccess) return bad(e);
@@ -402,6 +415,11 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   c.bpart = as<double>(w.bpart);
   c.gpart = as<double>(w.gpart);
   c.active = as<int32_t>(w.active);
+  c.ablk = as<int32_t>(w.ablk);
+  c.achk = as<int32_t>(w.achk);
+  c.loff = as<int32_t>(w.loff);
+  c.gblk = nblk;
+  c.gchk = nchunks;
   c.T[0] = as<double2>(w.T);
   c.inv = as<int32_t>(w.inv);
   c.T[1] = c.T[0] + N;
@@ -418,33 +436,18 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   s->M.sd_delta = as<int32_t>(w.sd_delta);
   s->M.sd_tab = as<double>(w.sd_tab);
   s->M.sd_code = as<uint16_t>(w.sd_code);
-  // one outer block over the first g/NG of the pool, captured once per g: a
-  // step replays the smallest one that covers every admitted system (the
-  // allocator is first-fit, so admitted rows stay low), so an idle tail of
-  // the pool costs no empty workgroups
-  for (int g = 0; g < NG; ++g) {
-    const int64_t ext = std::min(rows, ((rows * (g + 1) / NG) + ROW_UNIT - 1) / ROW_UNIT * ROW_UNIT);
-    s->extent[g] = ext;
-    BatchCfg cg = c;
-    cg.nblk = (int)(ext / BATCH_ROWS);
-    cg.nchunks = (int)(ext / ROW_UNIT);
-    DevMat Mg = s->M;
-    Mg.n = (int32_t)ext;
-    Mg.nslices = (int32_t)(ext / SSCG_WAVE);
-    e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return bad(e);
-    rc = batch_enqueue_block(ctx, Mg, cg, s->st);
-    e = hipStreamEndCapture(s->st, &s->graph[g]);
-    if (rc) {
-      server_free(s);
-      return rc;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&s->exec[g], s->graph[g], nullptr, nullptr, 0);
-    if (e != hipSuccess) return bad(e);
+  // one outer block over the whole pool, captured once per grid size (empty
+  // lists: no system yet)
+  e = launch_batch_count(c, s->st);
+  if (e != hipSuccess) return bad(e);
+  if ((rc = s->graphs.capture(ctx, s->M, c, s->st))) {
+    server_free(s);
+    return rc;
   }
   s->ra.init(rows / ROW_UNIT);
   s->na.init(pool_nnz);
   s->slot_req.assign(slots, 0);
+  s->adm_at.assign(slots, 0);
   s->hnew.resize(slots);
   for (int q = slots - 1; q >= 0; --q) s->free_slots.push_back(q);
   *out = s;
@@ -494,21 +497,25 @@ extern "C" int sscg_server_step(sscg_server* s, int32_t* running, int32_t* queue
   int rc = set_device(ctx);
   if (rc) return rc;
   int nret = 0;
-  // systems the last block finished
-  if (s->pending) {
-    HIPCHK(hipEventSynchronize(s->ev));
-    s->pending = false;
+  // systems the oldest replay in flight finished (read once PIPE are in
+  // flight, or when nothing runs any more)
+  if (s->launched - s->seen == PIPE || (s->running == 0 && s->launched > s->seen)) {
+    const int64_t k = s->seen++;
+    HIPCHK(hipEventSynchronize(s->ev[k % PIPE]));
+    const BatchSys* snap = s->hsys + (size_t)(k % PIPE) * s->slots;
     for (int q = 0; q < s->slots; ++q)
-      if (s->slot_req[q] && s->hsys[q].done) {
-        if ((rc = retire(s, q))) return rc;
+      if (s->slot_req[q] && k >= s->adm_at[q] && snap[q].done) {
+        if ((rc = retire(s, q, snap[q]))) return rc;
         ++nret;
       }
     if (nret) HIPCHK(hipEventRecord(s->ev_ret, s->st));
   }
   // first come, first served while the head fits
+  int nadm = 0;
   while (!s->queue.empty()) {
     rc = admit(s, s->queue.front());
     if (rc < 0) return rc;
+    nadm += rc;
     if (rc == 0 && s->running == 0) {  // empty pools and still no room: it never fits
       Req& r = s->reqs[s->queue.front()];
       r.state = 2;
@@ -519,20 +526,19 @@ extern "C" int sscg_server_step(sscg_server* s, int32_t* running, int32_t* queue
     s->queue.pop_front();
   }
   // systems finished at set-up (b = 0 or x_1 converged) are retired by the next step
+  // the lists of the next block take in the admitted systems
+  if (nadm) HIPCHK(launch_batch_count(s->c, s->st));
   if (s->running > 0) {
-    int64_t hi = 0;
+    int64_t act = 0;
     for (int q = 0; q < s->slots; ++q)
-      if (s->slot_req[q]) {
-        const Req& r = s->reqs[s->slot_req[q]];
-        hi = std::max(hi, r.row0 + r.npad);
-      }
-    int g = 0;
-    while (g < NG - 1 && s->extent[g] < hi) ++g;
-    HIPCHK(hipGraphLaunch(s->exec[g], s->st));
-    HIPCHK(hipMemcpyAsync(s->hsys, s->c.sys, sizeof(BatchSys) * s->slots, hipMemcpyDeviceToHost,
-                          s->st));
-    HIPCHK(hipEventRecord(s->ev, s->st));
-    s->pending = true;
+      if (s->slot_req[q]) act += s->reqs[s->slot_req[q]].npad;
+    const int b = (int)(s->launched % PIPE);
+    HIPCHK(hipGraphLaunch(s->graphs.pick(act / BATCH_ROWS, act / ROW_UNIT), s->st));
+    HIPCHK(hipMemcpyAsync(s->hsys + (size_t)b * s->slots, s->c.sys, sizeof(BatchSys) * s->slots,
+                          hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipEventRecord(s->ev[b], s->st));
+    ++s->launched;
+    s->st_rows_active += act;
   }
   // the retired systems' x copies are complete when this returns
   if (nret) HIPCHK(hipEventSynchronize(s->ev_ret));
@@ -554,6 +560,13 @@ extern "C" int sscg_server_poll(sscg_server* s, int64_t id, int32_t* state, int3
   if (blocks) *blocks = r.blocks;
   if (iters) *iters = r.iters;
   if (relres) *relres = r.relres;
+  return SSCG_OK;
+}
+
+extern "C" int sscg_server_stats(sscg_server* s, int64_t* replays, int64_t* rows_active) {
+  if (!s) return SSCG_ERR_ARG;
+  if (replays) *replays = s->launched;
+  if (rows_active) *rows_active = s->st_rows_active;
   return SSCG_OK;
 }
 

@@ -494,59 +494,68 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   if (RES) wg_store_partial(r2, rpart, lb);
 }
 
-// Batched pass j: every 256-row block belongs to one system (blk_sys), whose
-// basis parameters and state come from the system table; blocks of finished
-// systems (or of no system, -1) return at once.  A system flagged sd reads
+// Batched pass j over the 256-row blocks listed in ablk[0, *nlist) (those of
+// the systems not done when the list was made; a workgroup takes every
+// gridDim.x-th entry).  Every block belongs to one system (blk_sys), whose
+// basis parameters and state come from the system table; blocks of systems
+// finished since are skipped.  A system flagged sd reads
 // the slice-diagonal form, one flagged vt the value tables and 16-bit offsets
 // of k_sell_forms_batch, one flagged il the (P, R) pairs.
 template <int NRHS, bool CHEB, bool RES>
 __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, MpkSeq s1,
                                                   const BatchSys* __restrict__ sys,
                                                   const int32_t* __restrict__ blk_sys,
+                                                  const int32_t* __restrict__ ablk,
+                                                  const int32_t* __restrict__ nlist,
                                                   const double* __restrict__ xres,
                                                   const double* __restrict__ bres,
                                                   double* __restrict__ rpart,
                                                   const double2* __restrict__ tg,
                                                   double2* __restrict__ tw) {
-  int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
-  int lb = blockIdx.x;  // natural order, no XCD remap (see xcd_block)
-  if (lb >= nb) return;
-  const int q = blk_sys[lb];
-  if (q < 0 || sys[q].done) return;
-  const bool il = NRHS == 2 && sys[q].il;
-  const BasisPrm bp = sys[q].bp;
-  const double theta = CHEB ? bp.c0 : 0.0, sigma = CHEB ? bp.h2 : 0.0;
-  const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
-  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  dd r2;
-  if (sys[q].sd) {  // slice-diagonal form (stencils)
-    if (j >= 2)
-      r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true>(A, slice, theta, sigma,
-                                                                       gamma, s0, s1, xres, bres);
-    else
-      r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, true>(A, slice, theta, sigma,
-                                                                        gamma, s0, s1, xres, bres);
-  } else if (il) {
-    if (j >= 2)
-      r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
-                                                         xres, bres, tg, tw);
-    else
-      r2 = mpk_slice<NRHS, CHEB, false, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
-                                                          xres, bres, tg, tw);
-  } else if (sys[q].vt) {  // value tables and 16-bit offsets (k_sell_forms_batch)
-    if (j >= 2)
-      r2 = mpk_slice<NRHS, CHEB, CHEB, RES, true, false, true>(A, slice, theta, sigma, gamma, s0,
-                                                               s1, xres, bres);
-    else
-      r2 = mpk_slice<NRHS, CHEB, false, RES, true, false, true>(A, slice, theta, sigma, gamma, s0,
-                                                                s1, xres, bres);
-  } else {
-    if (j >= 2)
-      r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
-    else
-      r2 = mpk_slice<NRHS, CHEB, false, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+  const int nl = *nlist;
+  for (int li = blockIdx.x; li < nl; li += gridDim.x) {  // uniform over the workgroup
+    const int lb = ablk[li];
+    const int q = blk_sys[lb];
+    if (q < 0 || sys[q].done) continue;
+    const bool il = NRHS == 2 && sys[q].il;
+    const BasisPrm bp = sys[q].bp;
+    const double theta = CHEB ? bp.c0 : 0.0, sigma = CHEB ? bp.h2 : 0.0;
+    const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
+    const int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+    dd r2;
+    if (sys[q].sd) {  // slice-diagonal form (stencils)
+      if (j >= 2)
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true>(A, slice, theta, sigma,
+                                                                         gamma, s0, s1, xres, bres);
+      else
+        r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, true>(A, slice, theta, sigma,
+                                                                          gamma, s0, s1, xres,
+                                                                          bres);
+    } else if (il) {
+      if (j >= 2)
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
+                                                           xres, bres, tg, tw);
+      else
+        r2 = mpk_slice<NRHS, CHEB, false, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
+                                                            xres, bres, tg, tw);
+    } else if (sys[q].vt) {  // value tables and 16-bit offsets (k_sell_forms_batch)
+      if (j >= 2)
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, true, false, true>(A, slice, theta, sigma, gamma,
+                                                                 s0, s1, xres, bres);
+      else
+        r2 = mpk_slice<NRHS, CHEB, false, RES, true, false, true>(A, slice, theta, sigma, gamma,
+                                                                  s0, s1, xres, bres);
+    } else {
+      if (j >= 2)
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+      else
+        r2 = mpk_slice<NRHS, CHEB, false, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+    }
+    if (RES) {
+      wg_store_partial(r2, rpart, lb);
+      __syncthreads();  // the partial's LDS is read before the next block rewrites it
+    }
   }
-  if (RES) wg_store_partial(r2, rpart, lb);
 }
 
 // Reduce a per-thread dd over the workgroup and store it as partial `slot`.
@@ -1189,13 +1198,14 @@ hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, 
 }
 
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
-                            const BatchSys* sys, const int32_t* blk_sys, const MpkResidual& res,
+                            const BatchSys* sys, const int32_t* blk_sys, const int32_t* ablk,
+                            const int32_t* nl, int gblk, const MpkResidual& res,
                             const double2* tg, double2* tw, hipStream_t st) {
-  dim3 grid(xcd_grid(wg_count(A.nslices)));
+  dim3 grid(batch_grid(gblk));
   const bool r = res.x != nullptr;
 #define SSCG_MPK_BATCH(N, C, R)                                                                 \
   hipLaunchKernelGGL((k_mpk_batch<N, C, R>), grid, dim3(WG), 0, st, A, j, s0, s1, sys, blk_sys, \
-                     res.x, res.b, res.part, tg, tw)
+                     ablk, nl, res.x, res.b, res.part, tg, tw)
   if (nrhs == 2) {
     if (cheb) { if (r) SSCG_MPK_BATCH(2, true, true); else SSCG_MPK_BATCH(2, true, false); }
     else { if (r) SSCG_MPK_BATCH(2, false, true); else SSCG_MPK_BATCH(2, false, false); }

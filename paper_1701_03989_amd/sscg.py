@@ -156,6 +156,8 @@ EXPORTS = {
                                         _dp]),
     "sscg_server_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _ip,
                                            _ip, _dp, _ip]),
+    "sscg_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]),
     "sscg_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sscg_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
@@ -423,6 +425,13 @@ def sscg_server_history(ctx: int, server: int, rid: int, cap: int = 4096) -> dic
                                           ctypes.byref(rows)))
     k = rows.value
     return dict(s_k=sk[:k].tolist(), s_tilde=st[:k].tolist(), relres_true=rel[:k].tolist())
+
+
+def sscg_server_stats(ctx: int, server: int) -> dict:
+    """Replays launched and the sum over them of the admitted rows."""
+    v = [ctypes.c_int64() for _ in range(2)]
+    _check(ctx, lib().sscg_server_stats(server, *[ctypes.byref(x) for x in v]))
+    return dict(replays=v[0].value, rows_active=v[1].value)
 
 
 def sscg_residual(ctx: int, A: DeviceCsr, b, x, r, out2) -> int:

@@ -109,6 +109,10 @@ def test_server_results_equal_alone(ctx):
         say("server: all at once", [s.kind for s in systems])
         cl.drain()
         cl.check_all()
+        st = sscg.sscg_server_stats(ctx, srv)
+        # every replay ran some admitted rows, at most the pool's
+        assert st["replays"] >= 1
+        assert 0 < st["rows_active"] <= st["replays"] * (1 << 16)
     finally:
         sscg.sscg_server_destroy(srv)
 
