@@ -402,8 +402,12 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
                                    hist=hist)
         assert rc == sscg.OK, f"batch status {rc}"
 
+    # the first call of this batch shape times the launch-shape candidates
+    # (sscg_set_batch_tuning) after its first blocks; later calls reuse the
+    # choice
     for _ in range(warmup):
         batched()
+        tuning = tuning if _ else sscg.sscg_batch_tuning(ctx)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
@@ -411,8 +415,19 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
         ts = time.perf_counter()
         batched()
         lat.append(time.perf_counter() - ts)
+        if warmup == 0 and _ == 0:
+            tuning = sscg.sscg_batch_tuning(ctx)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same timed calls with the untuned default shapes, for the tuner's gain
+    sscg.sscg_set_batch_tuning(ctx, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batched()
+    torch.cuda.synchronize()
+    tuning["default_shapes_solves_per_s"] = len(systems) * steps / (time.perf_counter() - t0)
+    sscg.sscg_set_batch_tuning(ctx, 1)
     # accuracy: true relative residuals recomputed on the host (correctly
     # rounded residual rows and sums)
     worst = 0.0
@@ -462,6 +477,7 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
         "worst_relres": worst,
         "max_blocks": int(blocks.max()),
         "graph_replays": int(hist.res.graph_launches),
+        "tuning": tuning,
         "sequential_solves_per_s": nsys / t_seq,
         "speedup_vs_sequential": (nsys * steps / wall) / (nsys / t_seq),
         "generation_s": t_gen,

@@ -366,6 +366,28 @@ typedef struct {
 int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* batch, const sscg_opts* opts,
                      sscg_batch_result* res);
 
+/* Launch shapes of sscg_batch_solve (a tuner written for this library; no
+ * result bit depends on the shapes, only the time does).  Three shapes are
+ * tuned: the entries of a row whose loads a matrix-powers pass issues
+ * together (2, 4 or 8), the threads of each kappa(G_i) problem (64, 128, 192
+ * or 256; the Jacobi sweeps of Section 4.2's condition numbers) and the
+ * wavefronts per Gram workgroup (1, 2 or 4; one 1024-row group each).
+ * mode 1 (the default): after a batch's first four blocks every candidate of
+ * the next block's first pass, kappa and Gram launches is timed three times
+ * on the live state and the fastest is kept, once per batch shape (total
+ * rows, systems, s_max) and context; later batches of that shape reuse the
+ * choice.  mode 0: use kappa_threads, gram_waves and mpk_chunk as given (0:
+ * 128, 4 and 4).  Either call clears the remembered choices.  SSCG_ERR_ARG
+ * for another mode or shape. */
+int sscg_set_batch_tuning(sscg_ctx* ctx, int mode, int kappa_threads, int gram_waves,
+                          int mpk_chunk);
+/* The shapes the last sscg_batch_solve ran with and, if it timed them, the
+ * fastest of three runs of each candidate in microseconds (kappa_us[4] for
+ * 64, 128, 192, 256 threads; gram_us[3] for 1, 2, 4 wavefronts; mpk_us[3]
+ * for chunks of 2, 4, 8; NaN where not timed).  Any output may be NULL. */
+int sscg_batch_tuning(sscg_ctx* ctx, int32_t* kappa_threads, int32_t* gram_waves,
+                      int32_t* mpk_chunk, double* kappa_us, double* gram_us, double* mpk_us);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A solve server: continuous batching of independent systems on one GPU.

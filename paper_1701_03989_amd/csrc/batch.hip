@@ -28,6 +28,95 @@ namespace {
 
 constexpr int CHUNK_ROWS = 1024;  // rows per Gram work item
 constexpr int GROUP = 4;          // blocks replayed between checks of the active count
+constexpr int KBT_CAND[4] = {64, 128, 192, 256};  // threads per kappa problem
+constexpr int GW_CAND[3] = {1, 2, 4};             // wavefronts per Gram workgroup
+constexpr int MCH_CAND[3] = {2, 4, 8};            // matrix-powers load chunk
+constexpr int TUNE_REPS = 3;                      // timed runs per candidate (the fastest counts)
+
+// The launch shapes of a batch, timed on its live state after its first
+// GROUP blocks: every candidate of the next block's first matrix-powers pass,
+// kappa and Gram launches is run TUNE_REPS times on the current iterates,
+// Gram matrices and basis (their outputs, P_1, R_1, the residual partials,
+// the pairs of pass 2, kappa values and Gram partials, are recomputed by the
+// next block before anything reads them, and no bits depend on the shapes),
+// and the fastest of each is kept in c.  gblk, gchk: the grids the next
+// block will use.
+int tune_shapes(sscg_ctx* ctx, const DevMat& M, BatchCfg& c, int gblk, int gchk,
+                hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    HIPCHK(e);
+  }
+  BatchCfg t = c;
+  t.gblk = gblk;
+  t.gchk = gchk;
+  // pass 1 of the next block, as batch_enqueue_block launches it
+  const int rb = c.S + 1;
+  const MpkSeq sp{batch_col(c, 0), nullptr, batch_col(c, 1)};
+  const MpkSeq sr{batch_col(c, rb), nullptr, batch_col(c, rb + 1)};
+  const MpkResidual res{c.x, c.b, c.rpart};
+  auto pass1 = [&]() {
+    return launch_mpk_batch(M, 1, c.basis == SSCG_BASIS_CHEBYSHEV, c.S >= 2 ? 2 : 1, sp, sr,
+                            c.sys, c.blk_sys, c.ablk, c.active + 1, gblk, t.mch, res, c.T[0],
+                            c.S >= 3 ? c.T[1] : nullptr, st);
+  };
+  auto timed = [&](int what, double* us) -> hipError_t {
+    double best = INFINITY;
+    for (int r = 0; r < TUNE_REPS; ++r) {
+      hipError_t x = hipEventRecord(e0, st);
+      if (x == hipSuccess)
+        x = what == 0 ? pass1() : (what == 1 ? launch_kappa_batch(t, st) : launch_gram_batch(t, st));
+      if (x == hipSuccess) x = hipEventRecord(e1, st);
+      if (x == hipSuccess) x = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+      if (x != hipSuccess) return x;
+      best = std::min(best, 1e3 * (double)ms);
+    }
+    *us = best;
+    return hipSuccess;
+  };
+  e = hipSuccess;
+  int kbt = c.kbt, gw = c.gw, mch = c.mch;
+  double bk = INFINITY, bg = INFINITY, bm = INFINITY;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    t.mch = MCH_CAND[i];
+    e = timed(0, &ctx->last_mpk_us[i]);
+    if (e == hipSuccess && ctx->last_mpk_us[i] < bm) {
+      bm = ctx->last_mpk_us[i];
+      mch = MCH_CAND[i];
+    }
+  }
+  t.mch = mch;
+  if (c.mode == SSCG_MODE_ADAPTIVE)
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      t.kbt = KBT_CAND[i];
+      e = timed(1, &ctx->last_kappa_us[i]);
+      if (e == hipSuccess && ctx->last_kappa_us[i] < bk) {
+        bk = ctx->last_kappa_us[i];
+        kbt = KBT_CAND[i];
+      }
+    }
+  t.kbt = kbt;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    t.gw = GW_CAND[i];
+    e = timed(2, &ctx->last_gram_us[i]);
+    if (e == hipSuccess && ctx->last_gram_us[i] < bg) {
+      bg = ctx->last_gram_us[i];
+      gw = GW_CAND[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(e);
+  c.kbt = kbt;
+  c.gw = gw;
+  c.mch = mch;
+  return SSCG_OK;
+}
 
 }  // namespace
 
@@ -69,10 +158,53 @@ int sscg_host::BlockGraphs::capture(sscg_ctx* ctx, const DevMat& M, const BatchC
   return SSCG_OK;
 }
 
-hipGraphExec_t sscg_host::BlockGraphs::pick(int64_t nb, int64_t nc) const {
+size_t sscg_host::BlockGraphs::pick_index(int64_t nb, int64_t nc) const {
   size_t k = e.size() - 1;
   while (k > 0 && (gblk[k] < nb || gchk[k] < nc)) --k;
-  return e[k];
+  return k;
+}
+
+hipGraphExec_t sscg_host::BlockGraphs::pick(int64_t nb, int64_t nc) const {
+  return e[pick_index(nb, nc)];
+}
+
+extern "C" int sscg_set_batch_tuning(sscg_ctx* ctx, int mode, int kappa_threads, int gram_waves,
+                                     int mpk_chunk) {
+  if (!ctx) return SSCG_ERR_ARG;
+  ctx->err.clear();
+  if (mode != 0 && mode != 1) return fail(ctx, SSCG_ERR_ARG, "tuning mode must be 0 or 1");
+  if (mode == 0) {
+    const int kbt = kappa_threads ? kappa_threads : 128, gw = gram_waves ? gram_waves : 4;
+    if (kbt != 64 && kbt != 128 && kbt != 192 && kbt != 256)
+      return fail(ctx, SSCG_ERR_ARG, "kappa threads must be 64, 128, 192 or 256");
+    if (gw != 1 && gw != 2 && gw != 4)
+      return fail(ctx, SSCG_ERR_ARG, "Gram wavefronts must be 1, 2 or 4");
+    const int mch = mpk_chunk ? mpk_chunk : 4;
+    if (mch != 2 && mch != 4 && mch != 8)
+      return fail(ctx, SSCG_ERR_ARG, "matrix-powers load chunk must be 2, 4 or 8");
+    ctx->fixed_kbt = kbt;
+    ctx->fixed_gw = gw;
+    ctx->fixed_mch = mch;
+  }
+  ctx->tune_mode = mode;
+  ctx->tuned.clear();
+  return SSCG_OK;
+}
+
+extern "C" int sscg_batch_tuning(sscg_ctx* ctx, int32_t* kappa_threads, int32_t* gram_waves,
+                                 int32_t* mpk_chunk, double* kappa_us, double* gram_us,
+                                 double* mpk_us) {
+  if (!ctx) return SSCG_ERR_ARG;
+  if (kappa_threads) *kappa_threads = ctx->last_kbt;
+  if (gram_waves) *gram_waves = ctx->last_gw;
+  if (mpk_chunk) *mpk_chunk = ctx->last_mch;
+  if (mpk_us)
+    for (int i = 0; i < 3; ++i) mpk_us[i] = ctx->last_mpk_us[i];
+  if (kappa_us)
+    for (int i = 0; i < 4; ++i) kappa_us[i] = ctx->last_kappa_us[i];
+  if (gram_us)
+    for (int i = 0; i < 3; ++i) gram_us[i] = ctx->last_gram_us[i];
+  return SSCG_OK;
 }
 
 // One outer block for every unfinished system (enqueued on st; capturable).
@@ -92,7 +224,7 @@ int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCf
     // leave theirs in T[j & 1] when the next pass gathers pairs too
     double2* tw = j + 1 <= c.S - 1 ? c.T[j & 1] : nullptr;
     HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, c.ablk, c.active + 1,
-                            c.gblk, res, c.T[(j - 1) & 1], tw,
+                            c.gblk, c.mch, res, c.T[(j - 1) & 1], tw,
                             st));
     if (j == 1) HIPCHK(launch_batch_res_finalize(c, st));
   }
@@ -309,7 +441,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(launch_sell_forms_batch(M.col, M.val, off, width, 0, nslices, c.blk_sys,
                                  as<int16_t>(w.scol16), as<double>(w.svtab),
                                  as<uint8_t>(w.svidx), vtcnt, st));
-  HIPCHK(launch_set_vt(c.sys, vtcnt, 0, nsys, st));
+  if ((ctx->forms & SSCG_FMT_COL16) && (ctx->forms & SSCG_FMT_VTAB))
+    HIPCHK(launch_set_vt(c.sys, vtcnt, 0, nsys, st));
   M.col16 = as<int16_t>(w.scol16);
   M.vidx = as<uint8_t>(w.svidx);
   M.vtab = as<double>(w.svtab);
@@ -321,14 +454,14 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(ensure(w.sdcnt, sizeof(int32_t) * nsys));
   int32_t* sdcnt = as<int32_t>(w.sdcnt);
   HIPCHK(hipMemsetAsync(sdcnt, 0, sizeof(int32_t) * nsys, st));
-  for (int q = 0; q < nsys; ++q) {
+  for (int q = 0; q < nsys && (ctx->forms & SSCG_FMT_SDIA); ++q) {
     const int npad = (hs[q].blk1 - hs[q].blk0) * BATCH_ROWS;
     HIPCHK(launch_sell_sdia_sys(B->A[q].rowptr, perm + hs[q].row0, hs[q].row0 / SSCG_WAVE,
                                 npad / SSCG_WAVE, M.col, M.val, off, width,
                                 as<int32_t>(w.sd_nd), as<int32_t>(w.sd_delta),
                                 as<double>(w.sd_tab), as<uint16_t>(w.sd_code), sdcnt + q, st));
   }
-  HIPCHK(launch_set_sd(c.sys, sdcnt, 0, nsys, st));
+  if (ctx->forms & SSCG_FMT_SDIA) HIPCHK(launch_set_sd(c.sys, sdcnt, 0, nsys, st));
   M.sd_nd = as<int32_t>(w.sd_nd);
   M.sd_delta = as<int32_t>(w.sd_delta);
   M.sd_tab = as<double>(w.sd_tab);
@@ -344,6 +477,28 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   // ---- one outer block as a graph (grids in steps of 4), replayed; the
   // lists only shrink, so the grids picked after a check cover them until
   // the next one
+  // launch shapes: fixed, a choice made before for this batch shape, or
+  // timed after the first GROUP blocks
+  for (int i = 0; i < 4; ++i) ctx->last_kappa_us[i] = NAN;
+  for (int i = 0; i < 3; ++i) ctx->last_gram_us[i] = ctx->last_mpk_us[i] = NAN;
+  bool tune = false;
+  if (ctx->tune_mode == 0) {
+    c.kbt = ctx->fixed_kbt;
+    c.gw = ctx->fixed_gw;
+    c.mch = ctx->fixed_mch;
+  } else {
+    c.kbt = 128;
+    c.gw = 4;
+    c.mch = 4;
+    tune = true;
+    for (const auto& t : ctx->tuned)
+      if (t.rows == N && t.nsys == nsys && t.S == S) {
+        c.kbt = t.kbt;
+        c.gw = t.gw;
+        c.mch = t.mch;
+        tune = false;
+      }
+  }
   BlockGraphs gg;
   if ((rc = gg.capture(ctx, M, c, st))) return rc;
   // every replay adds >= 1 iteration to each unfinished system or finishes it
@@ -352,6 +507,13 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(hipMemcpyAsync(ctx->hactive, c.active, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   while (ctx->hactive[0] > 0 && launches < limit) {
+    if (tune && launches >= GROUP) {
+      tune = false;
+      const size_t k = gg.pick_index(ctx->hactive[1], ctx->hactive[2]);
+      if ((rc = tune_shapes(ctx, M, c, gg.gblk[k], gg.gchk[k], st))) return rc;
+      ctx->tuned.push_back(sscg_ctx::TuneEntry{N, nsys, S, c.kbt, c.gw, c.mch});
+      if ((rc = gg.capture(ctx, M, c, st))) return rc;
+    }
     const int g = (int)std::min<int64_t>(GROUP, limit - launches);
     hipGraphExec_t ge = gg.pick(ctx->hactive[1], ctx->hactive[2]);
     for (int i = 0; i < g; ++i) HIPCHK(hipGraphLaunch(ge, st));
@@ -360,6 +522,9 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
                           st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  ctx->last_kbt = c.kbt;
+  ctx->last_gw = c.gw;
+  ctx->last_mch = c.mch;
 
   // ---- results
   std::vector<BatchHist> hh((size_t)cap * nsys);

@@ -397,6 +397,9 @@ struct BatchCfg {
   int32_t* loff;              // per system: its first entry in ablk, in achk
   int32_t gblk, gchk;         // grids of the row launches: blocks (one per workgroup) and
                               // chunks (one per wavefront) covered at once
+  int32_t kbt, gw, mch;       // launch shapes (no bits depend on them): threads per kappa
+                              // problem (64, 128, 192, 256), wavefronts per Gram workgroup
+                              // (1, 2, 4), matrix-powers load chunk (2, 4, 8); 0: 128, 4, 4
   double2* T[2];              // (P_j, R_j) pairs for the gathers of pass j + 1 (T[j & 1])
   const int32_t* inv;         // inv[row0 + r]: position of row r of the system (row order)
 };
@@ -478,10 +481,11 @@ hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad,
 // Batched pass j; with two sequences the gathers read the pairs tg and the
 // outputs' pairs go to tw (if not NULL).
 // Batched pass over the blocks listed in ablk[0, *nl) (grid: gblk workgroups
-// striding over the list).
+// striding over the list); chunk: entries of a row whose loads are issued
+// together (2, 4 or 8; no bits depend on it).
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
                             const BatchSys* sys, const int32_t* blk_sys, const int32_t* ablk,
-                            const int32_t* nl, int gblk, const MpkResidual& res,
+                            const int32_t* nl, int gblk, int chunk, const MpkResidual& res,
                             const double2* tg, double2* tw, hipStream_t st);
 // t[i] = (a[i], b[i]), i < n.
 hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, hipStream_t st);

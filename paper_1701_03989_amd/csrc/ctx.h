@@ -89,6 +89,17 @@ struct sscg_ctx {
   sscg_host::Buf sval32, Y32, dx, r64;
   sscg_host::Buf xu, upart;  // equilibrated mixed solves: unscaled iterate, its residual partials
   void* scratch = nullptr;   // device address of the static scratch array on this device
+  // launch-shape tuning of batches (sscg_set_batch_tuning, sscg_batch_tuning)
+  int tune_mode = 1;                 // 1: time the candidates once per batch shape; 0: fixed
+  int fixed_kbt = 128, fixed_gw = 4, fixed_mch = 4;  // the shapes of mode 0
+  struct TuneEntry {
+    int64_t rows;
+    int nsys, S, kbt, gw, mch;
+  };
+  std::vector<TuneEntry> tuned;  // choices per batch shape (rows, systems, s_max)
+  int last_kbt = 0, last_gw = 0, last_mch = 0;  // the shapes the last batch ran with
+  double last_kappa_us[4] = {0, 0, 0, 0};       // its timings (NaN: not timed)
+  double last_gram_us[3] = {0, 0, 0}, last_mpk_us[3] = {0, 0, 0};
 };
 
 namespace sscg_host {
@@ -194,6 +205,7 @@ struct BlockGraphs {
   void clear();
   int capture(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c, hipStream_t st);
   // the smallest grids that cover nb blocks and nc chunks
+  size_t pick_index(int64_t nb, int64_t nc) const;
   hipGraphExec_t pick(int64_t nb, int64_t nc) const;
 };
 

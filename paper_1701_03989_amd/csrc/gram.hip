@@ -156,15 +156,16 @@ struct BatchRow {
 };
 
 // Batched: over the chunks listed in achk, wavefront w of workgroup b takes
-// entries b GW + w, then every gridDim.x GW-th after it; a chunk is one group
-// of the system that owns its rows (rows of the system past its n read as 0).
+// entries b W + w, then every gridDim.x W-th after it (W wavefronts per
+// workgroup: BatchCfg::gw, which changes no bits); a chunk is one group of
+// the system that owns its rows (rows of the system past its n read as 0).
 // The partials go to the chunk's own slot, whatever its place in the list.
-template <int NB>
-__global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
-  __shared__ double lds[GW * GTR * (16 * NB + 1)];
+template <int NB, int W>
+__global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
+  __shared__ double lds[W * GTR * (16 * NB + 1)];
   const int w = threadIdx.x / SSCG_WAVE;
   const int nl = c.active[2];
-  for (int li = blockIdx.x * GW + w; li < nl; li += gridDim.x * GW) {  // whole wavefronts
+  for (int li = blockIdx.x * W + w; li < nl; li += gridDim.x * W) {  // whole wavefronts
     const int ci = c.achk[li];
     const BatchChunk ch = c.chunks[ci];
     const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
@@ -304,12 +305,21 @@ hipError_t launch_gram_finalize(const double* part, int ng, int d, double* G, co
   return hipGetLastError();
 }
 
-hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
-  const dim3 grid((batch_grid(c.gchk) + GW - 1) / GW), block(GW * SSCG_WAVE);
+template <int W>
+void gram_batch_w(const BatchCfg& c, hipStream_t st) {
+  const dim3 grid((batch_grid(c.gchk) + W - 1) / W), block(W * SSCG_WAVE);
   switch (column_blocks(2 * c.S + 1)) {
-    case 1: hipLaunchKernelGGL(k_gram_batch<1>, grid, block, 0, st, c); break;
-    case 2: hipLaunchKernelGGL(k_gram_batch<2>, grid, block, 0, st, c); break;
-    default: hipLaunchKernelGGL(k_gram_batch<3>, grid, block, 0, st, c); break;
+    case 1: hipLaunchKernelGGL((k_gram_batch<1, W>), grid, block, 0, st, c); break;
+    case 2: hipLaunchKernelGGL((k_gram_batch<2, W>), grid, block, 0, st, c); break;
+    default: hipLaunchKernelGGL((k_gram_batch<3, W>), grid, block, 0, st, c); break;
+  }
+}
+
+hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
+  switch (c.gw) {
+    case 1: gram_batch_w<1>(c, st); break;
+    case 2: gram_batch_w<2>(c, st); break;
+    default: gram_batch_w<4>(c, st); break;
   }
   return hipGetLastError();
 }

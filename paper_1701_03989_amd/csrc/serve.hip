@@ -257,17 +257,18 @@ int admit(sscg_server* s, int64_t id) {
                                  as<int64_t>(s->w.off), as<int32_t>(s->w.width), (int)slice0, ns,
                                  as<int32_t>(s->w.blk_sys), as<int16_t>(s->w.scol16),
                                  as<double>(s->w.svtab), as<uint8_t>(s->w.svidx), vtcnt, s->st));
-  HIPCHK(launch_set_vt(c.sys, vtcnt, slot, 1, s->st));
+  if ((ctx->forms & SSCG_FMT_COL16) && (ctx->forms & SSCG_FMT_VTAB))
+    HIPCHK(launch_set_vt(c.sys, vtcnt, slot, 1, s->st));
   // its slice-diagonal form, read (in place of the above and the pairs) if
   // all of its slices fit
   int32_t* sdcnt = as<int32_t>(s->w.sdcnt);
   HIPCHK(hipMemsetAsync(sdcnt + slot, 0, sizeof(int32_t), s->st));
-  HIPCHK(launch_sell_sdia_sys(r.A.rowptr, perm + row0, (int)slice0, ns, as<int32_t>(s->w.scol),
+  if (ctx->forms & SSCG_FMT_SDIA) HIPCHK(launch_sell_sdia_sys(r.A.rowptr, perm + row0, (int)slice0, ns, as<int32_t>(s->w.scol),
                               as<double>(s->w.sval), as<int64_t>(s->w.off),
                               as<int32_t>(s->w.width), as<int32_t>(s->w.sd_nd),
                               as<int32_t>(s->w.sd_delta), as<double>(s->w.sd_tab),
                               as<uint16_t>(s->w.sd_code), sdcnt + slot, s->st));
-  HIPCHK(launch_set_sd(c.sys, sdcnt, slot, 1, s->st));
+  if (ctx->forms & SSCG_FMT_SDIA) HIPCHK(launch_set_sd(c.sys, sdcnt, slot, 1, s->st));
   HIPCHK(hipMemsetAsync(c.hist + (size_t)slot * s->cap, 0, sizeof(BatchHist) * s->cap, s->st));
   // r_1 = b - A x_1 into P_0 over the request's slices, then its set-up
   DevMat V = s->M;

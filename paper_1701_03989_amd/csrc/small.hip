@@ -642,19 +642,16 @@ __global__ void k_batch_plan(BatchCfg c) {
 }
 
 // grid (s_max, systems): kappa(G_i) of system blockIdx.y, i = blockIdx.x + 1, on
-// KBT threads each.
-#ifndef SSCG_KBT
-#define SSCG_KBT 128
-#endif
-constexpr int KBT = SSCG_KBT;
-__global__ __launch_bounds__(KBT) void k_kappa_batch(BatchCfg c) {
+// NT threads each (BatchCfg::kbt; the bits do not depend on NT).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_kappa_batch(BatchCfg c) {
   __shared__ JacobiLds L;
   const int q = blockIdx.y, i = blockIdx.x + 1;
   if (c.sys[q].done) return;
   const sscg_block_params prm = c.prm[q];
   if (!prm.adaptive || i > prm.s) return;
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
-  kappa_body<KBT>(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
+  kappa_body<NT>(L, c.G + (int64_t)q * BATCH_GSZ, d, prm.s, prm.first, i, c.info + q);
 }
 
 // Coordinate solve of system blockIdx.x, then the block's commit.
@@ -728,7 +725,13 @@ hipError_t launch_batch_plan(const BatchCfg& c, hipStream_t st) {
 }
 
 hipError_t launch_kappa_batch(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_kappa_batch, dim3(c.S, c.nsys), dim3(KBT), 0, st, c);
+  const dim3 grid(c.S, c.nsys);
+  switch (c.kbt) {
+    case 64: hipLaunchKernelGGL(k_kappa_batch<64>, grid, dim3(64), 0, st, c); break;
+    case 192: hipLaunchKernelGGL(k_kappa_batch<192>, grid, dim3(192), 0, st, c); break;
+    case 256: hipLaunchKernelGGL(k_kappa_batch<256>, grid, dim3(256), 0, st, c); break;
+    default: hipLaunchKernelGGL(k_kappa_batch<128>, grid, dim3(128), 0, st, c); break;
+  }
   return hipGetLastError();
 }
 

@@ -335,7 +335,7 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 // s1.u[c]), one 16-byte load instead of two 8-byte ones on different cache
 // lines (random gathers), and tw, if given, receives the pairs of the outputs.
 template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false,
-          bool VI = false, bool SD = false>
+          bool VI = false, bool SD = false, int CHK = 4>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeq& s0, const MpkSeq& s1,
                                         const double* __restrict__ xres,
@@ -362,7 +362,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
 #pragma unroll
       for (int i = 0; i < SD_VALS; ++i) tv[i] = A.sd_tab[(int64_t)us * 4 + i];
       const unsigned code = A.sd_code[row];
-      constexpr int CH = 4;
+      constexpr int CH = CHK;  // entries whose loads are in flight together
 #pragma unroll
       for (int k0 = 0; k0 < SD_DIAG; k0 += CH) {
         if (k0 < nd) {
@@ -407,7 +407,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
     }
     // chunks of CH entries: every load of a chunk is issued before its first
     // use (w is uniform over the wave, so the guards do not diverge)
-    constexpr int CH = 4;
+    constexpr int CH = CHK;  // entries whose loads are in flight together
     for (int j0 = 0; j0 < w; j0 += CH) {
       double v[CH], g0[CH], g1[CH], gx[CH];
       int c[CH];
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
 // finished since are skipped.  A system flagged sd reads
 // the slice-diagonal form, one flagged vt the value tables and 16-bit offsets
 // of k_sell_forms_batch, one flagged il the (P, R) pairs.
-template <int NRHS, bool CHEB, bool RES>
+template <int NRHS, bool CHEB, bool RES, int CHK>
 __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, MpkSeq s1,
                                                   const BatchSys* __restrict__ sys,
                                                   const int32_t* __restrict__ blk_sys,
@@ -525,31 +525,31 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
     dd r2;
     if (sys[q].sd) {  // slice-diagonal form (stencils)
       if (j >= 2)
-        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true>(A, slice, theta, sigma,
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true, CHK>(A, slice, theta, sigma,
                                                                          gamma, s0, s1, xres, bres);
       else
-        r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, true>(A, slice, theta, sigma,
+        r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, true, CHK>(A, slice, theta, sigma,
                                                                           gamma, s0, s1, xres,
                                                                           bres);
     } else if (il) {
       if (j >= 2)
-        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, true, false, false, CHK>(A, slice, theta, sigma, gamma, s0, s1,
                                                            xres, bres, tg, tw);
       else
-        r2 = mpk_slice<NRHS, CHEB, false, RES, false, true>(A, slice, theta, sigma, gamma, s0, s1,
+        r2 = mpk_slice<NRHS, CHEB, false, RES, false, true, false, false, CHK>(A, slice, theta, sigma, gamma, s0, s1,
                                                             xres, bres, tg, tw);
     } else if (sys[q].vt) {  // value tables and 16-bit offsets (k_sell_forms_batch)
       if (j >= 2)
-        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, true, false, true>(A, slice, theta, sigma, gamma,
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, true, false, true, false, CHK>(A, slice, theta, sigma, gamma,
                                                                  s0, s1, xres, bres);
       else
-        r2 = mpk_slice<NRHS, CHEB, false, RES, true, false, true>(A, slice, theta, sigma, gamma,
+        r2 = mpk_slice<NRHS, CHEB, false, RES, true, false, true, false, CHK>(A, slice, theta, sigma, gamma,
                                                                   s0, s1, xres, bres);
     } else {
       if (j >= 2)
-        r2 = mpk_slice<NRHS, CHEB, CHEB, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+        r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, false, CHK>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
       else
-        r2 = mpk_slice<NRHS, CHEB, false, RES>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
+        r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, false, CHK>(A, slice, theta, sigma, gamma, s0, s1, xres, bres);
     }
     if (RES) {
       wg_store_partial(r2, rpart, lb);
@@ -1199,13 +1199,22 @@ hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, 
 
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
                             const BatchSys* sys, const int32_t* blk_sys, const int32_t* ablk,
-                            const int32_t* nl, int gblk, const MpkResidual& res,
+                            const int32_t* nl, int gblk, int chunk, const MpkResidual& res,
                             const double2* tg, double2* tw, hipStream_t st) {
   dim3 grid(batch_grid(gblk));
   const bool r = res.x != nullptr;
 #define SSCG_MPK_BATCH(N, C, R)                                                                 \
-  hipLaunchKernelGGL((k_mpk_batch<N, C, R>), grid, dim3(WG), 0, st, A, j, s0, s1, sys, blk_sys, \
-                     ablk, nl, res.x, res.b, res.part, tg, tw)
+  do {                                                                                          \
+    if (chunk == 2)                                                                             \
+      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 2>), grid, dim3(WG), 0, st, A, j, s0, s1, sys,   \
+                         blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);                    \
+    else if (chunk == 8)                                                                        \
+      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 8>), grid, dim3(WG), 0, st, A, j, s0, s1, sys,   \
+                         blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);                    \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 4>), grid, dim3(WG), 0, st, A, j, s0, s1, sys,   \
+                         blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);                    \
+  } while (0)
   if (nrhs == 2) {
     if (cheb) { if (r) SSCG_MPK_BATCH(2, true, true); else SSCG_MPK_BATCH(2, true, false); }
     else { if (r) SSCG_MPK_BATCH(2, false, true); else SSCG_MPK_BATCH(2, false, false); }

@@ -158,6 +158,9 @@ EXPORTS = {
                                            _ip, _dp, _ip]),
     "sscg_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "sscg_set_batch_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int]),
+    "sscg_batch_tuning": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip, _dp, _dp, _dp]),
     "sscg_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sscg_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
@@ -425,6 +428,23 @@ def sscg_server_history(ctx: int, server: int, rid: int, cap: int = 4096) -> dic
                                           ctypes.byref(rows)))
     k = rows.value
     return dict(s_k=sk[:k].tolist(), s_tilde=st[:k].tolist(), relres_true=rel[:k].tolist())
+
+
+def sscg_set_batch_tuning(ctx: int, mode: int, kappa_threads: int = 0, gram_waves: int = 0,
+                          mpk_chunk: int = 0) -> int:
+    return _check(ctx, lib().sscg_set_batch_tuning(ctx, mode, kappa_threads, gram_waves,
+                                                   mpk_chunk))
+
+
+def sscg_batch_tuning(ctx: int) -> dict:
+    """Launch shapes of the last batch and the candidates' timings (us)."""
+    kt, gw, mc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ku, gu, mu = np.zeros(4), np.zeros(3), np.zeros(3)
+    _check(ctx, lib().sscg_batch_tuning(ctx, ctypes.byref(kt), ctypes.byref(gw), ctypes.byref(mc),
+                                        ku.ctypes.data_as(_dp), gu.ctypes.data_as(_dp),
+                                        mu.ctypes.data_as(_dp)))
+    return dict(kappa_threads=kt.value, gram_waves=gw.value, mpk_chunk=mc.value,
+                kappa_us=ku.tolist(), gram_us=gu.tolist(), mpk_us=mu.tolist())
 
 
 def sscg_server_stats(ctx: int, server: int) -> dict:

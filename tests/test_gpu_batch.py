@@ -204,3 +204,50 @@ def test_batch_uneven_rows_match_single_path_and_oracle(ctx):
         ref = sstep.solve(s.A, s.b, np.zeros(s.A.n), oracle_opts(kw, s))
         err = np.linalg.norm(xs[i] - ref.x) / np.linalg.norm(ref.x)
         assert hist.schedule(i) == ref.schedule and err <= 1e-12, (s.kind, err)
+
+
+def test_batch_launch_shapes_give_the_same_bits_and_the_tuner_picks_the_fastest(ctx):
+    """Every launch shape the batch tuner chooses from (threads per kappa
+    problem, wavefronts per Gram workgroup) gives the same bits; the tuner
+    times all of them on the live batch, keeps the fastest, and a second
+    batch of the same shape reuses that choice without timing again."""
+    systems = problems.batch_systems(8, seed=77, nlo=500, nhi=6000)
+    kw = CASES[0]
+
+    def bits(rc, xs, hist):
+        return (rc, [x.tobytes() for x in xs], hist.blocks.tolist(), hist.status.tolist())
+
+    ref = None
+    try:
+        shapes = [(kbt, gw, 4) for kbt in (64, 128, 192, 256) for gw in (1, 2, 4)]
+        shapes += [(128, 4, 2), (128, 4, 8), (64, 1, 8)]
+        for kbt, gw, mch in shapes:
+            sscg.sscg_set_batch_tuning(ctx, 0, kbt, gw, mch)
+            got = bits(*run_batch(ctx, systems, **kw))
+            t = sscg.sscg_batch_tuning(ctx)
+            assert (t["kappa_threads"], t["gram_waves"], t["mpk_chunk"]) == (kbt, gw, mch)
+            assert np.all(np.isnan(t["kappa_us"])) and np.all(np.isnan(t["gram_us"]))
+            if ref is None:
+                ref = got
+                say(f"  blocks {got[2]}")
+            assert got == ref, (kbt, gw, mch)
+        sscg.sscg_set_batch_tuning(ctx, 1)
+        got = bits(*run_batch(ctx, systems, **kw))
+        t = sscg.sscg_batch_tuning(ctx)
+        say(f"  tuned: {t}")
+        assert got == ref
+        assert all(v > 0 for v in t["kappa_us"] + t["gram_us"] + t["mpk_us"])
+        assert t["kappa_threads"] == (64, 128, 192, 256)[int(np.argmin(t["kappa_us"]))]
+        assert t["gram_waves"] == (1, 2, 4)[int(np.argmin(t["gram_us"]))]
+        assert t["mpk_chunk"] == (2, 4, 8)[int(np.argmin(t["mpk_us"]))]
+        got2 = bits(*run_batch(ctx, systems, **kw))
+        t2 = sscg.sscg_batch_tuning(ctx)
+        assert got2 == ref
+        assert (t2["kappa_threads"], t2["gram_waves"], t2["mpk_chunk"]) == \
+            (t["kappa_threads"], t["gram_waves"], t["mpk_chunk"])
+        assert np.all(np.isnan(t2["kappa_us"]))
+        for bad in ((2, 0, 0, 0), (0, 100, 4, 4), (0, 128, 3, 4), (0, 128, 4, 3)):
+            with pytest.raises(sscg.SscgError):
+                sscg.sscg_set_batch_tuning(ctx, *bad)
+    finally:
+        sscg.sscg_set_batch_tuning(ctx, 1)
