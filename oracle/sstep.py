@@ -48,6 +48,19 @@ notes of the repository):
       (Section 5); with s_i = 1/sqrt(D_i): a~_ij = (a_ij s_i) s_j, b~ = s b,
       x~_1 = x_1 / s, x = s x~ at the end.  Tolerance and eps* refer to the
       scaled system.
+  R17 variable precision (Section 6's closing remark, which rearranges eq. fb
+      into a bound eps_k <= eps* / (c kappa(Y_k) max ||r^||) on the unit
+      round-off of outer loop k and leaves the method as future work): with
+      precision='variable' (adaptive mode, constant c), block k >= 1 stores its
+      basis in FP32 when ((2^-24 c) gamma_{k-1}) sqrt(max(rr_{k-1}, 0)) <= eps*
+      (``fp32_block_allowed``): the previous block's gamma stands in for
+      kappa(Y_k), which is not built yet, and the residual norm the block
+      starts from for the maximum over the block.  In such a block every basis
+      column, P_0 = RN32(p) and R_0 = RN32(r) included, is the FP64 block's
+      column computed from the stored columns and rounded once to FP32; the
+      Gram matrix, kappa, the coefficient recurrence and the recovery are the
+      FP64 block's operations on these columns, and eqs. condy and check use
+      eps = 2^-24.  Block 0 is FP64.
 """
 from __future__ import annotations
 
@@ -61,6 +74,7 @@ from .arith import CR, ieee_div, ieee_sqrt
 from .kappa import kappa_spd
 
 EPS = 2.0 ** -53  # R1
+EPS32 = 2.0 ** -24  # R1 for an FP32 basis (R17)
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 
@@ -86,6 +100,7 @@ class Opts:
     kappa_a: Optional[float] = None  # theory mode: kappa(A)
     norm_a: Optional[float] = None  # theory mode: ||A||_2
     n_a: Optional[int] = None  # theory mode: max nonzeros per row (None: from A)
+    precision: str = "fp64"  # 'fp64' | 'variable': FP32 basis in the blocks R17 allows
 
 
 @dataclass
@@ -106,6 +121,7 @@ class Block:
     relres_true: float  # ||b - A x|| / ||b|| after the block
     status: int = OK
     rr_trace: list = field(default_factory=list)  # r'^T G r' after inner iteration j = 1..s_k
+    fp32: bool = False  # basis stored in FP32, eqs. condy and check with 2^-24 (R17)
 
 
 @dataclass
@@ -163,18 +179,41 @@ def poly_next(ar, A, u, w, j, prm):
     return ar.vdiv(num, gamma[j - 1])
 
 
-def krylov_basis(ar, A, p, r, s: int, first: bool, prm):
+def round32(v) -> np.ndarray:
+    """Every entry rounded once to FP32 (IEEE round to nearest even), kept as
+    FP64 values."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def krylov_basis(ar, A, p, r, s: int, first: bool, prm, fp32: bool = False):
     """Columns of Y_{k,s} = [P_{k,s}, R_{k,s}] in the paper's order
-    [P_0..P_s, R_0..R_{s-1}] (eq. cg-krylovbasis); block 0: P only (R4)."""
-    P = [p]
+    [P_0..P_s, R_0..R_{s-1}] (eq. cg-krylovbasis); block 0: P only (R4).
+    fp32 (R17): p, r and every new column are rounded to FP32 as soon as they
+    are formed, so each column is computed from the stored (rounded) ones."""
+    rnd = round32 if fp32 else (lambda v: v)
+    P = [rnd(p)]
     for j in range(1, s + 1):
-        P.append(poly_next(ar, A, P[j - 1], P[j - 2] if j >= 2 else None, j, prm))
+        P.append(rnd(poly_next(ar, A, P[j - 1], P[j - 2] if j >= 2 else None, j, prm)))
     if first:
         return P
-    R = [r]
+    R = [rnd(r)]
     for j in range(1, s):
-        R.append(poly_next(ar, A, R[j - 1], R[j - 2] if j >= 2 else None, j, prm))
+        R.append(rnd(poly_next(ar, A, R[j - 1], R[j - 2] if j >= 2 else None, j, prm)))
     return P + R
+
+
+def fp32_block_allowed(c_smax: float, gamma_prev: float, rr_prev: float,
+                       eps_star: float) -> bool:
+    """R17: Section 6 rearranges eq. fb into a bound on the unit round-off an
+    outer loop may use, eps_k <= eps* / (c kappa(Y_k) max ||r^||).  Block k takes
+    an FP32 basis when that bound admits 2^-24 with the previous block's
+    estimate gamma_{k-1} of kappa(Y) standing in for the basis not yet built
+    and the updated residual norm the block starts from,
+    sqrt(max(r'^T G r', 0)) of block k-1:
+        ((2^-24 c_{k,s_max}) gamma_{k-1}) sqrt(max(rr_{k-1}, 0)) <= eps*,
+    each operation one IEEE rounding in this order."""
+    lhs = ((EPS32 * c_smax) * gamma_prev) * ieee_sqrt(max(rr_prev, 0.0))
+    return lhs <= eps_star
 
 
 def assemble_B(ar, s: int, first: bool, prm):
@@ -342,11 +381,12 @@ def condy_accepts(kappa_i: float, thr: float) -> bool:
     return ieee_sqrt(kappa_i) <= thr
 
 
-def check_breaks(gam: float, eps_star: float, c_j: float, rr1: float) -> bool:
+def check_breaks(gam: float, eps_star: float, c_j: float, rr1: float, eps: float = EPS) -> bool:
     """eq. check after inner iteration j: break when
     gamma >= eps* / (c_{k,j} eps (r'^T G r')^(1/2)), with r' the coordinates
-    after iteration j's update and its quadratic form clamped at 0 (R7, R10)."""
-    rhs = ieee_div(eps_star, (c_j * EPS) * ieee_sqrt(max(rr1, 0.0)))
+    after iteration j's update and its quadratic form clamped at 0 (R7, R10);
+    eps = the unit round-off of the block's basis (R1, R17)."""
+    rhs = ieee_div(eps_star, (c_j * eps) * ieee_sqrt(max(rr1, 0.0)))
     return gam >= rhs
 
 
@@ -408,14 +448,23 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
             res.status = OK
             res.x = x if scale is None else x * scale
             return res
+    if opts.precision not in ("fp64", "variable"):
+        raise ValueError(opts.precision)
+    if opts.precision == "variable" and (opts.mode != "adaptive" or opts.c_mode != "const"
+                                         or ar.exact):
+        raise ValueError("variable precision: adaptive mode, constant c, FP64 arithmetic")
     m = 0
     s_prev = 0
     k = 0
+    gam_prev = rr_prev = math.nan
     while True:
         first = k == 0
         s_bar, s_built = next_s(opts, k, s_prev, m)
         prm = basis_params(opts.basis, s_built, opts.lmin, opts.lmax, ar, opts.shifts)
-        cols = krylov_basis(ar, A, p, r, s_built, first, prm)
+        fp32 = (opts.precision == "variable" and not first
+                and fp32_block_allowed(opts.c, gam_prev, rr_prev, eps_star))
+        ueps = EPS32 if fp32 else EPS
+        cols = krylov_basis(ar, A, p, r, s_built, first, prm, fp32)
         G = ar.gram(cols)
         kappas = []
         gam = math.nan
@@ -433,7 +482,7 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
                 def cfun(j):
                     return opts.c
             c_smax = cfun(opts.s_max)
-            thr = ar.div(eps_star, (c_smax * EPS) * rnorm)  # eq. condy
+            thr = ar.div(eps_star, (c_smax * ueps) * rnorm)  # eq. condy
             imax = s_built
             s_tilde = 1
             for i in range(1, imax + 1):  # R7
@@ -445,8 +494,8 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
                     break
             gam = ar.sqrt(kappas[s_tilde - 1])
             if opts.inner_check:
-                def check(j, rr1, _gam=gam, _c=cfun):
-                    return check_breaks(_gam, eps_star, _c(j), rr1)
+                def check(j, rr1, _gam=gam, _c=cfun, _e=ueps):
+                    return check_breaks(_gam, eps_star, _c(j), rr1, _e)
         else:
             s_tilde = s_built
         idx = sub_indices(s_built, s_tilde, first)
@@ -470,8 +519,9 @@ def solve(A, b, x1, opts: Opts, ar=None, diag=None) -> Result:
                     gamma=gam, thr=thr, rnorm=rnorm, kappas=kappas, alphas=alphas, betas=betas,
                     res_updated=(ar.sqrt(max(rr, 0.0)) if not ar.exact else rr),
                     relres_true=(relres_of(ar, A, b, x, nb) if not ar.exact else math.nan),
-                    status=st, rr_trace=rr_trace)
+                    status=st, rr_trace=rr_trace, fp32=fp32)
         res.blocks.append(blk)
+        gam_prev, rr_prev = gam, rr
         k += 1
         if not ar.exact and blk.relres_true <= opts.tol:
             res.status = OK
