@@ -368,13 +368,16 @@ def cpu_baseline(A, b, x1, wl, gpu_blocks, budget_s=20.0):
     }
 
 
-def run_batch(count: int, steps: int, warmup: int) -> dict:
+def run_batch(count: int, steps: int, warmup: int, precision: str = "fp64") -> dict:
     """The batch workload: uneven SPD systems (half Dirichlet Poisson 2-D/3-D,
     half shifted random graph Laplacians, sizes log-uniform in [1e3, 2e5]),
     adaptive s-step CG with the Chebyshev basis on each system's interval,
     s_max = 8, relres <= 1e-10 each.  A step is one batched solve of all
     systems (sscg_batch_solve); the same systems solved one at a time with
-    sscg_solve are timed beside it (same algorithm, same FP64 results)."""
+    sscg_solve are timed beside it (same algorithm, same FP64 results).  With
+    precision 'variable' the batched solves pick each block's basis precision
+    (FP32 where the rearranged eq. fb admits it); the one-at-a-time baseline
+    stays FP64, and each batched result is compared with it."""
     import torch
 
     from oracle.arith import CR  # host check of the results only (not timed)
@@ -391,7 +394,8 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
     xs = [torch.zeros(s.A.n, dtype=torch.float64, device=dev) for s in systems]
     lmin = [s.lmin for s in systems]
     lmax = [s.lmax for s in systems]
-    opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10,
+                          precision=precision)
     ctx = sscg.sscg_create(0)
     hist = sscg.BatchHistory(len(systems), 4096)
 
@@ -436,7 +440,10 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
         xh = x.cpu().numpy()
         worst = max(worst, float(relres_of(ar, s.A, s.b, xh, ar.sqrt(ar.dot(s.b, s.b)))))
     blocks = hist.blocks.copy()
-    # one at a time (same systems, same options, same results)
+    nfp32 = int(sum(sum(hist.precisions(i)) for i in range(len(systems))))
+    x_batched = [x.clone() for x in xs]
+    # one at a time (FP64: the same systems and options; the same results
+    # as a FP64 batch)
     h1 = sscg.History(4096, 8)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -448,6 +455,8 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
         assert rc == sscg.OK
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
+    err = [float(torch.linalg.norm(xb - x_) / torch.linalg.norm(x_)) for xb, x_ in
+           zip(x_batched, xs)]
     sscg.sscg_destroy(ctx)
     nsys = len(systems)
     rows = sum(s.A.n for s in systems)
@@ -463,7 +472,7 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": f"batch256: {nsys} SPD systems, rows log-uniform [1e3, 2e5] (total {rows}, "
@@ -478,6 +487,10 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
         "max_blocks": int(blocks.max()),
         "graph_replays": int(hist.res.graph_launches),
         "tuning": tuning,
+        "precision": precision,
+        "fp32_blocks": nfp32,
+        "blocks_total": int(blocks.sum()),
+        "max_error_vs_fp64_one_at_a_time": max(err),
         "sequential_solves_per_s": nsys / t_seq,
         "speedup_vs_sequential": (nsys * steps / wall) / (nsys / t_seq),
         "generation_s": t_gen,
@@ -485,7 +498,8 @@ def run_batch(count: int, steps: int, warmup: int) -> dict:
 
 
 def bench_batch(args) -> None:
-    print(json.dumps(run_batch(args.batch_count, args.steps, args.warmup)), flush=True)
+    print(json.dumps(run_batch(args.batch_count, args.steps, args.warmup, args.precision)),
+          flush=True)
 
 
 def bench_precision(args) -> None:
@@ -609,7 +623,8 @@ def bench_serve(args) -> None:
         n = ops[which[i]].A.n
         bs.append(torch.rand(n, dtype=torch.float64, device=dev, generator=gen) * 2.0 - 1.0)
     xs = [torch.zeros_like(b) for b in bs]
-    opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10)
+    opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10,
+                          precision=args.precision)
     ctx = sscg.sscg_create(0)
     rows_needed = sum(((ops[w].A.n + 1023) // 1024) * 1024 for w in which)
     pool_rows = int(min(rows_needed, args.serve_pool_rows))
@@ -650,6 +665,11 @@ def bench_serve(args) -> None:
     makespan = float(np.nanmax(done_at))
     lat = done_at - arrive
     occ = sscg.sscg_server_stats(ctx, srv)
+    nfp32 = nblk = 0
+    for r in rid:
+        h = sscg.sscg_server_history(ctx, srv, r)
+        nfp32 += sum(h["fp32"])
+        nblk += len(h["s_k"])
     sscg.sscg_server_destroy(srv)
     # accuracy of every served result, recomputed in FP64 on the host
     worst = 0.0
@@ -665,7 +685,8 @@ def bench_serve(args) -> None:
             unmet.append({"request": k, "n": s.A.n, "operator": s.kind, "tol": float(tols[k]),
                           "status": int(status[k]), "relres": rel})
     met = int(np.sum(status == sscg.OK))
-    # one at a time, first come first served, with the measured solve times
+    x_served = [x.clone() for x in xs]
+    # one at a time (FP64), first come first served, with the measured solve times
     h1 = sscg.History(8192, 8)
     clock, seq_lat = 0.0, []
     for k in range(nreq):
@@ -677,9 +698,12 @@ def bench_serve(args) -> None:
         ts = time.perf_counter()
         rc = sscg.sscg_solve(ctx, devA[which[k]], bs[k], xs[k], o1, h1)
         d = time.perf_counter() - ts
-        assert rc == status[k], (k, rc, status[k])  # the same bits as served
+        if args.precision == "fp64":
+            assert rc == status[k], (k, rc, status[k])  # the same bits as served
         clock = max(clock, arrive[k]) + d
         seq_lat.append(clock - arrive[k])
+    err = [float(torch.linalg.norm(xv - x_) / torch.linalg.norm(x_)) for xv, x_ in
+           zip(x_served, xs)]
     sscg.sscg_destroy(ctx)
     out = {
         "metric": "served solves/s + p50/p99 latency (arrival to result) at per-request relres",
@@ -692,7 +716,7 @@ def bench_serve(args) -> None:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": f"serve: {nreq} requests, Poisson arrivals {args.serve_rate}/s, "
@@ -705,6 +729,11 @@ def bench_serve(args) -> None:
         "offered_rate": args.serve_rate,
         "replays": occ["replays"],
         "mean_rows_per_replay": occ["rows_active"] / max(occ["replays"], 1),
+        "precision": args.precision,
+        "fp32_blocks": nfp32,
+        "blocks_total": nblk,
+        "max_error_vs_fp64_one_at_a_time": max(err),
+        "median_error_vs_fp64_one_at_a_time": float(np.median(err)),
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "worst_relres_over_tol": worst,
@@ -725,8 +754,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="poisson3d_128",
                     choices=sorted(WORKLOADS) + ["batch256", "serve", "diffusion2048"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
-                    help="mixed: time the mixed-precision solve against plain FP64")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "variable"],
+                    help="mixed: time the mixed-precision solve against plain FP64; variable: "
+                         "the batch256 / serve workloads with the basis precision chosen per "
+                         "outer block, against FP64 one at a time")
     ap.add_argument("--batch-count", type=int, default=256,
                     help="batch256 workload: number of systems")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -786,6 +817,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": x.numel() * 8, "copies": 5}))
         return
+    if args.precision == "variable" and args.workload not in ("batch256", "serve"):
+        print("bench.py: --precision variable applies to the batch256 and serve workloads "
+              "(batches and servers)", file=sys.stderr)
+        sys.exit(2)
     if args.workload == "batch256" and args.gpus == 1:
         bench_batch(args)
         return

@@ -99,8 +99,10 @@ typedef struct {
   double norm_a;         /*   and lambda_max of the spectral estimate              */
   const double* shifts;  /* host; BASIS_NEWTON: s_max shifts theta_0, theta_1, ...;
                             NULL: sscg_newton_shifts(m = s_max, lanczos_seed)     */
-  int32_t precision;    /* SSCG_PREC_FP64, or SSCG_PREC_MIXED (sscg_solve only):
-                            FP64 iterative refinement around FP32-basis solves    */
+  int32_t precision;    /* SSCG_PREC_FP64; SSCG_PREC_MIXED (sscg_solve only): FP64
+                            iterative refinement around FP32-basis solves;
+                            SSCG_PREC_VARIABLE (batches and servers): the basis
+                            precision chosen per outer block                      */
   int32_t max_outer;     /* MIXED: cap on refinement steps (default 30)          */
   double inner_tol;      /* MIXED: each inner solve reduces its residual by this
                             factor (default 1e-5)                                  */
@@ -117,7 +119,21 @@ typedef struct {
  * so the scaled-system reading of Section 5 does not apply to its stopping
  * test).  Supported by sscg_solve only.  The result field `iters` counts
  * inner iterations of all refinement steps, `blocks` their outer blocks. */
-enum { SSCG_PREC_FP64 = 0, SSCG_PREC_MIXED = 1 };
+/* VARIABLE (sscg_batch_solve and servers; adaptive mode, constant c): the
+ * mixed-precision method of Section 6's closing remark, which rearranges the
+ * residual-gap bound eq. fb into eps_k <= eps* / (c kappa(Y_k) max ||r^||), the
+ * largest unit round-off outer loop k may use.  Block k >= 1 stores its basis
+ * in FP32 when ((2^-24 c) gamma_{k-1}) ||r^|| <= eps*, with gamma_{k-1} the
+ * previous block's estimate of kappa(Y) (eq. yhk1) and ||r^|| = (r'^T G r')^(1/2)
+ * the updated residual norm it ended with; block 0 and the others are FP64.
+ * In an FP32 block each basis column (P_0 = RN32(p), R_0 = RN32(r) and every
+ * matrix-powers output) is the FP64 value rounded once to FP32, computed from
+ * the stored FP32 columns with the FP64 matrix; the Gram matrix (exact
+ * products of the widened columns), kappa, the coefficient recurrence and the
+ * recovery of x, r, p stay FP64, and eqs. condy and check use 2^-24.  No
+ * restart: x, r, p carry over between blocks of either precision, and the
+ * stopping test is the FP64 true residual as in Algorithm 4. */
+enum { SSCG_PREC_FP64 = 0, SSCG_PREC_MIXED = 1, SSCG_PREC_VARIABLE = 2 };
 
 /* Per-solve outputs.  The arrays are HOST memory owned by the caller, each
  * with room for `cap` blocks (any may be NULL); entry k describes outer
@@ -359,6 +375,7 @@ typedef struct {
   double* relres_true;    /* [nsys*cap] true relative residual after each block     */
   int32_t graph_launches; /* outer blocks replayed (all systems together)           */
   int32_t rows;           /* rows of the batch layout (each system padded to 256)    */
+  int32_t* fp32;          /* [nsys*cap] 1 where the block's basis was FP32 (VARIABLE) */
 } sscg_batch_result;
 
 /* Returns SSCG_OK when every system converged, else the largest positive
@@ -430,12 +447,13 @@ int sscg_server_step(sscg_server* server, int32_t* running, int32_t* queued, int
 int sscg_server_poll(sscg_server* server, int64_t id, int32_t* state, int32_t* status,
                      int32_t* blocks, int32_t* iters, double* relres);
 /* Per-block history of a finished request (Algorithm 4's s_k schedule, the
- * s~_k of eq. condy and the true relative residual after each block): HOST
+ * s~_k of eq. condy, the true relative residual after each block and, with
+ * SSCG_PREC_VARIABLE, 1 where the block's basis was FP32): HOST
  * arrays of `cap` entries (any may be NULL); *rows gets the number of entries
  * written, min(cap, blocks, the server's history depth max_iters + 2 capped at
  * 4096).  SSCG_ERR_ARG for an unknown request or one that is not done. */
 int sscg_server_history(sscg_server* server, int64_t id, int32_t cap, int32_t* s_k,
-                        int32_t* s_tilde, double* relres_true, int32_t* rows);
+                        int32_t* s_tilde, double* relres_true, int32_t* fp32, int32_t* rows);
 /* Counters since creation (any output may be NULL): outer-block replays
  * launched, and the sum over replays of the admitted systems' rows (each
  * padded to 1024); rows_active / replays is the mean rows per block. */

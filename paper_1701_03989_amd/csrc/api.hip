@@ -469,8 +469,11 @@ int validate_opts(sscg_ctx* ctx, const sscg_opts* o) {
       ((!isnan(o->kappa_a) && !(o->kappa_a >= 1.0 && isfinite(o->kappa_a))) ||
        (!isnan(o->norm_a) && !(o->norm_a > 0.0 && isfinite(o->norm_a)))))
     return fail(ctx, SSCG_ERR_ARG, "theoretical c needs kappa_a >= 1 and norm_a > 0 (or NaN)");
-  if (o->precision < 0 || o->precision > 1)
+  if (o->precision < 0 || o->precision > 2)
     return fail(ctx, SSCG_ERR_ARG, "bad precision %d", o->precision);
+  if (o->precision == SSCG_PREC_VARIABLE &&
+      (o->mode != SSCG_MODE_ADAPTIVE || o->c_mode != SSCG_C_CONST))
+    return fail(ctx, SSCG_ERR_ARG, "variable precision needs the adaptive mode and a constant c");
   if (o->precision == SSCG_PREC_MIXED && (o->max_outer < 1 || !(o->inner_tol > 0.0) ||
                                            !(o->inner_tol < 1.0)))
     return fail(ctx, SSCG_ERR_ARG, "mixed precision needs max_outer >= 1 and 0 < inner_tol < 1");
@@ -571,7 +574,7 @@ void sscg_destroy(sscg_ctx* c) {
                   &w.sys,   &w.prm,  &w.info, &w.G,    &w.coef,    &w.hist,   &w.blk_sys,
                   &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active, &w.perm, &w.inv, &w.T, &w.ilcnt,
                   &w.scol16, &w.svidx, &w.svtab, &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab,
-                  &w.sd_code, &w.sdcnt, &w.ablk, &w.achk, &w.loff};
+                  &w.sd_code, &w.sdcnt, &w.ablk, &w.achk, &w.loff, &w.Y32};
   for (Buf* b : bbufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : c->ev) {

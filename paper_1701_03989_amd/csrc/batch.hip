@@ -58,10 +58,15 @@ int tune_shapes(sscg_ctx* ctx, const DevMat& M, BatchCfg& c, int gblk, int gchk,
   const MpkSeq sp{batch_col(c, 0), nullptr, batch_col(c, 1)};
   const MpkSeq sr{batch_col(c, rb), nullptr, batch_col(c, rb + 1)};
   const MpkResidual res{c.x, c.b, c.rpart};
+  MpkSeq32 fp{nullptr, nullptr, nullptr}, fr{nullptr, nullptr, nullptr};
+  if (c.Y32) {
+    fp = MpkSeq32{c.Y32, nullptr, c.Y32 + c.ld};
+    fr = MpkSeq32{c.Y32 + (int64_t)rb * c.ld, nullptr, c.Y32 + (int64_t)(rb + 1) * c.ld};
+  }
   auto pass1 = [&]() {
-    return launch_mpk_batch(M, 1, c.basis == SSCG_BASIS_CHEBYSHEV, c.S >= 2 ? 2 : 1, sp, sr,
-                            c.sys, c.blk_sys, c.ablk, c.active + 1, gblk, t.mch, res, c.T[0],
-                            c.S >= 3 ? c.T[1] : nullptr, st);
+    return launch_mpk_batch(M, 1, c.basis == SSCG_BASIS_CHEBYSHEV, c.S >= 2 ? 2 : 1, sp, sr, fp,
+                            fr, c.sys, c.blk_sys, c.ablk, c.active + 1, gblk, t.mch, res,
+                            c.T[0], c.S >= 3 ? c.T[1] : nullptr, st);
   };
   auto timed = [&](int what, double* us) -> hipError_t {
     double best = INFINITY;
@@ -211,20 +216,24 @@ extern "C" int sscg_batch_tuning(sscg_ctx* ctx, int32_t* kappa_threads, int32_t*
 int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c,
                                    hipStream_t st) {
   HIPCHK(launch_batch_plan(c, st));
+  if (c.vprec) HIPCHK(launch_batch_cast32(c, st));
   const int cheb = c.basis == SSCG_BASIS_CHEBYSHEV;
+  auto col32 = [&](int col) { return c.Y32 ? c.Y32 + (int64_t)col * c.ld : nullptr; };
   for (int j = 1; j <= c.S; ++j) {
     MpkSeq sp{batch_col(c, j - 1), j >= 2 ? batch_col(c, j - 2) : nullptr, batch_col(c, j)};
     const int rb = c.S + 1;  // R_j at column rb + j
     MpkSeq sr{batch_col(c, rb + j - 1), j >= 2 ? batch_col(c, rb + j - 2) : nullptr,
               batch_col(c, rb + j)};
+    MpkSeq32 fp{col32(j - 1), j >= 2 ? col32(j - 2) : nullptr, col32(j)};
+    MpkSeq32 fr{col32(rb + j - 1), j >= 2 ? col32(rb + j - 2) : nullptr, col32(rb + j)};
     const int nrhs = j <= c.S - 1 ? 2 : 1;
     MpkResidual res{};
     if (j == 1) res = MpkResidual{c.x, c.b, c.rpart};
     // two-sequence passes gather (P_{j-1}, R_{j-1}) pairs from T[(j-1) & 1] and
     // leave theirs in T[j & 1] when the next pass gathers pairs too
     double2* tw = j + 1 <= c.S - 1 ? c.T[j & 1] : nullptr;
-    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, c.sys, c.blk_sys, c.ablk, c.active + 1,
-                            c.gblk, c.mch, res, c.T[(j - 1) & 1], tw,
+    HIPCHK(launch_mpk_batch(M, j, cheb, nrhs, sp, sr, fp, fr, c.sys, c.blk_sys, c.ablk,
+                            c.active + 1, c.gblk, c.mch, res, c.T[(j - 1) & 1], tw,
                             st));
     if (j == 1) HIPCHK(launch_batch_res_finalize(c, st));
   }
@@ -252,8 +261,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   if (o.equilibrate) return fail(ctx, SSCG_ERR_ARG, "batch: equilibration is not supported");
   if (o.basis == SSCG_BASIS_NEWTON || o.c_mode != SSCG_C_CONST)
     return fail(ctx, SSCG_ERR_ARG, "batch: the Newton basis and the theoretical c are not supported");
-  if (o.precision != SSCG_PREC_FP64)
-    return fail(ctx, SSCG_ERR_ARG, "batch: only SSCG_PREC_FP64 is supported");
+  if (o.precision == SSCG_PREC_MIXED)
+    return fail(ctx, SSCG_ERR_ARG, "batch: SSCG_PREC_MIXED is not supported (SSCG_PREC_VARIABLE is)");
   const int nsys = B->nsys;
   const bool cheb = o.basis == SSCG_BASIS_CHEBYSHEV;
   if (cheb && (!B->lambda_min || !B->lambda_max))
@@ -309,6 +318,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   HIPCHK(ensure(w.off, sizeof(int64_t) * (nslices + 1)));
   HIPCHK(ensure(w.flag, sizeof(int32_t) * 4));
   HIPCHK(ensure(w.Y, sizeof(double) * (size_t)N * ncols));
+  const bool vprec = o.precision == SSCG_PREC_VARIABLE;
+  if (vprec) HIPCHK(ensure(w.Y32, sizeof(float) * (size_t)N * ncols));
   HIPCHK(ensure(w.x, sizeof(double) * (size_t)N));
   HIPCHK(ensure(w.b, sizeof(double) * (size_t)N));
   HIPCHK(ensure(w.sys, sizeof(BatchSys) * nsys));
@@ -395,6 +406,8 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
   c.ld = N;
   c.c = o.c;
   c.Y = as<double>(w.Y);
+  c.Y32 = vprec ? as<float>(w.Y32) : nullptr;
+  c.vprec = vprec ? 1 : 0;
   c.x = as<double>(w.x);
   c.b = as<double>(w.b);
   c.sys = as<BatchSys>(w.sys);
@@ -554,6 +567,7 @@ extern "C" int sscg_batch_solve(sscg_ctx* ctx, const sscg_batch* B, const sscg_o
         if (res->s_k) res->s_k[(size_t)q * res->cap + k] = h ? h->s_k : 0;
         if (res->s_tilde) res->s_tilde[(size_t)q * res->cap + k] = h ? h->s_tilde : 0;
         if (res->relres_true) res->relres_true[(size_t)q * res->cap + k] = h ? h->relres_true : NAN;
+        if (res->fp32) res->fp32[(size_t)q * res->cap + k] = h ? h->fp32 : 0;
       }
   }
   HIPCHK(hipStreamSynchronize(st));

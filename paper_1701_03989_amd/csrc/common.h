@@ -207,11 +207,14 @@ hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, c
 
 // One matrix-powers pass: for each of nrhs (1 or 2) sequences v,
 // out = RN(A u - theta u - sigma w) / gamma_{j-1}, j >= 1 (w unused for j = 1).
-struct MpkSeq {
-  const double* u;  // rho_{j-1}(A) v
-  const double* w;  // rho_{j-2}(A) v  (j >= 2, Chebyshev)
-  double* out;      // rho_j(A) v
+template <class V>
+struct MpkSeqV {  // V: the stored type of the sequence (FP64, or FP32 for an FP32 basis)
+  const V* u;  // rho_{j-1}(A) v
+  const V* w;  // rho_{j-2}(A) v  (j >= 2, Chebyshev)
+  V* out;      // rho_j(A) v
 };
+using MpkSeq = MpkSeqV<double>;
+using MpkSeq32 = MpkSeqV<float>;
 // Optional fused true residual of the block's starting iterate (x != NULL):
 // per-workgroup dd partials of sum (b - A x)_i^2 into part.
 struct MpkResidual {
@@ -354,6 +357,7 @@ struct BatchSys {
   int32_t il;          // 1: two-sequence passes gather (P, R) pairs (scattered columns)
   int32_t vt;          // 1: passes read value tables and 16-bit offsets (all slices fit)
   int32_t sd;          // 1: passes read the slice-diagonal form (all slices fit; not il)
+  int32_t p32;         // 1: the current block's basis is FP32 (SSCG_PREC_VARIABLE)
   double tol;          // target relative residual
   double eps_star;     // tol * ||b||
   double b2;           // ||b||^2
@@ -364,6 +368,7 @@ struct BatchSys {
 
 struct BatchHist {  // one committed block of one system
   int32_t s_bar, s_built, s_tilde, s_k;
+  int32_t fp32, pad_;  // 1: its basis was FP32
   double relres_true;  // true relative residual of the iterate after the block
 };
 
@@ -377,6 +382,8 @@ struct BatchCfg {
   int64_t ld;                 // column stride of Y
   double c;                   // c_{k,j}
   double* Y;                  // columns P_0..P_S at 0..S, R_0..R_{S-1} at S+1..2S
+  float* Y32;                 // the same columns of FP32 blocks (SSCG_PREC_VARIABLE), or NULL
+  int32_t vprec;              // 1: each block picks its basis precision (k_batch_plan)
   double* x;                  // iterates, batch layout
   const double* b;
   BatchSys* sys;
@@ -431,6 +438,20 @@ __device__ __forceinline__ BatchCols batch_cols(const BatchCfg& c, int s, int fi
   return BatchCols{c.Y, c.ld, s, c.S};
 }
 
+// The same columns of an FP32 block (Y32, read widened to FP64).
+struct BatchCols32 {
+  const float* Y;
+  int64_t ld;
+  int s, S;
+  __device__ __forceinline__ const float* at(int a) const {
+    return Y + (int64_t)(a <= s ? a : S + 1 + (a - s - 1)) * ld;
+  }
+};
+
+__device__ __forceinline__ BatchCols32 batch_cols32(const BatchCfg& c, int s) {
+  return BatchCols32{c.Y32, c.ld, s, c.S};
+}
+
 hipError_t launch_sell_widths_n(const int32_t* rowptr, int n, int nslices, int32_t* width,
                                 hipStream_t st);
 hipError_t launch_sell_fill_off(const int32_t* rowptr, const int32_t* col, const double* val,
@@ -482,11 +503,15 @@ hipError_t launch_scatter_perm(const double* src, const int32_t* perm, int npad,
 // outputs' pairs go to tw (if not NULL).
 // Batched pass over the blocks listed in ablk[0, *nl) (grid: gblk workgroups
 // striding over the list); chunk: entries of a row whose loads are issued
-// together (2, 4 or 8; no bits depend on it).
+// together (2, 4 or 8; no bits depend on it).  Systems in an FP32 block read
+// and write the Y32 sequences f0, f1 instead of s0, s1.
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
-                            const BatchSys* sys, const int32_t* blk_sys, const int32_t* ablk,
-                            const int32_t* nl, int gblk, int chunk, const MpkResidual& res,
-                            const double2* tg, double2* tw, hipStream_t st);
+                            MpkSeq32 f0, MpkSeq32 f1, const BatchSys* sys,
+                            const int32_t* blk_sys, const int32_t* ablk, const int32_t* nl,
+                            int gblk, int chunk, const MpkResidual& res, const double2* tg,
+                            double2* tw, hipStream_t st);
+// FP32 blocks: P_0 and R_0 (columns 0 and S + 1 of Y) rounded into Y32.
+hipError_t launch_batch_cast32(const BatchCfg& c, hipStream_t st);
 // t[i] = (a[i], b[i]), i < n.
 hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, hipStream_t st);
 // Set-up from the residual of x_1 (rpart) and ||b||^2 (bpart): relres0, eps*;
@@ -512,11 +537,6 @@ hipError_t launch_batch_count(const BatchCfg& c, hipStream_t st);
 //
 // The FP32 basis of an inner solve: P_0..P_s at columns 0..s, R_0..R_{s-1} at
 // columns rcol..rcol+s-1 of a float buffer with column stride ld.
-struct MpkSeq32 {
-  const float* u;  // rho_{j-1}(A) v
-  const float* w;  // rho_{j-2}(A) v (j >= 2, Chebyshev)
-  float* out;      // rho_j(A) v
-};
 struct Cols32 {
   const float* Y;
   int64_t ld;

@@ -30,6 +30,7 @@ T* as(Buf& b) {
 struct BatchWs {
   Buf width, off, scol, sval, flag;  // block-diagonal SELL-64 matrix
   Buf Y, x, b;                       // basis columns, iterates, right-hand sides
+  Buf Y32;                           // FP32 basis columns (SSCG_PREC_VARIABLE)
   Buf sys, prm, info, G, coef, hist, blk_sys, chunks, rpart, bpart, gpart, active;
   Buf perm, inv;                     // row order of every system (position <-> row)
   Buf T;                             // (P_j, R_j) pairs for the gathers (two N-row halves)

@@ -288,11 +288,31 @@ __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
     const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
     const int i = lb * BATCH_ROWS + threadIdx.x;
     stage_coef(c.coef + (int64_t)q * BATCH_CSZ, d, cf);
-    recover_row(batch_cols(c, prm.s, prm.first), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
-                batch_col(c, 0));
+    if (c.sys[q].p32)  // an FP32 block's columns, widened
+      recover_row(batch_cols32(c, prm.s), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
+                  batch_col(c, 0));
+    else
+      recover_row(batch_cols(c, prm.s, prm.first), d, cf, i, c.x, c.x, batch_col(c, c.S + 1),
+                  batch_col(c, 0));
     // the (p, r) pairs the next block's first pass gathers (each thread its own row)
     if (c.sys[q].il) c.T[0][i] = make_double2(batch_col(c, 0)[i], batch_col(c, c.S + 1)[i]);
     __syncthreads();  // cf is read before the next block's system rewrites it
+  }
+}
+
+// FP32 blocks: their P_0 = RN32(p) and R_0 = RN32(r) into Y32, over the
+// listed blocks (the other columns of an FP32 basis are written in FP32 by
+// the passes).
+__global__ __launch_bounds__(WG) void k_batch_cast32(BatchCfg c) {
+  const int nl = c.active[1];
+  for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+    const int lb = c.ablk[li];
+    const int q = c.blk_sys[lb];
+    if (q < 0 || c.sys[q].done || !c.sys[q].p32) continue;
+    const int64_t i = (int64_t)lb * BATCH_ROWS + threadIdx.x;
+    const int64_t r0 = (int64_t)(c.S + 1) * c.ld;
+    c.Y32[i] = (float)c.Y[i];
+    c.Y32[r0 + i] = (float)c.Y[r0 + i];
   }
 }
 
@@ -550,6 +570,11 @@ hipError_t launch_div_vec(const double* w, const double* beta, int n, double* ou
 
 hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st) {
   hipLaunchKernelGGL(k_recover_batch, dim3(batch_grid(c.gblk)), dim3(WG), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_cast32(const BatchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_cast32, dim3(batch_grid(c.gblk)), dim3(WG), 0, st, c);
   return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@
 // time, one row per lane, loaded column by column: each load is 512
 // contiguous bytes); the next tile's loads are in flight while the current
 // one feeds the matrix cores.
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -61,19 +63,39 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
   for (int p = 0; p < NP; ++p) acc[p] = gd4{0.0, 0.0, 0.0, 0.0};
   // columns d..NC-1 of the tile stay 0 (they only feed outputs that are dropped)
   for (int a = d; a < NC; ++a) tile[lane * LD + a] = 0.0;
-  double nx[NC];
+  // the stored type of the columns: FP64, or FP32 (widened at the LDS store)
+  using T = std::remove_cv_t<std::remove_reference_t<decltype(*src.at(0))>>;
+  constexpr bool F32 = std::is_same<T, float>::value;
+  T nx[NC];
+  bool fin = false;  // the fetched row lies before rend
+  // FP32 columns: the loads of a row are unconditional in the lane (a lane
+  // condition would put each in a branch of its own, where the widening
+  // would wait for it): a row past rend reads position 0 and its values are
+  // replaced by 0 only at the LDS store one iteration later, so nothing waits
+  // for a load before that store.  FP64 columns: the select is made at the
+  // load, which measured faster for them.
   auto fetch = [&](int64_t rb) {
     const int64_t row = rb + lane;
     const bool in = row < rend;
     const int64_t pos = in ? map(row) : 0;
+    if constexpr (F32) {
+      fin = in;
 #pragma unroll
-    for (int a = 0; a < NC; ++a) nx[a] = (a < d && in) ? (double)src.at(a)[pos] : 0.0;
+      for (int a = 0; a < NC; ++a)
+        if (a < d) nx[a] = src.at(a)[pos];  // d is uniform over the wavefront
+    } else {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) nx[a] = (a < d && in) ? src.at(a)[pos] : 0.0;
+    }
   };
   fetch(r0);
   for (int t = 0; t < GRAM_GROUP / GTR; ++t) {
 #pragma unroll
     for (int a = 0; a < NC; ++a)
-      if (a < d) tile[lane * LD + a] = nx[a];
+      if (a < d) {
+        if constexpr (F32) tile[lane * LD + a] = fin ? (double)nx[a] : 0.0;
+        else tile[lane * LD + a] = nx[a];
+      }
     // every lane's row is in LDS before any lane reads another's (LDS
     // operations of one wavefront complete in order; this keeps the compiler
     // from moving them across)
@@ -160,7 +182,9 @@ struct BatchRow {
 // workgroup: BatchCfg::gw, which changes no bits); a chunk is one group of
 // the system that owns its rows (rows of the system past its n read as 0).
 // The partials go to the chunk's own slot, whatever its place in the list.
-template <int NB, int W>
+// P32: the launch for the systems in an FP32 block (the others skip them),
+// so that neither column type's code shares the other's registers.
+template <int NB, int W, bool P32>
 __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
   __shared__ double lds[W * GTR * (16 * NB + 1)];
   const int w = threadIdx.x / SSCG_WAVE;
@@ -169,13 +193,18 @@ __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
     const int ci = c.achk[li];
     const BatchChunk ch = c.chunks[ci];
     const int q = c.blk_sys[ch.r0 / BATCH_ROWS];  // the system that owns the chunk's rows now
-    if (q < 0 || c.sys[q].done) continue;
+    if (q < 0 || c.sys[q].done || (c.sys[q].p32 != 0) != P32) continue;
     const sscg_block_params prm = c.prm[q];
     const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
     const int64_t row0 = c.sys[q].row0;
     const int64_t rend = min((int64_t)ch.r1 - row0, (int64_t)c.sys[q].n);  // system-local rows
-    gram_group<NB>(batch_cols(c, prm.s, prm.first), d, ch.r0 - row0, rend, BatchRow{c.inv, row0},
-                   c.gpart, c.nchunks, ci, lds + w * GTR * (16 * NB + 1));
+    if constexpr (P32)  // an FP32 block: its columns widened (exact in FP64)
+      gram_group<NB>(batch_cols32(c, prm.s), d, ch.r0 - row0, rend, BatchRow{c.inv, row0},
+                     c.gpart, c.nchunks, ci, lds + w * GTR * (16 * NB + 1));
+    else
+      gram_group<NB>(batch_cols(c, prm.s, prm.first), d, ch.r0 - row0, rend,
+                     BatchRow{c.inv, row0}, c.gpart, c.nchunks, ci,
+                     lds + w * GTR * (16 * NB + 1));
   }
 }
 
@@ -305,22 +334,28 @@ hipError_t launch_gram_finalize(const double* part, int ng, int d, double* G, co
   return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool P32>
 void gram_batch_w(const BatchCfg& c, hipStream_t st) {
   const dim3 grid((batch_grid(c.gchk) + W - 1) / W), block(W * SSCG_WAVE);
   switch (column_blocks(2 * c.S + 1)) {
-    case 1: hipLaunchKernelGGL((k_gram_batch<1, W>), grid, block, 0, st, c); break;
-    case 2: hipLaunchKernelGGL((k_gram_batch<2, W>), grid, block, 0, st, c); break;
-    default: hipLaunchKernelGGL((k_gram_batch<3, W>), grid, block, 0, st, c); break;
+    case 1: hipLaunchKernelGGL((k_gram_batch<1, W, P32>), grid, block, 0, st, c); break;
+    case 2: hipLaunchKernelGGL((k_gram_batch<2, W, P32>), grid, block, 0, st, c); break;
+    default: hipLaunchKernelGGL((k_gram_batch<3, W, P32>), grid, block, 0, st, c); break;
+  }
+}
+
+template <bool P32>
+void gram_batch_p(const BatchCfg& c, hipStream_t st) {
+  switch (c.gw) {
+    case 1: gram_batch_w<1, P32>(c, st); break;
+    case 2: gram_batch_w<2, P32>(c, st); break;
+    default: gram_batch_w<4, P32>(c, st); break;
   }
 }
 
 hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
-  switch (c.gw) {
-    case 1: gram_batch_w<1>(c, st); break;
-    case 2: gram_batch_w<2>(c, st); break;
-    default: gram_batch_w<4>(c, st); break;
-  }
+  gram_batch_p<false>(c, st);
+  if (c.vprec) gram_batch_p<true>(c, st);
   return hipGetLastError();
 }
 

@@ -129,7 +129,7 @@ void server_free(sscg_server* s) {
                  &w.blk_sys, &w.chunks, &w.rpart, &w.bpart, &w.gpart, &w.active,
                  &w.perm,  &w.inv,  &w.T,    &w.ilcnt, &w.scol16, &w.svidx, &w.svtab,
                  &w.vtcnt, &w.sd_nd, &w.sd_delta, &w.sd_tab, &w.sd_code, &w.sdcnt,
-                 &w.ablk,  &w.achk, &w.loff};
+                 &w.ablk,  &w.achk, &w.loff, &w.Y32};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (s->hsys) (void)hipHostFree(s->hsys);
@@ -303,8 +303,8 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
     return fail(ctx, SSCG_ERR_ARG, "server: MODE_SCHEDULE and equilibration are not supported");
   if (opts->basis == SSCG_BASIS_NEWTON || opts->c_mode != SSCG_C_CONST)
     return fail(ctx, SSCG_ERR_ARG, "server: the Newton basis and the theoretical c are not supported");
-  if (opts->precision != SSCG_PREC_FP64)
-    return fail(ctx, SSCG_ERR_ARG, "server: only SSCG_PREC_FP64 is supported");
+  if (opts->precision == SSCG_PREC_MIXED)
+    return fail(ctx, SSCG_ERR_ARG, "server: SSCG_PREC_MIXED is not supported (SSCG_PREC_VARIABLE is)");
   if (slots < 1 || slots > 65536) return fail(ctx, SSCG_ERR_ARG, "server: bad slot count %d", slots);
   const int64_t rows = (std::max<int64_t>(pool_rows, 1) + ROW_UNIT - 1) / ROW_UNIT * ROW_UNIT;
   if (rows > INT32_MAX / 2) return fail(ctx, SSCG_ERR_ARG, "server: pool_rows too large");
@@ -358,6 +358,7 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
       {&w.sd_code, sizeof(uint16_t) * (size_t)N},
       {&w.sdcnt, sizeof(int32_t) * (size_t)slots},
       {&w.ablk, sizeof(int32_t) * (size_t)nblk},   {&w.achk, sizeof(int32_t) * (size_t)nchunks},
+      {&w.Y32, opts->precision == SSCG_PREC_VARIABLE ? sizeof(float) * (size_t)N * ncols : 0},
       {&w.loff, sizeof(int32_t) * 2 * (size_t)slots}};
   for (const auto& p : sizes)
     if (e == hipSuccess) e = ensure(*p.first, p.second);
@@ -402,6 +403,8 @@ extern "C" int sscg_server_create(sscg_ctx* ctx, const sscg_opts* opts, int64_t 
   c.ld = N;
   c.c = opts->c;
   c.Y = as<double>(w.Y);
+  c.Y32 = opts->precision == SSCG_PREC_VARIABLE ? as<float>(w.Y32) : nullptr;
+  c.vprec = opts->precision == SSCG_PREC_VARIABLE ? 1 : 0;
   c.x = as<double>(w.x);
   c.b = as<double>(w.b);
   c.sys = as<BatchSys>(w.sys);
@@ -572,7 +575,8 @@ extern "C" int sscg_server_stats(sscg_server* s, int64_t* replays, int64_t* rows
 }
 
 extern "C" int sscg_server_history(sscg_server* s, int64_t id, int32_t cap, int32_t* s_k,
-                                   int32_t* s_tilde, double* relres_true, int32_t* rows) {
+                                   int32_t* s_tilde, double* relres_true, int32_t* fp32,
+                                   int32_t* rows) {
   if (!s) return SSCG_ERR_ARG;
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return fail(s->ctx, SSCG_ERR_ARG, "server: unknown request %lld",
@@ -585,6 +589,7 @@ extern "C" int sscg_server_history(sscg_server* s, int64_t id, int32_t cap, int3
     if (s_k) s_k[k] = r.hist[k].s_k;
     if (s_tilde) s_tilde[k] = r.hist[k].s_tilde;
     if (relres_true) relres_true[k] = r.hist[k].relres_true;
+    if (fp32) fp32[k] = r.hist[k].fp32;
   }
   if (rows) *rows = nrec;
   return SSCG_OK;

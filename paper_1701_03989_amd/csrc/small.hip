@@ -16,6 +16,7 @@ namespace {
 constexpr int MAXK = 2 * SSCG_S_LIMIT + 1;  // largest sub-Gram dimension
 constexpr int LDK = MAXK;                  // odd row stride: column walks hit distinct banks
 constexpr double EPS = 0x1p-53;            // unit round-off (Section 5)
+constexpr double EPS32 = 0x1p-24;          // unit round-off of an FP32 basis
 constexpr int MAX_SWEEPS = 40;
 
 // Index of sub-basis column a (of G_i) in the full Gram matrix of s steps.
@@ -626,6 +627,16 @@ __global__ void k_batch_plan(BatchCfg c) {
   }
   s = min(s, c.S);
   sy.s_bar = s_bar;
+  // basis precision of the block (SSCG_PREC_VARIABLE): FP32 when the bound of
+  // eq. fb, rearranged for the unit round-off (Section 6's closing remark),
+  // admits 2^-24 with the previous block's gamma and the updated residual
+  // norm the block starts from; block 0 is FP64
+  sy.p32 = 0;
+  if (c.vprec && !sy.first) {
+    const sscg_block_info& I = c.info[q];
+    const double rr = I.rr < 0.0 ? 0.0 : I.rr;  // NaN stays NaN (then FP64)
+    sy.p32 = ((EPS32 * c.c) * I.gamma) * sqrt(rr) <= sy.eps_star ? 1 : 0;
+  }
   sscg_block_params prm = {};
   prm.s = s;
   prm.first = sy.first;
@@ -637,7 +648,7 @@ __global__ void k_batch_plan(BatchCfg c) {
   prm.lambda_max = sy.lmax;
   prm.eps_star = sy.eps_star;
   prm.c = c.c;
-  prm.unit_roundoff = 0.0;
+  prm.unit_roundoff = sy.p32 ? EPS32 : 0.0;
   c.prm[q] = prm;
 }
 
@@ -673,6 +684,7 @@ __global__ __launch_bounds__(SSCG_WAVE) void k_inner_batch(BatchCfg c) {
       h.s_built = prm.s;
       h.s_tilde = info->s_tilde;
       h.s_k = s_k;
+      h.fp32 = sy.p32;
       h.relres_true = __builtin_nan("");
     }
     if (s_k == 0) {  // no step possible: x stays, the system stops

@@ -58,6 +58,9 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   if ((rc = check_csr(ctx, A))) return rc;
   if (!b || !x) return fail(ctx, SSCG_ERR_ARG, "b and x must not be NULL");
   if (opts->precision == SSCG_PREC_MIXED) return solve_mixed(ctx, A, b, x, *opts, res);
+  if (opts->precision == SSCG_PREC_VARIABLE)
+    return fail(ctx, SSCG_ERR_ARG,
+                "SSCG_PREC_VARIABLE runs in sscg_batch_solve and servers (a batch of one system)");
   const sscg_opts& o = *opts;
   const int n = A->n;
   hipStream_t S1 = ctx->stream, S2 = ctx->side;

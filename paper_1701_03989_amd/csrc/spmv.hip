@@ -335,9 +335,9 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 // s1.u[c]), one 16-byte load instead of two 8-byte ones on different cache
 // lines (random gathers), and tw, if given, receives the pairs of the outputs.
 template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false,
-          bool VI = false, bool SD = false, int CHK = 4>
+          bool VI = false, bool SD = false, int CHK = 4, class V = double>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
-                                        double gamma, const MpkSeq& s0, const MpkSeq& s1,
+                                        double gamma, const MpkSeqV<V>& s0, const MpkSeqV<V>& s1,
                                         const double* __restrict__ xres,
                                         const double* __restrict__ bres,
                                         const double2* __restrict__ tg = nullptr,
@@ -346,8 +346,8 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   int row = slice * SSCG_WAVE + lane;
   dd r2 = dd_zero();
   if (slice < A.nslices) {
-    const double* __restrict__ u0 = s0.u;
-    const double* __restrict__ u1 = s1.u;
+    const V* __restrict__ u0 = s0.u;
+    const V* __restrict__ u1 = s1.u;
     dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
     if constexpr (SD) {
       // slice-diagonal form: distances and values of the slice (wave-uniform,
@@ -465,8 +465,9 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
         o0 = dd_round(a0);
         if (NRHS == 2) o1 = dd_round(a1);
       }
-      s0.out[row] = o0;
-      if (NRHS == 2) s1.out[row] = o1;
+      // an FP32 sequence stores the FP64 result rounded once (V = float)
+      s0.out[row] = (V)o0;
+      if (NRHS == 2) s1.out[row] = (V)o1;
       if (IL && NRHS == 2 && tw) tw[row] = make_double2(o0, o1);
       if (RES) {
         dd_add(ax, -bres[row]);
@@ -503,6 +504,7 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
 // of k_sell_forms_batch, one flagged il the (P, R) pairs.
 template <int NRHS, bool CHEB, bool RES, int CHK>
 __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, MpkSeq s1,
+                                                  MpkSeq32 f0, MpkSeq32 f1,
                                                   const BatchSys* __restrict__ sys,
                                                   const int32_t* __restrict__ blk_sys,
                                                   const int32_t* __restrict__ ablk,
@@ -523,7 +525,30 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
     const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
     const int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
     dd r2;
-    if (sys[q].sd) {  // slice-diagonal form (stencils)
+    if (sys[q].p32) {  // FP32 block: Y32 sequences, column gathers (no pairs)
+      if (sys[q].sd) {
+        if (j >= 2)
+          r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true, CHK, float>(
+              A, slice, theta, sigma, gamma, f0, f1, xres, bres);
+        else
+          r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, true, CHK, float>(
+              A, slice, theta, sigma, gamma, f0, f1, xres, bres);
+      } else if (sys[q].vt) {
+        if (j >= 2)
+          r2 = mpk_slice<NRHS, CHEB, CHEB, RES, true, false, true, false, CHK, float>(
+              A, slice, theta, sigma, gamma, f0, f1, xres, bres);
+        else
+          r2 = mpk_slice<NRHS, CHEB, false, RES, true, false, true, false, CHK, float>(
+              A, slice, theta, sigma, gamma, f0, f1, xres, bres);
+      } else {
+        if (j >= 2)
+          r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, false, CHK, float>(
+              A, slice, theta, sigma, gamma, f0, f1, xres, bres);
+        else
+          r2 = mpk_slice<NRHS, CHEB, false, RES, false, false, false, false, CHK, float>(
+              A, slice, theta, sigma, gamma, f0, f1, xres, bres);
+      }
+    } else if (sys[q].sd) {  // slice-diagonal form (stencils)
       if (j >= 2)
         r2 = mpk_slice<NRHS, CHEB, CHEB, RES, false, false, false, true, CHK>(A, slice, theta, sigma,
                                                                          gamma, s0, s1, xres, bres);
@@ -1198,22 +1223,23 @@ hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, 
 }
 
 hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s0, MpkSeq s1,
-                            const BatchSys* sys, const int32_t* blk_sys, const int32_t* ablk,
-                            const int32_t* nl, int gblk, int chunk, const MpkResidual& res,
-                            const double2* tg, double2* tw, hipStream_t st) {
+                            MpkSeq32 f0, MpkSeq32 f1, const BatchSys* sys,
+                            const int32_t* blk_sys, const int32_t* ablk, const int32_t* nl,
+                            int gblk, int chunk, const MpkResidual& res, const double2* tg,
+                            double2* tw, hipStream_t st) {
   dim3 grid(batch_grid(gblk));
   const bool r = res.x != nullptr;
 #define SSCG_MPK_BATCH(N, C, R)                                                                 \
   do {                                                                                          \
     if (chunk == 2)                                                                             \
-      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 2>), grid, dim3(WG), 0, st, A, j, s0, s1, sys,   \
-                         blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);                    \
+      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 2>), grid, dim3(WG), 0, st, A, j, s0, s1, f0, f1, \
+                         sys, blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);               \
     else if (chunk == 8)                                                                        \
-      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 8>), grid, dim3(WG), 0, st, A, j, s0, s1, sys,   \
-                         blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);                    \
+      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 8>), grid, dim3(WG), 0, st, A, j, s0, s1, f0, f1, \
+                         sys, blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);               \
     else                                                                                        \
-      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 4>), grid, dim3(WG), 0, st, A, j, s0, s1, sys,   \
-                         blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);                    \
+      hipLaunchKernelGGL((k_mpk_batch<N, C, R, 4>), grid, dim3(WG), 0, st, A, j, s0, s1, f0, f1, \
+                         sys, blk_sys, ablk, nl, res.x, res.b, res.part, tg, tw);               \
   } while (0)
   if (nrhs == 2) {
     if (cheb) { if (r) SSCG_MPK_BATCH(2, true, true); else SSCG_MPK_BATCH(2, true, false); }

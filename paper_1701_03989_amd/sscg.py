@@ -23,7 +23,7 @@ MODE_ADAPTIVE, MODE_FIXED, MODE_SCHEDULE = 0, 1, 2
 BASIS_MONOMIAL, BASIS_CHEBYSHEV, BASIS_NEWTON = 0, 1, 2
 FMT_COL16, FMT_VTAB, FMT_SDIA = 1, 2, 4
 C_CONST, C_THEORY = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_VARIABLE = 0, 1, 2
 S_LIMIT = 16
 FAMILIES = {"mpk": 0, "gram": 1, "recover": 2, "small": 3}
 
@@ -76,7 +76,7 @@ class Batch(ctypes.Structure):
 class BatchResult(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int32), ("status", _ip), ("blocks", _ip), ("iters", _ip),
                 ("relres", _dp), ("s_k", _ip), ("s_tilde", _ip), ("relres_true", _dp),
-                ("graph_launches", ctypes.c_int32), ("rows", ctypes.c_int32)]
+                ("graph_launches", ctypes.c_int32), ("rows", ctypes.c_int32), ("fp32", _ip)]
 
 
 class BlockInfo(ctypes.Structure):
@@ -155,7 +155,7 @@ EXPORTS = {
     "sscg_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _ip, _ip, _ip, _ip,
                                         _dp]),
     "sscg_server_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _ip,
-                                           _ip, _dp, _ip]),
+                                           _ip, _dp, _ip, _ip]),
     "sscg_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]),
     "sscg_set_batch_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -331,6 +331,7 @@ class BatchHistory:
         self.s_k = np.zeros(nsys * cap, np.int32)
         self.s_tilde = np.zeros(nsys * cap, np.int32)
         self.relres_true = np.full(nsys * cap, np.nan)
+        self.fp32 = np.zeros(nsys * cap, np.int32)
         r = self.res = BatchResult()
         r.cap = cap
         r.status = self.status.ctypes.data_as(_ip)
@@ -340,9 +341,14 @@ class BatchHistory:
         r.s_k = self.s_k.ctypes.data_as(_ip)
         r.s_tilde = self.s_tilde.ctypes.data_as(_ip)
         r.relres_true = self.relres_true.ctypes.data_as(_dp)
+        r.fp32 = self.fp32.ctypes.data_as(_ip)
 
     def schedule(self, i: int):
         return self.s_k[i * self.cap:i * self.cap + min(int(self.blocks[i]), self.cap)].tolist()
+
+    def precisions(self, i: int):
+        """1 per block whose basis was FP32 (SSCG_PREC_VARIABLE), else 0."""
+        return self.fp32[i * self.cap:i * self.cap + min(int(self.blocks[i]), self.cap)].tolist()
 
 
 def sscg_batch_solve(ctx: int, systems, bs, xs, opts: Opts, tol=None, lambda_min=None,
@@ -418,16 +424,19 @@ def sscg_server_poll(ctx: int, server: int, rid: int) -> dict:
 
 
 def sscg_server_history(ctx: int, server: int, rid: int, cap: int = 4096) -> dict:
-    """Per-block s_k, s~_k and true relative residual of a finished request."""
+    """Per-block s_k, s~_k, true relative residual and basis precision (1: FP32)
+    of a finished request."""
     sk = np.zeros(cap, np.int32)
     st = np.zeros(cap, np.int32)
     rel = np.full(cap, np.nan)
+    f32 = np.zeros(cap, np.int32)
     rows = ctypes.c_int32()
     _check(ctx, lib().sscg_server_history(server, rid, cap, sk.ctypes.data_as(_ip),
                                           st.ctypes.data_as(_ip), rel.ctypes.data_as(_dp),
-                                          ctypes.byref(rows)))
+                                          f32.ctypes.data_as(_ip), ctypes.byref(rows)))
     k = rows.value
-    return dict(s_k=sk[:k].tolist(), s_tilde=st[:k].tolist(), relres_true=rel[:k].tolist())
+    return dict(s_k=sk[:k].tolist(), s_tilde=st[:k].tolist(), relres_true=rel[:k].tolist(),
+                fp32=f32[:k].tolist())
 
 
 def sscg_set_batch_tuning(ctx: int, mode: int, kappa_threads: int = 0, gram_waves: int = 0,
@@ -606,7 +615,7 @@ def make_opts(mode="adaptive", basis="monomial", tol=1e-10, s_max=8, s0_bar=0, f
     o.equilibrate = int(equilibrate)
     o.inner_check = int(inner_check)
     o.max_iters = max_iters
-    o.precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
+    o.precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED, "variable": PREC_VARIABLE}[precision]
     o.max_outer = max_outer
     o.inner_tol = inner_tol
     return o

@@ -251,3 +251,39 @@ def test_batch_launch_shapes_give_the_same_bits_and_the_tuner_picks_the_fastest(
                 sscg.sscg_set_batch_tuning(ctx, *bad)
     finally:
         sscg.sscg_set_batch_tuning(ctx, 1)
+
+
+def test_batch_variable_precision_matches_oracle_and_each_system_alone(ctx):
+    """SSCG_PREC_VARIABLE (reading R17: an FP32 basis in the blocks the
+    rearranged eq. fb admits): every system has the oracle's s_k schedule,
+    s~_k and per-block precision, x within 1e-12, and the same bits alone in
+    a batch of one as in the mix; some blocks are FP32."""
+    systems = problems.batch_systems(6, seed=21, nlo=300, nhi=4000)
+    tols = [1e-6, 1e-8, 1e-10, 1e-12, 1e-10, 1e-8]
+    kw = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10, precision="variable")
+    rc, xs, hist = run_batch(ctx, systems, tols=tols, **kw)
+    n32 = 0
+    for i, s in enumerate(systems):
+        ref = sstep.solve(s.A, s.b, np.zeros(s.A.n), oracle_opts(kw, s, tols[i]))
+        prec = hist.precisions(i)
+        err = np.linalg.norm(xs[i] - ref.x) / np.linalg.norm(ref.x)
+        say(f"  {s.kind} n={s.A.n} tol {tols[i]:g}: precisions {prec}; error vs oracle {err:.1e}")
+        assert hist.status[i] == ref.status
+        assert hist.schedule(i) == ref.schedule
+        assert prec == [int(blk.fp32) for blk in ref.blocks]
+        assert err <= 1e-12
+        n32 += sum(prec)
+        rc1, xs1, h1 = run_batch(ctx, [s], tols=[tols[i]], **kw)
+        assert np.array_equal(xs1[0], xs[i]) and h1.precisions(0) == prec
+    assert n32 > 0
+
+
+def test_variable_precision_rejected_where_unsupported(ctx):
+    s = problems.batch_systems(1, seed=3, nlo=200, nhi=400)[0]
+    with pytest.raises(sscg.SscgError):  # the single solve: a batch of one instead
+        sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b),
+                        dvec(np.zeros(s.A.n)),
+                        sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8,
+                                       lmin=s.lmin, lmax=s.lmax, precision="variable"))
+    with pytest.raises(sscg.SscgError):  # needs the adaptive mode
+        run_batch(ctx, [s], mode="fixed", fixed_s=4, s_max=8, tol=1e-10, precision="variable")

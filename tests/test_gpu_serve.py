@@ -190,3 +190,50 @@ def test_server_refuses_what_never_fits(ctx):
             Client(ctx, srv).submit(s, 1e-10)
     finally:
         sscg.sscg_server_destroy(srv)
+
+
+def test_server_variable_precision_matches_oracle_and_batch_of_one(ctx):
+    """A SSCG_PREC_VARIABLE server: each request has the oracle's schedule,
+    s~_k and per-block basis precision (reading R17), x within 1e-12, and the
+    bits a batch of that one system gives, however the requests arrive."""
+    systems = problems.batch_systems(6, seed=71, nlo=300, nhi=4000)
+    tols = [1e-6, 1e-10, 1e-8, 1e-12, 1e-10, 1e-6]
+    kwv = dict(KW, precision="variable")
+    srv = sscg.sscg_server_create(ctx, sscg.make_opts(**kwv), 1 << 16, 1 << 20, 64)
+    try:
+        cl = Client(ctx, srv)
+        order = iter(range(len(systems)))
+        for burst, steps in ((2, 3), (3, 2), (1, 1)):
+            for _ in range(burst):
+                i = next(order)
+                cl.submit(systems[i], tols[i])
+            for _ in range(steps):
+                cl.step()
+        cl.drain()
+        n32 = 0
+        for rid, (s, tol, _, _, x) in cl.live.items():
+            p = sscg.sscg_server_poll(ctx, srv, rid)
+            h = sscg.sscg_server_history(ctx, srv, rid)
+            ref = sstep.solve(s.A, s.b, np.zeros(s.A.n),
+                              sstep.Opts(**dict(kwv, tol=tol, lmin=s.lmin, lmax=s.lmax)))
+            xh = x.cpu().numpy()
+            err = np.linalg.norm(xh - ref.x) / np.linalg.norm(ref.x)
+            say(f"  request {rid} ({s.kind}, n={s.A.n}, tol {tol:g}): precisions {h['fp32']}; "
+                f"error vs oracle {err:.1e}")
+            assert p["status"] == ref.status
+            assert h["s_k"] == ref.schedule
+            assert h["s_tilde"] == [blk.s_tilde for blk in ref.blocks]
+            assert h["fp32"] == [int(blk.fp32) for blk in ref.blocks]
+            assert err <= 1e-12
+            n32 += sum(h["fp32"])
+            # the same system as a batch of one
+            x1 = dvec(np.zeros(s.A.n))
+            hist = sscg.BatchHistory(1, 1024)
+            rc = sscg.sscg_batch_solve(ctx, [sscg.DeviceCsr.from_host(s.A, DEV)], [dvec(s.b)],
+                                       [x1], sscg.make_opts(**dict(kwv, tol=tol)),
+                                       lambda_min=[s.lmin], lambda_max=[s.lmax], hist=hist)
+            assert rc == p["status"]
+            assert np.array_equal(x1.cpu().numpy(), xh)
+        assert n32 > 0
+    finally:
+        sscg.sscg_server_destroy(srv)
