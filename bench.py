@@ -590,6 +590,10 @@ def bench_precision(args) -> None:
 
 
 def bench_serve(args) -> None:
+    print(json.dumps(run_serve(args, args.precision)), flush=True)
+
+
+def run_serve(args, precision: str) -> dict:
     """The serving workload: requests arrive as a Poisson process (rate
     --serve-rate per second, --serve-requests of them, seeded gaps); each asks
     for one SPD system drawn from a set of --serve-operators operators (sizes
@@ -624,7 +628,7 @@ def bench_serve(args) -> None:
         bs.append(torch.rand(n, dtype=torch.float64, device=dev, generator=gen) * 2.0 - 1.0)
     xs = [torch.zeros_like(b) for b in bs]
     opts = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10,
-                          precision=args.precision)
+                          precision=precision, max_iters=args.serve_max_iters)
     ctx = sscg.sscg_create(0)
     rows_needed = sum(((ops[w].A.n + 1023) // 1024) * 1024 for w in which)
     pool_rows = int(min(rows_needed, args.serve_pool_rows))
@@ -693,12 +697,13 @@ def bench_serve(args) -> None:
         s = ops[which[k]]
         xs[k].zero_()
         o1 = sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8, tol=float(tols[k]),
+                            max_iters=args.serve_max_iters,
                             lmin=s.lmin, lmax=s.lmax)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         rc = sscg.sscg_solve(ctx, devA[which[k]], bs[k], xs[k], o1, h1)
         d = time.perf_counter() - ts
-        if args.precision == "fp64":
+        if precision == "fp64":
             assert rc == status[k], (k, rc, status[k])  # the same bits as served
         clock = max(clock, arrive[k]) + d
         seq_lat.append(clock - arrive[k])
@@ -716,7 +721,7 @@ def bench_serve(args) -> None:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "dtype": "f64" if precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": f"serve: {nreq} requests, Poisson arrivals {args.serve_rate}/s, "
@@ -725,11 +730,12 @@ def bench_serve(args) -> None:
             "method": "continuous batching of adaptive s-step CG (Alg. 4), one outer block per "
                       "step for all admitted systems",
             "basis": "chebyshev", "s_max": 8, "pool_rows": pool_rows, "slots": args.serve_slots,
+            "max_iters": args.serve_max_iters,
         },
         "offered_rate": args.serve_rate,
         "replays": occ["replays"],
         "mean_rows_per_replay": occ["rows_active"] / max(occ["replays"], 1),
-        "precision": args.precision,
+        "precision": precision,
         "fp32_blocks": nfp32,
         "blocks_total": nblk,
         "max_error_vs_fp64_one_at_a_time": max(err),
@@ -744,7 +750,7 @@ def bench_serve(args) -> None:
         "sequential_p99_ms": float(np.percentile(seq_lat, 99) * 1e3),
         "generation_s": t_gen,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -765,6 +771,9 @@ def main():
     ap.add_argument("--serve-operators", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-pool-rows", type=int, default=96 << 20)
+    ap.add_argument("--serve-max-iters", type=int, default=20000,
+                    help="iteration cap of every served and one-at-a-time solve (the largest "
+                         "operator needs about 6900 at tol 1e-12)")
     ap.add_argument("--basis", choices=["chebyshev", "monomial", "newton"], default=None,
                     help="basis of the single-solve workloads (default: the workload's)")
     ap.add_argument("--c-mode", choices=["const", "theory"], default="const",
@@ -987,6 +996,9 @@ def main():
     if not variant and args.workload == "poisson3d_128" and not args.no_extra:
         out["roofline_plain"] = plain_passes()
         out["batch256"] = run_batch(256, 3, 1)
+        # serving with the basis precision chosen per outer block (the mixed
+        # FP32/FP64 path) against FP64 one at a time
+        out["serve"] = run_serve(args, "variable")
     if not args.no_cpu_baseline and not variant:
         out["cpu_baseline"] = cpu_baseline(A, b, x1, wl, hist.blocks, args.cpu_budget)
     print(json.dumps(out), flush=True)
