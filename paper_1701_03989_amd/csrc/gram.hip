@@ -49,14 +49,23 @@ struct SameRow {
 // as 0) of the d columns of src, written to part[q * pstride + slot]; row r
 // is read at position map(r).  tile: this wavefront's GTR x (16 NB + 1)
 // doubles of LDS.  Called by a whole wavefront.
-template <int NB, class Src, class Map>
+//
+// D17 (NB = 2, d = 17: the two-sequence blocks of s = 8): the 17 entries
+// (a, 16) need not take two more 16 x 16 blocks ((0, 1) and (1, 1)): one
+// block with row columns I = (15, 16, zero columns) and column columns
+// J = (0, .., 14, 16) holds them all, (a, 16) for a <= 14 and (16, 16) in its
+// row 16, (15, 16) in its row 15.  Every entry is still the chain of one
+// matrix-core FMA per row over the same rows in the same order, so the bits
+// are those of the general blocking.
+template <int NB, class Src, class Map, bool D17 = false>
 __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, int64_t rend,
                                            const Map& map, double* __restrict__ part,
                                            int64_t pstride, int64_t slot,
                                            double* __restrict__ tile) {
+  static_assert(!D17 || NB == 2, "the 17-column blocking has two column blocks");
   constexpr int NC = 16 * NB;
   constexpr int LD = NC + 1;  // odd row stride: the lanes' rows fall in different banks
-  constexpr int NP = NB * (NB + 1) / 2;
+  constexpr int NP = D17 ? 2 : NB * (NB + 1) / 2;
   const int lane = threadIdx.x & (SSCG_WAVE - 1);
   gd4 acc[NP];
 #pragma unroll
@@ -104,19 +113,30 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (t + 1 < GRAM_GROUP / GTR) fetch(r0 + (int64_t)(t + 1) * GTR);
     const int cc = lane & 15;
+    // D17: this lane's column in the row set I (column NC - 1 is a zero
+    // column of the tile) and in the column set J
+    const int ci = cc == 0 ? 15 : (cc == 1 ? 16 : NC - 1);
+    const int cj = cc < 15 ? cc : 16;
 #pragma unroll
     for (int k4 = 0; k4 < GTR / 4; ++k4) {
       const int rr = 4 * k4 + (lane >> 4);
-      double x[NB];
+      if constexpr (D17) {
+        const double x0 = tile[rr * LD + cc];
+        const double xi = tile[rr * LD + ci], xj = tile[rr * LD + cj];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, xj, acc[1], 0, 0, 0);
+      } else {
+        double x[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) x[b] = tile[rr * LD + 16 * b + cc];
-      int p = 0;
+        for (int b = 0; b < NB; ++b) x[b] = tile[rr * LD + 16 * b + cc];
+        int p = 0;
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
+        for (int i = 0; i < NB; ++i) {
 #pragma unroll
-        for (int j = i; j < NB; ++j) {
-          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], x[j], acc[p], 0, 0, 0);
-          ++p;
+          for (int j = i; j < NB; ++j) {
+            acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], x[j], acc[p], 0, 0, 0);
+            ++p;
+          }
         }
       }
     }
@@ -124,6 +144,20 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if constexpr (D17) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ii = (lane >> 4) + 4 * v, jj = lane & 15;
+      // block (0, 0)
+      if (ii <= jj) part[(int64_t)pair_index(ii, jj, d) * pstride + slot] = acc[0][v];
+      // the I x J block: row 1 is column 16 against J, row 0 column 15
+      // against J[15] = 16; the rest repeats block (0, 0) or is zero
+      const int a = jj < 15 ? jj : 16;
+      if (ii == 1) part[(int64_t)pair_index(a, 16, d) * pstride + slot] = acc[1][v];
+      if (ii == 0 && jj == 15) part[(int64_t)pair_index(15, 16, d) * pstride + slot] = acc[1][v];
+    }
+    return;
   }
   int p = 0;
 #pragma unroll
@@ -141,7 +175,7 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
   }
 }
 
-template <int NB>
+template <int NB, bool D17 = false>
 __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram(ColPtr cols, int n, int d,
                                                          double* __restrict__ part, int ng,
                                                          Gate gate) {
@@ -151,11 +185,11 @@ __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram(ColPtr cols, int n, int
   const int64_t g = (int64_t)blockIdx.x * GW + w;
   if (g >= ng) return;  // whole wavefronts; no workgroup barrier below
   const int64_t r0 = g * GRAM_GROUP;
-  gram_group<NB>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{}, part, ng, g,
-                 lds + w * GTR * (16 * NB + 1));
+  gram_group<NB, ColPtr, SameRow, D17>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
+                                       part, ng, g, lds + w * GTR * (16 * NB + 1));
 }
 
-template <int NB>
+template <int NB, bool D17 = false>
 __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram32(Cols32 cols, int n, int d,
                                                            double* __restrict__ part, int ng) {
   __shared__ double lds[GW * GTR * (16 * NB + 1)];
@@ -163,8 +197,8 @@ __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram32(Cols32 cols, int n, i
   const int64_t g = (int64_t)blockIdx.x * GW + w;
   if (g >= ng) return;
   const int64_t r0 = g * GRAM_GROUP;
-  gram_group<NB>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{}, part, ng, g,
-                 lds + w * GTR * (16 * NB + 1));
+  gram_group<NB, Cols32, SameRow, D17>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
+                                       part, ng, g, lds + w * GTR * (16 * NB + 1));
 }
 
 // A batched system's rows may be stored out of order (sorted by length within
@@ -198,13 +232,25 @@ __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
     const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
     const int64_t row0 = c.sys[q].row0;
     const int64_t rend = min((int64_t)ch.r1 - row0, (int64_t)c.sys[q].n);  // system-local rows
+    double* tile = lds + w * GTR * (16 * NB + 1);
+    // the blocking of the chunk's own d (d is uniform over the wavefront)
+    auto run = [&](const auto& cols) {
+      using S = std::remove_cv_t<std::remove_reference_t<decltype(cols)>>;
+      const BatchRow map{c.inv, row0};
+      if (NB >= 2 && d <= 16)
+        gram_group<1, S, BatchRow>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks, ci,
+                                   tile);
+      else if (NB == 2 && d == 17)
+        gram_group<2, S, BatchRow, true>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks,
+                                         ci, tile);
+      else
+        gram_group<NB, S, BatchRow>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks, ci,
+                                    tile);
+    };
     if constexpr (P32)  // an FP32 block: its columns widened (exact in FP64)
-      gram_group<NB>(batch_cols32(c, prm.s), d, ch.r0 - row0, rend, BatchRow{c.inv, row0},
-                     c.gpart, c.nchunks, ci, lds + w * GTR * (16 * NB + 1));
+      run(batch_cols32(c, prm.s));
     else
-      gram_group<NB>(batch_cols(c, prm.s, prm.first), d, ch.r0 - row0, rend,
-                     BatchRow{c.inv, row0}, c.gpart, c.nchunks, ci,
-                     lds + w * GTR * (16 * NB + 1));
+      run(batch_cols(c, prm.s, prm.first));
   }
 }
 
@@ -310,7 +356,12 @@ hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, Gate g, h
   const dim3 grid((ng + GW - 1) / GW), block(GW * SSCG_WAVE);
   switch (column_blocks(d)) {
     case 1: hipLaunchKernelGGL(k_gram<1>, grid, block, 0, st, cols, n, d, part, ng, g); break;
-    case 2: hipLaunchKernelGGL(k_gram<2>, grid, block, 0, st, cols, n, d, part, ng, g); break;
+    case 2:
+      if (d == 17)
+        hipLaunchKernelGGL((k_gram<2, true>), grid, block, 0, st, cols, n, d, part, ng, g);
+      else
+        hipLaunchKernelGGL((k_gram<2, false>), grid, block, 0, st, cols, n, d, part, ng, g);
+      break;
     default: hipLaunchKernelGGL(k_gram<3>, grid, block, 0, st, cols, n, d, part, ng, g); break;
   }
   return hipGetLastError();
@@ -321,7 +372,12 @@ hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, hipStre
   const dim3 grid((ng + GW - 1) / GW), block(GW * SSCG_WAVE);
   switch (column_blocks(d)) {
     case 1: hipLaunchKernelGGL(k_gram32<1>, grid, block, 0, st, cols, n, d, part, ng); break;
-    case 2: hipLaunchKernelGGL(k_gram32<2>, grid, block, 0, st, cols, n, d, part, ng); break;
+    case 2:
+      if (d == 17)
+        hipLaunchKernelGGL((k_gram32<2, true>), grid, block, 0, st, cols, n, d, part, ng);
+      else
+        hipLaunchKernelGGL((k_gram32<2, false>), grid, block, 0, st, cols, n, d, part, ng);
+      break;
     default: hipLaunchKernelGGL(k_gram32<3>, grid, block, 0, st, cols, n, d, part, ng); break;
   }
   return hipGetLastError();
