@@ -199,6 +199,46 @@ def summarize_trace(d: str, cmd: str) -> None:
     print("wrote", TRACE_SUMMARY)
 
 
+def summarize_trace_batched(d: str, cmd: str, workload: str, out: str | None = None) -> None:
+    """profiles/<workload>.kernel_trace.md from a rocprofv3 --kernel-trace --stats run
+    of bench.py --workload batch256|serve under d: the kernels of the batched
+    blocks (per graph replay) and those of the one-at-a-time baseline."""
+    import csv
+    import glob
+
+    f = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
+    stats = list(csv.DictReader(open(f)))
+    replays = sum(int(r["Calls"]) for r in stats if "k_batch_plan" in r["Name"])
+    batched = [r for r in stats if "_batch" in r["Name"] or "k_batch" in r["Name"]]
+    single = [r for r in stats if r not in batched and ("k_" in r["Name"])]
+    title = {"batch256": "a batch of 256 uneven systems (11.6 M rows; adaptive Chebyshev s_max = "
+                         "8, tol 1e-10), batched and one at a time",
+             "serve": "the serving trace (200 requests, Poisson arrivals 200/s, operators of "
+                      "1e4-4e6 rows, tol 1e-6-1e-12), served and one at a time"}[workload]
+    lines = [f"# Kernel trace: {title}", "",
+             "Command (repo root, MI355X; `cd /tmp && export TMPDIR=/tmp` first, R = repo root):",
+             "", "    " + cmd, "",
+             f"Batched blocks: {replays} graph replays (one outer block for every admitted "
+             f"system each); durations in microseconds:", "",
+             "| kernel | calls | avg us | per replay us | total ms |", "|---|---|---|---|---|"]
+    tot = 0.0
+    for r in sorted(batched, key=lambda r: -float(r["TotalDurationNs"])):
+        t = float(r["TotalDurationNs"])
+        tot += t
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{t / 1e3 / max(replays, 1):.1f} | {t / 1e6:.1f} |")
+    lines += ["", f"Sum per replay: {tot / 1e3 / max(replays, 1):.0f} us.", "",
+              "One-at-a-time baseline (sscg_solve per system), largest totals:", "",
+              "| kernel | calls | avg us | total ms |", "|---|---|---|---|"]
+    for r in sorted(single, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} |")
+    path = out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               f"{workload}.kernel_trace.md")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print("wrote", path)
+
+
 def summarize_trace_plain(d: str, cmd: str) -> None:
     """profiles/<plain trace summary> from a rocprofv3 --kernel-trace --stats run
     of bench.py --plain-passes-only under d."""
@@ -800,6 +840,9 @@ def main():
     ap.add_argument("--summarize-trace-plain", metavar="DIR",
                     help="the kernel-trace summary of the plain-form passes")
     ap.add_argument("--profile-cmd", default="", help="the command(s) to quote in a summary")
+    ap.add_argument("--summarize-trace-batched", metavar="DIR",
+                    help="the kernel-trace summary of --workload batch256|serve")
+    ap.add_argument("--summary-out", default=None, help="where to write that summary")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc, args.profile_cmd)
@@ -812,6 +855,10 @@ def main():
         return
     if args.summarize_trace_plain:
         summarize_trace_plain(args.summarize_trace_plain, args.profile_cmd)
+        return
+    if args.summarize_trace_batched:
+        summarize_trace_batched(args.summarize_trace_batched, args.profile_cmd, args.workload,
+                                args.summary_out)
         return
     if args.plain_passes_only:
         plain_passes(reps=args.steps, only=True)

@@ -101,8 +101,8 @@ typedef struct {
                             NULL: sscg_newton_shifts(m = s_max, lanczos_seed)     */
   int32_t precision;    /* SSCG_PREC_FP64; SSCG_PREC_MIXED (sscg_solve only): FP64
                             iterative refinement around FP32-basis solves;
-                            SSCG_PREC_VARIABLE (batches and servers): the basis
-                            precision chosen per outer block                      */
+                            SSCG_PREC_VARIABLE: the basis precision chosen per
+                            outer block                                          */
   int32_t max_outer;     /* MIXED: cap on refinement steps (default 30)          */
   double inner_tol;      /* MIXED: each inner solve reduces its residual by this
                             factor (default 1e-5)                                  */
@@ -119,7 +119,9 @@ typedef struct {
  * so the scaled-system reading of Section 5 does not apply to its stopping
  * test).  Supported by sscg_solve only.  The result field `iters` counts
  * inner iterations of all refinement steps, `blocks` their outer blocks. */
-/* VARIABLE (sscg_batch_solve and servers; adaptive mode, constant c): the
+/* VARIABLE (batches, servers, and sscg_solve as a batch of one system with no
+ * equilibration, whose history then leaves s_bar, s_built, gamma, thr,
+ * res_updated and kappa unset; adaptive mode, constant c): the
  * mixed-precision method of Section 6's closing remark, which rearranges the
  * residual-gap bound eq. fb into eps_k <= eps* / (c kappa(Y_k) max ||r^||), the
  * largest unit round-off outer loop k may use.  Block k >= 1 stores its basis
@@ -161,6 +163,7 @@ typedef struct {
   int32_t spec_blocks;   /* blocks run ahead speculatively (s_k = s assumed while
                             the exact s~/break decisions ran alongside)           */
   int32_t spec_rejected; /* of those, blocks redone because the decisions differed */
+  int32_t* fp32;         /* 1 where the block's basis was FP32 (SSCG_PREC_VARIABLE)  */
 } sscg_result;
 
 /* Device-side record of one block's coordinate solve (sscg_small_solve). */

@@ -156,6 +156,9 @@ struct MethodSetup {
   }
 };
 int method_setup(sscg_ctx* ctx, const DevMat& M, const sscg_opts& o, MethodSetup* ms);
+// sscg_solve with SSCG_PREC_VARIABLE (a batch of one system).
+int solve_variable(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x,
+                   const sscg_opts& o, sscg_result* res);
 // m Newton shifts (host output) from an m-step Lanczos run on M.
 int newton_shifts_dev(sscg_ctx* ctx, const DevMat& M, int m, uint64_t seed, double* shifts);
 // Most nonzeros in a row of M (from the SELL widths).

@@ -48,6 +48,76 @@ struct Pending {
 
 }  // namespace
 
+// SSCG_PREC_VARIABLE: the blocks pick their basis precision on the device
+// (the batched path's plan), so the solve runs as a batch of one system; the
+// Chebyshev interval is estimated first when not given.  The per-block
+// outputs the batched path does not record (s_bar, s_built, gamma, thr,
+// res_updated, kappa) are NaN / 0.
+int sscg_host::solve_variable(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x,
+                              const sscg_opts& o, sscg_result* res) {
+  if (o.equilibrate)
+    return fail(ctx, SSCG_ERR_ARG, "variable precision: equilibration is not supported");
+  double lmin = o.lambda_min, lmax = o.lambda_max;
+  if (o.basis == SSCG_BASIS_CHEBYSHEV && !(lmax > lmin)) {
+    DevMat M;
+    int rc = build_mat(ctx, A, 0, &M);
+    if (rc) return rc;
+    MethodSetup ms;
+    if ((rc = method_setup(ctx, M, o, &ms))) return rc;
+    lmin = ms.lmin;
+    lmax = ms.lmax;
+  }
+  const double* bs[1] = {b};
+  double* xs[1] = {x};
+  sscg_batch B;
+  memset(&B, 0, sizeof B);
+  B.nsys = 1;
+  B.A = A;
+  B.b = bs;
+  B.x = xs;
+  B.lambda_min = &lmin;
+  B.lambda_max = &lmax;
+  int32_t st = 0, bl = 0, it = 0;
+  double rel = NAN;
+  sscg_batch_result br;
+  memset(&br, 0, sizeof br);
+  br.cap = res ? res->cap : 0;
+  br.status = &st;
+  br.blocks = &bl;
+  br.iters = &it;
+  br.relres = &rel;
+  if (res) {
+    br.s_k = res->s_k;
+    br.s_tilde = res->s_tilde;
+    br.relres_true = res->relres_true;
+    br.fp32 = res->fp32;
+  }
+  const int rc = sscg_batch_solve(ctx, &B, &o, &br);
+  if (rc < 0) return rc;
+  if (res) {
+    sscg_result& R = *res;
+    R.blocks = bl;
+    R.iters = it;
+    R.status = st;
+    R.relres0 = NAN;
+    R.relres = rel;
+    R.lambda_min = lmin;
+    R.lambda_max = lmax;
+    R.basis_vectors = R.wasted_vectors = 0;
+    R.spec_blocks = R.spec_rejected = 0;
+    for (int k = 0; k < std::min(R.cap, bl); ++k) {
+      if (R.s_bar) R.s_bar[k] = 0;
+      if (R.s_built) R.s_built[k] = 0;
+      if (R.gamma) R.gamma[k] = NAN;
+      if (R.thr) R.thr[k] = NAN;
+      if (R.res_updated) R.res_updated[k] = NAN;
+      if (R.kappa)
+        for (int i = 0; i < o.s_max; ++i) R.kappa[(int64_t)k * o.s_max + i] = NAN;
+    }
+  }
+  return st;
+}
+
 extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, double* x,
                           const sscg_opts* opts, sscg_result* res) {
   if (!ctx) return SSCG_ERR_ARG;
@@ -58,9 +128,7 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
   if ((rc = check_csr(ctx, A))) return rc;
   if (!b || !x) return fail(ctx, SSCG_ERR_ARG, "b and x must not be NULL");
   if (opts->precision == SSCG_PREC_MIXED) return solve_mixed(ctx, A, b, x, *opts, res);
-  if (opts->precision == SSCG_PREC_VARIABLE)
-    return fail(ctx, SSCG_ERR_ARG,
-                "SSCG_PREC_VARIABLE runs in sscg_batch_solve and servers (a batch of one system)");
+  if (opts->precision == SSCG_PREC_VARIABLE) return solve_variable(ctx, A, b, x, *opts, res);
   const sscg_opts& o = *opts;
   const int n = A->n;
   hipStream_t S1 = ctx->stream, S2 = ctx->side;

@@ -64,7 +64,8 @@ class Result(ctypes.Structure):
                 ("wasted_vectors", ctypes.c_int64), ("s_bar", _ip), ("s_built", _ip),
                 ("s_tilde", _ip), ("s_k", _ip), ("gamma", _dp), ("thr", _dp),
                 ("res_updated", _dp), ("relres_true", _dp), ("kappa", _dp),
-                ("spec_blocks", ctypes.c_int32), ("spec_rejected", ctypes.c_int32)]
+                ("spec_blocks", ctypes.c_int32), ("spec_rejected", ctypes.c_int32),
+                ("fp32", _ip)]
 
 
 class Batch(ctypes.Structure):
@@ -281,6 +282,7 @@ class History:
         self.res_updated = np.full(cap, np.nan)
         self.relres_true = np.full(cap, np.nan)
         self.kappa = np.full(cap * s_max, np.nan)
+        self.fp32 = np.zeros(cap, np.int32)
         self.res = Result()
         r = self.res
         r.cap = cap
@@ -293,6 +295,7 @@ class History:
         r.res_updated = self.res_updated.ctypes.data_as(_dp)
         r.relres_true = self.relres_true.ctypes.data_as(_dp)
         r.kappa = self.kappa.ctypes.data_as(_dp)
+        r.fp32 = self.fp32.ctypes.data_as(_ip)
 
     @property
     def blocks(self):

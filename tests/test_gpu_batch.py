@@ -278,12 +278,32 @@ def test_batch_variable_precision_matches_oracle_and_each_system_alone(ctx):
     assert n32 > 0
 
 
-def test_variable_precision_rejected_where_unsupported(ctx):
-    s = problems.batch_systems(1, seed=3, nlo=200, nhi=400)[0]
-    with pytest.raises(sscg.SscgError):  # the single solve: a batch of one instead
-        sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b),
-                        dvec(np.zeros(s.A.n)),
-                        sscg.make_opts(mode="adaptive", basis="chebyshev", s_max=8,
-                                       lmin=s.lmin, lmax=s.lmax, precision="variable"))
+def test_single_solve_variable_precision_is_the_batch_of_one(ctx):
+    """sscg_solve with SSCG_PREC_VARIABLE runs as a batch of one: the same bits,
+    schedule and per-block precisions as sscg_batch_solve on that system with
+    the same interval; with the interval estimated on the device it reaches
+    the tolerance; unsupported combinations are refused."""
+    s = problems.batch_systems(1, seed=3, nlo=2000, nhi=4000)[0]
+    kw = dict(mode="adaptive", basis="chebyshev", s_max=8, tol=1e-10, precision="variable")
+    x = dvec(np.zeros(s.A.n))
+    h = sscg.History(1024, 8)
+    rc = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b), x,
+                         sscg.make_opts(**dict(kw, lmin=s.lmin, lmax=s.lmax)), h)
+    rcb, xs, hist = run_batch(ctx, [s], **kw)
+    say(f"  {s.kind} n={s.A.n}: precisions {h.fp32[:h.blocks].tolist()}")
+    assert rc == rcb and h.blocks == int(hist.blocks[0])
+    assert np.array_equal(x.cpu().numpy(), xs[0])
+    assert h.schedule == hist.schedule(0)
+    assert h.fp32[:h.blocks].tolist() == hist.precisions(0) and sum(hist.precisions(0)) > 0
+    h2 = sscg.History(1024, 8)
+    x.zero_()
+    rc2 = sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b), x,
+                          sscg.make_opts(**kw), h2)
+    xh = x.cpu().numpy()
+    assert rc2 == sscg.OK and h2.res.lambda_max > h2.res.lambda_min > 0
+    assert np.linalg.norm(s.b - s.A.matvec(xh)) <= 1e-10 * np.linalg.norm(s.b) * (1 + 1e-6)
     with pytest.raises(sscg.SscgError):  # needs the adaptive mode
         run_batch(ctx, [s], mode="fixed", fixed_s=4, s_max=8, tol=1e-10, precision="variable")
+    with pytest.raises(sscg.SscgError):  # no equilibration
+        sscg.sscg_solve(ctx, sscg.DeviceCsr.from_host(s.A, DEV), dvec(s.b), x,
+                        sscg.make_opts(**dict(kw, lmin=s.lmin, lmax=s.lmax, equilibrate=True)))
