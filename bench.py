@@ -199,7 +199,8 @@ def summarize_trace(d: str, cmd: str) -> None:
     print("wrote", TRACE_SUMMARY)
 
 
-def summarize_trace_batched(d: str, cmd: str, workload: str, out: str | None = None) -> None:
+def summarize_trace_batched(d: str, cmd: str, workload: str, out: str | None = None,
+                            precision: str = "fp64") -> None:
     """profiles/<workload>.kernel_trace.md from a rocprofv3 --kernel-trace --stats run
     of bench.py --workload batch256|serve under d: the kernels of the batched
     blocks (per graph replay) and those of the one-at-a-time baseline."""
@@ -215,6 +216,8 @@ def summarize_trace_batched(d: str, cmd: str, workload: str, out: str | None = N
                          "8, tol 1e-10), batched and one at a time",
              "serve": "the serving trace (200 requests, Poisson arrivals 200/s, operators of "
                       "1e4-4e6 rows, tol 1e-6-1e-12), served and one at a time"}[workload]
+    if precision == "variable":
+        title += " (basis precision chosen per outer block in the batched path; FP64 one at a time)"
     lines = [f"# Kernel trace: {title}", "",
              "Command (repo root, MI355X; `cd /tmp && export TMPDIR=/tmp` first, R = repo root):",
              "", "    " + cmd, "",
@@ -858,7 +861,7 @@ def main():
         return
     if args.summarize_trace_batched:
         summarize_trace_batched(args.summarize_trace_batched, args.profile_cmd, args.workload,
-                                args.summary_out)
+                                args.summary_out, args.precision)
         return
     if args.plain_passes_only:
         plain_passes(reps=args.steps, only=True)
