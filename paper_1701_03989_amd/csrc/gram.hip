@@ -16,8 +16,8 @@
 // other model tried).  With the contraction index k = four consecutive rows
 // and the accumulator chained through the group's rows in order, each output
 // element is exactly the group partial above.  Columns come in blocks of 16;
-// block pairs (0,0) for d <= 16, (0,0) (0,1) (1,1) for d <= 32, six pairs for
-// d <= 48.  Operand layouts: lane l holds A[l % 16][l / 16] and
+// block pairs (0,0) for d <= 16, two blocks of a split for 17 <= d <= 24
+// (below), (0,0) (0,1) (1,1) for d <= 32, six pairs for d <= 48.  Operand layouts: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; element v of the accumulator of lane l is
 // D[l / 16 + 4 v][l % 16].
 //
@@ -50,22 +50,25 @@ struct SameRow {
 // is read at position map(r).  tile: this wavefront's GTR x (16 NB + 1)
 // doubles of LDS.  Called by a whole wavefront.
 //
-// D17 (NB = 2, d = 17: the two-sequence blocks of s = 8): the 17 entries
-// (a, 16) need not take two more 16 x 16 blocks ((0, 1) and (1, 1)): one
-// block with row columns I = (15, 16, zero columns) and column columns
-// J = (0, .., 14, 16) holds them all, (a, 16) for a <= 14 and (16, 16) in its
-// row 16, (15, 16) in its row 15.  Every entry is still the chain of one
-// matrix-core FMA per row over the same rows in the same order, so the bits
-// are those of the general blocking.
-template <int NB, class Src, class Map, bool D17 = false>
+// SPLIT (NB = 2, 17 <= d <= 24: the two-sequence blocks of s = 8 .. 11):
+// two 16 x 16 blocks instead of the three block pairs (0,0) (0,1) (1,1).
+// With m = 32 - d, block A takes the row columns I = (0, .., m-1, 16, .., d-1)
+// against the column columns J = (0, .., 15), block B the columns
+// (m, .., d-1) (padded with a zero column) against themselves.  A holds the
+// entries (a, b) with a < m, b <= 15 and, transposed, every (a, b) with
+// a <= 15 < b; B those with m <= a <= b <= 15 and 16 <= a <= b.  Every entry
+// is still the chain of one matrix-core FMA per row over the same rows in the
+// same order (the product of two doubles does not depend on their order), so
+// the bits are those of the general blocking.
+template <int NB, class Src, class Map, bool SPLIT = false>
 __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, int64_t rend,
                                            const Map& map, double* __restrict__ part,
                                            int64_t pstride, int64_t slot,
                                            double* __restrict__ tile) {
-  static_assert(!D17 || NB == 2, "the 17-column blocking has two column blocks");
+  static_assert(!SPLIT || NB == 2, "the split blocking has two column blocks");
   constexpr int NC = 16 * NB;
   constexpr int LD = NC + 1;  // odd row stride: the lanes' rows fall in different banks
-  constexpr int NP = D17 ? 2 : NB * (NB + 1) / 2;
+  constexpr int NP = SPLIT ? 2 : NB * (NB + 1) / 2;
   const int lane = threadIdx.x & (SSCG_WAVE - 1);
   gd4 acc[NP];
 #pragma unroll
@@ -113,18 +116,19 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (t + 1 < GRAM_GROUP / GTR) fetch(r0 + (int64_t)(t + 1) * GTR);
     const int cc = lane & 15;
-    // D17: this lane's column in the row set I (column NC - 1 is a zero
-    // column of the tile) and in the column set J
-    const int ci = cc == 0 ? 15 : (cc == 1 ? 16 : NC - 1);
-    const int cj = cc < 15 ? cc : 16;
+    // SPLIT: this lane's column in block A's row set and in block B's set
+    // (column NC - 1 is a zero column of the tile: d <= 24 < NC - 1)
+    const int m = 32 - d;
+    const int ia = cc < m ? cc : 16 + cc - m;
+    const int ib = m + cc < d ? m + cc : NC - 1;
 #pragma unroll
     for (int k4 = 0; k4 < GTR / 4; ++k4) {
       const int rr = 4 * k4 + (lane >> 4);
-      if constexpr (D17) {
+      if constexpr (SPLIT) {
         const double x0 = tile[rr * LD + cc];
-        const double xi = tile[rr * LD + ci], xj = tile[rr * LD + cj];
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, xj, acc[1], 0, 0, 0);
+        const double xa = tile[rr * LD + ia], xb = tile[rr * LD + ib];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, x0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb, xb, acc[1], 0, 0, 0);
       } else {
         double x[NB];
 #pragma unroll
@@ -145,17 +149,21 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if constexpr (D17) {
+  if constexpr (SPLIT) {
+    const int m = 32 - d;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ii = (lane >> 4) + 4 * v, jj = lane & 15;
-      // block (0, 0)
-      if (ii <= jj) part[(int64_t)pair_index(ii, jj, d) * pstride + slot] = acc[0][v];
-      // the I x J block: row 1 is column 16 against J, row 0 column 15
-      // against J[15] = 16; the rest repeats block (0, 0) or is zero
-      const int a = jj < 15 ? jj : 16;
-      if (ii == 1) part[(int64_t)pair_index(a, 16, d) * pstride + slot] = acc[1][v];
-      if (ii == 0 && jj == 15) part[(int64_t)pair_index(15, 16, d) * pstride + slot] = acc[1][v];
+      const int i = (lane >> 4) + 4 * v, j = lane & 15;
+      // block A: row i is column i (i < m) or column 16 + i - m against J
+      if (i < m) {
+        if (i <= j) part[(int64_t)pair_index(i, j, d) * pstride + slot] = acc[0][v];
+      } else {
+        part[(int64_t)pair_index(j, 16 + i - m, d) * pstride + slot] = acc[0][v];
+      }
+      // block B: columns m + i and m + j, less the entries block A holds
+      const int a = m + i, b = m + j;
+      if (i <= j && b < d && (a >= 16 || b < 16))
+        part[(int64_t)pair_index(a, b, d) * pstride + slot] = acc[1][v];
     }
     return;
   }
@@ -175,7 +183,7 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
   }
 }
 
-template <int NB, bool D17 = false>
+template <int NB, bool SPLIT = false>
 __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram(ColPtr cols, int n, int d,
                                                          double* __restrict__ part, int ng,
                                                          Gate gate) {
@@ -185,11 +193,11 @@ __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram(ColPtr cols, int n, int
   const int64_t g = (int64_t)blockIdx.x * GW + w;
   if (g >= ng) return;  // whole wavefronts; no workgroup barrier below
   const int64_t r0 = g * GRAM_GROUP;
-  gram_group<NB, ColPtr, SameRow, D17>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
+  gram_group<NB, ColPtr, SameRow, SPLIT>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
                                        part, ng, g, lds + w * GTR * (16 * NB + 1));
 }
 
-template <int NB, bool D17 = false>
+template <int NB, bool SPLIT = false>
 __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram32(Cols32 cols, int n, int d,
                                                            double* __restrict__ part, int ng) {
   __shared__ double lds[GW * GTR * (16 * NB + 1)];
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram32(Cols32 cols, int n, i
   const int64_t g = (int64_t)blockIdx.x * GW + w;
   if (g >= ng) return;
   const int64_t r0 = g * GRAM_GROUP;
-  gram_group<NB, Cols32, SameRow, D17>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
+  gram_group<NB, Cols32, SameRow, SPLIT>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
                                        part, ng, g, lds + w * GTR * (16 * NB + 1));
 }
 
@@ -240,9 +248,12 @@ __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
       if (NB >= 2 && d <= 16)
         gram_group<1, S, BatchRow>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks, ci,
                                    tile);
-      else if (NB == 2 && d == 17)
+      else if (NB >= 2 && d <= 24)
         gram_group<2, S, BatchRow, true>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks,
                                          ci, tile);
+      else if (NB == 3 && d <= 32)
+        gram_group<2, S, BatchRow>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks, ci,
+                                   tile);
       else
         gram_group<NB, S, BatchRow>(cols, d, ch.r0 - row0, rend, map, c.gpart, c.nchunks, ci,
                                     tile);
@@ -357,7 +368,7 @@ hipError_t launch_gram(const ColPtr& cols, int n, int d, double* part, Gate g, h
   switch (column_blocks(d)) {
     case 1: hipLaunchKernelGGL(k_gram<1>, grid, block, 0, st, cols, n, d, part, ng, g); break;
     case 2:
-      if (d == 17)
+      if (d <= 24)
         hipLaunchKernelGGL((k_gram<2, true>), grid, block, 0, st, cols, n, d, part, ng, g);
       else
         hipLaunchKernelGGL((k_gram<2, false>), grid, block, 0, st, cols, n, d, part, ng, g);
@@ -373,7 +384,7 @@ hipError_t launch_gram32(const Cols32& cols, int n, int d, double* part, hipStre
   switch (column_blocks(d)) {
     case 1: hipLaunchKernelGGL(k_gram32<1>, grid, block, 0, st, cols, n, d, part, ng); break;
     case 2:
-      if (d == 17)
+      if (d <= 24)
         hipLaunchKernelGGL((k_gram32<2, true>), grid, block, 0, st, cols, n, d, part, ng);
       else
         hipLaunchKernelGGL((k_gram32<2, false>), grid, block, 0, st, cols, n, d, part, ng);

@@ -77,8 +77,9 @@ def test_mpk32_matches_its_definition_bitwise(ctx, k):
             assert np.array_equal(got, R[j]), ("R", j)
 
 
-def test_gram32_matches_the_oracle_bitwise(ctx):
-    n, s = 20000, 8
+@pytest.mark.parametrize("s", [5, 8, 10, 12])
+def test_gram32_matches_the_oracle_bitwise(ctx, s):
+    n = 20000
     ld = n + 64
     rcol = s + 1
     rng = np.random.default_rng(5)

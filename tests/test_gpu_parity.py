@@ -209,6 +209,37 @@ def _solve(ctx, A, b, x1, cap=4096, **kw):
     return rc, host(x), hist
 
 
+@pytest.mark.parametrize("first", [True, False])
+def test_gram_every_width_matches_oracle(ctx, first):
+    """Every column count the Gram takes (d = s + 1 or 2 s + 1, s = 1..16:
+    one block pair, the split blocking of 17..24 columns, three and six block
+    pairs) over three groups of rows with a ragged last one, bit for bit
+    against the oracle's Gram in the stated order."""
+    n = 2 * 1024 + 333
+    rng = np.random.default_rng(17)
+    for s in range(1, 17):
+        d = s + 1 if first else 2 * s + 1
+        base = rng.standard_normal(n)
+        cols = []
+        for a in range(d):
+            v = rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 3)
+            if a % 4 == 1:  # nearly parallel to another column: cancellation in G
+                v = base + 1e-9 * v
+            cols.append(v)
+        ld = n + 64
+        rcol = s + 2
+        Y = torch.zeros((2 * s + 3) * ld, dtype=torch.float64, device=DEV)
+        for a in range(d):
+            c = a if a <= s else rcol + (a - s - 1)
+            Y[c * ld: c * ld + n] = dvec(cols[a])
+        G = torch.full((d * d,), float("nan"), dtype=torch.float64, device=DEV)
+        sscg.sscg_gram(ctx, n, s, first, Y, ld, rcol, G)
+        Gh = host(G).reshape(d, d)
+        Go = np.array(CR().gram(cols))
+        say(f"gram s={s} first={first} d={d}: {int(np.sum(Gh == Go))}/{d * d} equal")
+        assert np.array_equal(Gh, Go), (s, d)
+
+
 SOLVES = [
     # the 32 x 32 workload exactly as stated: adaptive monomial, s_max 8, tol
     # 1e-10, in-loop checks on, no equilibration; and its fixed s = 4 run
