@@ -294,16 +294,19 @@ def test_fp32_pass_table_form_matches_wider_forms_bitwise(ctx):
 
 
 @pytest.mark.parametrize("name", ["poisson3d_12", "poisson2d_25x41", "poisson2d_explicit_zero",
-                                  "poisson3d_9"])
+                                  "poisson3d_9", "poisson3d_20", "poisson2d_256x9"])
 def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
     """The slice-diagonal form against the oracle's row sums and against the
     value-table, 16-bit and 32-bit forms of the same matrix (sscg_set_forms),
     bit for bit: two-sequence Chebyshev passes, ragged last slice, a stored
-    explicit zero among three values."""
+    explicit zero among three values; distances of 400 rows (20^3) and 256
+    rows (256 x 9)."""
     A = {"poisson3d_12": lambda: problems.poisson3d(12),
          "poisson2d_25x41": lambda: problems.poisson2d(25, 41),
          "poisson2d_explicit_zero": lambda: with_explicit_zero(problems.poisson2d(24), 100),
-         "poisson3d_9": lambda: problems.poisson3d(9)}[name]()
+         "poisson3d_9": lambda: problems.poisson3d(9),
+         "poisson3d_20": lambda: problems.poisson3d(20),
+         "poisson2d_256x9": lambda: problems.poisson2d(256, 9)}[name]()
     p, r = vecs(A.n, 61)
     outs = {}
     try:
