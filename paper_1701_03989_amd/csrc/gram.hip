@@ -36,6 +36,15 @@ constexpr int GTR = 64;  // rows per tile (one per lane)
 
 typedef double gd4 __attribute__((ext_vector_type(4)));
 
+// Row stride of a wavefront's LDS tile (doubles; odd: the lanes' rows fall
+// in different banks): 16 NB columns, or for the split blocking (d <= 24)
+// columns 0..23 and the zero column SPLIT_ZC.
+constexpr int SPLIT_NC = 24, SPLIT_ZC = 24;
+template <int NB, bool SPLIT>
+__host__ __device__ constexpr int tile_ld() {
+  return SPLIT ? SPLIT_ZC + 1 : 16 * NB + 1;
+}
+
 __device__ __forceinline__ int pair_index(int a, int b, int d) {
   return a * d - a * (a - 1) / 2 + (b - a);  // row-major upper triangle, a <= b
 }
@@ -66,15 +75,15 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
                                            int64_t pstride, int64_t slot,
                                            double* __restrict__ tile) {
   static_assert(!SPLIT || NB == 2, "the split blocking has two column blocks");
-  constexpr int NC = 16 * NB;
-  constexpr int LD = NC + 1;  // odd row stride: the lanes' rows fall in different banks
+  constexpr int NC = SPLIT ? SPLIT_NC : 16 * NB;  // columns fetched (at most)
+  constexpr int LD = tile_ld<NB, SPLIT>();
   constexpr int NP = SPLIT ? 2 : NB * (NB + 1) / 2;
   const int lane = threadIdx.x & (SSCG_WAVE - 1);
   gd4 acc[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) acc[p] = gd4{0.0, 0.0, 0.0, 0.0};
-  // columns d..NC-1 of the tile stay 0 (they only feed outputs that are dropped)
-  for (int a = d; a < NC; ++a) tile[lane * LD + a] = 0.0;
+  // columns d..LD-1 of the tile stay 0 (they only feed outputs that are dropped)
+  for (int a = d; a < LD; ++a) tile[lane * LD + a] = 0.0;
   // the stored type of the columns: FP64, or FP32 (widened at the LDS store)
   using T = std::remove_cv_t<std::remove_reference_t<decltype(*src.at(0))>>;
   constexpr bool F32 = std::is_same<T, float>::value;
@@ -117,10 +126,10 @@ __device__ __forceinline__ void gram_group(const Src& src, int d, int64_t r0, in
     if (t + 1 < GRAM_GROUP / GTR) fetch(r0 + (int64_t)(t + 1) * GTR);
     const int cc = lane & 15;
     // SPLIT: this lane's column in block A's row set and in block B's set
-    // (column NC - 1 is a zero column of the tile: d <= 24 < NC - 1)
+    // (SPLIT_ZC is a zero column of the tile)
     const int m = 32 - d;
     const int ia = cc < m ? cc : 16 + cc - m;
-    const int ib = m + cc < d ? m + cc : NC - 1;
+    const int ib = m + cc < d ? m + cc : SPLIT_ZC;
 #pragma unroll
     for (int k4 = 0; k4 < GTR / 4; ++k4) {
       const int rr = 4 * k4 + (lane >> 4);
@@ -188,25 +197,25 @@ __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram(ColPtr cols, int n, int
                                                          double* __restrict__ part, int ng,
                                                          Gate gate) {
   if (gate_closed(gate)) return;
-  __shared__ double lds[GW * GTR * (16 * NB + 1)];
+  __shared__ double lds[GW * GTR * tile_ld<NB, SPLIT>()];
   const int w = threadIdx.x / SSCG_WAVE;
   const int64_t g = (int64_t)blockIdx.x * GW + w;
   if (g >= ng) return;  // whole wavefronts; no workgroup barrier below
   const int64_t r0 = g * GRAM_GROUP;
   gram_group<NB, ColPtr, SameRow, SPLIT>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
-                                       part, ng, g, lds + w * GTR * (16 * NB + 1));
+                                       part, ng, g, lds + w * GTR * tile_ld<NB, SPLIT>());
 }
 
 template <int NB, bool SPLIT = false>
 __global__ __launch_bounds__(GW * SSCG_WAVE) void k_gram32(Cols32 cols, int n, int d,
                                                            double* __restrict__ part, int ng) {
-  __shared__ double lds[GW * GTR * (16 * NB + 1)];
+  __shared__ double lds[GW * GTR * tile_ld<NB, SPLIT>()];
   const int w = threadIdx.x / SSCG_WAVE;
   const int64_t g = (int64_t)blockIdx.x * GW + w;
   if (g >= ng) return;
   const int64_t r0 = g * GRAM_GROUP;
   gram_group<NB, Cols32, SameRow, SPLIT>(cols, d, r0, min((int64_t)n, r0 + GRAM_GROUP), SameRow{},
-                                       part, ng, g, lds + w * GTR * (16 * NB + 1));
+                                       part, ng, g, lds + w * GTR * tile_ld<NB, SPLIT>());
 }
 
 // A batched system's rows may be stored out of order (sorted by length within
@@ -228,7 +237,8 @@ struct BatchRow {
 // so that neither column type's code shares the other's registers.
 template <int NB, int W, bool P32>
 __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
-  __shared__ double lds[W * GTR * (16 * NB + 1)];
+  constexpr int TLD = 16 * NB + 1;  // holds every blocking's tile
+  __shared__ double lds[W * GTR * TLD];
   const int w = threadIdx.x / SSCG_WAVE;
   const int nl = c.active[2];
   for (int li = blockIdx.x * W + w; li < nl; li += gridDim.x * W) {  // whole wavefronts
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
     const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
     const int64_t row0 = c.sys[q].row0;
     const int64_t rend = min((int64_t)ch.r1 - row0, (int64_t)c.sys[q].n);  // system-local rows
-    double* tile = lds + w * GTR * (16 * NB + 1);
+    double* tile = lds + w * GTR * TLD;
     // the blocking of the chunk's own d (d is uniform over the wavefront)
     auto run = [&](const auto& cols) {
       using S = std::remove_cv_t<std::remove_reference_t<decltype(cols)>>;
