@@ -285,8 +285,11 @@ hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_inf
                         const int* stop, hipStream_t st);
 // The coordinate recurrence; with stop != NULL a block that cannot take a
 // single step (BREAKDOWN) sets *stop = 3.
+// done, if given, is signalled when the kernel completes (by its own launch:
+// no separate event record on the stream).
 hipError_t launch_inner(const double* G, const sscg_block_params& prm, double* coef,
-                        sscg_block_info* info, int* stop, hipStream_t st);
+                        sscg_block_info* info, int* stop, hipStream_t st,
+                        hipEvent_t done = nullptr);
 // Replays the decisions of eq. condy and eq. check from the kappa list and
 // the recorded r'^T G r' of a block run speculatively with s~ = s and no
 // break; if they would have chosen s_k != s, sets *stop = 2 (redo the block).

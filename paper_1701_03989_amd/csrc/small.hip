@@ -9,6 +9,8 @@
 //   update of the rotated 2x2 blocks), so equal inputs give equal bits.
 // k_inner: s~ by eq. condy, B by eq. AVVB, the coordinate recurrence with the
 //   break of eq. check; one wave, lane a owns coordinate a.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace {
@@ -708,8 +710,12 @@ hipError_t launch_kappa(const double* G, int d, int s, int first, sscg_block_inf
 }
 
 hipError_t launch_inner(const double* G, const sscg_block_params& prm, double* coef,
-                        sscg_block_info* info, int* stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner, dim3(1), dim3(SSCG_WAVE), 0, st, G, prm, coef, info, stop);
+                        sscg_block_info* info, int* stop, hipStream_t st, hipEvent_t done) {
+  if (done)
+    hipExtLaunchKernelGGL(k_inner, dim3(1), dim3(SSCG_WAVE), 0, st, nullptr, done, 0, G, prm,
+                          coef, info, stop);
+  else
+    hipLaunchKernelGGL(k_inner, dim3(1), dim3(SSCG_WAVE), 0, st, G, prm, coef, info, stop);
   return hipGetLastError();
 }
 

@@ -298,12 +298,12 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
       HIPCHK(hipEventRecord(ctx->evV[slot], S1));
     } else {
       HIPCHK(ev_begin(ctx, 3, 0.0, S1, &slot_t));
-      HIPCHK(launch_inner(Gk, prm, coef, info, stop, S1));
+      // one event for both side-stream kernels, signalled by the coordinate
+      // solve's own launch: a separate event record costs the launch stream
+      // several microseconds, and kappa has a whole block's time to finish
+      // before the next recovery waits for it
+      HIPCHK(launch_inner(Gk, prm, coef, info, stop, S1, ctx->evI[slot]));
       HIPCHK(ev_end(ctx, slot_t, S1));
-      // one event for both side-stream kernels: every event record or wait
-      // costs the launch stream a few microseconds, and kappa has a whole
-      // block's time to finish before the next recovery waits for it
-      HIPCHK(hipEventRecord(ctx->evI[slot], S1));
       // exact decisions on the side stream (they run even after a stop so
       // that a rejected speculation is always reported)
       HIPCHK(hipStreamWaitEvent(S2, ctx->evI[slot], 0));
