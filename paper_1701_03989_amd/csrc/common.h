@@ -172,6 +172,14 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
   if (g.ran && blockIdx.x == 0 && threadIdx.x == 0) *g.ran = 1;
   return false;
 }
+// The two halves of gate_closed, for kernels whose loads at the start should
+// come before any store (a store there may alias what they read, which keeps
+// uniform loads off the scalar path): the stop test first, the ran mark at
+// the end (workgroup 0, thread 0 must reach it).
+__device__ __forceinline__ bool gate_stopped(const Gate& g) { return g.stop && *g.stop; }
+__device__ __forceinline__ void gate_mark_ran(const Gate& g) {
+  if (g.ran && blockIdx.x == 0 && threadIdx.x == 0) *g.ran = 1;
+}
 
 // Sets *flag if rowptr decreases or a column index lies outside [0, n).
 hipError_t launch_check_csr(const int32_t* rowptr, const int32_t* col, int n, int64_t nnz,

@@ -349,6 +349,10 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
     const V* __restrict__ u0 = s0.u;
     const V* __restrict__ u1 = s1.u;
     dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();
+    // SD: the row's own u values as gathered at distance 0 (hc: it has that
+    // entry), so that the centre terms below need no load of their own
+    V c0 = 0, c1 = 0;
+    bool hc = false;
     if constexpr (SD) {
       // slice-diagonal form: distances and values of the slice (wave-uniform,
       // scalar registers), one 16-bit code word per row; every gather address
@@ -391,6 +395,11 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
               dd_add_prod(a0, v[u], g0[u]);
               if (NRHS == 2) dd_add_prod(a1, v[u], g1[u]);
               if (RES) dd_add_prod(ax, v[u], gx[u]);
+              if (CHEB && k0 + u < nd && dl[k0 + u] == 0) {  // uniform test
+                c0 = g0[u];
+                if (NRHS == 2) c1 = g1[u];
+                hc = true;
+              }
             }
           }
         }
@@ -453,11 +462,15 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
     if (row < A.n) {
       double o0, o1 = 0.0;
       if (CHEB) {
-        dd_add_prod(a0, -theta, u0[row]);
+        if (!(SD && hc)) {
+          c0 = u0[row];
+          if (NRHS == 2) c1 = u1[row];
+        }
+        dd_add_prod(a0, -theta, c0);
         if (HASW) dd_add_prod(a0, -sigma, s0.w[row]);
         o0 = dd_round(a0) / gamma;
         if (NRHS == 2) {
-          dd_add_prod(a1, -theta, u1[row]);
+          dd_add_prod(a1, -theta, c1);
           if (HASW) dd_add_prod(a1, -sigma, s1.w[row]);
           o1 = dd_round(a1) / gamma;
         }
@@ -485,14 +498,15 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
                                             const double* __restrict__ xres,
                                             const double* __restrict__ bres,
                                             double* __restrict__ rpart) {
-  if (gate_closed(gate)) return;
+  if (gate_stopped(gate)) return;
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
-  if (lb >= nb) return;
+  if (lb >= nb) return;  // not workgroup 0 (nb >= 1 and xcd_block(nb) maps 0 to 0)
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
   dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD>(A, slice, theta, sigma, gamma, s0,
                                                                 s1, xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
+  gate_mark_ran(gate);
 }
 
 // Batched pass j over the 256-row blocks listed in ablk[0, *nlist) (those of
