@@ -278,14 +278,18 @@ __global__ __launch_bounds__(W * SSCG_WAVE) void k_gram_batch(BatchCfg c) {
 // ---------------------------------------------------------------- pairwise sums
 //
 // Pairwise sum of v[0..count) zero-padded to P (a power of two >= count),
-// by the WG threads of a workgroup: thread t sums the aligned run
-// [t L, (t + 1) L) of L = P / T leaves (T = min(P, WG)) with a binary-counter
-// stack (the same tree), then the T run sums are added pairwise in LDS.
-// Returns the sum on every thread.
+// by the NT threads of a workgroup: thread t sums the aligned run
+// [t L, (t + 1) L) of L = P / T leaves (T = min(P, NT)) with a binary-counter
+// stack (the same tree), then the T run sums are added pairwise in LDS.  The
+// tree is the complete binary tree over the P leaves for any power of two
+// NT.  Returns the sum on every thread.
 constexpr int WG = 256;
 constexpr int PW_DEPTH = 24;  // stack levels: runs of up to 2^23 leaves per thread
 
+template <int NT = WG>
 __device__ double pairwise_sum(const double* __restrict__ v, int64_t count, int64_t P) {
+  static_assert((NT & (NT - 1)) == 0, "a power of two");
+  constexpr int WG = NT;
   __shared__ double s[WG];
   __shared__ double stk[WG * PW_DEPTH];
   const int t = threadIdx.x;
@@ -342,8 +346,11 @@ __global__ __launch_bounds__(WG) void k_gram_finalize(const double* __restrict__
   }
 }
 
-// grid (pairs, systems): entry blockIdx.x of system blockIdx.y.
-__global__ __launch_bounds__(WG) void k_gram_finalize_batch(BatchCfg c) {
+// grid (pairs, systems): entry blockIdx.x of system blockIdx.y, by one
+// wavefront (most systems have few chunks; a small workgroup with a small
+// stack lets many run on a CU).
+constexpr int FB_NT = SSCG_WAVE;
+__global__ __launch_bounds__(FB_NT) void k_gram_finalize_batch(BatchCfg c) {
   const int q = blockIdx.y, e = blockIdx.x;
   const BatchSys& sy = c.sys[q];
   if (sy.done) return;
@@ -351,8 +358,8 @@ __global__ __launch_bounds__(WG) void k_gram_finalize_batch(BatchCfg c) {
   const int d = prm.first ? prm.s + 1 : 2 * prm.s + 1;
   if (e >= d * (d + 1) / 2) return;
   const int ngs = sy.ch1 - sy.ch0;
-  const double g = pairwise_sum(c.gpart + (int64_t)e * c.nchunks + sy.ch0, ngs,
-                                pow2_at_least(ngs));
+  const double g = pairwise_sum<FB_NT>(c.gpart + (int64_t)e * c.nchunks + sy.ch0, ngs,
+                                       pow2_at_least(ngs));
   if (threadIdx.x == 0) {
     int a = 0, rem = e;
     while (rem >= d - a) {
@@ -438,6 +445,7 @@ hipError_t launch_gram_batch(const BatchCfg& c, hipStream_t st) {
 
 hipError_t launch_gram_finalize_batch(const BatchCfg& c, hipStream_t st) {
   const int dm = 2 * c.S + 1;
-  hipLaunchKernelGGL(k_gram_finalize_batch, dim3(dm * (dm + 1) / 2, c.nsys), dim3(WG), 0, st, c);
+  hipLaunchKernelGGL(k_gram_finalize_batch, dim3(dm * (dm + 1) / 2, c.nsys), dim3(FB_NT), 0, st,
+                     c);
   return hipGetLastError();
 }
