@@ -334,8 +334,11 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 // IL (two sequences): the gathers of u read the pairs tg[c] = (s0.u[c],
 // s1.u[c]), one 16-byte load instead of two 8-byte ones on different cache
 // lines (random gathers), and tw, if given, receives the pairs of the outputs.
+// CEN (slice-diagonal form): the centre terms take the row's own u from its
+// distance-0 gather (k_mpk; in the batched pass's larger kernel the extra
+// state cost more than the load it saves).
 template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false,
-          bool VI = false, bool SD = false, int CHK = 4, class V = double>
+          bool VI = false, bool SD = false, int CHK = 4, class V = double, bool CEN = false>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeqV<V>& s0, const MpkSeqV<V>& s1,
                                         const double* __restrict__ xres,
@@ -395,7 +398,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
               dd_add_prod(a0, v[u], g0[u]);
               if (NRHS == 2) dd_add_prod(a1, v[u], g1[u]);
               if (RES) dd_add_prod(ax, v[u], gx[u]);
-              if (CHEB && k0 + u < nd && dl[k0 + u] == 0) {  // uniform test
+              if (CHEB && CEN && k0 + u < nd && dl[k0 + u] == 0) {  // uniform test
                 c0 = g0[u];
                 if (NRHS == 2) c1 = g1[u];
                 hc = true;
@@ -462,7 +465,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
     if (row < A.n) {
       double o0, o1 = 0.0;
       if (CHEB) {
-        if (!(SD && hc)) {
+        if (!(SD && CEN && hc)) {
           c0 = u0[row];
           if (NRHS == 2) c1 = u1[row];
         }
@@ -503,8 +506,8 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   int lb = xcd_block(nb);
   if (lb >= nb) return;  // not workgroup 0 (nb >= 1 and xcd_block(nb) maps 0 to 0)
   int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
-  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD>(A, slice, theta, sigma, gamma, s0,
-                                                                s1, xres, bres);
+  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD, 4, double, SD>(
+      A, slice, theta, sigma, gamma, s0, s1, xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
   gate_mark_ran(gate);
 }
