@@ -67,6 +67,9 @@ CASES = [
     dict(mode="fixed", fixed_s=4, s_max=8, tol=1e-10),
     dict(mode="adaptive", s_max=8, tol=1e-10, inner_check=False, c=10.0),
     dict(mode="adaptive", basis="chebyshev", s_max=16, tol=1e-10),  # 33 x 33 sub-Gram matrices
+    # growing blocks s = 2, 5, 8, 11, 12: Gram widths 5, 11, 17, 23, 25 (one column
+    # block, the split blocking, two full column blocks in one batched launch)
+    dict(mode="adaptive", basis="chebyshev", s_max=12, tol=1e-10, s0_bar=2, f=3),
 ]
 
 
