@@ -717,8 +717,10 @@ __global__ __launch_bounds__(WG) void k_gershgorin(DevMat A, double* __restrict_
 }
 
 // Lanczos: w_i = RN((A v)_i - beta_prev vprev_i); partials of w.v.  VI: the
-// values come from the slice's value table (same bits), as in the passes.
-template <bool C16, bool VI = false>
+// values come from the slice's value table (same bits), as in the passes;
+// SD: the slice-diagonal form (its terms in distance order: every row sum is
+// correctly rounded, so the order does not change it).
+template <bool C16, bool VI = false, bool SD = false>
 __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __restrict__ v,
                                                      const double* __restrict__ vprev,
                                                      const double* __restrict__ beta_prev,
@@ -732,9 +734,35 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
   int row = slice * SSCG_WAVE + lane;
   dd d = dd_zero();
   if (slice < A.nslices) {
+    dd a = dd_zero();
+    if constexpr (SD) {
+      const int us = __builtin_amdgcn_readfirstlane(slice);
+      const int nd = A.sd_nd[us];
+      int dl[SD_DIAG];
+      double sv[SD_VALS];
+#pragma unroll
+      for (int k = 0; k < SD_DIAG; ++k) dl[k] = A.sd_delta[(int64_t)us * SD_DIAG + k];
+#pragma unroll
+      for (int i = 0; i < SD_VALS; ++i) sv[i] = A.sd_tab[(int64_t)us * 4 + i];
+      const unsigned code = A.sd_code[row];
+      unsigned pm = 0;  // bit k: the row has an entry at distance k
+#pragma unroll
+      for (int k = 0; k < SD_DIAG; ++k)
+        if (k < nd && ((code >> (2 * k)) & 3u) != (unsigned)SD_ABSENT) pm |= 1u << k;
+      double g[SD_DIAG];
+#pragma unroll
+      for (int k = 0; k < SD_DIAG; ++k)
+        if (pm & (1u << k)) g[k] = v[row + dl[k]];
+#pragma unroll
+      for (int k = 0; k < SD_DIAG; ++k) {
+        if (pm & (1u << k)) {
+          const unsigned cd = (code >> (2 * k)) & 3u;
+          dd_add_prod(a, cd == 0u ? sv[0] : (cd == 1u ? sv[1] : sv[2]), g[k]);
+        }
+      }
+    } else {
     int64_t o = A.off[slice] + lane;
     int wd = A.width[slice];
-    dd a = dd_zero();
     double tv[VTAB];
     if (VI) {
       const int us = __builtin_amdgcn_readfirstlane(slice);
@@ -770,6 +798,7 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
       for (int u = 0; u < CH; ++u)
         if (j0 + u < wd) dd_add_prod(a, av[u], g[u]);
     }
+    }  // SELL forms
     if (row < A.n) {
       if (vprev) dd_add_prod(a, -(*beta_prev), vprev[row]);
       double wi = dd_round(a);
@@ -1359,7 +1388,10 @@ hipError_t launch_lanczos_step(const DevMat& A, const double* v, const double* v
                                hipStream_t st) {
   int nb = wg_count(A.nslices);
   *nparts = nb;
-  if (A.col16 && A.vidx)
+  if (A.sd_code)
+    hipLaunchKernelGGL((k_lanczos_spmv<false, false, true>), dim3(xcd_grid(nb)), dim3(WG), 0, st,
+                       A, v, vprev, beta_prev, w, part);
+  else if (A.col16 && A.vidx)
     hipLaunchKernelGGL((k_lanczos_spmv<true, true>), dim3(xcd_grid(nb)), dim3(WG), 0, st, A, v,
                        vprev, beta_prev, w, part);
   else if (A.col16)
