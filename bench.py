@@ -59,16 +59,36 @@ def source_hash(paths) -> str:
 
 def form_bytes(fmt: int, stored: int, n: int) -> float:
     """Bytes of A one matrix-powers pass reads in the stored form it uses (the
-    library's accounting): per SELL-64 entry 3 (value index + 16-bit offset), 10
-    (value + 16-bit offset) or 12 (value + 32-bit index); per 64-row slice its
-    offset and width, and with value tables its 4-entry table."""
+    library's accounting): in the slice-diagonal form a 16-bit code per row
+    and per 64-row slice its count, 8 distances and 4-entry table; otherwise
+    per SELL-64 entry 3 (value index + 16-bit offset), 10 (value + 16-bit
+    offset) or 12 (value + 32-bit index), per slice its offset and width, and
+    with value tables its 4-entry table."""
     from paper_1701_03989_amd import sscg
 
+    if fmt & sscg.FMT_SDIA:
+        nslices = (n + 63) // 64
+        return 2.0 * 64 * nslices + (4.0 + 4.0 * 8 + 32.0) * nslices
     vt = bool(fmt & sscg.FMT_VTAB)
     c16 = bool(fmt & sscg.FMT_COL16)
     per_entry = 3.0 if vt else (10.0 if c16 else 12.0)
     nslices = (n + 63) // 64
     return per_entry * stored + (12.0 + (32.0 if vt else 0.0)) * nslices
+
+
+def form_name(fmt: int) -> str:
+    """The matrix-powers kernel and the stored form it reads, for format bits fmt."""
+    from paper_1701_03989_amd import sscg
+
+    if fmt & sscg.FMT_SDPAIR:
+        return "k_mpk_sdp (matrix-powers pass), slice-diagonal form, two slices per wavefront"
+    if fmt & sscg.FMT_SDIA:
+        return "k_mpk (matrix-powers pass), slice-diagonal form"
+    if fmt & sscg.FMT_VTAB:
+        return "k_mpk (matrix-powers pass), value tables + 16-bit column offsets"
+    if fmt & sscg.FMT_COL16:
+        return "k_mpk (matrix-powers pass), FP64 values + 16-bit column offsets"
+    return "k_mpk (matrix-powers pass), FP64 values + 32-bit column indices"
 
 
 def traffic_from_profile(path=PMC_SUMMARY):
@@ -113,7 +133,7 @@ def summarize_pmc(d: str, cmd: str, plain: bool = False) -> None:
         v = [x for k, xs in rows.items() if "copyBuffer" in k for x in xs]
         scale[c] = COPY_BYTES / (float(np.median(v)) * 1024.0)
     title = ("variable-coefficient 2-D diffusion 2048^2 (no value tables), sscg_mpk s = 10"
-             if plain else "3-D Poisson 128^3 (value tables, 16-bit offsets), whole solves")
+             if plain else "3-D Poisson 128^3 (slice-diagonal form, two slices per wavefront), whole solves")
     lines = [f"# HBM traffic of the matrix-powers pass (k_mpk), {title}", "",
              "Commands (repo root, MI355X; `cd /tmp && export TMPDIR=/tmp` first, R = repo root):", ""]
     lines += ["    " + l for l in cmd.splitlines()]
@@ -313,7 +333,7 @@ def plain_passes(reps: int = 10, only: bool = False):
     eff = (alg + csr_extra) / (avg_ms * 1e-3) / 1e9
     traffic = traffic_from_profile(PMC_SUMMARY_PLAIN)
     return {
-        "kernel": "k_mpk (matrix-powers pass), FP64 values + 16-bit column offsets",
+        "kernel": form_name(fmt),
         "workload": "diffusion2048 operator (n=4194304, nnz=20963328, variable coefficients), "
                     "sscg_mpk s=10, two sequences, Chebyshev",
         "format": {"col16": bool(fmt & sscg.FMT_COL16), "value_tables": bool(fmt & sscg.FMT_VTAB),
@@ -1023,7 +1043,7 @@ def main():
         "kernel_ms": {f: brk[f][1] / max(brk[f][0], 1) for f in brk},
         "kernel_launches_per_solve": {f: brk[f][0] for f in brk},
         "roofline": {
-            "kernel": "k_mpk (matrix-powers pass), value tables + 16-bit column offsets",
+            "kernel": form_name(fmt),
             "bound": "hbm",
             "achieved": mpk_gbs,
             "peak": HBM_PEAK_GBS,
@@ -1033,8 +1053,8 @@ def main():
             "traffic_frac": (traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
             "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": alg,
-            "algorithmic_note": "bytes of the stored form the pass reads (3 B per SELL-64 entry, "
-                                "per-slice offset/width/table) + 8 B per vector element",
+            "algorithmic_note": "bytes of the stored form the pass reads (slice-diagonal form: "
+                                "2 B per row + per-slice tables) + 8 B per vector element",
             "effective_gbs": eff_gbs,
             "effective_frac": eff_gbs / HBM_PEAK_GBS,
             "effective_note": "the same passes priced at plain CSR (12 B per nonzero + 4 B per "

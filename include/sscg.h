@@ -271,9 +271,14 @@ int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, d
  * gathers row i's inputs at i + d without loading an index.  It takes
  * precedence over the other forms; the same bits result. */
 #define SSCG_FMT_SDIA 4
+/* SSCG_FMT_SDPAIR (with SSCG_FMT_SDIA, n >= 2): for every t, slices 2 t and
+ * 2 t + 1 (rows 128 t .. 128 t + 127) have the same distances and the same
+ * values, bit for bit, so the pass takes such a pair in one wavefront, two
+ * rows per lane, with 16-byte loads.  The same bits result. */
+#define SSCG_FMT_SDPAIR 8
 int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* stored);
 /* Which of the compact forms above the context's later calls may build and
- * read (bit mask of SSCG_FMT_*, default all three; 0 = the stored FP64 values
+ * read (bit mask of SSCG_FMT_*, default all four; 0 = the stored FP64 values
  * with 32-bit indices).  For timing and testing the forms against each
  * other: every form gives the same bits.  Value tables are only used together
  * with 16-bit offsets. */

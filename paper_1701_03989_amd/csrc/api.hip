@@ -213,7 +213,11 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
                           as<int32_t>(ctx->sd_nd), as<int32_t>(ctx->sd_delta),
                           as<double>(ctx->sd_tab), as<uint16_t>(ctx->sd_code), flag + 2,
                           ctx->stream));
-  int32_t fl[3] = {1, 1, 1};
+  // whether consecutive slices share their slice-diagonal tables
+  HIPCHK(hipMemsetAsync(flag + 3, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_sd_pairs(as<int32_t>(ctx->sd_nd), as<int32_t>(ctx->sd_delta),
+                         as<double>(ctx->sd_tab), nslices, flag + 3, ctx->stream));
+  int32_t fl[4] = {1, 1, 1, 1};
   HIPCHK(hipMemcpyAsync(fl, flag, sizeof fl, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   // forms the caller allowed (sscg_set_forms); tables only with 16-bit offsets
@@ -233,6 +237,7 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   M->sd_delta = nosd ? nullptr : as<int32_t>(ctx->sd_delta);
   M->sd_tab = nosd ? nullptr : as<double>(ctx->sd_tab);
   M->sd_code = nosd ? nullptr : as<uint16_t>(ctx->sd_code);
+  M->sd_pair = !nosd && fl[3] == 0 && (ctx->forms & SSCG_FMT_SDPAIR) && n >= 2 ? 1 : 0;
   ctx->mat_bytes = mpk_matrix_bytes(*M, total);
   return SSCG_OK;
 }
@@ -673,7 +678,7 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
   if ((rc = build_mat(ctx, A, 0, &M))) return rc;
   // the forms the matrix-powers pass dispatches on: tables only with 16-bit offsets
   const int f = (M.col16 ? SSCG_FMT_COL16 : 0) | (M.col16 && M.vidx ? SSCG_FMT_VTAB : 0) |
-                (M.sd_code ? SSCG_FMT_SDIA : 0);
+                (M.sd_code ? SSCG_FMT_SDIA : 0) | (M.sd_code && M.sd_pair ? SSCG_FMT_SDPAIR : 0);
   if (format) *format = f;
   if (stored) *stored = ctx->sell_total;
   return SSCG_OK;
@@ -682,8 +687,9 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
 int sscg_set_forms(sscg_ctx* ctx, int forms) {
   if (!ctx) return SSCG_ERR_ARG;
   ctx->err.clear();
-  if (forms & ~(SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA))
-    return fail(ctx, SSCG_ERR_ARG, "forms = %d: bits SSCG_FMT_COL16 | VTAB | SDIA only", forms);
+  if (forms & ~(SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA | SSCG_FMT_SDPAIR))
+    return fail(ctx, SSCG_ERR_ARG, "forms = %d: bits SSCG_FMT_COL16 | VTAB | SDIA | SDPAIR only",
+                forms);
   ctx->forms = forms;
   return SSCG_OK;
 }

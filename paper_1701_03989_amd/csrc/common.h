@@ -126,6 +126,11 @@ struct DevMat {
   const int32_t* sd_delta = nullptr;
   const double* sd_tab = nullptr;
   const uint16_t* sd_code = nullptr;
+  // With the slice-diagonal form: 1 when every pair of slices (2t, 2t + 1)
+  // has the same distances and values (their tables are stored in one
+  // canonical order), so that the pass may take the pair's 128 rows in one
+  // wavefront with the tables uniform over it.
+  int32_t sd_pair = 0;
 };
 constexpr int VTAB = 4;  // values in the table of a slice
 constexpr int SD_DIAG = 8, SD_VALS = 3, SD_ABSENT = 3;
@@ -208,6 +213,10 @@ hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
                                hipStream_t st);
 // The slice-diagonal form of the SELL copy (DevMat::sd_*; sd_code has one
 // word per row of the padded slices); *flag = 1 if some slice does not fit it.
+// *flag = 1 if some pair of slices (2t, 2t + 1) differs in its distances or
+// values.
+hipError_t launch_sd_pairs(const int32_t* sd_nd, const int32_t* sd_delta, const double* sd_tab,
+                           int nslices, int32_t* flag, hipStream_t st);
 hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, const double* sval,
                             const int64_t* off, const int32_t* width, int nslices, int32_t* sd_nd,
                             int32_t* sd_delta, double* sd_tab, uint16_t* sd_code, int32_t* flag,

@@ -4,6 +4,8 @@
 // Every row sum is accumulated exactly in double-double and rounded once, so
 // it equals (up to a vanishingly rare near-tie) the correctly rounded exact
 // row sum, independent of the order of the terms.
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -251,10 +253,31 @@ __device__ __forceinline__ bool sdia_slice(int slice, int row, int len,
     }
   }
   over |= __ballot(dup) != 0;
-  if (lane < SD_DIAG) sd_delta[(int64_t)slice * SD_DIAG + lane] = lane < nd ? ds : 0;
-  if (lane < 4) sd_tab[(int64_t)slice * 4 + lane] = lane < m ? __longlong_as_double(tb) : 0.0;
+  // Canonical order: distances ascending, values by their bits ascending
+  // (the codes renumbered to match), so that slices with the same distances
+  // and values store the same tables.  (Every row sum is correctly rounded:
+  // the order of its terms does not change it.)
+  int dr = 0, vr = 0;  // lane k < nd: rank of distance k; lane c < m: rank of value c
+  for (int i = 0; i < nd; ++i) dr += __shfl(ds, i, SSCG_WAVE) < ds ? 1 : 0;
+  for (int i = 0; i < m; ++i)
+    vr += (unsigned long long)__shfl(tb, i, SSCG_WAVE) < (unsigned long long)tb ? 1 : 0;
+  const int vr0 = __shfl(vr, 0, SSCG_WAVE), vr1 = __shfl(vr, 1, SSCG_WAVE),
+            vr2 = __shfl(vr, 2, SSCG_WAVE);
+  unsigned sorted = 0xFFFFu;
+  for (int k = 0; k < nd; ++k) {
+    const unsigned f = (code >> (2 * k)) & 3u;
+    const unsigned to = 2u * (unsigned)__shfl(dr, k, SSCG_WAVE);
+    if (f != (unsigned)SD_ABSENT) {
+      const unsigned nv = (unsigned)(f == 0u ? vr0 : (f == 1u ? vr1 : vr2));
+      sorted = (sorted & ~(3u << to)) | (nv << to);
+    }
+  }
+  if (lane < SD_DIAG && lane >= nd) sd_delta[(int64_t)slice * SD_DIAG + lane] = 0;
+  if (lane < nd) sd_delta[(int64_t)slice * SD_DIAG + dr] = ds;
+  if (lane < 4 && lane >= m) sd_tab[(int64_t)slice * 4 + lane] = 0.0;
+  if (lane < m) sd_tab[(int64_t)slice * 4 + vr] = __longlong_as_double(tb);
   if (lane == 0) sd_nd[slice] = nd;
-  sd_code[row] = (uint16_t)code;
+  sd_code[row] = (uint16_t)(over ? code : sorted);
   return over;
 }
 
@@ -327,6 +350,7 @@ __global__ void k_set_sd(BatchSys* __restrict__ sys, const int32_t* __restrict__
 // x, res_i = RN(b_i - (A x)_i), from the same stream of A (x gathered as a
 // third sequence), and stores per-workgroup dd partials of sum res_i^2.
 // The gate: the pass does nothing once the solve has stopped.
+template <int NW = SLICES_PER_WG>
 __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 
 // The rows of one slice (lane = row within it); returns the lane's res_i^2
@@ -512,6 +536,222 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   gate_mark_ran(gate);
 }
 
+// Two rows' worth of a sequence: 8-byte alignment is all the pair form's
+// addresses (row + distance, row even) guarantee.
+// (A vector type, so that each access stays one 16-byte instruction.)
+typedef double sd2 __attribute__((ext_vector_type(2), aligned(8)));
+
+// The pass in the pair form (DevMat::sd_pair): a wavefront takes the 128 rows
+// of slices 2t and 2t + 1, lane l the rows 128 t + 2 l and 128 t + 2 l + 1,
+// with the pair's common distances and values in scalar registers.  For each
+// distance one 16-byte load brings both rows' u values, so a row costs half
+// the memory instructions of the one-row-per-lane form.  Where every row of
+// the pair and every neighbour it names lie in [0, n) (the interior), the
+// loads of all nd distances are issued unconditionally; a boundary pair loads
+// each row's value through a clamped index.  Each row adds its terms in the
+// order of its distances with the same dd steps as mpk_slice, so the result
+// is the same to the bit.  Workgroups of two wavefronts cover four slices, as
+// the k_mpk workgroups do, so the residual partials keep their slots.
+template <int NRHS, bool CHEB, bool HASW, bool RES>
+__global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double theta, double sigma,
+                                                           double gamma, MpkSeq s0, MpkSeq s1,
+                                                           Gate gate,
+                                                           const double* __restrict__ xres,
+                                                           const double* __restrict__ bres,
+                                                           double* __restrict__ rpart) {
+  static_assert(SLICES_PER_WG == 4, "two wavefronts of two slices each");
+  if (gate_stopped(gate)) return;
+  const int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
+  const int lb = xcd_block(nb);
+  if (lb >= nb) return;  // not workgroup 0 (nb >= 1 and xcd_block(nb) maps 0 to 0)
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  const int t = lb * 2 + (int)(threadIdx.x / SSCG_WAVE);  // the pair of slices
+  const int n = A.n;
+  dd r2 = dd_zero();
+  if (2 * t < A.nslices) {
+    const int us = __builtin_amdgcn_readfirstlane(2 * t);
+    const int nd = A.sd_nd[us];
+    int dl[SD_DIAG];
+    double tv[SD_VALS];
+#pragma unroll
+    for (int k = 0; k < SD_DIAG; ++k) dl[k] = A.sd_delta[(int64_t)us * SD_DIAG + k];
+#pragma unroll
+    for (int i = 0; i < SD_VALS; ++i) tv[i] = A.sd_tab[(int64_t)us * 4 + i];
+    const int base = t * 2 * SSCG_WAVE;  // first row of the pair
+    const int r = base + 2 * lane;
+    // uniform: the lowest and highest distance, and which one is 0
+    int dmin = 0, dmax = 0, kc = -1;
+#pragma unroll
+    for (int k = 0; k < SD_DIAG; ++k)
+      if (k < nd) {
+        dmin = (k == 0 || dl[k] < dmin) ? dl[k] : dmin;
+        dmax = (k == 0 || dl[k] > dmax) ? dl[k] : dmax;
+        kc = dl[k] == 0 ? k : kc;
+      }
+    const bool inner = 2 * t + 1 < A.nslices && base + 2 * SSCG_WAVE <= n && base + dmin >= 0 &&
+                       base + 2 * SSCG_WAVE - 1 + dmax <= n - 1;
+    // codes of the two rows (padding rows and rows past the last slice: none)
+    unsigned ca, cb;
+    if (inner) {
+      const uint32_t w2 = *(const uint32_t*)(A.sd_code + r);
+      ca = w2 & 0xFFFFu;
+      cb = w2 >> 16;
+    } else {
+      const int lim = A.nslices * SSCG_WAVE;
+      ca = r < lim ? A.sd_code[r] : 0xFFFFu;
+      cb = r + 1 < lim ? A.sd_code[r + 1] : 0xFFFFu;
+    }
+    dd a0 = dd_zero(), a1 = dd_zero(), ax = dd_zero();  // row r
+    dd b0 = dd_zero(), b1 = dd_zero(), bx = dd_zero();  // row r + 1
+    double ca0 = 0, ca1 = 0, cb0 = 0, cb1 = 0;           // centre values from distance 0
+    // chunks of 4, 3 and 1 distances (the loads of a chunk are in flight
+    // together; larger chunks cost occupancy): a seven-point stencil loads no
+    // distance twice
+    auto chunk = [&](auto k0c, auto chc) {
+      constexpr int k0 = decltype(k0c)::value, CH = decltype(chc)::value;
+      if (k0 < nd) {
+        sd2 g0[CH], g1[CH], gx[CH];
+        if (inner) {
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int off = r + (k0 + u < nd ? dl[k0 + u] : 0);
+            g0[u] = *(const sd2*)(s0.u + off);
+            if (NRHS == 2) g1[u] = *(const sd2*)(s1.u + off);
+            if (RES) gx[u] = *(const sd2*)(xres + off);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int d = k0 + u < nd ? dl[k0 + u] : 0;
+            const int ia = min(max(r + d, 0), n - 1), ib = min(max(r + 1 + d, 0), n - 1);
+            g0[u].x = s0.u[ia];
+            g0[u].y = s0.u[ib];
+            if (NRHS == 2) {
+              g1[u].x = s1.u[ia];
+              g1[u].y = s1.u[ib];
+            }
+            if (RES) {
+              gx[u].x = xres[ia];
+              gx[u].y = xres[ib];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int k = k0 + u;
+          const unsigned da = k < nd ? (ca >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
+          const unsigned db = k < nd ? (cb >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
+          if (da != (unsigned)SD_ABSENT) {
+            const double v = da == 0u ? tv[0] : (da == 1u ? tv[1] : tv[2]);
+            dd_add_prod(a0, v, g0[u].x);
+            if (NRHS == 2) dd_add_prod(a1, v, g1[u].x);
+            if (RES) dd_add_prod(ax, v, gx[u].x);
+          }
+          if (db != (unsigned)SD_ABSENT) {
+            const double v = db == 0u ? tv[0] : (db == 1u ? tv[1] : tv[2]);
+            dd_add_prod(b0, v, g0[u].y);
+            if (NRHS == 2) dd_add_prod(b1, v, g1[u].y);
+            if (RES) dd_add_prod(bx, v, gx[u].y);
+          }
+          if (CHEB && k == kc) {  // uniform: the distance-0 loads are the rows' own u
+            ca0 = g0[u].x;
+            cb0 = g0[u].y;
+            if (NRHS == 2) {
+              ca1 = g1[u].x;
+              cb1 = g1[u].y;
+            }
+          }
+        }
+            }
+    };
+    chunk(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
+    chunk(std::integral_constant<int, 4>{}, std::integral_constant<int, 3>{});
+    chunk(std::integral_constant<int, 7>{}, std::integral_constant<int, 1>{});
+    if (CHEB && kc < 0) {  // no distance 0 in this pair of slices
+      const int ia = min(r, n - 1), ib = min(r + 1, n - 1);
+      ca0 = s0.u[ia];
+      cb0 = s0.u[ib];
+      if (NRHS == 2) {
+        ca1 = s1.u[ia];
+        cb1 = s1.u[ib];
+      }
+    }
+    // outputs of rows r and r + 1 (both in [0, n) in the interior)
+    double oa0, oa1 = 0.0, ob0, ob1 = 0.0;
+    if (CHEB) {
+      double wa0 = 0, wb0 = 0, wa1 = 0, wb1 = 0;
+      if (HASW) {
+        if (inner) {
+          const sd2 w = *(const sd2*)(s0.w + r);
+          wa0 = w.x;
+          wb0 = w.y;
+          if (NRHS == 2) {
+            const sd2 v = *(const sd2*)(s1.w + r);
+            wa1 = v.x;
+            wb1 = v.y;
+          }
+        } else {
+          const int ia = min(r, n - 1), ib = min(r + 1, n - 1);
+          wa0 = s0.w[ia];
+          wb0 = s0.w[ib];
+          if (NRHS == 2) {
+            wa1 = s1.w[ia];
+            wb1 = s1.w[ib];
+          }
+        }
+      }
+      dd_add_prod(a0, -theta, ca0);
+      if (HASW) dd_add_prod(a0, -sigma, wa0);
+      oa0 = dd_round(a0) / gamma;
+      dd_add_prod(b0, -theta, cb0);
+      if (HASW) dd_add_prod(b0, -sigma, wb0);
+      ob0 = dd_round(b0) / gamma;
+      if (NRHS == 2) {
+        dd_add_prod(a1, -theta, ca1);
+        if (HASW) dd_add_prod(a1, -sigma, wa1);
+        oa1 = dd_round(a1) / gamma;
+        dd_add_prod(b1, -theta, cb1);
+        if (HASW) dd_add_prod(b1, -sigma, wb1);
+        ob1 = dd_round(b1) / gamma;
+      }
+    } else {
+      oa0 = dd_round(a0);
+      ob0 = dd_round(b0);
+      if (NRHS == 2) {
+        oa1 = dd_round(a1);
+        ob1 = dd_round(b1);
+      }
+    }
+    if (inner) {
+      *(sd2*)(s0.out + r) = sd2{oa0, ob0};
+      if (NRHS == 2) *(sd2*)(s1.out + r) = sd2{oa1, ob1};
+    } else {
+      if (r < n) {
+        s0.out[r] = oa0;
+        if (NRHS == 2) s1.out[r] = oa1;
+      }
+      if (r + 1 < n) {
+        s0.out[r + 1] = ob0;
+        if (NRHS == 2) s1.out[r + 1] = ob1;
+      }
+    }
+    if (RES) {
+      if (r < n) {
+        dd_add(ax, -bres[r]);
+        const double ri = -dd_round(ax);
+        dd_add_prod(r2, ri, ri);
+      }
+      if (r + 1 < n) {
+        dd_add(bx, -bres[r + 1]);
+        const double ri = -dd_round(bx);
+        dd_add_prod(r2, ri, ri);
+      }
+    }
+  }
+  if (RES) wg_store_partial<2>(r2, rpart, lb);
+  gate_mark_ran(gate);
+}
+
 // Batched pass j over the 256-row blocks listed in ablk[0, *nlist) (those of
 // the systems not done when the list was made; a workgroup takes every
 // gridDim.x-th entry).  Every block belongs to one system (blk_sys), whose
@@ -600,9 +840,11 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
   }
 }
 
-// Reduce a per-thread dd over the workgroup and store it as partial `slot`.
+// Reduce a per-thread dd over the NW waves of the workgroup and store it as
+// partial `slot`.
+template <int NW>
 __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot) {
-  __shared__ double ls[SLICES_PER_WG], le[SLICES_PER_WG];
+  __shared__ double ls[NW], le[NW];
   a = dd_wave_reduce(a);
   int wv = threadIdx.x / SSCG_WAVE;
   if ((threadIdx.x & (SSCG_WAVE - 1)) == 0) {
@@ -612,7 +854,7 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot) {
   __syncthreads();
   if (threadIdx.x == 0) {
     dd t{ls[0], le[0]};
-    for (int q = 1; q < SLICES_PER_WG; ++q) dd_merge(t, dd{ls[q], le[q]});
+    for (int q = 1; q < NW; ++q) dd_merge(t, dd{ls[q], le[q]});
     part[2 * slot] = t.s;
     part[2 * slot + 1] = t.e;
   }
@@ -1163,6 +1405,30 @@ hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, c
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(WG) void k_sd_pairs(const int32_t* __restrict__ sd_nd,
+                                                 const int32_t* __restrict__ sd_delta,
+                                                 const double* __restrict__ sd_tab, int nslices,
+                                                 int32_t* __restrict__ flag) {
+  const int t = blockIdx.x * WG + threadIdx.x;
+  const int a = 2 * t, b = 2 * t + 1;
+  if (b >= nslices) return;
+  bool same = sd_nd[a] == sd_nd[b];
+  for (int k = 0; k < SD_DIAG; ++k)
+    same = same && sd_delta[(int64_t)a * SD_DIAG + k] == sd_delta[(int64_t)b * SD_DIAG + k];
+  for (int i = 0; i < 4; ++i)
+    same = same && __double_as_longlong(sd_tab[(int64_t)a * 4 + i]) ==
+                       __double_as_longlong(sd_tab[(int64_t)b * 4 + i]);
+  if (!same) atomicOr(flag, 1);
+}
+
+hipError_t launch_sd_pairs(const int32_t* sd_nd, const int32_t* sd_delta, const double* sd_tab,
+                           int nslices, int32_t* flag, hipStream_t st) {
+  const int np = (nslices + 1) / 2;
+  hipLaunchKernelGGL(k_sd_pairs, dim3((np + WG - 1) / WG), dim3(WG), 0, st, sd_nd, sd_delta,
+                     sd_tab, nslices, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_sell_sdia_sys(const int32_t* rowptr, const int32_t* perm, int slice0, int nsl,
                                 const int32_t* scol, const double* sval, const int64_t* off,
                                 const int32_t* width, int32_t* sd_nd, int32_t* sd_delta,
@@ -1309,12 +1575,20 @@ void mpk_launch_c(dim3 grid, const DevMat& A, double theta, double sigma, double
                        theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
 }
 
-// The compact forms the copy has: the slice-diagonal form, else 16-bit
-// column offsets, and value indices with them.
+// The compact forms the copy has: the slice-diagonal form (in pairs of
+// slices where they agree), else 16-bit column offsets, and value indices
+// with them.
 template <int NRHS, bool CHEB, bool HASW>
 void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                 MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
-  if (A.sd_code)
+  if (A.sd_code && A.sd_pair) {
+    if (res.x)
+      hipLaunchKernelGGL((k_mpk_sdp<NRHS, CHEB, HASW, true>), grid, dim3(2 * SSCG_WAVE), 0, st, A,
+                         theta, sigma, gamma, s0, s1, g, res.x, res.b, res.part);
+    else
+      hipLaunchKernelGGL((k_mpk_sdp<NRHS, CHEB, HASW, false>), grid, dim3(2 * SSCG_WAVE), 0, st,
+                         A, theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
+  } else if (A.sd_code)
     mpk_launch_c<NRHS, CHEB, HASW, false, false, true>(grid, A, theta, sigma, gamma, s0, s1, g,
                                                        res, st);
   else if (A.col16 && A.vidx)

@@ -29,7 +29,8 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 FULL = sscg.FMT_COL16 | sscg.FMT_VTAB
 SDIA = FULL | sscg.FMT_SDIA
-ALL_FORMS = sscg.FMT_COL16 | sscg.FMT_VTAB | sscg.FMT_SDIA
+SDP = SDIA | sscg.FMT_SDPAIR
+ALL_FORMS = sscg.FMT_COL16 | sscg.FMT_VTAB | sscg.FMT_SDIA | sscg.FMT_SDPAIR
 
 
 def say(*a):
@@ -148,27 +149,68 @@ def far_ring(n=33000):
     return A
 
 
-def mpk(ctx, A, s, p, r, lmin, lmax):
+def mpk(ctx, A, s, p, r, lmin, lmax, basis="chebyshev", first=False):
     n = A.n
     ld = (n + 63) // 64 * 64
     rcol = s + 1
-    Y = torch.zeros((2 * s + 1) * ld, dtype=torch.float64, device=DEV)
+    ncol = s + 1 if first else 2 * s + 1
+    Y = torch.zeros(ncol * ld, dtype=torch.float64, device=DEV)
     Y[:n] = dvec(p)
-    Y[rcol * ld: rcol * ld + n] = dvec(r)
-    sscg.sscg_mpk(ctx, sscg.DeviceCsr.from_host(A, DEV), s, False, sscg.BASIS_CHEBYSHEV, lmin, lmax,
-                  Y, ld, rcol)
+    if not first:
+        Y[rcol * ld: rcol * ld + n] = dvec(r)
+    code = sscg.BASIS_CHEBYSHEV if basis == "chebyshev" else sscg.BASIS_MONOMIAL
+    sscg.sscg_mpk(ctx, sscg.DeviceCsr.from_host(A, DEV), s, first, code, lmin, lmax, Y, ld, rcol)
     Yh = host(Y)
-    return [Yh[c * ld: c * ld + n] for c in range(2 * s + 1)]
+    return [Yh[c * ld: c * ld + n] for c in range(ncol)]
 
 
-def oracle_basis(A, s, p, r, lmin, lmax):
+def oracle_basis(A, s, p, r, lmin, lmax, basis="chebyshev", first=False):
     ar = CR()
-    prm = sstep.basis_params("chebyshev", s, lmin, lmax, ar)
-    return sstep.krylov_basis(ar, A, p, r, s, False, prm)
+    prm = sstep.basis_params(basis, s, lmin, lmax, ar)
+    return sstep.krylov_basis(ar, A, p, r, s, first, prm)
 
 
-def check_against_oracle(got, A, s, p, r, lmin, lmax, what):
-    ref = oracle_basis(A, s, p, r, lmin, lmax)
+def slice_tables(A):
+    """Per 64-row slice: its sorted column distances and the sorted bit
+    patterns of its stored values (the slice-diagonal form's tables)."""
+    out = []
+    for t in range((A.n + 63) // 64):
+        ds, vs = set(), set()
+        for i in range(64 * t, min(A.n, 64 * t + 64)):
+            for k in range(int(A.rowptr[i]), int(A.rowptr[i + 1])):
+                ds.add(int(A.col[k]) - i)
+                vs.add(np.float64(A.val[k]).tobytes())
+        out.append((tuple(sorted(ds)), tuple(sorted(vs))))
+    return out
+
+
+def pairs_agree(A):
+    """Whether slices 2t and 2t + 1 have the same tables for every t (the
+    condition of the paired pass)."""
+    t = slice_tables(A)
+    return all(t[2 * i] == t[2 * i + 1] for i in range(len(t) // 2))
+
+
+def laplace1d(n):
+    return problems._stencil_csr((n,), 2.0)
+
+
+def pair_weighted(n, seed):
+    """Tridiagonal, row i scaled by c[i // 128] (+ 0.1 on the diagonal):
+    values change from one pair of slices to the next and agree within it."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.5, 2.0, size=(n + 127) // 128)
+    i = np.arange(n)
+    ci = c[i // 128]
+    lo, hi = i > 0, i < n - 1
+    rows = np.concatenate([i, i[lo], i[hi]])
+    cols = np.concatenate([i, i[lo] - 1, i[hi] + 1])
+    vals = np.concatenate([2.0 * ci + 0.1, -ci[lo], -ci[hi]])
+    return csr_of(n, rows, cols, vals)
+
+
+def check_against_oracle(got, A, s, p, r, lmin, lmax, what, basis="chebyshev", first=False):
+    ref = oracle_basis(A, s, p, r, lmin, lmax, basis, first)
     worst, exact = 0.0, 0
     for g, o in zip(got, ref):
         worst = max(worst, float((np.abs(g - o) / np.maximum(np.abs(o), 1e-300)).max()))
@@ -195,7 +237,11 @@ def test_forms_chosen_as_documented(ctx):
         ("column 32999 rows away", far_ring(), 0),
         ("ring, per-slice weights", ring(64 * 8, 4)[0], FULL),
         ("3-D Poisson", problems.poisson3d(12), SDIA),
-        ("2-D Poisson, ragged n", problems.poisson2d(25, 41), SDIA),
+        ("3-D Poisson, planes of 4 slices", problems.poisson3d(16), SDP),
+        ("2-D Poisson, ragged n", problems.poisson2d(25, 41), SDP),
+        ("1-D Laplacian, ragged last pair", laplace1d(64 * 7 + 17), SDP),
+        ("1-D Laplacian, odd slice count", laplace1d(64 * 8 + 5), SDP),
+        ("1-D Laplacian, one-row last slice", laplace1d(64 * 9 + 1), SDIA),
         ("9-point stencil: 9 distances", nine_point(20), FULL),
         ("a repeated column in a row", with_duplicate(problems.poisson2d(16)), FULL),
         ("graph Laplacian", problems.graph_laplacian(3001, 7), sscg.FMT_COL16),
@@ -208,6 +254,8 @@ def test_forms_chosen_as_documented(ctx):
         pad[:A.n] = lens
         want_stored = int(pad.reshape(nsl, 64).max(axis=1).sum()) * 64
         say(f"{what}: n={A.n} format {f} stored {stored}")
+        if want & sscg.FMT_SDIA:
+            assert bool(want & sscg.FMT_SDPAIR) == pairs_agree(A), what  # the case's premise
         assert f == want, what
         assert stored == want_stored, what
 
@@ -293,31 +341,48 @@ def test_fp32_pass_table_form_matches_wider_forms_bitwise(ctx):
     say("FP32 pass: table, 16-bit and 32-bit forms bit-identical on the first block")
 
 
-@pytest.mark.parametrize("name", ["poisson3d_12", "poisson2d_25x41", "poisson2d_explicit_zero",
-                                  "poisson3d_9", "poisson3d_20", "poisson2d_256x9"])
+SD_CASES = {
+    "poisson3d_12": lambda: problems.poisson3d(12),
+    "poisson2d_25x41": lambda: problems.poisson2d(25, 41),
+    "poisson2d_explicit_zero": lambda: with_explicit_zero(problems.poisson2d(24), 100),
+    "poisson3d_9": lambda: problems.poisson3d(9),
+    "poisson3d_20": lambda: problems.poisson3d(20),
+    "poisson2d_256x9": lambda: problems.poisson2d(256, 9),
+    "poisson3d_16": lambda: problems.poisson3d(16),
+    "poisson2d_128x9": lambda: problems.poisson2d(128, 9),
+    "laplace1d_465": lambda: laplace1d(64 * 7 + 17),
+    "laplace1d_517": lambda: laplace1d(64 * 8 + 5),
+    "pair_weighted_1400": lambda: pair_weighted(1400, 81),
+    "pair_weighted_2": lambda: pair_weighted(2, 82),
+}
+
+
+@pytest.mark.parametrize("name", list(SD_CASES))
 def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
-    """The slice-diagonal form against the oracle's row sums and against the
-    value-table, 16-bit and 32-bit forms of the same matrix (sscg_set_forms),
-    bit for bit: two-sequence Chebyshev passes, ragged last slice, a stored
-    explicit zero among three values; distances of 400 rows (20^3) and 256
-    rows (256 x 9)."""
-    A = {"poisson3d_12": lambda: problems.poisson3d(12),
-         "poisson2d_25x41": lambda: problems.poisson2d(25, 41),
-         "poisson2d_explicit_zero": lambda: with_explicit_zero(problems.poisson2d(24), 100),
-         "poisson3d_9": lambda: problems.poisson3d(9),
-         "poisson3d_20": lambda: problems.poisson3d(20),
-         "poisson2d_256x9": lambda: problems.poisson2d(256, 9)}[name]()
+    """The slice-diagonal form, taken one slice or (where consecutive slices
+    agree) two slices per wavefront, against the oracle's row sums and
+    against the value-table, 16-bit and 32-bit forms of the same matrix
+    (sscg_set_forms), bit for bit: two-sequence Chebyshev passes, ragged last
+    slice, a stored explicit zero among three values; distances of 400 rows
+    (20^3) and 256 rows (256 x 9); for the paired pass an odd slice count, a
+    ragged last pair, boundary pairs whose neighbours leave [0, n), values
+    that change from pair to pair, and n = 2."""
+    A = SD_CASES[name]()
     p, r = vecs(A.n, 61)
+    paired = pairs_agree(A)
     outs = {}
     try:
-        for forms in (ALL_FORMS, sscg.FMT_COL16 | sscg.FMT_VTAB, sscg.FMT_COL16, 0):
+        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDPAIR, sscg.FMT_COL16 | sscg.FMT_VTAB,
+                      sscg.FMT_COL16, 0):
             sscg.sscg_set_forms(ctx, forms)
             f, _ = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
             outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX)
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    assert sorted(outs) == [0, sscg.FMT_COL16, FULL, SDIA] or (
-        name == "poisson2d_explicit_zero" and sorted(outs) == [0, sscg.FMT_COL16, SDIA]), sorted(outs)
+    want = [0, sscg.FMT_COL16, FULL, SDIA] + ([SDP] if paired else [])
+    assert sorted(outs) == want or (
+        name == "poisson2d_explicit_zero" and sorted(outs) == [f for f in want if f != FULL]), \
+        sorted(outs)
     check_against_oracle(outs[SDIA], A, S, p, r, LMIN, LMAX, f"slice-diagonal {name}")
     for f, y in outs.items():
         for c in range(2 * S + 1):
@@ -325,18 +390,44 @@ def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
     say(f"{name}: slice-diagonal form bit-identical to forms {sorted(outs)}")
 
 
-def test_slice_diagonal_whole_solve_with_fused_residual(ctx):
+@pytest.mark.parametrize("basis,first", [("monomial", False), ("monomial", True),
+                                         ("chebyshev", True)])
+@pytest.mark.parametrize("name", ["poisson3d_16", "laplace1d_517", "pair_weighted_1400"])
+def test_paired_pass_other_bases_match_oracle_and_single_slices(ctx, name, basis, first):
+    """The paired pass's monomial and one-sequence (first block) forms: the
+    oracle's basis, and the one-slice-per-wavefront pass bit for bit."""
+    A = SD_CASES[name]()
+    assert pairs_agree(A)
+    p, r = vecs(A.n, 67)
+    outs = {}
+    try:
+        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDPAIR):
+            sscg.sscg_set_forms(ctx, forms)
+            f, _ = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
+            outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX, basis, first)
+    finally:
+        sscg.sscg_set_forms(ctx, ALL_FORMS)
+    assert sorted(outs) == [SDIA, SDP]
+    check_against_oracle(outs[SDP], A, S, p, r, LMIN, LMAX, f"paired {name} {basis} first={first}",
+                         basis, first)
+    for a, b in zip(outs[SDP], outs[SDIA]):
+        assert np.array_equal(a, b), name
+
+
+@pytest.mark.parametrize("N", [14, 16])
+def test_slice_diagonal_whole_solve_with_fused_residual(ctx, N):
     """Whole adaptive solves (the first pass of every block also forms the
     true residual through the form) with and without the slice-diagonal
-    form: same schedule, same bits, and the oracle's iterates."""
-    A = problems.poisson3d(14)
+    form, and with and without pairs of slices (16^3: planes of four
+    slices): same schedule, same bits, and the oracle's iterates."""
+    A = problems.poisson3d(N)
     b = problems.uniform(A.n, 71)
     x1 = np.zeros(A.n)
     kw = dict(mode="adaptive", s_max=10, tol=1e-12, basis="chebyshev", lmin=0.05, lmax=12.0)
     ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
     xs = []
     try:
-        for forms in (ALL_FORMS, sscg.FMT_COL16 | sscg.FMT_VTAB):
+        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDPAIR, sscg.FMT_COL16 | sscg.FMT_VTAB):
             sscg.sscg_set_forms(ctx, forms)
             x = dvec(x1)
             hist = sscg.History(4096, 10)
@@ -346,10 +437,10 @@ def test_slice_diagonal_whole_solve_with_fused_residual(ctx):
             xs.append(host(x))
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    assert np.array_equal(xs[0], xs[1])
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
     assert np.linalg.norm(xs[0] - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
 
 
 def test_set_forms_rejects_unknown_bits(ctx):
     with pytest.raises(sscg.SscgError):
-        sscg.sscg_set_forms(ctx, 8)
+        sscg.sscg_set_forms(ctx, 16)
