@@ -841,10 +841,10 @@ def main():
                     help="basis of the single-solve workloads (default: the workload's)")
     ap.add_argument("--c-mode", choices=["const", "theory"], default="const",
                     help="c_{k,j}: the constant 1, or 6 N_k j kappa(A) of Section 4.1")
-    ap.add_argument("--forms", type=int, default=15,
+    ap.add_argument("--forms", type=int, default=31,
                     help="compact forms of A the library may use (bits: 1 16-bit offsets, "
                          "2 value tables, 4 slice-diagonal, 8 slice-diagonal in pairs of "
-                         "slices; default all)")
+                         "slices, 16 one value per distance; default all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-classical", action="store_true",
                     help="skip timing classical CG (s = 1) beside the s-step solve")
@@ -920,7 +920,7 @@ def main():
     from paper_1701_03989_amd import problems, sscg
 
     wl = dict(WORKLOADS[args.workload])
-    variant = args.basis not in (None, wl["basis"]) or args.c_mode != "const" or args.forms != 15
+    variant = args.basis not in (None, wl["basis"]) or args.c_mode != "const" or args.forms != 31
     if args.basis:
         wl["basis"] = args.basis
     A, b, x1 = problems.poisson3d_128_system(0, N=wl["N"])

@@ -276,9 +276,15 @@ int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, d
  * values, bit for bit, so the pass takes such a pair in one wavefront, two
  * rows per lane, with 16-byte loads.  The same bits result. */
 #define SSCG_FMT_SDPAIR 8
+/* SSCG_FMT_SDVAL (with SSCG_FMT_SDPAIR): in every slice, all rows with an
+ * entry at a given distance have the same value there (stencils with
+ * constant coefficients), and the two slices of each pair agree: the pass
+ * then takes each distance's value from scalar registers instead of
+ * decoding it per row.  The same bits result. */
+#define SSCG_FMT_SDVAL 16
 int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* stored);
 /* Which of the compact forms above the context's later calls may build and
- * read (bit mask of SSCG_FMT_*, default all four; 0 = the stored FP64 values
+ * read (bit mask of SSCG_FMT_*, default all five; 0 = the stored FP64 values
  * with 32-bit indices).  For timing and testing the forms against each
  * other: every form gives the same bits.  Value tables are only used together
  * with 16-bit offsets. */

@@ -159,7 +159,7 @@ int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
 int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   const int n = A->n;
   const int nslices = (n + SSCG_WAVE - 1) / SSCG_WAVE;
-  HIPCHK(ensure(ctx->width, sizeof(int32_t) * (nslices + 4)));
+  HIPCHK(ensure(ctx->width, sizeof(int32_t) * (nslices + 8)));
   HIPCHK(ensure(ctx->off, sizeof(int64_t) * (nslices + 1)));
   // every later kernel gathers through col[]
   int32_t* flag = as<int32_t>(ctx->width) + nslices;
@@ -217,7 +217,12 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   HIPCHK(hipMemsetAsync(flag + 3, 0, sizeof(int32_t), ctx->stream));
   HIPCHK(launch_sd_pairs(as<int32_t>(ctx->sd_nd), as<int32_t>(ctx->sd_delta),
                          as<double>(ctx->sd_tab), nslices, flag + 3, ctx->stream));
-  int32_t fl[4] = {1, 1, 1, 1};
+  // whether each distance of a slice has one value
+  HIPCHK(ensure(ctx->sd_vk, sizeof(uint32_t) * std::max(nslices, 1)));
+  HIPCHK(hipMemsetAsync(flag + 4, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_sd_values(as<int32_t>(ctx->sd_nd), as<uint16_t>(ctx->sd_code), nslices,
+                          as<uint32_t>(ctx->sd_vk), flag + 4, ctx->stream));
+  int32_t fl[5] = {1, 1, 1, 1, 1};
   HIPCHK(hipMemcpyAsync(fl, flag, sizeof fl, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   // forms the caller allowed (sscg_set_forms); tables only with 16-bit offsets
@@ -238,6 +243,8 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   M->sd_tab = nosd ? nullptr : as<double>(ctx->sd_tab);
   M->sd_code = nosd ? nullptr : as<uint16_t>(ctx->sd_code);
   M->sd_pair = !nosd && fl[3] == 0 && (ctx->forms & SSCG_FMT_SDPAIR) && n >= 2 ? 1 : 0;
+  M->sd_vk = M->sd_pair && fl[4] == 0 && (ctx->forms & SSCG_FMT_SDVAL) ? as<uint32_t>(ctx->sd_vk)
+                                                                      : nullptr;
   ctx->mat_bytes = mpk_matrix_bytes(*M, total);
   return SSCG_OK;
 }
@@ -571,7 +578,7 @@ void sscg_destroy(sscg_ctx* c) {
                  &c->rpart, &c->G,   &c->coef, &c->info, &c->scal,  &c->xw,   &c->bw,
                  &c->x1,    &c->lz,  &c->lzab, &c->ctl,  &c->ran,   &c->scol16, &c->svidx, &c->svtab,
                  &c->sval32, &c->Y32, &c->dx,  &c->r64, &c->xu, &c->upart,
-                 &c->sd_nd, &c->sd_delta, &c->sd_tab, &c->sd_code};
+                 &c->sd_nd, &c->sd_delta, &c->sd_tab, &c->sd_code, &c->sd_vk};
   for (Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   BatchWs& w = c->batch;
@@ -678,7 +685,8 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
   if ((rc = build_mat(ctx, A, 0, &M))) return rc;
   // the forms the matrix-powers pass dispatches on: tables only with 16-bit offsets
   const int f = (M.col16 ? SSCG_FMT_COL16 : 0) | (M.col16 && M.vidx ? SSCG_FMT_VTAB : 0) |
-                (M.sd_code ? SSCG_FMT_SDIA : 0) | (M.sd_code && M.sd_pair ? SSCG_FMT_SDPAIR : 0);
+                (M.sd_code ? SSCG_FMT_SDIA : 0) | (M.sd_code && M.sd_pair ? SSCG_FMT_SDPAIR : 0) |
+                (M.sd_code && M.sd_pair && M.sd_vk ? SSCG_FMT_SDVAL : 0);
   if (format) *format = f;
   if (stored) *stored = ctx->sell_total;
   return SSCG_OK;
@@ -687,9 +695,9 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
 int sscg_set_forms(sscg_ctx* ctx, int forms) {
   if (!ctx) return SSCG_ERR_ARG;
   ctx->err.clear();
-  if (forms & ~(SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA | SSCG_FMT_SDPAIR))
-    return fail(ctx, SSCG_ERR_ARG, "forms = %d: bits SSCG_FMT_COL16 | VTAB | SDIA | SDPAIR only",
-                forms);
+  if (forms & ~(SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA | SSCG_FMT_SDPAIR | SSCG_FMT_SDVAL))
+    return fail(ctx, SSCG_ERR_ARG,
+                "forms = %d: bits SSCG_FMT_COL16 | VTAB | SDIA | SDPAIR | SDVAL only", forms);
   ctx->forms = forms;
   return SSCG_OK;
 }

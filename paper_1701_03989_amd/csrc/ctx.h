@@ -64,7 +64,9 @@ struct sscg_ctx {
   sscg_host::Buf scol16;  // 16-bit column offsets of the SELL copy (when they fit)
   sscg_host::Buf svidx, svtab;  // value indices and per-slice value tables (when few values)
   sscg_host::Buf sd_nd, sd_delta, sd_tab, sd_code;  // slice-diagonal form (stencils)
-  int forms = SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA | SSCG_FMT_SDPAIR;  // allowed
+  sscg_host::Buf sd_vk;  // per slice: the value code of each distance, if one per distance
+  int forms = SSCG_FMT_COL16 | SSCG_FMT_VTAB | SSCG_FMT_SDIA | SSCG_FMT_SDPAIR |
+              SSCG_FMT_SDVAL;  // allowed
   // solver workspace
   sscg_host::Buf Y, part, rpart, G, coef, info, scal, xw, bw, x1, lz, lzab, ctl;
   sscg_block_info* hinfo = nullptr;  // pinned, RING entries

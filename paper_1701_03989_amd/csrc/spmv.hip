@@ -552,7 +552,7 @@ typedef double sd2 __attribute__((ext_vector_type(2), aligned(8)));
 // order of its distances with the same dd steps as mpk_slice, so the result
 // is the same to the bit.  Workgroups of two wavefronts cover four slices, as
 // the k_mpk workgroups do, so the residual partials keep their slots.
-template <int NRHS, bool CHEB, bool HASW, bool RES>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool UV>
 __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double theta, double sigma,
                                                            double gamma, MpkSeq s0, MpkSeq s1,
                                                            Gate gate,
@@ -565,7 +565,8 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
   const int lb = xcd_block(nb);
   if (lb >= nb) return;  // not workgroup 0 (nb >= 1 and xcd_block(nb) maps 0 to 0)
   const int lane = threadIdx.x & (SSCG_WAVE - 1);
-  const int t = lb * 2 + (int)(threadIdx.x / SSCG_WAVE);  // the pair of slices
+  // the pair of slices (uniform over the wavefront: scalar registers)
+  const int t = __builtin_amdgcn_readfirstlane(lb * 2 + (int)(threadIdx.x / SSCG_WAVE));
   const int n = A.n;
   dd r2 = dd_zero();
   if (2 * t < A.nslices) {
@@ -577,8 +578,19 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
     for (int k = 0; k < SD_DIAG; ++k) dl[k] = A.sd_delta[(int64_t)us * SD_DIAG + k];
 #pragma unroll
     for (int i = 0; i < SD_VALS; ++i) tv[i] = A.sd_tab[(int64_t)us * 4 + i];
+    // UV: the value of each distance, the same for every row that has it
+    double vu[SD_DIAG];
+    if (UV) {
+      const uint32_t vw = A.sd_vk[us];
+#pragma unroll
+      for (int k = 0; k < SD_DIAG; ++k) {
+        const uint32_t c = (vw >> (2 * k)) & 3u;
+        vu[k] = c == 0u ? tv[0] : (c == 1u ? tv[1] : tv[2]);
+      }
+    }
     const int base = t * 2 * SSCG_WAVE;  // first row of the pair
     const int r = base + 2 * lane;
+    const unsigned lo = 2u * (unsigned)lane;  // the lane's offset from a uniform base
     // uniform: the lowest and highest distance, and which one is 0
     int dmin = 0, dmax = 0, kc = -1;
 #pragma unroll
@@ -593,7 +605,7 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
     // codes of the two rows (padding rows and rows past the last slice: none)
     unsigned ca, cb;
     if (inner) {
-      const uint32_t w2 = *(const uint32_t*)(A.sd_code + r);
+      const uint32_t w2 = ((const uint32_t*)(A.sd_code + base))[(unsigned)lane];
       ca = w2 & 0xFFFFu;
       cb = w2 >> 16;
     } else {
@@ -614,10 +626,11 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
         if (inner) {
 #pragma unroll
           for (int u = 0; u < CH; ++u) {
-            const int off = r + (k0 + u < nd ? dl[k0 + u] : 0);
-            g0[u] = *(const sd2*)(s0.u + off);
-            if (NRHS == 2) g1[u] = *(const sd2*)(s1.u + off);
-            if (RES) gx[u] = *(const sd2*)(xres + off);
+            // a uniform base (scalar registers) + 16 bytes per lane
+            const int ob = base + (k0 + u < nd ? dl[k0 + u] : 0);
+            g0[u] = *(const sd2*)((s0.u + ob) + lo);
+            if (NRHS == 2) g1[u] = *(const sd2*)((s1.u + ob) + lo);
+            if (RES) gx[u] = *(const sd2*)((xres + ob) + lo);
           }
         } else {
 #pragma unroll
@@ -642,13 +655,13 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
           const unsigned da = k < nd ? (ca >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
           const unsigned db = k < nd ? (cb >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
           if (da != (unsigned)SD_ABSENT) {
-            const double v = da == 0u ? tv[0] : (da == 1u ? tv[1] : tv[2]);
+            const double v = UV ? vu[k] : (da == 0u ? tv[0] : (da == 1u ? tv[1] : tv[2]));
             dd_add_prod(a0, v, g0[u].x);
             if (NRHS == 2) dd_add_prod(a1, v, g1[u].x);
             if (RES) dd_add_prod(ax, v, gx[u].x);
           }
           if (db != (unsigned)SD_ABSENT) {
-            const double v = db == 0u ? tv[0] : (db == 1u ? tv[1] : tv[2]);
+            const double v = UV ? vu[k] : (db == 0u ? tv[0] : (db == 1u ? tv[1] : tv[2]));
             dd_add_prod(b0, v, g0[u].y);
             if (NRHS == 2) dd_add_prod(b1, v, g1[u].y);
             if (RES) dd_add_prod(bx, v, gx[u].y);
@@ -682,11 +695,11 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
       double wa0 = 0, wb0 = 0, wa1 = 0, wb1 = 0;
       if (HASW) {
         if (inner) {
-          const sd2 w = *(const sd2*)(s0.w + r);
+          const sd2 w = *(const sd2*)((s0.w + base) + lo);
           wa0 = w.x;
           wb0 = w.y;
           if (NRHS == 2) {
-            const sd2 v = *(const sd2*)(s1.w + r);
+            const sd2 v = *(const sd2*)((s1.w + base) + lo);
             wa1 = v.x;
             wb1 = v.y;
           }
@@ -723,8 +736,8 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
       }
     }
     if (inner) {
-      *(sd2*)(s0.out + r) = sd2{oa0, ob0};
-      if (NRHS == 2) *(sd2*)(s1.out + r) = sd2{oa1, ob1};
+      *(sd2*)((s0.out + base) + lo) = sd2{oa0, ob0};
+      if (NRHS == 2) *(sd2*)((s1.out + base) + lo) = sd2{oa1, ob1};
     } else {
       if (r < n) {
         s0.out[r] = oa0;
@@ -1429,6 +1442,49 @@ hipError_t launch_sd_pairs(const int32_t* sd_nd, const int32_t* sd_delta, const 
   return hipGetLastError();
 }
 
+// One wavefront per slice: for each distance k, the value code of the rows
+// that have an entry there, if they all have the same one.
+__global__ __launch_bounds__(WG) void k_sd_values(const int32_t* __restrict__ sd_nd,
+                                                  const uint16_t* __restrict__ sd_code,
+                                                  int nslices, uint32_t* __restrict__ sd_vk,
+                                                  int32_t* __restrict__ flag) {
+  const int t = blockIdx.x * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  const int lane = threadIdx.x & (SSCG_WAVE - 1);
+  if (t >= nslices) return;  // uniform over the wavefront
+  const int nd = sd_nd[t];
+  const unsigned code = sd_code[(int64_t)t * SSCG_WAVE + lane];
+  uint32_t vk = 0;
+  bool bad = false;
+  for (int k = 0; k < SD_DIAG; ++k) {
+    const unsigned ck = k < nd ? (code >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
+    const bool pr = ck != (unsigned)SD_ABSENT;
+    const unsigned long long m = __ballot(pr);
+    const unsigned ref = m ? (unsigned)__shfl((int)ck, __ffsll((long long)m) - 1, SSCG_WAVE)
+                           : (unsigned)SD_ABSENT;
+    bad = bad || __ballot(pr && ck != ref) != 0ull;
+    vk |= ref << (2 * k);
+  }
+  if (lane == 0) {
+    sd_vk[t] = vk;
+    if (bad) atomicOr(flag, 1);
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_sd_vpairs(const uint32_t* __restrict__ sd_vk, int nslices,
+                                                  int32_t* __restrict__ flag) {
+  const int t = blockIdx.x * WG + threadIdx.x;
+  if (2 * t + 1 < nslices && sd_vk[2 * t] != sd_vk[2 * t + 1]) atomicOr(flag, 1);
+}
+
+hipError_t launch_sd_values(const int32_t* sd_nd, const uint16_t* sd_code, int nslices,
+                            uint32_t* sd_vk, int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_sd_values, dim3(wg_count(nslices)), dim3(WG), 0, st, sd_nd, sd_code,
+                     nslices, sd_vk, flag);
+  const int np = (nslices + 1) / 2;
+  hipLaunchKernelGGL(k_sd_vpairs, dim3((np + WG - 1) / WG), dim3(WG), 0, st, sd_vk, nslices, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_sell_sdia_sys(const int32_t* rowptr, const int32_t* perm, int slice0, int nsl,
                                 const int32_t* scol, const double* sval, const int64_t* off,
                                 const int32_t* width, int32_t* sd_nd, int32_t* sd_delta,
@@ -1575,6 +1631,17 @@ void mpk_launch_c(dim3 grid, const DevMat& A, double theta, double sigma, double
                        theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
 }
 
+template <int NRHS, bool CHEB, bool HASW, bool UV>
+void mpk_launch_sdp(dim3 grid, const DevMat& A, double theta, double sigma, double gamma,
+                    MpkSeq s0, MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
+  if (res.x)
+    hipLaunchKernelGGL((k_mpk_sdp<NRHS, CHEB, HASW, true, UV>), grid, dim3(2 * SSCG_WAVE), 0, st,
+                       A, theta, sigma, gamma, s0, s1, g, res.x, res.b, res.part);
+  else
+    hipLaunchKernelGGL((k_mpk_sdp<NRHS, CHEB, HASW, false, UV>), grid, dim3(2 * SSCG_WAVE), 0, st,
+                       A, theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
+}
+
 // The compact forms the copy has: the slice-diagonal form (in pairs of
 // slices where they agree), else 16-bit column offsets, and value indices
 // with them.
@@ -1582,12 +1649,10 @@ template <int NRHS, bool CHEB, bool HASW>
 void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                 MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
   if (A.sd_code && A.sd_pair) {
-    if (res.x)
-      hipLaunchKernelGGL((k_mpk_sdp<NRHS, CHEB, HASW, true>), grid, dim3(2 * SSCG_WAVE), 0, st, A,
-                         theta, sigma, gamma, s0, s1, g, res.x, res.b, res.part);
+    if (A.sd_vk)
+      mpk_launch_sdp<NRHS, CHEB, HASW, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
     else
-      hipLaunchKernelGGL((k_mpk_sdp<NRHS, CHEB, HASW, false>), grid, dim3(2 * SSCG_WAVE), 0, st,
-                         A, theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
+      mpk_launch_sdp<NRHS, CHEB, HASW, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
   } else if (A.sd_code)
     mpk_launch_c<NRHS, CHEB, HASW, false, false, true>(grid, A, theta, sigma, gamma, s0, s1, g,
                                                        res, st);

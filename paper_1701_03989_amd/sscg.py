@@ -21,7 +21,7 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_OOM = -1, -2, -3
 MODE_ADAPTIVE, MODE_FIXED, MODE_SCHEDULE = 0, 1, 2
 BASIS_MONOMIAL, BASIS_CHEBYSHEV, BASIS_NEWTON = 0, 1, 2
-FMT_COL16, FMT_VTAB, FMT_SDIA, FMT_SDPAIR = 1, 2, 4, 8
+FMT_COL16, FMT_VTAB, FMT_SDIA, FMT_SDPAIR, FMT_SDVAL = 1, 2, 4, 8, 16
 C_CONST, C_THEORY = 0, 1
 PREC_FP64, PREC_MIXED, PREC_VARIABLE = 0, 1, 2
 S_LIMIT = 16
@@ -489,8 +489,8 @@ def sscg_mpk(ctx: int, A: DeviceCsr, s: int, first: bool, basis: int, lmin: floa
 
 
 def sscg_matrix_format(ctx: int, A: DeviceCsr):
-    """(format bits FMT_COL16 | FMT_VTAB | FMT_SDIA | FMT_SDPAIR, padded SELL-64
-    entry count)."""
+    """(format bits FMT_COL16 | FMT_VTAB | FMT_SDIA | FMT_SDPAIR | FMT_SDVAL,
+    padded SELL-64 entry count)."""
     c = A.cstruct()
     f = ctypes.c_int()
     st = ctypes.c_int64()
@@ -499,7 +499,8 @@ def sscg_matrix_format(ctx: int, A: DeviceCsr):
 
 
 def sscg_set_forms(ctx: int, forms: int) -> int:
-    """Allowed compact forms of A (FMT_COL16 | FMT_VTAB | FMT_SDIA | FMT_SDPAIR bits)."""
+    """Allowed compact forms of A (FMT_COL16 | FMT_VTAB | FMT_SDIA | FMT_SDPAIR |
+    FMT_SDVAL bits)."""
     return _check(ctx, lib().sscg_set_forms(ctx, forms))
 
 

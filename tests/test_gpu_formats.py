@@ -30,7 +30,8 @@ DEV = "cuda"
 FULL = sscg.FMT_COL16 | sscg.FMT_VTAB
 SDIA = FULL | sscg.FMT_SDIA
 SDP = SDIA | sscg.FMT_SDPAIR
-ALL_FORMS = sscg.FMT_COL16 | sscg.FMT_VTAB | sscg.FMT_SDIA | sscg.FMT_SDPAIR
+SDV = SDP | sscg.FMT_SDVAL
+ALL_FORMS = sscg.FMT_COL16 | sscg.FMT_VTAB | sscg.FMT_SDIA | sscg.FMT_SDPAIR | sscg.FMT_SDVAL
 
 
 def say(*a):
@@ -191,8 +192,36 @@ def pairs_agree(A):
     return all(t[2 * i] == t[2 * i + 1] for i in range(len(t) // 2))
 
 
+def values_per_distance_agree(A):
+    """Whether in every slice all rows with an entry at one distance have the
+    same value there, and slices 2t and 2t + 1 agree on those values (the
+    condition of the pass that keeps each distance's value in scalar
+    registers)."""
+    per = []
+    for t in range((A.n + 63) // 64):
+        m = {}
+        for i in range(64 * t, min(A.n, 64 * t + 64)):
+            for k in range(int(A.rowptr[i]), int(A.rowptr[i + 1])):
+                m.setdefault(int(A.col[k]) - i, set()).add(np.float64(A.val[k]).tobytes())
+        if any(len(v) > 1 for v in m.values()):
+            return False
+        per.append(m)
+    return all(per[2 * i] == per[2 * i + 1] for i in range(len(per) // 2))
+
+
 def laplace1d(n):
     return problems._stencil_csr((n,), 2.0)
+
+
+def laplace1d_alternating(n):
+    """Tridiagonal with diagonal 2 on even rows and 2.5 on odd ones: every
+    pair of slices agrees, but distance 0 has two values in each slice."""
+    i = np.arange(n)
+    lo, hi = i > 0, i < n - 1
+    rows = np.concatenate([i, i[lo], i[hi]])
+    cols = np.concatenate([i, i[lo] - 1, i[hi] + 1])
+    vals = np.concatenate([2.0 + 0.5 * (i % 2), np.full(lo.sum(), -1.0), np.full(hi.sum(), -1.0)])
+    return csr_of(n, rows, cols, vals)
 
 
 def pair_weighted(n, seed):
@@ -237,11 +266,13 @@ def test_forms_chosen_as_documented(ctx):
         ("column 32999 rows away", far_ring(), 0),
         ("ring, per-slice weights", ring(64 * 8, 4)[0], FULL),
         ("3-D Poisson", problems.poisson3d(12), SDIA),
-        ("3-D Poisson, planes of 4 slices", problems.poisson3d(16), SDP),
-        ("2-D Poisson, ragged n", problems.poisson2d(25, 41), SDP),
-        ("1-D Laplacian, ragged last pair", laplace1d(64 * 7 + 17), SDP),
-        ("1-D Laplacian, odd slice count", laplace1d(64 * 8 + 5), SDP),
+        ("3-D Poisson, planes of 4 slices", problems.poisson3d(16), SDV),
+        ("2-D Poisson, ragged n", problems.poisson2d(25, 41), SDV),
+        ("1-D Laplacian, ragged last pair", laplace1d(64 * 7 + 17), SDV),
+        ("1-D Laplacian, odd slice count", laplace1d(64 * 8 + 5), SDV),
         ("1-D Laplacian, one-row last slice", laplace1d(64 * 9 + 1), SDIA),
+        ("1-D, two diagonal values per slice", laplace1d_alternating(64 * 6 + 9), SDP),
+        ("weights changing from pair to pair", pair_weighted(64 * 6 + 9, 83), SDV),
         ("9-point stencil: 9 distances", nine_point(20), FULL),
         ("a repeated column in a row", with_duplicate(problems.poisson2d(16)), FULL),
         ("graph Laplacian", problems.graph_laplacian(3001, 7), sscg.FMT_COL16),
@@ -254,8 +285,10 @@ def test_forms_chosen_as_documented(ctx):
         pad[:A.n] = lens
         want_stored = int(pad.reshape(nsl, 64).max(axis=1).sum()) * 64
         say(f"{what}: n={A.n} format {f} stored {stored}")
-        if want & sscg.FMT_SDIA:
-            assert bool(want & sscg.FMT_SDPAIR) == pairs_agree(A), what  # the case's premise
+        if want & sscg.FMT_SDIA:  # the case's premises
+            assert bool(want & sscg.FMT_SDPAIR) == pairs_agree(A), what
+            if want & sscg.FMT_SDPAIR:
+                assert bool(want & sscg.FMT_SDVAL) == values_per_distance_agree(A), what
         assert f == want, what
         assert stored == want_stored, what
 
@@ -354,6 +387,7 @@ SD_CASES = {
     "laplace1d_517": lambda: laplace1d(64 * 8 + 5),
     "pair_weighted_1400": lambda: pair_weighted(1400, 81),
     "pair_weighted_2": lambda: pair_weighted(2, 82),
+    "laplace1d_alternating_1289": lambda: laplace1d_alternating(64 * 20 + 9),
 }
 
 
@@ -370,16 +404,17 @@ def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
     A = SD_CASES[name]()
     p, r = vecs(A.n, 61)
     paired = pairs_agree(A)
+    uniform = paired and values_per_distance_agree(A)
     outs = {}
     try:
-        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDPAIR, sscg.FMT_COL16 | sscg.FMT_VTAB,
-                      sscg.FMT_COL16, 0):
+        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDVAL, ALL_FORMS & ~sscg.FMT_SDPAIR,
+                      sscg.FMT_COL16 | sscg.FMT_VTAB, sscg.FMT_COL16, 0):
             sscg.sscg_set_forms(ctx, forms)
             f, _ = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
             outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX)
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    want = [0, sscg.FMT_COL16, FULL, SDIA] + ([SDP] if paired else [])
+    want = [0, sscg.FMT_COL16, FULL, SDIA] + ([SDP] if paired else []) + ([SDV] if uniform else [])
     assert sorted(outs) == want or (
         name == "poisson2d_explicit_zero" and sorted(outs) == [f for f in want if f != FULL]), \
         sorted(outs)
@@ -392,26 +427,30 @@ def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
 
 @pytest.mark.parametrize("basis,first", [("monomial", False), ("monomial", True),
                                          ("chebyshev", True)])
-@pytest.mark.parametrize("name", ["poisson3d_16", "laplace1d_517", "pair_weighted_1400"])
+@pytest.mark.parametrize("name", ["poisson3d_16", "laplace1d_517", "pair_weighted_1400",
+                                  "laplace1d_alternating_1289"])
 def test_paired_pass_other_bases_match_oracle_and_single_slices(ctx, name, basis, first):
-    """The paired pass's monomial and one-sequence (first block) forms: the
-    oracle's basis, and the one-slice-per-wavefront pass bit for bit."""
+    """The paired pass's monomial and one-sequence (first block) forms, with
+    per-row and per-distance values: the oracle's basis, and the
+    one-slice-per-wavefront pass bit for bit."""
     A = SD_CASES[name]()
     assert pairs_agree(A)
+    uniform = values_per_distance_agree(A)
     p, r = vecs(A.n, 67)
     outs = {}
     try:
-        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDPAIR):
+        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDVAL, ALL_FORMS & ~sscg.FMT_SDPAIR):
             sscg.sscg_set_forms(ctx, forms)
             f, _ = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
             outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX, basis, first)
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    assert sorted(outs) == [SDIA, SDP]
+    assert sorted(outs) == [SDIA, SDP] + ([SDV] if uniform else [])
     check_against_oracle(outs[SDP], A, S, p, r, LMIN, LMAX, f"paired {name} {basis} first={first}",
                          basis, first)
-    for a, b in zip(outs[SDP], outs[SDIA]):
-        assert np.array_equal(a, b), name
+    for f, y in outs.items():
+        for a, b in zip(y, outs[SDIA]):
+            assert np.array_equal(a, b), (name, f)
 
 
 @pytest.mark.parametrize("N", [14, 16])
@@ -427,7 +466,8 @@ def test_slice_diagonal_whole_solve_with_fused_residual(ctx, N):
     ref = sstep.solve(A, b, x1, sstep.Opts(**kw))
     xs = []
     try:
-        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDPAIR, sscg.FMT_COL16 | sscg.FMT_VTAB):
+        for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDVAL, ALL_FORMS & ~sscg.FMT_SDPAIR,
+                      sscg.FMT_COL16 | sscg.FMT_VTAB):
             sscg.sscg_set_forms(ctx, forms)
             x = dvec(x1)
             hist = sscg.History(4096, 10)
@@ -437,10 +477,10 @@ def test_slice_diagonal_whole_solve_with_fused_residual(ctx, N):
             xs.append(host(x))
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    assert all(np.array_equal(xs[0], x) for x in xs[1:])
     assert np.linalg.norm(xs[0] - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
 
 
 def test_set_forms_rejects_unknown_bits(ctx):
     with pytest.raises(sscg.SscgError):
-        sscg.sscg_set_forms(ctx, 16)
+        sscg.sscg_set_forms(ctx, 32)
