@@ -529,7 +529,8 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;  // not workgroup 0 (nb >= 1 and xcd_block(nb) maps 0 to 0)
-  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  const int slice =  // uniform over the wavefront
+      __builtin_amdgcn_readfirstlane(lb * SLICES_PER_WG + (int)(threadIdx.x / SSCG_WAVE));
   dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD, 4, double, SD>(
       A, slice, theta, sigma, gamma, s0, s1, xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
@@ -793,7 +794,8 @@ __global__ __launch_bounds__(WG) void k_mpk_batch(DevMat A, int j, MpkSeq s0, Mp
     const BasisPrm bp = sys[q].bp;
     const double theta = CHEB ? bp.c0 : 0.0, sigma = CHEB ? bp.h2 : 0.0;
     const double gamma = CHEB ? (j == 1 ? bp.h : bp.h2) : 1.0;
-    const int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+    const int slice =  // uniform over the wavefront
+        __builtin_amdgcn_readfirstlane(lb * SLICES_PER_WG + (int)(threadIdx.x / SSCG_WAVE));
     dd r2;
     if (sys[q].p32) {  // FP32 block: Y32 sequences, column gathers (no pairs)
       if (sys[q].sd) {
@@ -882,7 +884,8 @@ __global__ __launch_bounds__(WG) void k_residual(DevMat A, const double* __restr
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
-  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  const int slice =  // uniform over the wavefront
+      __builtin_amdgcn_readfirstlane(lb * SLICES_PER_WG + (int)(threadIdx.x / SSCG_WAVE));
   int lane = threadIdx.x & (SSCG_WAVE - 1);
   int row = slice * SSCG_WAVE + lane;
   dd r2 = dd_zero(), b2 = dd_zero();
@@ -984,7 +987,8 @@ __global__ __launch_bounds__(WG) void k_lanczos_spmv(DevMat A, const double* __r
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
-  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  const int slice =  // uniform over the wavefront
+      __builtin_amdgcn_readfirstlane(lb * SLICES_PER_WG + (int)(threadIdx.x / SSCG_WAVE));
   int lane = threadIdx.x & (SSCG_WAVE - 1);
   int row = slice * SSCG_WAVE + lane;
   dd d = dd_zero();
@@ -1077,7 +1081,8 @@ __global__ __launch_bounds__(WG) void k_mpk32(DevMat A, const float* __restrict_
   int nb = (A.nslices + SLICES_PER_WG - 1) / SLICES_PER_WG;
   int lb = xcd_block(nb);
   if (lb >= nb) return;
-  int slice = lb * SLICES_PER_WG + threadIdx.x / SSCG_WAVE;
+  const int slice =  // uniform over the wavefront
+      __builtin_amdgcn_readfirstlane(lb * SLICES_PER_WG + (int)(threadIdx.x / SSCG_WAVE));
   if (slice >= A.nslices) return;
   int lane = threadIdx.x & (SSCG_WAVE - 1);
   int row = slice * SSCG_WAVE + lane;
