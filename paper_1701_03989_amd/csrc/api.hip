@@ -266,12 +266,19 @@ ColPtr colptr_of(const BasisCols& bc, int s, int first) {
 }
 
 int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
-               double mat_bytes, const int* stop, const MpkResidual& res) {
+               double mat_bytes, const int* stop, const MpkResidual& res, const ResCheck& chk) {
   const int n = M.n;
   // the s passes run back to back: one timed interval, a ran flag per pass
+  // (two intervals around the residual test when it runs between them)
   size_t slot = 0;
   HIPCHK(ev_begin(ctx, 0, 0.0, ctx->stream, &slot));
   for (int j = 1; j <= s; ++j) {
+    if (j == 2 && res.x && chk.b2) {
+      HIPCHK(ev_end(ctx, slot, ctx->stream));
+      HIPCHK(launch_res_finalize(res.part, chk.nparts, chk.b2, chk.tol, chk.info, chk.stop,
+                                 ctx->stream));
+      HIPCHK(ev_begin(ctx, 0, 0.0, ctx->stream, &slot));
+    }
     MpkSeq sp{bc.P(j - 1), j >= 2 ? bc.P(j - 2) : nullptr, bc.P(j)};
     MpkSeq sr{nullptr, nullptr, nullptr};
     int nrhs = 1;
@@ -286,6 +293,9 @@ int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, co
                            withres ? res : MpkResidual{}, ctx->stream));
   }
   HIPCHK(ev_end(ctx, slot, ctx->stream));
+  if (s == 1 && res.x && chk.b2)  // no second pass to place the test before
+    HIPCHK(launch_res_finalize(res.part, chk.nparts, chk.b2, chk.tol, chk.info, chk.stop,
+                               ctx->stream));
   return SSCG_OK;
 }
 

@@ -181,10 +181,21 @@ struct BasisCols {
 };
 ColPtr colptr_of(const BasisCols& bc, int s, int first);
 
+// The test of the block's starting iterate on its fused residual: after the
+// first pass, relres_in = ||res|| / sqrt(*b2) into info and *stop set at
+// tol, so that a converged block's remaining passes stand down.
+struct ResCheck {
+  const double* b2 = nullptr;  // null: no test inside the passes
+  int nparts = 0;
+  double tol = 0.0;
+  sscg_block_info* info = nullptr;
+  int* stop = nullptr;  // the solve's stop flag (the passes' gate)
+};
 // The s passes of the matrix powers kernel of one block (res: fused residual
 // of the block's start, may be {NULL}); stop may be NULL.
 int mpk_passes(sscg_ctx* ctx, const DevMat& M, int s, int first, BasisPrm bp, const BasisCols& bc,
-               double mat_bytes, const int* stop, const MpkResidual& res);
+               double mat_bytes, const int* stop, const MpkResidual& res,
+               const ResCheck& chk = ResCheck{});
 // Bytes of A one matrix-powers pass reads in the form it dispatches on: per
 // stored SELL-64 entry 3 (one-byte value index, 16-bit column offset), 10
 // (value, 16-bit offset) or 12 (value, 32-bit index), plus per slice its

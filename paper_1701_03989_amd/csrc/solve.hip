@@ -267,10 +267,10 @@ extern "C" int sscg_solve(sscg_ctx* ctx, const sscg_csr* A, const double* b, dou
     BasisCols bc{P0[par], R0[par], Y, ld, rcol};
     MpkResidual rres{};
     if (!first) rres = MpkResidual{X[par], bw, as<double>(ctx->rpart)};
-    int rc2 = mpk_passes(ctx, M, s, first, bp, bc, ctx->mat_bytes, stop, rres);
+    ResCheck chk{};
+    if (!first) chk = ResCheck{scal + 1, np_res, o.tol, info, stop};
+    int rc2 = mpk_passes(ctx, M, s, first, bp, bc, ctx->mat_bytes, stop, rres, chk);
     if (rc2) return rc2;
-    if (!first)
-      HIPCHK(launch_res_finalize(as<double>(ctx->rpart), np_res, scal + 1, o.tol, info, stop, S1));
     const ColPtr cols = colptr_of(bc, s, first);
     double* Gk = Gbuf + (size_t)par * gsz;
     if ((rc2 = gram_into(ctx, cols, n, d, Gk, stop))) return rc2;
