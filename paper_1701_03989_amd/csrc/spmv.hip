@@ -601,8 +601,10 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
         dmax = (k == 0 || dl[k] > dmax) ? dl[k] : dmax;
         kc = dl[k] == 0 ? k : kc;
       }
-    const bool inner = 2 * t + 1 < A.nslices && base + 2 * SSCG_WAVE <= n && base + dmin >= 0 &&
-                       base + 2 * SSCG_WAVE - 1 + dmax <= n - 1;
+    // (in 64 bits: base + 127 + dmax may exceed the int range for n > 2^30)
+    const bool inner = 2 * t + 1 < A.nslices && (int64_t)base + 2 * SSCG_WAVE <= n &&
+                       (int64_t)base + dmin >= 0 &&
+                       (int64_t)base + 2 * SSCG_WAVE - 1 + dmax <= (int64_t)n - 1;
     // codes of the two rows (padding rows and rows past the last slice: none)
     unsigned ca, cb;
     if (inner) {
@@ -638,7 +640,9 @@ __global__ __launch_bounds__(2 * SSCG_WAVE) void k_mpk_sdp(DevMat A, double thet
 #pragma unroll
           for (int u = 0; u < CH; ++u) {
             const int d = k0 + u < nd ? dl[k0 + u] : 0;
-            const int ia = min(max(r + d, 0), n - 1), ib = min(max(r + 1 + d, 0), n - 1);
+            // clamped in 64 bits (an absent entry's row + distance may leave the int range)
+            const int ia = (int)min(max((int64_t)r + d, (int64_t)0), (int64_t)n - 1);
+            const int ib = (int)min(max((int64_t)r + 1 + d, (int64_t)0), (int64_t)n - 1);
             g0[u].x = s0.u[ia];
             g0[u].y = s0.u[ib];
             if (NRHS == 2) {
