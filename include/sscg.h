@@ -65,8 +65,10 @@ typedef struct sscg_ctx sscg_ctx;
  * non-decreasing, rowptr[n] = nnz; col entries in [0, n).  Only the values
  * are read as given: symmetry and positive definiteness are the caller's
  * promise (a violation shows up as SSCG_BREAKDOWN or SSCG_NOT_CONVERGED).
- * nnz is 64-bit; with the 32-bit rowptr of this form it must stay below 2^31
- * (larger values are rejected with SSCG_ERR_ARG). */
+ * nnz is 64-bit; with the 32-bit rowptr of this form it must stay below 2^31,
+ * and 1 <= n <= 2^31 - 4096 (row indices padded to whole slices and pairs of
+ * slices stay in the int range); other values are rejected with
+ * SSCG_ERR_ARG. */
 typedef struct {
   int32_t n;
   int64_t nnz;

@@ -138,7 +138,8 @@ hipError_t ev_collect(sscg_ctx* c) {
 
 int check_csr(sscg_ctx* ctx, const sscg_csr* A) {
   if (!A) return fail(ctx, SSCG_ERR_ARG, "A is NULL");
-  if (A->n < 1) return fail(ctx, SSCG_ERR_ARG, "n = %d must be >= 1", A->n);
+  if (A->n < 1 || A->n > INT32_MAX - 4095)
+    return fail(ctx, SSCG_ERR_ARG, "n = %d outside [1, 2^31 - 4096]", A->n);
   if (A->nnz < 0 || A->nnz > INT32_MAX)
     return fail(ctx, SSCG_ERR_ARG, "nnz = %lld outside [0, 2^31) (rowptr is 32-bit)",
                 (long long)A->nnz);

@@ -424,6 +424,16 @@ def test_breakdown_and_argument_errors(ctx):
         sscg.sscg_solve(ctx, short, b, x, sscg.make_opts())
     assert not host(x).any()
 
+    # n beyond 2^31 - 4096 is refused before any array is read
+    class Huge(sscg.DeviceCsr):
+        @property
+        def n(self):
+            return 2 ** 31 - 4095
+
+    with pytest.raises(sscg.SscgError) as e:
+        sscg.sscg_matrix_format(ctx, Huge(Ad.rowptr, Ad.col, Ad.val))
+    assert e.value.code == sscg.ERR_ARG and "outside" in str(e.value)
+
 
 def test_bitwise_deterministic(ctx):
     A, b, x1, _ = problems.poisson2d_32_system(1)
