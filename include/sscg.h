@@ -278,11 +278,12 @@ int sscg_newton_shifts(sscg_ctx* ctx, const sscg_csr* A, int m, uint64_t seed, d
  * values, bit for bit, so the pass takes such a pair in one wavefront, two
  * rows per lane, with 16-byte loads.  The same bits result. */
 #define SSCG_FMT_SDPAIR 8
-/* SSCG_FMT_SDVAL (with SSCG_FMT_SDPAIR): in every slice, all rows with an
+/* SSCG_FMT_SDVAL (with SSCG_FMT_SDIA): in every slice, all rows with an
  * entry at a given distance have the same value there (stencils with
- * constant coefficients), and the two slices of each pair agree: the pass
- * then takes each distance's value from scalar registers instead of
- * decoding it per row.  The same bits result. */
+ * constant coefficients): the pass then takes each distance's value from
+ * scalar registers instead of decoding it per row.  With SSCG_FMT_SDPAIR as
+ * well, the two slices of each pair also agree on these values (else the
+ * pairs are not used).  The same bits result. */
 #define SSCG_FMT_SDVAL 16
 int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* stored);
 /* Which of the compact forms above the context's later calls may build and

@@ -220,10 +220,10 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
                          as<double>(ctx->sd_tab), nslices, flag + 3, ctx->stream));
   // whether each distance of a slice has one value
   HIPCHK(ensure(ctx->sd_vk, sizeof(uint32_t) * std::max(nslices, 1)));
-  HIPCHK(hipMemsetAsync(flag + 4, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(hipMemsetAsync(flag + 4, 0, 2 * sizeof(int32_t), ctx->stream));
   HIPCHK(launch_sd_values(as<int32_t>(ctx->sd_nd), as<uint16_t>(ctx->sd_code), nslices,
                           as<uint32_t>(ctx->sd_vk), flag + 4, ctx->stream));
-  int32_t fl[5] = {1, 1, 1, 1, 1};
+  int32_t fl[6] = {1, 1, 1, 1, 1, 1};
   HIPCHK(hipMemcpyAsync(fl, flag, sizeof fl, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   // forms the caller allowed (sscg_set_forms); tables only with 16-bit offsets
@@ -243,9 +243,13 @@ int build_mat(sscg_ctx* ctx, const sscg_csr* A, int equilibrate, DevMat* M) {
   M->sd_delta = nosd ? nullptr : as<int32_t>(ctx->sd_delta);
   M->sd_tab = nosd ? nullptr : as<double>(ctx->sd_tab);
   M->sd_code = nosd ? nullptr : as<uint16_t>(ctx->sd_code);
-  M->sd_pair = !nosd && fl[3] == 0 && (ctx->forms & SSCG_FMT_SDPAIR) && n >= 2 ? 1 : 0;
-  M->sd_vk = M->sd_pair && fl[4] == 0 && (ctx->forms & SSCG_FMT_SDVAL) ? as<uint32_t>(ctx->sd_vk)
-                                                                      : nullptr;
+  M->sd_vk = !nosd && fl[4] == 0 && (ctx->forms & SSCG_FMT_SDVAL) ? as<uint32_t>(ctx->sd_vk)
+                                                                   : nullptr;
+  // pairs of slices also agree on the per-distance values when those are used
+  M->sd_pair = !nosd && fl[3] == 0 && (!M->sd_vk || fl[5] == 0) &&
+                       (ctx->forms & SSCG_FMT_SDPAIR) && n >= 2
+                   ? 1
+                   : 0;
   ctx->mat_bytes = mpk_matrix_bytes(*M, total);
   return SSCG_OK;
 }
@@ -697,7 +701,7 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
   // the forms the matrix-powers pass dispatches on: tables only with 16-bit offsets
   const int f = (M.col16 ? SSCG_FMT_COL16 : 0) | (M.col16 && M.vidx ? SSCG_FMT_VTAB : 0) |
                 (M.sd_code ? SSCG_FMT_SDIA : 0) | (M.sd_code && M.sd_pair ? SSCG_FMT_SDPAIR : 0) |
-                (M.sd_code && M.sd_pair && M.sd_vk ? SSCG_FMT_SDVAL : 0);
+                (M.sd_code && M.sd_vk ? SSCG_FMT_SDVAL : 0);
   if (format) *format = f;
   if (stored) *stored = ctx->sell_total;
   return SSCG_OK;

@@ -131,10 +131,11 @@ struct DevMat {
   // canonical order), so that the pass may take the pair's 128 rows in one
   // wavefront with the tables uniform over it.
   int32_t sd_pair = 0;
-  // With sd_pair: per slice, bits 2k, 2k + 1 the value code that every row
-  // with an entry at distance k has (3 where no row has one), when every
-  // distance of every slice has one value and both slices of each pair agree
-  // (stencils with constant coefficients); else null.
+  // With the slice-diagonal form: per slice, bits 2k, 2k + 1 the value code
+  // that every row with an entry at distance k has (3 where no row has one),
+  // when every distance of every slice has one value (stencils with constant
+  // coefficients); else null.  With sd_pair as well, both slices of each pair
+  // agree on these codes.
   const uint32_t* sd_vk = nullptr;
 };
 constexpr int VTAB = 4;  // values in the table of a slice
@@ -222,8 +223,9 @@ hipError_t launch_sell_compact(const int32_t* scol, int n, const int64_t* off,
 // values.
 hipError_t launch_sd_pairs(const int32_t* sd_nd, const int32_t* sd_delta, const double* sd_tab,
                            int nslices, int32_t* flag, hipStream_t st);
-// sd_vk[t] for every slice t (see DevMat::sd_vk); *flag = 1 if a distance of
-// some slice has two values, or slices 2t and 2t + 1 differ in sd_vk.
+// sd_vk[t] for every slice t (see DevMat::sd_vk); flag[0] = 1 if a distance
+// of some slice has two values, flag[1] = 1 if slices 2t and 2t + 1 differ in
+// sd_vk for some t.
 hipError_t launch_sd_values(const int32_t* sd_nd, const uint16_t* sd_code, int nslices,
                             uint32_t* sd_vk, int32_t* flag, hipStream_t st);
 hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, const double* sval,

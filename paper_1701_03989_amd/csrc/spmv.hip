@@ -362,7 +362,8 @@ __device__ __forceinline__ void wg_store_partial(dd a, double* part, int slot);
 // distance-0 gather (k_mpk; in the batched pass's larger kernel the extra
 // state cost more than the load it saves).
 template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16 = false, bool IL = false,
-          bool VI = false, bool SD = false, int CHK = 4, class V = double, bool CEN = false>
+          bool VI = false, bool SD = false, int CHK = 4, class V = double, bool CEN = false,
+          bool UV = false>
 __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta, double sigma,
                                         double gamma, const MpkSeqV<V>& s0, const MpkSeqV<V>& s1,
                                         const double* __restrict__ xres,
@@ -392,6 +393,16 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
       for (int k = 0; k < SD_DIAG; ++k) dl[k] = A.sd_delta[(int64_t)us * SD_DIAG + k];
 #pragma unroll
       for (int i = 0; i < SD_VALS; ++i) tv[i] = A.sd_tab[(int64_t)us * 4 + i];
+      // UV: each distance's value, the same for every row that has it
+      double vu[SD_DIAG];
+      if (UV) {
+        const uint32_t vw = A.sd_vk[us];
+#pragma unroll
+        for (int k = 0; k < SD_DIAG; ++k) {
+          const uint32_t c = (vw >> (2 * k)) & 3u;
+          vu[k] = c == 0u ? tv[0] : (c == 1u ? tv[1] : tv[2]);
+        }
+      }
       const unsigned code = A.sd_code[row];
       constexpr int CH = CHK;  // entries whose loads are in flight together
 #pragma unroll
@@ -405,7 +416,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
             const int k = k0 + u;
             const unsigned cd = k < nd ? (code >> (2 * k)) & 3u : (unsigned)SD_ABSENT;
             pr[u] = cd != (unsigned)SD_ABSENT;
-            v[u] = cd == 0u ? tv[0] : (cd == 1u ? tv[1] : tv[2]);
+            v[u] = UV ? vu[k] : (cd == 0u ? tv[0] : (cd == 1u ? tv[1] : tv[2]));
             c[u] = row + dl[k];
           }
 #pragma unroll
@@ -519,7 +530,7 @@ __device__ __forceinline__ dd mpk_slice(const DevMat& A, int slice, double theta
   return r2;
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16, bool VI, bool SD>
+template <int NRHS, bool CHEB, bool HASW, bool RES, bool C16, bool VI, bool SD, bool UV>
 __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma, double gamma,
                                             MpkSeq s0, MpkSeq s1, Gate gate,
                                             const double* __restrict__ xres,
@@ -531,7 +542,7 @@ __global__ __launch_bounds__(WG) void k_mpk(DevMat A, double theta, double sigma
   if (lb >= nb) return;  // not workgroup 0 (nb >= 1 and xcd_block(nb) maps 0 to 0)
   const int slice =  // uniform over the wavefront
       __builtin_amdgcn_readfirstlane(lb * SLICES_PER_WG + (int)(threadIdx.x / SSCG_WAVE));
-  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD, 4, double, SD>(
+  dd r2 = mpk_slice<NRHS, CHEB, HASW, RES, C16, false, VI, SD, 4, double, SD, UV>(
       A, slice, theta, sigma, gamma, s0, s1, xres, bres);
   if (RES) wg_store_partial(r2, rpart, lb);
   gate_mark_ran(gate);
@@ -1498,7 +1509,8 @@ hipError_t launch_sd_values(const int32_t* sd_nd, const uint16_t* sd_code, int n
   hipLaunchKernelGGL(k_sd_values, dim3(wg_count(nslices)), dim3(WG), 0, st, sd_nd, sd_code,
                      nslices, sd_vk, flag);
   const int np = (nslices + 1) / 2;
-  hipLaunchKernelGGL(k_sd_vpairs, dim3((np + WG - 1) / WG), dim3(WG), 0, st, sd_vk, nslices, flag);
+  hipLaunchKernelGGL(k_sd_vpairs, dim3((np + WG - 1) / WG), dim3(WG), 0, st, sd_vk, nslices,
+                     flag + 1);
   return hipGetLastError();
 }
 
@@ -1637,15 +1649,15 @@ hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s
   return hipGetLastError();
 }
 
-template <int NRHS, bool CHEB, bool HASW, bool C16, bool VI, bool SD = false>
+template <int NRHS, bool CHEB, bool HASW, bool C16, bool VI, bool SD = false, bool UV = false>
 void mpk_launch_c(dim3 grid, const DevMat& A, double theta, double sigma, double gamma, MpkSeq s0,
                   MpkSeq s1, Gate g, const MpkResidual& res, hipStream_t st) {
   if (res.x)
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16, VI, SD>), grid, dim3(WG), 0, st, A,
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, true, C16, VI, SD, UV>), grid, dim3(WG), 0, st, A,
                        theta, sigma, gamma, s0, s1, g, res.x, res.b, res.part);
   else
-    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16, VI, SD>), grid, dim3(WG), 0, st, A,
-                       theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_mpk<NRHS, CHEB, HASW, false, C16, VI, SD, UV>), grid, dim3(WG), 0, st,
+                       A, theta, sigma, gamma, s0, s1, g, nullptr, nullptr, nullptr);
 }
 
 template <int NRHS, bool CHEB, bool HASW, bool UV>
@@ -1670,7 +1682,10 @@ void mpk_launch(dim3 grid, const DevMat& A, double theta, double sigma, double g
       mpk_launch_sdp<NRHS, CHEB, HASW, true>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
     else
       mpk_launch_sdp<NRHS, CHEB, HASW, false>(grid, A, theta, sigma, gamma, s0, s1, g, res, st);
-  } else if (A.sd_code)
+  } else if (A.sd_code && A.sd_vk)
+    mpk_launch_c<NRHS, CHEB, HASW, false, false, true, true>(grid, A, theta, sigma, gamma, s0, s1,
+                                                             g, res, st);
+  else if (A.sd_code)
     mpk_launch_c<NRHS, CHEB, HASW, false, false, true>(grid, A, theta, sigma, gamma, s0, s1, g,
                                                        res, st);
   else if (A.col16 && A.vidx)

@@ -192,11 +192,11 @@ def pairs_agree(A):
     return all(t[2 * i] == t[2 * i + 1] for i in range(len(t) // 2))
 
 
-def values_per_distance_agree(A):
-    """Whether in every slice all rows with an entry at one distance have the
-    same value there, and slices 2t and 2t + 1 agree on those values (the
-    condition of the pass that keeps each distance's value in scalar
-    registers)."""
+def values_per_distance(A):
+    """(uniform, pairs): whether in every slice all rows with an entry at one
+    distance have the same value there (the condition of the pass that keeps
+    each distance's value in scalar registers), and whether slices 2t and
+    2t + 1 then agree on those values (needed to take them in pairs)."""
     per = []
     for t in range((A.n + 63) // 64):
         m = {}
@@ -204,9 +204,17 @@ def values_per_distance_agree(A):
             for k in range(int(A.rowptr[i]), int(A.rowptr[i + 1])):
                 m.setdefault(int(A.col[k]) - i, set()).add(np.float64(A.val[k]).tobytes())
         if any(len(v) > 1 for v in m.values()):
-            return False
+            return False, False
         per.append(m)
-    return all(per[2 * i] == per[2 * i + 1] for i in range(len(per) // 2))
+    return True, all(per[2 * i] == per[2 * i + 1] for i in range(len(per) // 2))
+
+
+def expected_sd_format(A):
+    """The slice-diagonal format bits the library must choose for A (which
+    has the slice-diagonal form), from the host's own reading of A."""
+    uniform, vpairs = values_per_distance(A)
+    paired = pairs_agree(A) and (not uniform or vpairs)
+    return SDIA | (sscg.FMT_SDPAIR if paired else 0) | (sscg.FMT_SDVAL if uniform else 0)
 
 
 def laplace1d(n):
@@ -265,12 +273,12 @@ def test_forms_chosen_as_documented(ctx):
         ("5 values in a slice", slice_valued(n, 3, np.full(n, 6), 40, 5), sscg.FMT_COL16),
         ("column 32999 rows away", far_ring(), 0),
         ("ring, per-slice weights", ring(64 * 8, 4)[0], FULL),
-        ("3-D Poisson", problems.poisson3d(12), SDIA),
+        ("3-D Poisson", problems.poisson3d(12), SDIA | sscg.FMT_SDVAL),
         ("3-D Poisson, planes of 4 slices", problems.poisson3d(16), SDV),
         ("2-D Poisson, ragged n", problems.poisson2d(25, 41), SDV),
         ("1-D Laplacian, ragged last pair", laplace1d(64 * 7 + 17), SDV),
         ("1-D Laplacian, odd slice count", laplace1d(64 * 8 + 5), SDV),
-        ("1-D Laplacian, one-row last slice", laplace1d(64 * 9 + 1), SDIA),
+        ("1-D Laplacian, one-row last slice", laplace1d(64 * 9 + 1), SDIA | sscg.FMT_SDVAL),
         ("1-D, two diagonal values per slice", laplace1d_alternating(64 * 6 + 9), SDP),
         ("weights changing from pair to pair", pair_weighted(64 * 6 + 9, 83), SDV),
         ("9-point stencil: 9 distances", nine_point(20), FULL),
@@ -285,10 +293,8 @@ def test_forms_chosen_as_documented(ctx):
         pad[:A.n] = lens
         want_stored = int(pad.reshape(nsl, 64).max(axis=1).sum()) * 64
         say(f"{what}: n={A.n} format {f} stored {stored}")
-        if want & sscg.FMT_SDIA:  # the case's premises
-            assert bool(want & sscg.FMT_SDPAIR) == pairs_agree(A), what
-            if want & sscg.FMT_SDPAIR:
-                assert bool(want & sscg.FMT_SDVAL) == values_per_distance_agree(A), what
+        if want & sscg.FMT_SDIA:  # the case's premise, from the host's reading of A
+            assert want == expected_sd_format(A), what
         assert f == want, what
         assert stored == want_stored, what
 
@@ -403,18 +409,22 @@ def test_slice_diagonal_form_matches_oracle_and_other_forms_bitwise(ctx, name):
     that change from pair to pair, and n = 2."""
     A = SD_CASES[name]()
     p, r = vecs(A.n, 61)
-    paired = pairs_agree(A)
-    uniform = paired and values_per_distance_agree(A)
+    uniform, vpairs = values_per_distance(A)
+    paired_any = pairs_agree(A)  # pairs taken when the values are decoded per row
     outs = {}
     try:
         for forms in (ALL_FORMS, ALL_FORMS & ~sscg.FMT_SDVAL, ALL_FORMS & ~sscg.FMT_SDPAIR,
+                      ALL_FORMS & ~(sscg.FMT_SDVAL | sscg.FMT_SDPAIR),
                       sscg.FMT_COL16 | sscg.FMT_VTAB, sscg.FMT_COL16, 0):
             sscg.sscg_set_forms(ctx, forms)
             f, _ = sscg.sscg_matrix_format(ctx, sscg.DeviceCsr.from_host(A, DEV))
             outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX)
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    want = [0, sscg.FMT_COL16, FULL, SDIA] + ([SDP] if paired else []) + ([SDV] if uniform else [])
+    # ALL, ALL without per-distance values, ALL without pairs, neither; the plain forms
+    want = {expected_sd_format(A), SDP if paired_any else SDIA,
+            SDIA | (sscg.FMT_SDVAL if uniform else 0), SDIA, FULL, sscg.FMT_COL16, 0}
+    want = sorted(want)
     assert sorted(outs) == want or (
         name == "poisson2d_explicit_zero" and sorted(outs) == [f for f in want if f != FULL]), \
         sorted(outs)
@@ -435,7 +445,8 @@ def test_paired_pass_other_bases_match_oracle_and_single_slices(ctx, name, basis
     one-slice-per-wavefront pass bit for bit."""
     A = SD_CASES[name]()
     assert pairs_agree(A)
-    uniform = values_per_distance_agree(A)
+    uniform, vpairs = values_per_distance(A)
+    assert not uniform or vpairs
     p, r = vecs(A.n, 67)
     outs = {}
     try:
@@ -445,11 +456,11 @@ def test_paired_pass_other_bases_match_oracle_and_single_slices(ctx, name, basis
             outs[f] = mpk(ctx, A, S, p, r, LMIN, LMAX, basis, first)
     finally:
         sscg.sscg_set_forms(ctx, ALL_FORMS)
-    assert sorted(outs) == [SDIA, SDP] + ([SDV] if uniform else [])
+    assert sorted(outs) == sorted({SDP, SDV if uniform else SDP, SDIA | (sscg.FMT_SDVAL if uniform else 0)})
     check_against_oracle(outs[SDP], A, S, p, r, LMIN, LMAX, f"paired {name} {basis} first={first}",
                          basis, first)
     for f, y in outs.items():
-        for a, b in zip(y, outs[SDIA]):
+        for a, b in zip(y, outs[SDP]):
             assert np.array_equal(a, b), (name, f)
 
 
