@@ -255,8 +255,9 @@ __device__ __forceinline__ bool sdia_slice(int slice, int row, int len,
   over |= __ballot(dup) != 0;
   // Canonical order: distances ascending, values by their bits ascending
   // (the codes renumbered to match), so that slices with the same distances
-  // and values store the same tables.  (Every row sum is correctly rounded:
-  // the order of its terms does not change it.)
+  // and values store the same tables.  (Each row sum is formed in
+  // double-double and rounded once: whatever the order of its terms, that is
+  // the correctly rounded sum but for vanishingly rare near-ties.)
   int dr = 0, vr = 0;  // lane k < nd: rank of distance k; lane c < m: rank of value c
   for (int i = 0; i < nd; ++i) dr += __shfl(ds, i, SSCG_WAVE) < ds ? 1 : 0;
   for (int i = 0; i < m; ++i)
@@ -1446,6 +1447,9 @@ hipError_t launch_sell_sdia(const int32_t* rowptr, int n, const int32_t* scol, c
   return hipGetLastError();
 }
 
+// *flag = 1 if slices 2t and 2t + 1 differ in their count, distances or
+// values (bit patterns) for some t; the tables are stored sorted, so equal
+// slices have equal tables.
 __global__ __launch_bounds__(WG) void k_sd_pairs(const int32_t* __restrict__ sd_nd,
                                                  const int32_t* __restrict__ sd_delta,
                                                  const double* __restrict__ sd_tab, int nslices,
@@ -1498,6 +1502,7 @@ __global__ __launch_bounds__(WG) void k_sd_values(const int32_t* __restrict__ sd
   }
 }
 
+// *flag = 1 if slices 2t and 2t + 1 differ in their value codes for some t.
 __global__ __launch_bounds__(WG) void k_sd_vpairs(const uint32_t* __restrict__ sd_vk, int nslices,
                                                   int32_t* __restrict__ flag) {
   const int t = blockIdx.x * WG + threadIdx.x;
