@@ -216,7 +216,6 @@ extern "C" int sscg_batch_tuning(sscg_ctx* ctx, int32_t* kappa_threads, int32_t*
 int sscg_host::batch_enqueue_block(sscg_ctx* ctx, const DevMat& M, const BatchCfg& c,
                                    hipStream_t st) {
   HIPCHK(launch_batch_plan(c, st));
-  if (c.vprec) HIPCHK(launch_batch_cast32(c, st));
   const int cheb = c.basis == SSCG_BASIS_CHEBYSHEV;
   auto col32 = [&](int col) { return c.Y32 ? c.Y32 + (int64_t)col * c.ld : nullptr; };
   for (int j = 1; j <= c.S; ++j) {

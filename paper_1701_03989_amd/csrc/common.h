@@ -541,8 +541,6 @@ hipError_t launch_mpk_batch(const DevMat& A, int j, int cheb, int nrhs, MpkSeq s
                             const int32_t* blk_sys, const int32_t* ablk, const int32_t* nl,
                             int gblk, int chunk, const MpkResidual& res, const double2* tg,
                             double2* tw, hipStream_t st);
-// FP32 blocks: P_0 and R_0 (columns 0 and S + 1 of Y) rounded into Y32.
-hipError_t launch_batch_cast32(const BatchCfg& c, hipStream_t st);
 // t[i] = (a[i], b[i]), i < n.
 hipError_t launch_pair(const double* a, const double* b, int64_t n, double2* t, hipStream_t st);
 // Set-up from the residual of x_1 (rpart) and ||b||^2 (bpart): relres0, eps*;

@@ -296,23 +296,13 @@ __global__ __launch_bounds__(WG) void k_recover_batch(BatchCfg c) {
                   batch_col(c, 0));
     // the (p, r) pairs the next block's first pass gathers (each thread its own row)
     if (c.sys[q].il) c.T[0][i] = make_double2(batch_col(c, 0)[i], batch_col(c, c.S + 1)[i]);
+    // and the FP32 P_0 = RN32(p), R_0 = RN32(r) the next block reads if the
+    // plan makes it an FP32 block (its other columns the passes write)
+    if (c.vprec && c.Y32) {
+      c.Y32[i] = (float)batch_col(c, 0)[i];
+      c.Y32[(int64_t)(c.S + 1) * c.ld + i] = (float)batch_col(c, c.S + 1)[i];
+    }
     __syncthreads();  // cf is read before the next block's system rewrites it
-  }
-}
-
-// FP32 blocks: their P_0 = RN32(p) and R_0 = RN32(r) into Y32, over the
-// listed blocks (the other columns of an FP32 basis are written in FP32 by
-// the passes).
-__global__ __launch_bounds__(WG) void k_batch_cast32(BatchCfg c) {
-  const int nl = c.active[1];
-  for (int li = blockIdx.x; li < nl; li += gridDim.x) {
-    const int lb = c.ablk[li];
-    const int q = c.blk_sys[lb];
-    if (q < 0 || c.sys[q].done || !c.sys[q].p32) continue;
-    const int64_t i = (int64_t)lb * BATCH_ROWS + threadIdx.x;
-    const int64_t r0 = (int64_t)(c.S + 1) * c.ld;
-    c.Y32[i] = (float)c.Y[i];
-    c.Y32[r0 + i] = (float)c.Y[r0 + i];
   }
 }
 
@@ -570,11 +560,6 @@ hipError_t launch_div_vec(const double* w, const double* beta, int n, double* ou
 
 hipError_t launch_recover_batch(const BatchCfg& c, hipStream_t st) {
   hipLaunchKernelGGL(k_recover_batch, dim3(batch_grid(c.gblk)), dim3(WG), 0, st, c);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_cast32(const BatchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_cast32, dim3(batch_grid(c.gblk)), dim3(WG), 0, st, c);
   return hipGetLastError();
 }
 
