@@ -290,10 +290,10 @@ int sscg_matrix_format(sscg_ctx* ctx, const sscg_csr* A, int* format, int64_t* s
  * read (bit mask of SSCG_FMT_*, default all five; 0 = the stored FP64 values
  * with 32-bit indices).  For timing and testing the forms against each
  * other: every form gives the same bits.  Value tables are only used together
- * with 16-bit offsets.  The pair and per-distance value forms serve the
- * single-system calls (sscg_solve, sscg_mpk and the other per-stage calls);
- * batches and servers read the slice-diagonal form one slice per wavefront
- * with per-row value codes. */
+ * with 16-bit offsets.  The pair and per-distance value forms serve the FP64
+ * passes of single systems (sscg_solve, sscg_mpk, sscg_mpk_newton); the FP32
+ * passes, batches and servers read the slice-diagonal form one slice per
+ * wavefront with per-row value codes. */
 int sscg_set_forms(sscg_ctx* ctx, int forms);
 
 /* Matrix powers (eqs. cg-krylovbasis, polybasiscg): Y is n x ncol, column-major
